@@ -1,0 +1,162 @@
+"""MI355X (gfx950) inverse ray shooting for microlensing magnification maps.
+
+Python binding of the C ABI in include/irs.h (libirs.so, built from csrc/).
+Argument marshalling only: every step of the path runs in the HIP kernels.
+Device buffers and streams may come from PyTorch tensors; the library itself
+does not depend on torch.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _ffi
+from ._ffi import (IRS_DIRECT, IRS_INTERP, IRS_FP64, IRS_FP32_KAHAN, IRS_SHEET_OFF,
+                   IRS_OUT_ON_DEVICE, EXPORTS, Params, GeometryInfo, MapStats)
+
+__all__ = ["IrsError", "make_params", "params_from_workload", "geometry", "Plan", "load",
+           "IRS_DIRECT", "IRS_INTERP", "IRS_FP64", "IRS_FP32_KAHAN", "EXPORTS"]
+
+load = _ffi.load
+
+_METHODS = {"direct": IRS_DIRECT, "interp": IRS_INTERP}
+_PRECISIONS = {"fp64": IRS_FP64, "fp32": IRS_FP32_KAHAN, "fp32_kahan": IRS_FP32_KAHAN}
+
+
+class IrsError(RuntimeError):
+    def __init__(self, status, where):
+        lib = _ffi.load()
+        msg = lib.irs_last_error().decode(errors="replace")
+        self.status = status
+        super().__init__(f"{where}: {_ffi.STATUS_NAMES.get(status, status)}: {msg}")
+
+
+def _check(status, where):
+    if status != 0:
+        raise IrsError(status, where)
+
+
+def make_params(kappa_star, kappa_c, gamma, source_side, npix, rays_per_pixel=0.0, n_rays=0,
+                border=-1.0, method="direct", precision="fp64", level2_spacing=0.0,
+                level2_ray_multiple=0.0, crit_eps=0.0, sheet=True) -> Params:
+    return Params(float(kappa_star), float(kappa_c), float(gamma), float(source_side),
+                  int(npix), float(rays_per_pixel), int(n_rays),
+                  float(-1.0 if border is None else border),
+                  _METHODS[method] if isinstance(method, str) else int(method),
+                  _PRECISIONS[precision] if isinstance(precision, str) else int(precision),
+                  float(level2_spacing or 0.0), float(level2_ray_multiple or 0.0),
+                  float(crit_eps), 0 if sheet else IRS_SHEET_OFF)
+
+
+def params_from_workload(w, method="direct", precision="fp64", **over) -> Params:
+    """Params from any object with the workload fields (kappa_star, kappa_c,
+    gamma, source_side, npix, rays_per_pixel, n_rays, level2_ray_multiple)."""
+    kw = dict(kappa_star=w.kappa_star, kappa_c=w.kappa_c, gamma=w.gamma,
+              source_side=w.source_side, npix=w.npix, rays_per_pixel=w.rays_per_pixel,
+              n_rays=w.n_rays, level2_ray_multiple=getattr(w, "level2_ray_multiple", 0.0),
+              method=method, precision=precision)
+    kw.update(over)
+    return make_params(**kw)
+
+
+def geometry(params: Params, n_lens: int = 0) -> dict:
+    """irs_geometry: the plan geometry on the host (no GPU needed)."""
+    lib = _ffi.load()
+    out = GeometryInfo()
+    _check(lib.irs_geometry(C.byref(params), int(n_lens), C.byref(out)), "irs_geometry")
+    return out.as_dict()
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _vp(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _dev_ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A plan: geometry + lenses resident on the current HIP device."""
+
+    def __init__(self, params: Params, x, y, m=None, stream=None):
+        lib = _ffi.load()
+        self._lib = lib
+        self.params = params
+        x, y, m = _f64(x), _f64(y), _f64(m)
+        if x.shape != y.shape or (m is not None and m.shape != x.shape):
+            raise ValueError("x, y (and m) must have the same length")
+        handle = C.c_void_p()
+        s = None if stream is None else C.c_void_p(int(stream))
+        _check(lib.irs_plan(C.byref(params), int(x.size), _vp(x), _vp(y), _vp(m), s,
+                            C.byref(handle)), "irs_plan")
+        self._h = handle
+        gi = GeometryInfo()
+        _check(lib.irs_plan_geometry(self._h, C.byref(gi)), "irs_plan_geometry")
+        self.geometry = gi.as_dict()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.irs_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def n_rays(self) -> int:
+        return self.geometry["nx"] * self.geometry["ny"]
+
+    def deflect_grid(self, first_ray: int, n: int, alpha=True, pixel=True):
+        """Per-ray alpha1, alpha2 (FP64) and pixel index (-1 off map), host arrays."""
+        a1 = np.empty(n) if alpha else None
+        a2 = np.empty(n) if alpha else None
+        px = np.empty(n, np.int64) if pixel else None
+        _check(self._lib.irs_deflect_grid(self._h, int(first_ray), int(n), _vp(a1), _vp(a2),
+                                          _vp(px), 0), "irs_deflect_grid")
+        return a1, a2, px
+
+    def deflect_grid_device(self, first_ray: int, n: int, a1, a2, px):
+        """Same as deflect_grid into caller-owned device tensors (any may be None)."""
+        _check(self._lib.irs_deflect_grid(self._h, int(first_ray), int(n),
+                                          None if a1 is None else _dev_ptr(a1),
+                                          None if a2 is None else _dev_ptr(a2),
+                                          None if px is None else _dev_ptr(px),
+                                          IRS_OUT_ON_DEVICE), "irs_deflect_grid")
+
+    def shoot_map(self):
+        """Full map on the host: (counts uint32 [npix, npix], stats dict)."""
+        npix = self.params.npix_side
+        counts = np.zeros(npix * npix, np.uint32)
+        st = MapStats()
+        _check(self._lib.irs_shoot_map(self._h, _vp(counts), C.byref(st), 0), "irs_shoot_map")
+        return counts.reshape(npix, npix), st.as_dict()
+
+    def shoot_rows(self, row0: int, nrows: int, counts):
+        """Add rows [row0, row0+nrows) into counts: a host uint32 array or a
+        device tensor of npix^2 32-bit integers.  Returns the stats dict."""
+        st = MapStats()
+        if isinstance(counts, np.ndarray):
+            if counts.dtype != np.uint32 or not counts.flags.c_contiguous:
+                raise ValueError("host counts must be a contiguous uint32 array")
+            _check(self._lib.irs_shoot_rows(self._h, int(row0), int(nrows), _vp(counts),
+                                            C.byref(st), 0), "irs_shoot_rows")
+        else:
+            _check(self._lib.irs_shoot_rows(self._h, int(row0), int(nrows), _dev_ptr(counts),
+                                            C.byref(st), IRS_OUT_ON_DEVICE), "irs_shoot_rows")
+        return st.as_dict()

@@ -1,0 +1,79 @@
+"""ctypes declarations of the C ABI in include/irs.h (marshalling only)."""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libirs.so")
+
+IRS_OK, IRS_E_INVALID, IRS_E_CRITICAL, IRS_E_NOMEM, IRS_E_DEVICE, IRS_E_UNSUPPORTED = range(6)
+STATUS_NAMES = {0: "IRS_OK", 1: "IRS_E_INVALID", 2: "IRS_E_CRITICAL", 3: "IRS_E_NOMEM",
+                4: "IRS_E_DEVICE", 5: "IRS_E_UNSUPPORTED"}
+IRS_DIRECT, IRS_INTERP = 0, 1
+IRS_FP64, IRS_FP32_KAHAN = 0, 1
+IRS_SHEET_OFF = 1 << 0
+IRS_OUT_ON_DEVICE = 1 << 8
+
+# every function include/irs.h declares
+EXPORTS = ("irs_geometry", "irs_plan", "irs_deflect_grid", "irs_shoot_rows", "irs_shoot_map",
+           "irs_plan_geometry", "irs_free", "irs_last_error")
+
+
+class Params(C.Structure):
+    _fields_ = [("kappa_star", C.c_double), ("kappa_c", C.c_double), ("gamma", C.c_double),
+                ("source_side", C.c_double), ("npix_side", C.c_int64),
+                ("rays_per_pixel", C.c_double), ("n_rays", C.c_int64), ("border", C.c_double),
+                ("method", C.c_int32), ("precision", C.c_int32),
+                ("level2_spacing", C.c_double), ("level2_ray_multiple", C.c_double),
+                ("crit_eps", C.c_double), ("flags", C.c_uint64)]
+
+
+class GeometryInfo(C.Structure):
+    _fields_ = [("kappa", C.c_double), ("border", C.c_double), ("ix", C.c_double),
+                ("iy", C.c_double), ("a1", C.c_double), ("a2", C.c_double), ("b1", C.c_double),
+                ("b2", C.c_double), ("n_rays_target", C.c_int64), ("dx3", C.c_double),
+                ("nx", C.c_int64), ("ny", C.c_int64), ("ray_dx", C.c_double),
+                ("ray_dy", C.c_double), ("n_lens", C.c_int64), ("dx1", C.c_double),
+                ("n1x", C.c_int64), ("n1y", C.c_int64), ("dx2", C.c_double), ("q", C.c_int64),
+                ("dpix", C.c_double), ("s_img", C.c_double), ("s_src", C.c_double),
+                ("mu_th", C.c_double), ("n_stars_expected", C.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class MapStats(C.Structure):
+    _fields_ = [("rays_shot", C.c_int64), ("rays_landed", C.c_int64), ("rays_off", C.c_int64),
+                ("n_lens", C.c_int64), ("kappa_star_eff", C.c_double), ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libirs.so, failing loudly when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is missing: build it first "
+                           "(python -m paper_2204_10871_amd.build or __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    P, vp, i64, u64 = C.POINTER, C.c_void_p, C.c_int64, C.c_uint64
+    lib.irs_geometry.argtypes = [P(Params), i64, P(GeometryInfo)]
+    lib.irs_plan.argtypes = [P(Params), i64, vp, vp, vp, vp, P(vp)]
+    lib.irs_deflect_grid.argtypes = [vp, i64, i64, vp, vp, vp, u64]
+    lib.irs_shoot_rows.argtypes = [vp, i64, i64, vp, P(MapStats), u64]
+    lib.irs_shoot_map.argtypes = [vp, vp, P(MapStats), u64]
+    lib.irs_plan_geometry.argtypes = [vp, P(GeometryInfo)]
+    lib.irs_free.argtypes = [vp]
+    lib.irs_free.restype = None
+    lib.irs_last_error.argtypes = []
+    lib.irs_last_error.restype = C.c_char_p
+    for name in ("irs_geometry", "irs_plan", "irs_deflect_grid", "irs_shoot_rows",
+                 "irs_shoot_map", "irs_plan_geometry"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib

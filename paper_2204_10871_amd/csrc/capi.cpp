@@ -1,0 +1,334 @@
+// C ABI of the ray-shooting library: argument checks, plan lifetime, output
+// staging between host and device, and error reporting.  All arithmetic of
+// the path runs in the kernels (k_level1.hip, k_direct.hip, k_interp.hip).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace irs {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+irs_status hip_fail(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory) return IRS_E_NOMEM;
+    return IRS_E_DEVICE;
+}
+
+namespace {
+
+DevGeom make_dev_geom(const HostGeometry &hg)
+{
+    const irs_geometry_info &g = hg.info;
+    DevGeom d{};
+    d.a1 = g.a1;
+    d.a2 = g.a2;
+    d.b1 = g.b1;
+    d.b2 = g.b2;
+    d.ray_dx = g.ray_dx;
+    d.ray_dy = g.ray_dy;
+    d.nx = g.nx;
+    d.ny = g.ny;
+    d.kappa_star = hg.kappa_star;
+    d.kpg = g.kappa + hg.gamma;
+    d.kmg = g.kappa - hg.gamma;
+    d.half_side = 0.5 * hg.source_side;
+    d.dpix = g.dpix;
+    d.npix = (int32_t)hg.npix;
+    d.sheet = hg.sheet ? 1 : 0;
+    d.n1x = (int32_t)g.n1x;
+    d.n1y = (int32_t)g.n1y;
+    d.q = (int32_t)g.q;
+    d.w1 = (g.a2 - g.a1) / (double)g.n1x;
+    d.h1 = (g.b2 - g.b1) / (double)g.n1y;
+    d.w2 = (g.a2 - g.a1) / (double)(g.n1x * g.q);
+    d.h2 = (g.b2 - g.b1) / (double)(g.n1y * g.q);
+    return d;
+}
+
+void release(irs_plan_s *p)
+{
+    if (!p) return;
+    dev_free(p->d_x);
+    dev_free(p->d_y);
+    dev_free(p->d_m);
+    dev_free(p->d_cell_start);
+    dev_free(p->d_coef);
+    dev_free(p->d_counts);
+    dev_free(p->d_tmp);
+    dev_free(p->d_landed);
+    delete p;
+}
+
+irs_status ensure_tmp(irs_plan_s *p, size_t bytes)
+{
+    if (p->tmp_bytes >= bytes) return IRS_OK;
+    dev_free(p->d_tmp);
+    p->d_tmp = nullptr;
+    p->tmp_bytes = 0;
+    IRS_HIP(hipMalloc(&p->d_tmp, bytes));
+    p->tmp_bytes = bytes;
+    return IRS_OK;
+}
+
+irs_status run(irs_plan_s *p, const RaySel &sel)
+{
+    if (p->params.method == IRS_DIRECT) return launch_direct(p, sel);
+    return launch_interp(p, sel);
+}
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    explicit Timer(hipStream_t st) : s(st)
+    {
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) a = b = nullptr;
+        if (a) (void)hipEventRecord(a, s);
+    }
+    double stop()
+    {
+        float ms = 0.0f;
+        if (a && hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess)
+            (void)hipEventElapsedTime(&ms, a, b);
+        return ms;
+    }
+    ~Timer()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+}  // namespace
+}  // namespace irs
+
+using namespace irs;
+
+extern "C" {
+
+const char *irs_last_error(void) { return g_last_error.c_str(); }
+
+irs_status irs_geometry(const irs_params *params, int64_t n_lens, irs_geometry_info *out)
+{
+    if (!params || !out) {
+        set_error("irs_geometry: NULL argument");
+        return IRS_E_INVALID;
+    }
+    HostGeometry hg;
+    std::string err;
+    const irs_status st = derive_geometry(*params, n_lens, hg, err);
+    if (st != IRS_OK) {
+        set_error("irs_geometry: " + err);
+        return st;
+    }
+    *out = hg.info;
+    set_error("");
+    return IRS_OK;
+}
+
+irs_status irs_plan(const irs_params *params, int64_t n_lens, const double *x, const double *y,
+                    const double *m, void *hip_stream, irs_plan_t *out)
+{
+    if (out) *out = nullptr;
+    if (!params || !out || (n_lens > 0 && (!x || !y))) {
+        set_error("irs_plan: NULL argument");
+        return IRS_E_INVALID;
+    }
+    HostGeometry hg;
+    std::string err;
+    irs_status st = derive_geometry(*params, n_lens, hg, err);
+    if (st != IRS_OK) {
+        set_error("irs_plan: " + err);
+        return st;
+    }
+    double msum = 0.0;
+    for (int64_t i = 0; i < n_lens; ++i) {
+        if (!std::isfinite(x[i]) || !std::isfinite(y[i]) || (m && !(std::isfinite(m[i]) && m[i] >= 0.0))) {
+            set_error("irs_plan: lens positions must be finite and masses finite and >= 0");
+            return IRS_E_INVALID;
+        }
+        msum += m ? m[i] : 1.0;
+    }
+    irs_plan_s *p = new (std::nothrow) irs_plan_s();
+    if (!p) {
+        set_error("irs_plan: host allocation failed");
+        return IRS_E_NOMEM;
+    }
+    p->params = *params;
+    p->geo = hg;
+    p->dg = make_dev_geom(hg);
+    p->stream = (hipStream_t)hip_stream;
+    p->n_lens = n_lens;
+    p->unit_mass = (m == nullptr);
+    p->kappa_star_eff = M_PI * msum / (hg.info.ix * hg.info.iy);
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        st = hip_fail(e, "hipGetDevice");
+        release(p);
+        return st;
+    }
+    e = hipMalloc(&p->d_landed, sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        st = hip_fail(e, "hipMalloc");
+        release(p);
+        return st;
+    }
+    st = pack_level1(p, x, y, m);
+    if (st != IRS_OK) {
+        release(p);
+        return st;
+    }
+    *out = p;
+    set_error("");
+    return IRS_OK;
+}
+
+irs_status irs_plan_geometry(irs_plan_t plan, irs_geometry_info *out)
+{
+    if (!plan || !out) {
+        set_error("irs_plan_geometry: NULL argument");
+        return IRS_E_INVALID;
+    }
+    *out = plan->geo.info;
+    return IRS_OK;
+}
+
+irs_status irs_deflect_grid(irs_plan_t plan, int64_t first_ray, int64_t n, double *alpha1,
+                            double *alpha2, int64_t *pixel, uint64_t flags)
+{
+    if (!plan) {
+        set_error("irs_deflect_grid: NULL plan");
+        return IRS_E_INVALID;
+    }
+    const irs_geometry_info &g = plan->geo.info;
+    const int64_t total = g.nx * g.ny;
+    if (first_ray < 0 || n < 0 || first_ray > total || n > total - first_ray) {
+        set_error("irs_deflect_grid: ray range outside [0, nx*ny)");
+        return IRS_E_INVALID;
+    }
+    if (n == 0) return IRS_OK;
+    const bool on_dev = (flags & IRS_OUT_ON_DEVICE) != 0;
+    RaySel sel{};
+    sel.row0 = first_ray / g.nx;
+    sel.row1 = (first_ray + n - 1) / g.nx + 1;
+    sel.ray_first = first_ray;
+    sel.ray_last = first_ray + n;
+    irs_status st;
+    if (on_dev) {
+        sel.alpha1 = alpha1;
+        sel.alpha2 = alpha2;
+        sel.pixel = pixel;
+    } else {
+        const size_t per = (size_t)n * sizeof(double);
+        st = ensure_tmp(plan, 3 * per);
+        if (st != IRS_OK) return st;
+        char *base = (char *)plan->d_tmp;
+        sel.alpha1 = alpha1 ? (double *)base : nullptr;
+        sel.alpha2 = alpha2 ? (double *)(base + per) : nullptr;
+        sel.pixel = pixel ? (int64_t *)(base + 2 * per) : nullptr;
+    }
+    st = run(plan, sel);
+    if (st != IRS_OK) return st;
+    if (!on_dev) {
+        const size_t per = (size_t)n * sizeof(double);
+        if (alpha1) IRS_HIP(hipMemcpyAsync(alpha1, sel.alpha1, per, hipMemcpyDeviceToHost, plan->stream));
+        if (alpha2) IRS_HIP(hipMemcpyAsync(alpha2, sel.alpha2, per, hipMemcpyDeviceToHost, plan->stream));
+        if (pixel) IRS_HIP(hipMemcpyAsync(pixel, sel.pixel, per, hipMemcpyDeviceToHost, plan->stream));
+    }
+    IRS_HIP(hipStreamSynchronize(plan->stream));
+    set_error("");
+    return IRS_OK;
+}
+
+static irs_status shoot(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t *counts,
+                        irs_map_stats *stats, uint64_t flags, bool overwrite, const char *who)
+{
+    if (!plan || !counts) {
+        set_error(std::string(who) + ": NULL argument");
+        return IRS_E_INVALID;
+    }
+    const irs_geometry_info &g = plan->geo.info;
+    if (row0 < 0 || nrows < 0 || row0 > g.ny || nrows > g.ny - row0) {
+        set_error(std::string(who) + ": row range outside [0, ny)");
+        return IRS_E_INVALID;
+    }
+    const bool on_dev = (flags & IRS_OUT_ON_DEVICE) != 0;
+    const size_t map_bytes = sizeof(uint32_t) * (size_t)plan->geo.npix * (size_t)plan->geo.npix;
+    hipStream_t s = plan->stream;
+    Timer timer(s);
+    uint32_t *dst = counts;
+    if (!on_dev) {
+        if (!plan->d_counts) IRS_HIP(hipMalloc(&plan->d_counts, map_bytes));
+        dst = plan->d_counts;
+    }
+    if (!on_dev || overwrite) IRS_HIP(hipMemsetAsync(dst, 0, map_bytes, s));
+    IRS_HIP(hipMemsetAsync(plan->d_landed, 0, sizeof(unsigned long long), s));
+    RaySel sel{};
+    sel.row0 = row0;
+    sel.row1 = row0 + nrows;
+    sel.ray_first = 0;
+    sel.ray_last = g.nx * g.ny;
+    sel.counts = dst;
+    sel.landed = plan->d_landed;
+    irs_status st = run(plan, sel);
+    if (st != IRS_OK) return st;
+    unsigned long long landed = 0;
+    IRS_HIP(hipMemcpyAsync(&landed, plan->d_landed, sizeof landed, hipMemcpyDeviceToHost, s));
+    if (!on_dev) {
+        std::vector<uint32_t> tmp((size_t)plan->geo.npix * (size_t)plan->geo.npix);
+        IRS_HIP(hipMemcpyAsync(tmp.data(), dst, map_bytes, hipMemcpyDeviceToHost, s));
+        IRS_HIP(hipStreamSynchronize(s));
+        if (overwrite) std::memcpy(counts, tmp.data(), map_bytes);
+        else
+            for (size_t k = 0; k < tmp.size(); ++k) counts[k] += tmp[k];
+    }
+    IRS_HIP(hipStreamSynchronize(s));
+    const double ms = timer.stop();
+    if (stats) {
+        stats->rays_shot = nrows * g.nx;
+        stats->rays_landed = (int64_t)landed;
+        stats->rays_off = stats->rays_shot - stats->rays_landed;
+        stats->n_lens = plan->n_lens;
+        stats->kappa_star_eff = plan->kappa_star_eff;
+        stats->ms_total = ms;
+    }
+    set_error("");
+    return IRS_OK;
+}
+
+irs_status irs_shoot_rows(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t *counts,
+                          irs_map_stats *stats, uint64_t flags)
+{
+    return shoot(plan, row0, nrows, counts, stats, flags, false, "irs_shoot_rows");
+}
+
+irs_status irs_shoot_map(irs_plan_t plan, uint32_t *counts, irs_map_stats *stats,
+                         uint64_t flags)
+{
+    if (!plan) {
+        set_error("irs_shoot_map: NULL plan");
+        return IRS_E_INVALID;
+    }
+    return shoot(plan, 0, plan->geo.info.ny, counts, stats, flags, true, "irs_shoot_map");
+}
+
+void irs_free(irs_plan_t plan)
+{
+    if (!plan) return;
+    (void)hipStreamSynchronize(plan->stream);
+    release(plan);
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Device-side helpers shared by the ray-shooting kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace irs {
+
+// Geometry as the kernels see it; filled on the host from the plan.
+struct DevGeom {
+    double a1, a2, b1, b2;      // lens/image rectangle
+    double ray_dx, ray_dy;      // ray spacing (rays at cell centres)
+    int64_t nx, ny;             // ray grid
+    double kappa_star;          // sheet density
+    double kpg, kmg;            // kappa + gamma, kappa - gamma (macro term, Eq. 6)
+    double half_side, dpix;     // S/2 and S/npix: map [-S/2, S/2)^2
+    int32_t npix;               // pixels per side
+    int32_t sheet;              // 1: include the negative sheet
+    int32_t n1x, n1y;           // level-1 cells
+    int32_t q;                  // level-2 points per level-1 cell side
+    int32_t pad_;
+    double w1, h1;              // level-1 cell sides (I_x/n1x, I_y/n1y)
+    double w2, h2;              // level-2 subcell sides (w1/q, h1/q)
+};
+
+constexpr int kWave = 64;
+
+// theta of ray column i / row j, rounded as a1 + (i + 1/2) dx with the
+// product and the sum rounded separately (contraction into an fma is switched
+// off here), so that rays sit exactly where the geometry puts them: a one-ulp
+// shift of theta changes the term of a lens at distance d by ulp/d.
+__device__ __forceinline__ double ray_x(const DevGeom &g, int64_t i)
+{
+#pragma clang fp contract(off)
+    return g.a1 + ((double)i + 0.5) * g.ray_dx;
+}
+__device__ __forceinline__ double ray_y(const DevGeom &g, int64_t j)
+{
+#pragma clang fp contract(off)
+    return g.b1 + ((double)j + 0.5) * g.ray_dy;
+}
+
+// Level-2 column/row of ray column i / row j: the level-2 grid splits the
+// rectangle into n1x*q columns, so the ray at (i + 1/2) ray_dx lies in column
+// floor((2i+1) n1x q / (2 nx)) -- exact integer arithmetic, no rounding.
+__device__ __forceinline__ int64_t level2_col(const DevGeom &g, int64_t i)
+{
+    return ((2 * i + 1) * (int64_t)g.n1x * g.q) / (2 * g.nx);
+}
+__device__ __forceinline__ int64_t level2_row(const DevGeom &g, int64_t j)
+{
+    return ((2 * j + 1) * (int64_t)g.n1y * g.q) / (2 * g.ny);
+}
+
+// Deflection of a uniform sheet of unit density over the rectangle, times pi
+// (the two closed-form integrals of Appendix A with A = 1), arranged as a sum
+// over the four corners: with u = theta_1 - a, v = theta_2 - b and sign +1 at
+// (a1,b1), (a2,b2) and -1 at (a2,b1), (a1,b2),
+//   I1 = sum sign * [ v/2 ln(u^2+v^2) + u atan(v/u) ]
+//   I2 = sum sign * [ u/2 ln(u^2+v^2) + v atan(u/v) ]
+// (p atan(q/p) and p ln(.) are taken as 0 where p = 0).  The negative sheet's
+// deflection is -(kappa_*/pi) (I1, I2).
+__device__ __forceinline__ void sheet_unit(const DevGeom &g, double t1, double t2,
+                                           double &I1, double &I2)
+{
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double a = (c == 0 || c == 3) ? g.a1 : g.a2;
+        const double b = (c < 2) ? g.b1 : g.b2;
+        const double sgn = (c == 0 || c == 2) ? 1.0 : -1.0;   // (a1,b1) (a2,b1) (a2,b2) (a1,b2)
+        const double u = t1 - a, v = t2 - b;
+        const double lr = log(u * u + v * v);
+        const double tu = (u != 0.0) ? u * atan(v / u) : 0.0;
+        const double tv = (v != 0.0) ? v * atan(u / v) : 0.0;
+        const double lv = (v != 0.0) ? 0.5 * v * lr : 0.0;
+        const double lu = (u != 0.0) ? 0.5 * u * lr : 0.0;
+        s1 += sgn * (lv + tu);
+        s2 += sgn * (lu + tv);
+    }
+    I1 = s1;
+    I2 = s2;
+}
+
+// Source pixel of beta, -1 off the map.
+__device__ __forceinline__ int32_t pixel_of(const DevGeom &g, double b1, double b2)
+{
+    const double fx = floor((b1 + g.half_side) / g.dpix);
+    const double fy = floor((b2 + g.half_side) / g.dpix);
+    const double n = (double)g.npix;
+    if (!(fx >= 0.0 && fx < n && fy >= 0.0 && fy < n)) return -1;
+    return (int32_t)fy * g.npix + (int32_t)fx;
+}
+
+// Wavefront-aggregated histogram update: lanes hitting the same pixel are
+// merged (ballot on the leader's pixel) and one lane issues a single atomic
+// with the group's count.  Must be called by every lane of the wave
+// (pix = -1 for lanes with nothing to add).
+__device__ __forceinline__ void bin_wave(uint32_t *__restrict__ counts, int32_t pix)
+{
+    uint64_t todo = __ballot(pix >= 0);
+    const int lane = (int)__lane_id();
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int32_t lp = __shfl(pix, leader);
+        const uint64_t same = __ballot(pix == lp) & todo;
+        if (lane == leader) atomicAdd(&counts[lp], (uint32_t)__popcll(same));
+        todo &= ~same;
+    }
+}
+
+}  // namespace irs

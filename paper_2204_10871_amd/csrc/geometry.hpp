@@ -1,0 +1,28 @@
+// Host-side plan geometry (no HIP dependency).
+//
+// Sizing rules follow the flow chart of Sec. 2.4: protective border
+// P = 10 sqrt(kappa_*), rectangle I_x = (S+2P)/|1-kappa-gamma|,
+// I_y = (S+2P)/|1-kappa+gamma|; level-1 resolution min(L0, min(I_x,I_y)/10)
+// with L0 = sqrt(I_x I_y / N_*); level-2 resolution dx1/20; level-3 (ray)
+// resolution sqrt(I_x I_y / N_rays) with N_rays = N_av N_pix.
+#pragma once
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/irs.h"
+
+namespace irs {
+
+struct HostGeometry {
+    irs_geometry_info info;
+    double kappa_star, kappa_c, gamma, source_side;
+    int64_t npix;
+    bool sheet;
+};
+
+// Fills `out` or returns an error status with a message in `err`.
+irs_status derive_geometry(const irs_params &p, int64_t n_lens, HostGeometry &out,
+                           std::string &err);
+
+}  // namespace irs

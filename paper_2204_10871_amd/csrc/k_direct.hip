@@ -1,0 +1,343 @@
+// Direct ray shooting: every ray sums every lens (Eq. 6), then the macro term
+// and the rectangle's negative sheet (Appendix A), the mapping
+// beta = theta - alpha (Eq. 4) and the source-pixel binning.  This is the
+// ordinary IRS the paper compares against (Sec. 3.1), whose cost grows as
+// N_rays * N_* (Eq. 12).
+//
+// Two kernels:
+//   k_direct_f64  -- plain double precision, one ray per lane, lens tiles in LDS.
+//   k_direct_f32  -- the FP32 VALU-bound form: each workgroup owns a compact
+//                    64 x 16 tile of rays and works in coordinates relative to
+//                    the tile centre (rounded to FP32 from FP64 once per
+//                    lens and tile), lens tiles are staged in LDS and read as
+//                    broadcasts, four rays per lane share every LDS read, and
+//                    each ray's sum is compensated: 32 lenses are summed
+//                    plainly, then added with Kahan's correction.  The lenses
+//                    of the 3 x 3 level-1 cells around the ray are then
+//                    re-evaluated in FP64 and the difference to their FP32
+//                    terms is added (FP32 quantisation of a lens at distance d
+//                    errs by ~1e-7/d^2, which only matters close by).  The
+//                    macro term, the sheet and beta are assembled in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "plan.hpp"
+
+namespace irs {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / kWave;
+
+// -------------------------------------------------------------------------
+// Epilogue shared by both kernels: macro term + sheet + beta + pixel.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ void assemble(const DevGeom &g, double t1, double t2, double s1,
+                                         double s2, double &a1, double &a2, int32_t &pix)
+{
+    double h1 = 0.0, h2 = 0.0;
+    if (g.sheet) {
+        double I1, I2;
+        sheet_unit(g, t1, t2, I1, I2);
+        const double f = -g.kappa_star / M_PI;
+        h1 = f * I1;
+        h2 = f * I2;
+    }
+    a1 = g.kpg * t1 + s1 + h1;
+    a2 = g.kmg * t2 + s2 + h2;
+    pix = pixel_of(g, t1 - a1, t2 - a2);
+}
+
+// Per-ray output or binning, called by every lane.
+__device__ __forceinline__ void emit(bool valid, int64_t out_idx, double a1, double a2,
+                                     int32_t pix, double *a1o, double *a2o, int64_t *pixo,
+                                     uint32_t *counts, unsigned long long *landed)
+{
+    if (counts) {
+        const int32_t pv = valid ? pix : -1;
+        bin_wave(counts, pv);
+        const uint64_t got = __ballot(pv >= 0);
+        if (__lane_id() == 0 && got) atomicAdd(landed, (unsigned long long)__popcll(got));
+    } else if (valid) {
+        if (a1o) a1o[out_idx] = a1;
+        if (a2o) a2o[out_idx] = a2;
+        if (pixo) pixo[out_idx] = pix;
+    }
+}
+
+// -------------------------------------------------------------------------
+// FP64
+// -------------------------------------------------------------------------
+constexpr int kLens64 = 256;
+
+template <bool UNIT>
+__global__ __launch_bounds__(kThreads) void k_direct_f64(
+    DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
+    const double *__restrict__ lm, int32_t nl, int64_t r_begin, int64_t r_end,
+    int64_t out_base, double *a1o, double *a2o, int64_t *pixo, uint32_t *counts,
+    unsigned long long *landed)
+{
+    __shared__ double s_x[kLens64], s_y[kLens64], s_m[UNIT ? 1 : kLens64];
+    const int tid = threadIdx.x;
+    const int64_t r = r_begin + (int64_t)blockIdx.x * kThreads + tid;
+    const bool valid = r < r_end;
+    const int64_t rr = valid ? r : r_begin;
+    const double t1 = ray_x(g, rr % g.nx), t2 = ray_y(g, rr / g.nx);
+    double s1 = 0.0, s2 = 0.0;
+    for (int32_t base = 0; base < nl; base += kLens64) {
+        __syncthreads();
+        if (base + tid < nl) {
+            s_x[tid] = lx[base + tid];
+            s_y[tid] = ly[base + tid];
+            if (!UNIT) s_m[tid] = lm[base + tid];
+        }
+        __syncthreads();
+        const int cnt = min(kLens64, nl - base);
+        for (int t = 0; t < cnt; ++t) {
+            const double d1 = t1 - s_x[t], d2 = t2 - s_y[t];
+            const double r2 = d1 * d1 + d2 * d2;
+            if (r2 > 0.0) {
+                const double w = (UNIT ? 1.0 : s_m[t]) / r2;
+                s1 += w * d1;
+                s2 += w * d2;
+            }
+        }
+    }
+    double a1, a2;
+    int32_t pix;
+    assemble(g, t1, t2, s1, s2, a1, a2, pix);
+    emit(valid, r - out_base, a1, a2, pix, a1o, a2o, pixo, counts, landed);
+}
+
+// -------------------------------------------------------------------------
+// FP32 with compensation
+// -------------------------------------------------------------------------
+constexpr int kTX = kWave;            // ray columns per tile: one per lane
+constexpr int kRPT = 4;               // ray rows per lane
+constexpr int kTY = kRPT * kWaves;    // ray rows per tile
+constexpr int kLT = 512;              // lenses per LDS stage
+constexpr int kChunk = 32;            // lenses per uncompensated partial sum
+constexpr float kTiny = 1e-30f;       // keeps 1/r^2 finite for a lens on a ray
+
+// 1/r^2 for an FP32 offset: hardware reciprocal refined by one Newton step,
+// so that the result is (nearly) correctly rounded and unbiased.  A lens on
+// the ray gives r^2 = kTiny and a zero term (its offset is 0).
+__device__ __forceinline__ float inv_r2(float d1, float d2)
+{
+    const float r2 = fmaf(d2, d2, fmaf(d1, d1, kTiny));
+    const float v = __builtin_amdgcn_rcpf(r2);
+    const float e = fmaf(-r2, v, 1.0f);
+    return fmaf(v, e, v);
+}
+
+__device__ __forceinline__ void kahan_add(float &s, float &c, float x)
+{
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+template <bool UNIT>
+__global__ __launch_bounds__(kThreads) void k_direct_f32(
+    DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
+    const double *__restrict__ lm, const int32_t *__restrict__ cell_start, int32_t nl,
+    int64_t ntx, int64_t ty0, int64_t row0, int64_t row1, int64_t ray_first,
+    int64_t ray_last, double *a1o, double *a2o, int64_t *pixo, uint32_t *counts,
+    unsigned long long *landed)
+{
+    __shared__ float4 s_x4[kLT / 4], s_y4[kLT / 4], s_m4[UNIT ? 1 : kLT / 4];
+    float *s_x = reinterpret_cast<float *>(s_x4);
+    float *s_y = reinterpret_cast<float *>(s_y4);
+    float *s_m = reinterpret_cast<float *>(s_m4);
+
+    const int tid = threadIdx.x;
+    const int lane = tid % kWave, wave = tid / kWave;
+    const int64_t tx = (int64_t)blockIdx.x % ntx;
+    const int64_t ty = ty0 + (int64_t)blockIdx.x / ntx;
+
+    // tile origin (FP64) and this lane's rays in tile-local FP32 coordinates
+    const double ox = ray_x(g, tx * kTX + kTX / 2);
+    const double oy = ray_y(g, ty * kTY + kTY / 2);
+    const int64_t i = tx * kTX + lane;
+    const double t1 = ray_x(g, i);
+    const float xr = (float)(t1 - ox);
+    float yr[kRPT];
+    int64_t jrow[kRPT];
+#pragma unroll
+    for (int k = 0; k < kRPT; ++k) {
+        jrow[k] = ty * kTY + wave * kRPT + k;
+        yr[k] = (float)(ray_y(g, jrow[k]) - oy);
+    }
+
+    float in1[kRPT], in2[kRPT], s1[kRPT], c1[kRPT], s2[kRPT], c2[kRPT];
+#pragma unroll
+    for (int k = 0; k < kRPT; ++k) in1[k] = in2[k] = s1[k] = c1[k] = s2[k] = c2[k] = 0.0f;
+
+    for (int32_t base = 0; base < nl; base += kLT) {
+        __syncthreads();
+        for (int t = tid; t < kLT; t += kThreads) {
+            const int32_t li = base + t;
+            if (li < nl) {
+                s_x[t] = (float)(lx[li] - ox);
+                s_y[t] = (float)(ly[li] - oy);
+                if (!UNIT) s_m[t] = (float)lm[li];
+            }
+        }
+        __syncthreads();
+        const int cnt = min(kLT, nl - base);
+        const int full = cnt - cnt % kChunk;
+        for (int c = 0; c < full; c += kChunk) {
+#pragma unroll
+            for (int t = 0; t < kChunk; t += 4) {
+                const float4 X = s_x4[(c + t) / 4];
+                const float4 Y = s_y4[(c + t) / 4];
+                float4 M;
+                if (!UNIT) M = s_m4[(c + t) / 4];
+                const float xs[4] = {X.x, X.y, X.z, X.w};
+                const float ys[4] = {Y.x, Y.y, Y.z, Y.w};
+                float ms[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+                if (!UNIT) { ms[0] = M.x; ms[1] = M.y; ms[2] = M.z; ms[3] = M.w; }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float d1 = xr - xs[u];
+#pragma unroll
+                    for (int k = 0; k < kRPT; ++k) {
+                        const float d2 = yr[k] - ys[u];
+                        float w = inv_r2(d1, d2);
+                        if (!UNIT) w = ms[u] * w;
+                        in1[k] = fmaf(d1, w, in1[k]);
+                        in2[k] = fmaf(d2, w, in2[k]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kRPT; ++k) {
+                kahan_add(s1[k], c1[k], in1[k]);
+                kahan_add(s2[k], c2[k], in2[k]);
+                in1[k] = in2[k] = 0.0f;
+            }
+        }
+        if (full < cnt) {
+            for (int t = full; t < cnt; ++t) {
+                const float d1 = xr - s_x[t];
+                const float m = UNIT ? 1.0f : s_m[t];
+#pragma unroll
+                for (int k = 0; k < kRPT; ++k) {
+                    const float d2 = yr[k] - s_y[t];
+                    float w = inv_r2(d1, d2);
+                    if (!UNIT) w = m * w;
+                    in1[k] = fmaf(d1, w, in1[k]);
+                    in2[k] = fmaf(d2, w, in2[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kRPT; ++k) {
+                kahan_add(s1[k], c1[k], in1[k]);
+                kahan_add(s2[k], c2[k], in2[k]);
+                in1[k] = in2[k] = 0.0f;
+            }
+        }
+    }
+
+    // FP64 near-lens residual, assembly and output, ray by ray
+    const int64_t cx = ((2 * i + 1) * (int64_t)g.n1x) / (2 * g.nx);
+    const int64_t cxl = cx > 0 ? cx - 1 : 0;
+    const int64_t cxh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
+#pragma unroll
+    for (int k = 0; k < kRPT; ++k) {
+        const int64_t j = jrow[k];
+        const int64_t r = j * g.nx + i;
+        const bool valid = i < g.nx && j >= row0 && j < row1 && r >= ray_first && r < ray_last;
+        const double t2 = ray_y(g, j < g.ny ? j : g.ny - 1);
+        double sum1 = (double)s1[k] - (double)c1[k];
+        double sum2 = (double)s2[k] - (double)c2[k];
+        if (valid) {
+            const int64_t cy = ((2 * j + 1) * (int64_t)g.n1y) / (2 * g.ny);
+            const int64_t cyl = cy > 0 ? cy - 1 : 0;
+            const int64_t cyh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
+            double r1 = 0.0, r2s = 0.0;
+            for (int64_t row = cyl; row <= cyh; ++row) {
+                const int32_t pb = cell_start[row * g.n1x + cxl];
+                const int32_t pe = cell_start[row * g.n1x + cxh + 1];
+                for (int32_t pl = pb; pl < pe; ++pl) {
+                    const double X = lx[pl], Y = ly[pl];
+                    const double m64 = UNIT ? 1.0 : lm[pl];
+                    // the FP32 term exactly as the main loop formed it
+                    const float d1f = xr - (float)(X - ox);
+                    const float d2f = yr[k] - (float)(Y - oy);
+                    float w = inv_r2(d1f, d2f);
+                    if (!UNIT) w = (float)m64 * w;
+                    // the FP64 term
+                    const double e1 = t1 - X, e2 = t2 - Y;
+                    const double rr2 = e1 * e1 + e2 * e2;
+                    const double w64 = rr2 > 0.0 ? m64 / rr2 : 0.0;
+                    r1 += w64 * e1 - (double)d1f * (double)w;
+                    r2s += w64 * e2 - (double)d2f * (double)w;
+                }
+            }
+            sum1 += r1;
+            sum2 += r2s;
+        }
+        double a1, a2;
+        int32_t pix;
+        assemble(g, t1, t2, sum1, sum2, a1, a2, pix);
+        emit(valid, r - ray_first, a1, a2, pix, a1o, a2o, pixo, counts, landed);
+    }
+}
+
+}  // namespace
+
+irs_status launch_direct(irs_plan_s *p, const RaySel &sel)
+{
+    const DevGeom &g = p->dg;
+    const int32_t nl = (int32_t)p->n_lens;
+    hipStream_t s = p->stream;
+    const bool unit = p->unit_mass;
+    if (sel.row1 <= sel.row0) return IRS_OK;
+
+    if (p->params.precision == IRS_FP64) {
+        const int64_t rb = std::max(sel.row0 * g.nx, sel.ray_first);
+        const int64_t re = std::min(sel.row1 * g.nx, sel.ray_last);
+        const int64_t chunk = (int64_t)kThreads << 22;   // rays per launch
+        for (int64_t c0 = rb; c0 < re; c0 += chunk) {
+            const int64_t c1 = std::min(re, c0 + chunk);
+            const unsigned nb = (unsigned)((c1 - c0 + kThreads - 1) / kThreads);
+            if (unit)
+                hipLaunchKernelGGL(k_direct_f64<true>, dim3(nb), dim3(kThreads), 0, s, g, p->d_x,
+                                   p->d_y, p->d_m, nl, c0, c1, sel.ray_first, sel.alpha1,
+                                   sel.alpha2, sel.pixel, sel.counts, sel.landed);
+            else
+                hipLaunchKernelGGL(k_direct_f64<false>, dim3(nb), dim3(kThreads), 0, s, g,
+                                   p->d_x, p->d_y, p->d_m, nl, c0, c1, sel.ray_first,
+                                   sel.alpha1, sel.alpha2, sel.pixel, sel.counts, sel.landed);
+            IRS_HIP(hipGetLastError());
+        }
+        return IRS_OK;
+    }
+
+    const int64_t ntx = (g.nx + kTX - 1) / kTX;
+    const int64_t ty_lo = sel.row0 / kTY;
+    const int64_t ty_hi = (sel.row1 - 1) / kTY;          // inclusive
+    const int64_t max_rows_of_tiles = std::max<int64_t>(1, ((int64_t)1 << 22) / ntx);
+    for (int64_t t0 = ty_lo; t0 <= ty_hi; t0 += max_rows_of_tiles) {
+        const int64_t t1 = std::min(ty_hi + 1, t0 + max_rows_of_tiles);
+        const unsigned nb = (unsigned)((t1 - t0) * ntx);
+        if (unit)
+            hipLaunchKernelGGL(k_direct_f32<true>, dim3(nb), dim3(kThreads), 0, s, g, p->d_x,
+                               p->d_y, p->d_m, p->d_cell_start, nl, ntx, t0, sel.row0, sel.row1,
+                               sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2, sel.pixel,
+                               sel.counts, sel.landed);
+        else
+            hipLaunchKernelGGL(k_direct_f32<false>, dim3(nb), dim3(kThreads), 0, s, g, p->d_x,
+                               p->d_y, p->d_m, p->d_cell_start, nl, ntx, t0, sel.row0, sel.row1,
+                               sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2, sel.pixel,
+                               sel.counts, sel.landed);
+        IRS_HIP(hipGetLastError());
+    }
+    return IRS_OK;
+}
+
+}  // namespace irs

@@ -1,0 +1,359 @@
+// Three-level-grid interpolation (Sec. 2.3 and the flow chart of Sec. 2.4).
+//
+// Level 1: lenses are packed into n1x x n1y cells (k_level1.hip).  For a ray
+// or level-2 point in cell (cx, cy) the lenses of the 3 x 3 block of cells
+// around it are "nearby", all others "distant".
+//
+// Level 2 (k_level2): every level-1 cell is split into q x q subcells whose
+// centres are the level-2 points.  At each point z0 the distant lenses give,
+// in complex notation (z = theta_1 + i theta_2, conj(alpha) = m/(z - z_i) for
+// one lens),
+//     c_k = sum_far m_i (-1)^k / (z0 - z_i)^(k+1),   k = 0..4,
+// the Taylor coefficients of conj(alpha_far)(z0 + h) = sum_k c_k h^k up to
+// fourth order ("eight Taylor coefficients" = Re/Im of c_1..c_4).  The
+// negative sheet is added in the same step: with F = (I1 - i I2)/pi its
+// conjugated deflection is -kappa_* F(z), and inside the rectangle
+// F = conj(z) + G(z) with G analytic,
+//     G'(z)    = 1 - (i/pi) sum_k s_k Log(z - c_k),
+//     G^(n)(z) = -(i/pi) sum_k s_k (-1)^n (n-2)! / (z - c_k)^(n-1),  n >= 2,
+// over the corners c_k = (a1,b1), (a2,b1), (a2,b2), (a1,b2), s_k = +,-,+,-.
+// So C_0 = c_0 - kappa_* F(z0), C_k = c_k - kappa_* G^(k)(z0)/k!, and the
+// remaining sheet term -kappa_* conj(h) is exactly linear.  The four corner
+// cells store c_k only (G is singular at the corners); their rays evaluate
+// the sheet in closed form.  Everything in FP64.
+//
+// Level 3 (k_level3): for every ray, conj(alpha_far + alpha_sheet) =
+// C_0 + C_1 h + ... + C_4 h^4 - kappa_* conj(h) (Horner), plus the nearby
+// lenses summed exactly in FP64, plus the macro term; then beta and the pixel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "plan.hpp"
+
+namespace irs {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kL2Lens = 256;    // lenses per LDS stage
+constexpr int kL2PPT = 2;       // level-2 points per lane per pass
+
+__device__ __forceinline__ bool corner_cell(const DevGeom &g, int64_t cx, int64_t cy)
+{
+    return (cx == 0 || cx == g.n1x - 1) && (cy == 0 || cy == g.n1y - 1);
+}
+
+// level-2 point of column gx / row gy: centre of its subcell (no contraction)
+__device__ __forceinline__ double level2_x(const DevGeom &g, int64_t gx)
+{
+#pragma clang fp contract(off)
+    return g.a1 + ((double)gx + 0.5) * g.w2;
+}
+__device__ __forceinline__ double level2_y(const DevGeom &g, int64_t gy)
+{
+#pragma clang fp contract(off)
+    return g.b1 + ((double)gy + 0.5) * g.h2;
+}
+
+struct cplx {
+    double r, i;
+};
+__device__ __forceinline__ cplx cmul(cplx a, cplx b)
+{
+    return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+
+// Sheet part of the level-2 coefficients at z0 (non-corner cells):
+// out[k] = -kappa_* g_k, g_0 = F(z0), g_k = G^(k)(z0)/k!.
+__device__ void sheet_coeffs(const DevGeom &g, double x0, double y0, cplx out[5])
+{
+    double I1, I2;
+    sheet_unit(g, x0, y0, I1, I2);
+    const double ipi = 1.0 / M_PI;
+    cplx gk[5];
+    gk[0] = {I1 * ipi, -I2 * ipi};
+    double lr = 0.0, li = 0.0;          // sum s_k Log(z0 - c_k)
+    cplx y2 = {0, 0}, y3 = {0, 0}, y4 = {0, 0};   // sum s_k (-1)^n (n-2)!/(z0-c_k)^(n-1)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double a = (c == 0 || c == 3) ? g.a1 : g.a2;
+        const double b = (c < 2) ? g.b1 : g.b2;
+        const double sgn = (c == 0 || c == 2) ? 1.0 : -1.0;
+        const double u = x0 - a, v = y0 - b;
+        const double d2 = u * u + v * v;
+        lr += sgn * 0.5 * log(d2);
+        li += sgn * atan2(v, u);
+        const cplx w = {u / d2, -v / d2};        // 1/(z0 - c)
+        const cplx w2 = cmul(w, w), w3 = cmul(w2, w);
+        y2.r += sgn * w.r;          y2.i += sgn * w.i;            // n = 2: +0!/(z-c)
+        y3.r -= sgn * w2.r;         y3.i -= sgn * w2.i;           // n = 3: -1!/(z-c)^2
+        y4.r += sgn * 2.0 * w3.r;   y4.i += sgn * 2.0 * w3.i;     // n = 4: +2!/(z-c)^3
+    }
+    // -(i/pi) (X + iY) = (Y - i X)/pi
+    gk[1] = {1.0 + li * ipi, -lr * ipi};
+    gk[2] = {y2.i * ipi / 2.0, -y2.r * ipi / 2.0};
+    gk[3] = {y3.i * ipi / 6.0, -y3.r * ipi / 6.0};
+    gk[4] = {y4.i * ipi / 24.0, -y4.r * ipi / 24.0};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) out[k] = {-g.kappa_star * gk[k].r, -g.kappa_star * gk[k].i};
+}
+
+template <bool UNIT>
+__global__ __launch_bounds__(kThreads) void k_level2(
+    DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
+    const double *__restrict__ lm, const int32_t *__restrict__ cell_start, int32_t nl,
+    int32_t cy0, double *__restrict__ coef)
+{
+    __shared__ double s_x[kL2Lens], s_y[kL2Lens], s_m[UNIT ? 1 : kL2Lens];
+    const int tid = threadIdx.x;
+    const int32_t cx = (int32_t)(blockIdx.x % (uint32_t)g.n1x);
+    const int32_t cy = cy0 + (int32_t)(blockIdx.x / (uint32_t)g.n1x);
+    const int q = g.q;
+    const int npts = q * q;
+
+    // distant lenses = complement of the 3 x 3 block: at most 4 sorted ranges
+    int32_t rb[4], re[4];
+    int nr = 0;
+    {
+        int32_t prev = 0;
+        const int32_t xl = cx > 0 ? cx - 1 : 0, xh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
+        const int32_t yl = cy > 0 ? cy - 1 : 0, yh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
+        for (int32_t row = yl; row <= yh; ++row) {
+            const int32_t nb = cell_start[row * g.n1x + xl];
+            const int32_t ne = cell_start[row * g.n1x + xh + 1];
+            if (nb > prev) { rb[nr] = prev; re[nr] = nb; ++nr; }
+            prev = ne;
+        }
+        if (prev < nl) { rb[nr] = prev; re[nr] = nl; ++nr; }
+    }
+    const bool corner = corner_cell(g, cx, cy);
+    const int64_t nxq = (int64_t)g.n1x * q;
+
+    for (int p0 = 0; p0 < npts; p0 += kThreads * kL2PPT) {
+        double zr[kL2PPT], zi[kL2PPT];
+        cplx c[kL2PPT][5];
+#pragma unroll
+        for (int k = 0; k < kL2PPT; ++k) {
+            const int pt = min(p0 + tid + k * kThreads, npts - 1);
+            zr[k] = level2_x(g, (int64_t)cx * q + pt % q);
+            zi[k] = level2_y(g, (int64_t)cy * q + pt / q);
+#pragma unroll
+            for (int o = 0; o < 5; ++o) c[k][o] = {0.0, 0.0};
+        }
+        for (int rg = 0; rg < nr; ++rg) {
+            for (int32_t base = rb[rg]; base < re[rg]; base += kL2Lens) {
+                __syncthreads();
+                if (base + tid < re[rg]) {
+                    s_x[tid] = lx[base + tid];
+                    s_y[tid] = ly[base + tid];
+                    if (!UNIT) s_m[tid] = lm[base + tid];
+                }
+                __syncthreads();
+                const int cnt = min(kL2Lens, re[rg] - base);
+                for (int t = 0; t < cnt; ++t) {
+                    const double X = s_x[t], Y = s_y[t];
+                    const double M = UNIT ? 1.0 : s_m[t];
+#pragma unroll
+                    for (int k = 0; k < kL2PPT; ++k) {
+                        const double wr = zr[k] - X, wi = zi[k] - Y;
+                        const double inv = 1.0 / (wr * wr + wi * wi);
+                        const cplx u = {wr * inv, -wi * inv};       // 1/(z0 - z_i)
+                        cplx t1 = UNIT ? u : cplx{M * u.r, M * u.i};
+                        c[k][0].r += t1.r; c[k][0].i += t1.i;
+                        cplx t2 = cmul(t1, u);
+                        c[k][1].r -= t2.r; c[k][1].i -= t2.i;
+                        cplx t3 = cmul(t2, u);
+                        c[k][2].r += t3.r; c[k][2].i += t3.i;
+                        cplx t4 = cmul(t3, u);
+                        c[k][3].r -= t4.r; c[k][3].i -= t4.i;
+                        cplx t5 = cmul(t4, u);
+                        c[k][4].r += t5.r; c[k][4].i += t5.i;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kL2PPT; ++k) {
+            const int pt = p0 + tid + k * kThreads;
+            if (pt >= npts) continue;
+            if (g.sheet && !corner) {
+                cplx sh[5];
+                sheet_coeffs(g, zr[k], zi[k], sh);
+#pragma unroll
+                for (int o = 0; o < 5; ++o) { c[k][o].r += sh[o].r; c[k][o].i += sh[o].i; }
+            }
+            const int64_t gx = (int64_t)cx * q + pt % q;
+            const int64_t gyb = (int64_t)(cy - cy0) * q + pt / q;
+            double *dst = coef + (gyb * nxq + gx) * 10;
+#pragma unroll
+            for (int o = 0; o < 5; ++o) {
+                dst[2 * o] = c[k][o].r;
+                dst[2 * o + 1] = c[k][o].i;
+            }
+        }
+    }
+}
+
+template <bool UNIT>
+__global__ __launch_bounds__(kThreads) void k_level3(
+    DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
+    const double *__restrict__ lm, const int32_t *__restrict__ cell_start,
+    const double *__restrict__ coef, int32_t cy0, int64_t ntx, int64_t jr0, int64_t jr1,
+    int64_t ray_first, int64_t ray_last, double *a1o, double *a2o, int64_t *pixo,
+    uint32_t *counts, unsigned long long *landed)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid % kWave, wave = tid / kWave;
+    const int64_t tx = (int64_t)blockIdx.x % ntx;
+    const int64_t ty = (int64_t)blockIdx.x / ntx;
+    const int64_t i = tx * kWave + lane;
+    const int64_t j = jr0 + ty * (kThreads / kWave) + wave;
+    const int64_t r = j * g.nx + i;
+    const bool valid = i < g.nx && j < jr1 && r >= ray_first && r < ray_last;
+    double a1 = 0.0, a2 = 0.0;
+    int32_t pix = -1;
+    if (valid) {
+        const double t1 = ray_x(g, i), t2 = ray_y(g, j);
+        const int64_t gx = level2_col(g, i), gy = level2_row(g, j);
+        const int64_t cx = gx / g.q, cy = gy / g.q;
+        const double hr = t1 - level2_x(g, gx), hi = t2 - level2_y(g, gy);
+        const double *C = coef + (((gy - (int64_t)cy0 * g.q) * ((int64_t)g.n1x * g.q)) + gx) * 10;
+        // Horner: C0 + h (C1 + h (C2 + h (C3 + h C4)))
+        cplx A = {C[8], C[9]};
+#pragma unroll
+        for (int o = 3; o >= 0; --o) {
+            A = cmul(A, cplx{hr, hi});
+            A.r += C[2 * o];
+            A.i += C[2 * o + 1];
+        }
+        if (g.sheet) {
+            if (corner_cell(g, cx, cy)) {
+                double I1, I2;
+                sheet_unit(g, t1, t2, I1, I2);
+                const double f = -g.kappa_star / M_PI;
+                A.r += f * I1;
+                A.i -= f * I2;
+            } else {
+                A.r -= g.kappa_star * hr;     // -kappa_* conj(h)
+                A.i += g.kappa_star * hi;
+            }
+        }
+        // nearby lenses, exactly
+        double n1 = 0.0, n2 = 0.0;
+        const int64_t xl = cx > 0 ? cx - 1 : 0, xh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
+        const int64_t yl = cy > 0 ? cy - 1 : 0, yh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
+        for (int64_t row = yl; row <= yh; ++row) {
+            const int32_t pb = cell_start[row * g.n1x + xl];
+            const int32_t pe = cell_start[row * g.n1x + xh + 1];
+            for (int32_t p = pb; p < pe; ++p) {
+                const double d1 = t1 - lx[p], d2 = t2 - ly[p];
+                const double rr = d1 * d1 + d2 * d2;
+                if (rr > 0.0) {
+                    const double w = (UNIT ? 1.0 : lm[p]) / rr;
+                    n1 += w * d1;
+                    n2 += w * d2;
+                }
+            }
+        }
+        a1 = g.kpg * t1 + n1 + A.r;          // conj(A) is the far + sheet deflection
+        a2 = g.kmg * t2 + n2 - A.i;
+        pix = pixel_of(g, t1 - a1, t2 - a2);
+    }
+    if (counts) {
+        bin_wave(counts, pix);
+        const uint64_t got = __ballot(pix >= 0);
+        if (lane == 0 && got) atomicAdd(landed, (unsigned long long)__popcll(got));
+    } else if (valid) {
+        const int64_t o = r - ray_first;
+        if (a1o) a1o[o] = a1;
+        if (a2o) a2o[o] = a2;
+        if (pixo) pixo[o] = pix;
+    }
+}
+
+// first ray row j with level2_row(j) >= G (level2_row is non-decreasing)
+int64_t first_row_at(const DevGeom &g, int64_t G)
+{
+    int64_t lo = 0, hi = g.ny;
+    const int64_t M = (int64_t)g.n1y * g.q;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (((2 * mid + 1) * M) / (2 * g.ny) >= G) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+int64_t level2_row_host(const DevGeom &g, int64_t j)
+{
+    return ((2 * j + 1) * (int64_t)g.n1y * g.q) / (2 * g.ny);
+}
+
+}  // namespace
+
+irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
+{
+    const DevGeom &g = p->dg;
+    hipStream_t s = p->stream;
+    const int32_t nl = (int32_t)p->n_lens;
+    if (sel.row1 <= sel.row0) return IRS_OK;
+    const int64_t q = g.q;
+    const int64_t row_pts = (int64_t)g.n1x * q * q;            // level-2 points per level-1 row
+    const int64_t row_bytes = row_pts * 10 * (int64_t)sizeof(double);
+    const int64_t cyA = level2_row_host(g, sel.row0) / q;
+    const int64_t cyB = level2_row_host(g, sel.row1 - 1) / q;  // inclusive
+    const int64_t want = cyB - cyA + 1;
+    // band buffer: as many level-1 rows as fit in 2 GiB (at least one)
+    const int64_t fit = std::max<int64_t>(1, ((int64_t)2 << 30) / row_bytes);
+    const int64_t rows = std::min(fit, want);
+    if (p->coef_rows_cap < rows) {
+        dev_free(p->d_coef);
+        p->d_coef = nullptr;
+        p->coef_rows_cap = 0;
+        if (hipMalloc(&p->d_coef, (size_t)(rows * row_bytes)) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("cannot allocate the level-2 coefficient band");
+            return IRS_E_NOMEM;
+        }
+        p->coef_rows_cap = rows;
+    }
+    const int64_t ntx = (g.nx + kWave - 1) / kWave;
+    const int rows_per_block = kThreads / kWave;
+    for (int64_t c0 = cyA; c0 <= cyB; c0 += p->coef_rows_cap) {
+        const int64_t c1 = std::min(cyB, c0 + p->coef_rows_cap - 1);
+        const unsigned nb2 = (unsigned)((c1 - c0 + 1) * g.n1x);
+        if (p->unit_mass)
+            hipLaunchKernelGGL(k_level2<true>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x, p->d_y,
+                               p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
+        else
+            hipLaunchKernelGGL(k_level2<false>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,
+                               p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
+        IRS_HIP(hipGetLastError());
+        const int64_t jA = std::max(sel.row0, first_row_at(g, c0 * q));
+        const int64_t jB = std::min(sel.row1, first_row_at(g, (c1 + 1) * q));
+        if (jB <= jA) continue;
+        const int64_t nty = (jB - jA + rows_per_block - 1) / rows_per_block;
+        const int64_t max_ty = std::max<int64_t>(1, ((int64_t)1 << 24) / ntx);
+        for (int64_t t0 = 0; t0 < nty; t0 += max_ty) {
+            const int64_t t1 = std::min(nty, t0 + max_ty);
+            const unsigned nb3 = (unsigned)((t1 - t0) * ntx);
+            const int64_t j0 = jA + t0 * rows_per_block;
+            const int64_t j1 = std::min(jB, jA + t1 * rows_per_block);
+            if (p->unit_mass)
+                hipLaunchKernelGGL(k_level3<true>, dim3(nb3), dim3(kThreads), 0, s, g, p->d_x,
+                                   p->d_y, p->d_m, p->d_cell_start, p->d_coef, (int32_t)c0, ntx,
+                                   j0, j1, sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2,
+                                   sel.pixel, sel.counts, sel.landed);
+            else
+                hipLaunchKernelGGL(k_level3<false>, dim3(nb3), dim3(kThreads), 0, s, g, p->d_x,
+                                   p->d_y, p->d_m, p->d_cell_start, p->d_coef, (int32_t)c0, ntx,
+                                   j0, j1, sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2,
+                                   sel.pixel, sel.counts, sel.landed);
+            IRS_HIP(hipGetLastError());
+        }
+    }
+    return IRS_OK;
+}
+
+}  // namespace irs

@@ -1,0 +1,76 @@
+// Internal plan object and the launch wrappers of the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/irs.h"
+#include "device_common.hpp"
+#include "geometry.hpp"
+
+struct irs_plan_s {
+    irs_params params;
+    irs::HostGeometry geo;
+    irs::DevGeom dg;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int64_t n_lens = 0;
+    bool unit_mass = true;
+    double kappa_star_eff = 0.0;
+
+    // Lenses packed into level-1 cells (row-major cell order; inside a cell in
+    // increasing input order).  FP64 positions and masses.
+    double *d_x = nullptr, *d_y = nullptr, *d_m = nullptr;   // d_m null when unit masses
+    int32_t *d_cell_start = nullptr;                         // n1x*n1y + 1
+
+    // Level-2 coefficients of one band of level-1 rows: 10 doubles per point
+    // (Re/Im of C0..C4), point (gx, gy) at ((gy - band_row0*q) * n1x*q + gx).
+    double *d_coef = nullptr;
+    int64_t coef_rows_cap = 0;   // level-1 rows the buffer holds
+
+    // Scratch for host-side outputs.
+    uint32_t *d_counts = nullptr;  // npix^2, used when counts are on the host
+    unsigned long long *d_landed = nullptr;   // rays binned by the current call
+    void *d_tmp = nullptr;
+    size_t tmp_bytes = 0;
+};
+
+namespace irs {
+
+inline void dev_free(void *ptr)
+{
+    if (ptr) (void)hipFree(ptr);
+}
+
+// Status plumbing shared by the launch wrappers and the C ABI.
+void set_error(const std::string &msg);
+irs_status hip_fail(hipError_t e, const char *what);
+
+#define IRS_HIP(call)                                                  \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) return ::irs::hip_fail(e_, #call);       \
+    } while (0)
+
+// Level-1 packing: fills plan->d_x/d_y/d_m/d_cell_start from host lenses.
+irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const double *hm);
+
+// Per-call ray selection for the ray kernels: rays (i, j) with rows
+// [row0, row1) and, when ray_first/ray_last are set, ray index r = j*nx + i
+// in [ray_first, ray_last).  Outputs: per-ray arrays indexed r - ray_first
+// (any may be null), or counts (null when per-ray outputs are wanted).
+struct RaySel {
+    int64_t row0, row1;
+    int64_t ray_first, ray_last;
+    double *alpha1, *alpha2;
+    int64_t *pixel;
+    uint32_t *counts;
+    unsigned long long *landed;   // device counter of rays binned (with counts)
+};
+
+irs_status launch_direct(irs_plan_s *p, const RaySel &sel);
+irs_status launch_interp(irs_plan_s *p, const RaySel &sel);
+
+}  // namespace irs

@@ -1,0 +1,188 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Sizes are ones the oracle finishes in seconds while spanning many ray tiles
+(64 x 16 rays for the FP32 direct kernel, 64 x 4 for level 3) with ragged
+edges in both directions, several level-1 cells and level-2 bands."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import Case, check_map, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def irs():
+    import paper_2204_10871_amd as irs
+    irs.load()
+    return irs
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def _hist(px, npix):
+    v = px[px >= 0]
+    return np.bincount(v, minlength=npix * npix).astype(np.int64)
+
+
+# ---------------------------------------------------------------------------
+# direct sum, FP64
+# ---------------------------------------------------------------------------
+def test_direct_fp64_config1_full_map(irs):
+    """The plain FP64 brute-force map (kappa_* = gamma = 0.3, S = 10, 256^2
+    pixels, 2048^2 rays): every ray's alpha and pixel, and the map."""
+    c = Case(0.3, 0.0, 0.3, 10.0, 256, n_rays=2048 ** 2, seed=synth.configs.CFG1.seed)
+    say(f"cfg1 fp64: nx={c.geo.nx} ny={c.geo.ny} N*={c.lenses.n}")
+    ref = c.oracle_direct()
+    with c.plan("direct", "fp64") as pl:
+        a1, a2, px = pl.deflect_grid(0, pl.n_rays)
+        counts, st = pl.shoot_map()
+    e = rel_err(a1, a2, ref["alpha1"], ref["alpha2"])
+    assert e.max() < 1e-12, e.max()
+    assert (px != ref["pix"]).sum() <= 2          # only exact pixel-edge ties may differ
+    check_map(counts, ref["counts"], px, ref["pix"], min_agree=1 - 1e-6, max_rel_l1=1e-6)
+    assert np.array_equal(_hist(px, 256), counts.ravel().astype(np.int64))
+    assert st["rays_landed"] == int(counts.sum()) and st["rays_shot"] == pl.n_rays
+
+
+# ---------------------------------------------------------------------------
+# direct sum, FP32 with compensation
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mass", ["unit", "salpeter"])
+def test_direct_fp32_ragged(irs, mass):
+    """Near-critical aspect (19:1) like the 4096^2 workloads, ~1000 lenses,
+    a ray grid that is ragged against the 64 x 16 tiles in both directions."""
+    c = Case(0.45, 0.05, 0.45, 5.0, 128, n_rays=1_000_003, mass=mass, seed=31)
+    assert c.geo.nx % 64 and c.geo.ny % 16
+    say(f"fp32 {mass}: nx={c.geo.nx} ny={c.geo.ny} N*={c.lenses.n}")
+    ref = c.oracle_direct()
+    with c.plan("direct", "fp32") as pl:
+        a1, a2, px = pl.deflect_grid(0, pl.n_rays)
+        counts, _ = pl.shoot_map()
+    e = rel_err(a1, a2, ref["alpha1"], ref["alpha2"])
+    say(f"  max e_r {e.max():.3e}  p99.99 {np.quantile(e, 0.9999):.3e}")
+    assert np.mean(e <= 1e-5) >= 0.9999
+    check_map(counts, ref["counts"], px, ref["pix"])
+    assert np.array_equal(_hist(px, 128), counts.ravel().astype(np.int64))
+
+
+def test_direct_fp32_large_plane(irs):
+    """A plane ~370 theta_E long with N_* ~ 4500: the stars' mean field reaches
+    ~80 theta_E at the ends, which FP32 only survives with compensation."""
+    c = Case(0.45, 0.05, 0.45, 14.0, 256, n_rays=600_000, seed=32)
+    say(f"fp32 large: ix={c.geo.ix:.1f} N*={c.lenses.n}")
+    ids = np.arange(c.geo.n_rays)
+    ref = c.oracle_direct()
+    with c.plan("direct", "fp32") as pl:
+        a1, a2, px = pl.deflect_grid(0, pl.n_rays)
+    e = rel_err(a1, a2, ref["alpha1"], ref["alpha2"])
+    say(f"  max e_r {e.max():.3e}")
+    assert np.mean(e <= 1e-5) >= 0.9999
+    assert np.mean(px == ref["pix"]) >= 0.9999
+    del ids
+
+
+# ---------------------------------------------------------------------------
+# interpolation
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["short_side", "l0_cells", "ray_multiple", "salpeter"])
+def test_interp_matches_oracle(irs, kind):
+    """GPU level-2/level-3 against the oracle's step-by-step interpolation
+    (same approximation: agreement to rounding) and against the direct
+    definition (the interpolation error budget)."""
+    if kind == "short_side":
+        c = Case(0.35, 0.1, 0.25, 4.0, 64, n_rays=400_000, seed=41)
+    elif kind == "l0_cells":
+        c = Case(0.35, 0.1, 0.25, 20.0, 96, n_rays=500_000, seed=42)
+    elif kind == "ray_multiple":
+        c = Case(0.45, 0.05, 0.45, 6.0, 128, n_rays=2_000_003, level2_ray_multiple=4.0, seed=43)
+    else:
+        c = Case(0.6, 0.0, 0.6, 12.0, 96, n_rays=500_000, mass="salpeter", seed=44)
+    say(f"interp {kind}: n1={c.geo.n1x}x{c.geo.n1y} q={c.geo.q} N*={c.lenses.n}")
+    ref2 = c.oracle_interp()
+    ref1 = c.oracle_direct()
+    with c.plan("interp", "fp64") as pl:
+        assert pl.geometry["q"] == c.geo.q and pl.geometry["n1x"] == c.geo.n1x
+        a1, a2, px = pl.deflect_grid(0, pl.n_rays)
+        counts, _ = pl.shoot_map()
+    e2 = rel_err(a1, a2, ref2["alpha1"], ref2["alpha2"])
+    say(f"  vs O-2 max e_r {e2.max():.3e}")
+    assert e2.max() < 1e-10
+    assert np.mean(px == ref2["pix"]) >= 1 - 1e-5
+    check_map(counts, ref2["counts"], px, ref2["pix"], min_agree=1 - 1e-5, max_rel_l1=1e-5)
+    e1 = rel_err(a1, a2, ref1["alpha1"], ref1["alpha2"])
+    say(f"  vs O-1 max e_r {e1.max():.3e}")
+    assert np.mean(e1 <= 1e-4) >= 0.9999
+    check_map(counts, ref1["counts"], px, ref1["pix"])
+    assert np.array_equal(_hist(px, c.geo.npix), counts.ravel().astype(np.int64))
+
+
+# ---------------------------------------------------------------------------
+# edge cases and bookkeeping
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("method,precision", [("direct", "fp64"), ("direct", "fp32"),
+                                              ("interp", "fp64")])
+def test_star_free_map_exact(irs, method, precision):
+    """No lenses: the map is the macro model's, identical to the oracle's."""
+    empty = synth.Lenses(np.zeros(0), np.zeros(0), None)
+    c = Case(0.0, 0.23, 0.11, 3.7, 37, n_rays=611 * 577, border=0.37, lenses=empty)
+    ref = c.oracle_direct()
+    with c.plan(method, precision) as pl:
+        counts, st = pl.shoot_map()
+        _, _, px = pl.deflect_grid(0, pl.n_rays, alpha=False)
+    assert np.array_equal(px, ref["pix"])
+    assert np.array_equal(counts.ravel(), ref["counts"])
+    assert st["rays_landed"] == ref["landed"]
+
+
+@pytest.mark.parametrize("method,precision", [("direct", "fp64"), ("direct", "fp32"),
+                                              ("interp", "fp64")])
+def test_single_ray_and_single_lens(irs, method, precision):
+    """One ray (a 1 x 1 grid) and one lens off the ray, sheet off."""
+    L = synth.Lenses(np.array([0.3]), np.array([-0.2]), None)
+    c = Case(0.0, 0.0, 0.0, 2.0, 4, n_rays=1, border=1.0, sheet=False, lenses=L)
+    assert c.geo.nx == 1 and c.geo.ny == 1
+    ref = c.oracle_direct()
+    with c.plan(method, precision) as pl:
+        a1, a2, px = pl.deflect_grid(0, 1)
+    e = rel_err(a1, a2, ref["alpha1"], ref["alpha2"])
+    assert e.max() < (1e-12 if precision == "fp64" else 1e-6)
+    assert px[0] == ref["pix"][0]
+
+
+@pytest.mark.parametrize("method,precision", [("direct", "fp32"), ("interp", "fp64")])
+def test_row_bands_add_up_and_are_deterministic(irs, method, precision):
+    """Disjoint row bands sum exactly to the full map (resume by bands), two
+    runs are bitwise identical, and an unaligned ray range equals the same
+    slice of a full per-ray evaluation."""
+    c = Case(0.45, 0.05, 0.45, 5.0, 96, n_rays=300_007, seed=51)
+    with c.plan(method, precision) as pl:
+        full, _ = pl.shoot_map()
+        again, _ = pl.shoot_map()
+        assert np.array_equal(full, again)
+        ny = pl.geometry["ny"]
+        acc = np.zeros(96 * 96, np.uint32)
+        cuts = [0, 7, ny // 3, ny // 3 + 1, ny - 5, ny]
+        for r0, r1 in zip(cuts[:-1], cuts[1:]):
+            pl.shoot_rows(r0, r1 - r0, acc)
+        assert np.array_equal(acc.reshape(96, 96), full)
+        a1, a2, px = pl.deflect_grid(0, pl.n_rays)
+        first, n = 12345, 54321
+        b1, b2, qx = pl.deflect_grid(first, n)
+        assert np.array_equal(b1, a1[first:first + n]) and np.array_equal(qx, px[first:first + n])
+
+
+def test_critical_and_invalid_plans(irs):
+    p = irs.make_params(0.5, 0.0, 0.5, 100.0, 64, rays_per_pixel=10.0)
+    with pytest.raises(irs.IrsError) as e:
+        irs.Plan(p, np.zeros(3), np.zeros(3))
+    assert e.value.status == 2
+    c = Case(0.3, 0.0, 0.3, 3.0, 16, n_rays=10_000, seed=3)
+    with c.plan("direct", "fp64") as pl:
+        with pytest.raises(irs.IrsError):
+            pl.deflect_grid(pl.n_rays - 5, 10)
+        with pytest.raises(irs.IrsError):
+            pl.shoot_rows(-1, 3, np.zeros(16 * 16, np.uint32))
