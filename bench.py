@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the inverse-ray-shooting hot path on one MI355X.
+
+Workload: the large-regime map -- kappa_* = gamma = 0.6, kappa_c = 0,
+N_* = 1e6 lenses with Salpeter masses on [0.1, 1] M_sun, a 10000^2 pixel
+source map and 1000 rays per pixel (1e11 rays over a 5117 x 1023 theta_E
+rectangle).  Inputs are seeded and synthetic and resident in HBM before the
+timed region.
+
+One step = one band of ray rows whose level-2 points fall in one level-1
+row of the three-level grid (~2.2e8 rays): the level-2 far-field Taylor
+coefficients of that row (FP64), then every ray of the band (near lenses
+exactly, distant lenses and the sheet by the Taylor series, macro term,
+binning into the device-resident count map).  Steps walk consecutive
+level-1 rows from the middle of the plane; the full map is n1y = 448 steps.
+
+Printed: one JSON line (stdout) with the whole-job throughput in rays/s, the
+roofline of the dominant kernel (level-2, FP64 VALU) from HIP-event timings
+of its launches on the plan's stream, the oracle timed on a bounded ray
+sample of the same band (also the source of the index-agreement figure and
+the map rel-L1 bound), and the FP32 direct sum at N_* = 1e6 for reference.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "rays/sec and ray-lens interactions/sec at N_*=1e6; map rel-L1 vs FP64 oracle"
+FP64_PEAK = 78.6     # TFLOP/s, MI355X vector FP64
+FP32_PEAK = 157.3    # TFLOP/s, MI355X vector FP32 (packed)
+L2_FLOPS_PER_PAIR = 44   # (level-2 point, distant lens) pair, see the design doc
+DIRECT_FLOPS_PER_PAIR = 11
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=16000,
+                    help="rays of the oracle sample (each sums all 1e6 lenses)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-direct", action="store_true")
+    ap.add_argument("--direct-rows", type=int, default=48)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md, 'How the path would shard'); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2204_10871_amd as irs
+    import synth
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    w = synth.configs.CFG3
+    p = irs.params_from_workload(w, method="interp", precision="fp64")
+    g0 = irs.geometry(p, 0)
+    n_star = g0["n_stars_expected"]
+    rect = (g0["a1"], g0["a2"], g0["b1"], g0["b2"])
+    L = synth.uniform_lenses(n_star, rect, w.seed, mass=w.mass, m_min=w.m_min, m_max=w.m_max)
+    plan = irs.Plan(p, L.x, L.y, L.m, stream=stream.cuda_stream)
+    G = plan.geometry
+    log(f"plan: {G['nx']}x{G['ny']} rays, N*={n_star}, level-1 {G['n1x']}x{G['n1y']}, q={G['q']}")
+    counts = torch.zeros(w.npix * w.npix, dtype=torch.int32, device="cuda:0")
+
+    c_mid = G["n1y"] // 2
+    bands = [plan.level1_row_rays(c_mid + k) for k in range(args.warmup + args.steps)]
+    for k in range(args.warmup):
+        j0, j1 = bands[k]
+        plan.shoot_rows(j0, j1 - j0, counts)
+        log(f"warmup {k}: rows {j0}..{j1}")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(args.warmup, args.warmup + args.steps):
+        j0, j1 = bands[k]
+        st = plan.shoot_rows(j0, j1 - j0, counts, time_phases=True)
+        stats.append(st)
+        log(f"step {k - args.warmup}: rows {j0}..{j1} rays {st['rays_shot']:.3e} "
+            f"level-2 {st['ms_level2']:.1f} ms, rays {st['ms_rays']:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    rays = sum(s["rays_shot"] for s in stats)
+    landed = sum(s["rays_landed"] for s in stats)
+    value = rays / elapsed
+    l2_pairs = sum(s["level2_pairs"] for s in stats)
+    l2_ms = sum(s["ms_level2"] for s in stats)
+    l2_launches = sum(s["n_level2_launches"] for s in stats)
+    l2_achieved = L2_FLOPS_PER_PAIR * l2_pairs / (l2_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(l2_achieved, 3), "peak": FP64_PEAK,
+                "unit": "TFLOP/s", "frac": round(l2_achieved / FP64_PEAK, 4), "traffic": None,
+                "kernel": "k_level2 (FP64 far-field Taylor coefficients)",
+                "launches": l2_launches, "ms_per_launch": round(l2_ms / max(1, l2_launches), 3),
+                "flops_per_launch": L2_FLOPS_PER_PAIR * l2_pairs / max(1, l2_launches)}
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "kappa*=0.6 kappa_c=0 gamma=0.6, N*=1e6 Salpeter [0.1,1] Msun, "
+                               "10000^2 px, N_av=1000 (1e11 rays), interpolated "
+                               "(level-2 FP64, dx2=dx1/20); step = one level-1 row band",
+                   "n_star": n_star, "rays_per_step": rays / args.steps,
+                   "full_map_steps": G["n1y"], "method": "interp", "precision": "fp64"},
+        "interactions_per_s": {"direct_equivalent": value * n_star,
+                               "level2_pairs_per_s": l2_pairs / elapsed},
+        "full_map_seconds_extrapolated": G["nx"] * G["ny"] / value,
+        "landed_fraction": landed / rays,
+        "roofline": roofline,
+    }
+
+    # ---- the oracle on a bounded sample of the last band (rays it sums one by one)
+    if not args.no_cpu_baseline:
+        import oracle as orc
+        threads = min(16, os.cpu_count() or 1)
+        og = orc.geometry(w.kappa_star, w.kappa_c, w.gamma, w.source_side, w.npix,
+                          rays_per_pixel=w.rays_per_pixel, n_lens=n_star)
+        assert og.nx == G["nx"] and og.ny == G["ny"]
+        j0, j1 = bands[-1]
+        rng = np.random.default_rng(7)
+        nchunk = 16
+        per = max(1, args.cpu_sample // nchunk)
+        firsts = np.sort(rng.integers(j0 * G["nx"], j1 * G["nx"] - per, nchunk))
+        ids = np.concatenate([np.arange(f, f + per) for f in firsts])
+        gpu_pix = np.concatenate([plan.deflect_grid(int(f), per, alpha=False)[2] for f in firsts])
+        log(f"oracle sample: {ids.size} rays x {n_star} lenses on {threads} threads")
+        tc = time.perf_counter()
+        ref = orc.shoot_direct(og, L, ray_ids=ids, threads=threads, want_counts=False)
+        tcpu = time.perf_counter() - tc
+        mism = int(np.sum(gpu_pix != ref["pix"]))
+        n = ids.size
+        # 95% upper bound on the mismatch fraction (Wilson), then the deterministic
+        # bound rel-L1 <= 2 f_mis N_rays / sum(N_ref) (each mismatched ray moves one count)
+        z = 1.96
+        ph = mism / n
+        up = (ph + z * z / (2 * n) + z * math.sqrt(ph * (1 - ph) / n + z * z / (4 * n * n))) / (1 + z * z / n)
+        result["cpu_baseline"] = {"value": n / tcpu, "unit": "rays/s", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": f"{n} rays (16 contiguous runs) of one band of this "
+                                            f"workload, direct FP64 definition over all {n_star} "
+                                            f"lenses; {tcpu:.1f} s"}
+        result["parity_sample"] = {"rays": n, "index_mismatches": mism,
+                                   "agreement": 1 - ph, "f_mis_95": up,
+                                   "map_rel_l1_bound": 2 * up * rays / max(1, landed)}
+
+    # ---- reference: the FP32 direct sum at N_* = 1e6 on a few tile rows
+    if not args.no_direct:
+        pd = irs.params_from_workload(w, method="direct", precision="fp32")
+        with irs.Plan(pd, L.x, L.y, L.m, stream=stream.cuda_stream) as dplan:
+            r0 = (G["ny"] // 2) // 16 * 16
+            dplan.shoot_rows(r0, 16, counts)             # warm-up tile row
+            torch.cuda.synchronize()
+            td = time.perf_counter()
+            st = dplan.shoot_rows(r0 + 16, args.direct_rows, counts, time_phases=True)
+            torch.cuda.synchronize()
+            td = time.perf_counter() - td
+        pairs = st["direct_pairs"]
+        tf = DIRECT_FLOPS_PER_PAIR * pairs / (st["ms_rays"] * 1e-3) / 1e12
+        result["direct_fp32"] = {"rays_per_s": st["rays_shot"] / td,
+                                 "interactions_per_s": pairs / td,
+                                 "kernel_tflops_alg": tf, "frac_fp32_peak": tf / FP32_PEAK,
+                                 "rays": st["rays_shot"], "seconds": td,
+                                 "speedup_interp_over_direct": value / (st["rays_shot"] / td)}
+        log(f"direct fp32: {pairs / td:.3e} pairs/s, {tf:.1f} TFLOP/s")
+
+    plan.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

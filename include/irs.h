@@ -72,6 +72,8 @@ enum { IRS_FP64 = 0,        /* every step in double precision                  *
 #define IRS_SHEET_OFF      (1ull << 0)  /* omit the negative mass sheet (point-lens tests) */
 /* per-call flags */
 #define IRS_OUT_ON_DEVICE  (1ull << 8)  /* output pointers are device pointers          */
+#define IRS_TIME_PHASES    (1ull << 9)  /* time each kernel launch with HIP events on
+                                           the plan's stream (fills the ms_* stats)     */
 
 typedef struct {
     double   kappa_star;          /* compact convergence kappa_* (Eq. 2), >= 0        */
@@ -118,6 +120,16 @@ typedef struct {
     int64_t n_lens;               /* lenses in the plan                               */
     double  kappa_star_eff;       /* pi * sum(m) / (I_x I_y)                          */
     double  ms_total;             /* wall time of the call on the plan's stream       */
+    /* work done by the call (interpolation: level-2 points computed and
+       (point, distant lens) pairs summed; direct: ray-lens pairs)                   */
+    int64_t level2_points;
+    int64_t level2_pairs;
+    int64_t direct_pairs;
+    /* with IRS_TIME_PHASES: summed HIP-event durations of the launches          */
+    int32_t n_level2_launches;    /* level-2 (far field) launches                     */
+    int32_t n_ray_launches;       /* level-3 or direct-sum launches                   */
+    double  ms_level2;
+    double  ms_rays;
 } irs_map_stats;
 
 /*

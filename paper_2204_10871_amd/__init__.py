@@ -11,7 +11,7 @@ import numpy as np
 
 from . import _ffi
 from ._ffi import (IRS_DIRECT, IRS_INTERP, IRS_FP64, IRS_FP32_KAHAN, IRS_SHEET_OFF,
-                   IRS_OUT_ON_DEVICE, EXPORTS, Params, GeometryInfo, MapStats)
+                   IRS_OUT_ON_DEVICE, IRS_TIME_PHASES, EXPORTS, Params, GeometryInfo, MapStats)
 
 __all__ = ["IrsError", "make_params", "params_from_workload", "geometry", "Plan", "load",
            "IRS_DIRECT", "IRS_INTERP", "IRS_FP64", "IRS_FP32_KAHAN", "EXPORTS"]
@@ -139,24 +139,44 @@ class Plan:
                                           None if px is None else _dev_ptr(px),
                                           IRS_OUT_ON_DEVICE), "irs_deflect_grid")
 
-    def shoot_map(self):
+    def shoot_map(self, time_phases=False):
         """Full map on the host: (counts uint32 [npix, npix], stats dict)."""
         npix = self.params.npix_side
         counts = np.zeros(npix * npix, np.uint32)
         st = MapStats()
-        _check(self._lib.irs_shoot_map(self._h, _vp(counts), C.byref(st), 0), "irs_shoot_map")
+        fl = IRS_TIME_PHASES if time_phases else 0
+        _check(self._lib.irs_shoot_map(self._h, _vp(counts), C.byref(st), fl), "irs_shoot_map")
         return counts.reshape(npix, npix), st.as_dict()
 
-    def shoot_rows(self, row0: int, nrows: int, counts):
+    def shoot_rows(self, row0: int, nrows: int, counts, time_phases=False):
         """Add rows [row0, row0+nrows) into counts: a host uint32 array or a
         device tensor of npix^2 32-bit integers.  Returns the stats dict."""
         st = MapStats()
+        fl = IRS_TIME_PHASES if time_phases else 0
         if isinstance(counts, np.ndarray):
             if counts.dtype != np.uint32 or not counts.flags.c_contiguous:
                 raise ValueError("host counts must be a contiguous uint32 array")
             _check(self._lib.irs_shoot_rows(self._h, int(row0), int(nrows), _vp(counts),
-                                            C.byref(st), 0), "irs_shoot_rows")
+                                            C.byref(st), fl), "irs_shoot_rows")
         else:
             _check(self._lib.irs_shoot_rows(self._h, int(row0), int(nrows), _dev_ptr(counts),
-                                            C.byref(st), IRS_OUT_ON_DEVICE), "irs_shoot_rows")
+                                            C.byref(st), fl | IRS_OUT_ON_DEVICE),
+                   "irs_shoot_rows")
         return st.as_dict()
+
+    def level1_row_rays(self, c: int):
+        """Ray rows [j0, j1) whose level-2 points lie in level-1 row c: ray row j
+        sits in level-2 row floor((2j+1) n1y q / (2 ny))."""
+        g = self.geometry
+        M, ny = g["n1y"] * g["q"], g["ny"]
+
+        def first_at(G):
+            lo, hi = 0, ny
+            while lo < hi:
+                mid = (lo + hi) // 2
+                if ((2 * mid + 1) * M) // (2 * ny) >= G:
+                    hi = mid
+                else:
+                    lo = mid + 1
+            return lo
+        return first_at(c * g["q"]), first_at((c + 1) * g["q"])

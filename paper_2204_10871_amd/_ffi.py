@@ -12,6 +12,7 @@ IRS_DIRECT, IRS_INTERP = 0, 1
 IRS_FP64, IRS_FP32_KAHAN = 0, 1
 IRS_SHEET_OFF = 1 << 0
 IRS_OUT_ON_DEVICE = 1 << 8
+IRS_TIME_PHASES = 1 << 9
 
 # every function include/irs.h declares
 EXPORTS = ("irs_geometry", "irs_plan", "irs_deflect_grid", "irs_shoot_rows", "irs_shoot_map",
@@ -43,7 +44,11 @@ class GeometryInfo(C.Structure):
 
 class MapStats(C.Structure):
     _fields_ = [("rays_shot", C.c_int64), ("rays_landed", C.c_int64), ("rays_off", C.c_int64),
-                ("n_lens", C.c_int64), ("kappa_star_eff", C.c_double), ("ms_total", C.c_double)]
+                ("n_lens", C.c_int64), ("kappa_star_eff", C.c_double), ("ms_total", C.c_double),
+                ("level2_points", C.c_int64), ("level2_pairs", C.c_int64),
+                ("direct_pairs", C.c_int64), ("n_level2_launches", C.c_int32),
+                ("n_ray_launches", C.c_int32), ("ms_level2", C.c_double),
+                ("ms_rays", C.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -27,6 +27,47 @@ irs_status hip_fail(hipError_t e, const char *what)
     return IRS_E_DEVICE;
 }
 
+irs_status CallStats::begin(hipStream_t s, int k)
+{
+    if (!timed) return IRS_OK;
+    hipEvent_t a, b;
+    IRS_HIP(hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        set_error("hipEventCreate failed");
+        return IRS_E_DEVICE;
+    }
+    ev.push_back(a);
+    ev.push_back(b);
+    ev_kind.push_back(k);
+    IRS_HIP(hipEventRecord(a, s));
+    return IRS_OK;
+}
+
+irs_status CallStats::end(hipStream_t s)
+{
+    if (!timed) return IRS_OK;
+    IRS_HIP(hipEventRecord(ev.back(), s));
+    return IRS_OK;
+}
+
+irs_status CallStats::collect()
+{
+    for (size_t k = 0; k < ev_kind.size(); ++k) {
+        IRS_HIP(hipEventSynchronize(ev[2 * k + 1]));
+        float ms = 0.0f;
+        IRS_HIP(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+        if (ev_kind[k] == 0) ms_level2 += ms;
+        else ms_rays += ms;
+    }
+    return IRS_OK;
+}
+
+CallStats::~CallStats()
+{
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+}
+
 namespace {
 
 DevGeom make_dev_geom(const HostGeometry &hg)
@@ -220,7 +261,9 @@ irs_status irs_deflect_grid(irs_plan_t plan, int64_t first_ray, int64_t n, doubl
     }
     if (n == 0) return IRS_OK;
     const bool on_dev = (flags & IRS_OUT_ON_DEVICE) != 0;
+    CallStats cs;
     RaySel sel{};
+    sel.stats = &cs;
     sel.row0 = first_ray / g.nx;
     sel.row1 = (first_ray + n - 1) / g.nx + 1;
     sel.ray_first = first_ray;
@@ -275,7 +318,10 @@ static irs_status shoot(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t *
     }
     if (!on_dev || overwrite) IRS_HIP(hipMemsetAsync(dst, 0, map_bytes, s));
     IRS_HIP(hipMemsetAsync(plan->d_landed, 0, sizeof(unsigned long long), s));
+    CallStats cs;
+    cs.timed = (flags & IRS_TIME_PHASES) != 0;
     RaySel sel{};
+    sel.stats = &cs;
     sel.row0 = row0;
     sel.row1 = row0 + nrows;
     sel.ray_first = 0;
@@ -296,7 +342,16 @@ static irs_status shoot(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t *
     }
     IRS_HIP(hipStreamSynchronize(s));
     const double ms = timer.stop();
+    st = cs.collect();
+    if (st != IRS_OK) return st;
     if (stats) {
+        stats->level2_points = cs.level2_points;
+        stats->level2_pairs = cs.level2_pairs;
+        stats->direct_pairs = cs.direct_pairs;
+        stats->n_level2_launches = cs.n_level2;
+        stats->n_ray_launches = cs.n_rays;
+        stats->ms_level2 = cs.ms_level2;
+        stats->ms_rays = cs.ms_rays;
         stats->rays_shot = nrows * g.nx;
         stats->rays_landed = (int64_t)landed;
         stats->rays_off = stats->rays_shot - stats->rays_landed;

@@ -302,9 +302,15 @@ irs_status launch_direct(irs_plan_s *p, const RaySel &sel)
         const int64_t rb = std::max(sel.row0 * g.nx, sel.ray_first);
         const int64_t re = std::min(sel.row1 * g.nx, sel.ray_last);
         const int64_t chunk = (int64_t)kThreads << 22;   // rays per launch
+        if (sel.stats) sel.stats->direct_pairs += std::max<int64_t>(0, re - rb) * (int64_t)nl;
         for (int64_t c0 = rb; c0 < re; c0 += chunk) {
             const int64_t c1 = std::min(re, c0 + chunk);
             const unsigned nb = (unsigned)((c1 - c0 + kThreads - 1) / kThreads);
+            if (sel.stats) {
+                irs_status st = sel.stats->begin(s, 1);
+                if (st != IRS_OK) return st;
+                sel.stats->n_rays++;
+            }
             if (unit)
                 hipLaunchKernelGGL(k_direct_f64<true>, dim3(nb), dim3(kThreads), 0, s, g, p->d_x,
                                    p->d_y, p->d_m, nl, c0, c1, sel.ray_first, sel.alpha1,
@@ -314,6 +320,10 @@ irs_status launch_direct(irs_plan_s *p, const RaySel &sel)
                                    p->d_x, p->d_y, p->d_m, nl, c0, c1, sel.ray_first,
                                    sel.alpha1, sel.alpha2, sel.pixel, sel.counts, sel.landed);
             IRS_HIP(hipGetLastError());
+            if (sel.stats) {
+                irs_status st = sel.stats->end(s);
+                if (st != IRS_OK) return st;
+            }
         }
         return IRS_OK;
     }
@@ -322,9 +332,19 @@ irs_status launch_direct(irs_plan_s *p, const RaySel &sel)
     const int64_t ty_lo = sel.row0 / kTY;
     const int64_t ty_hi = (sel.row1 - 1) / kTY;          // inclusive
     const int64_t max_rows_of_tiles = std::max<int64_t>(1, ((int64_t)1 << 22) / ntx);
+    if (sel.stats) {
+        const int64_t r0 = std::max(sel.row0 * g.nx, sel.ray_first);
+        const int64_t r1 = std::min(sel.row1 * g.nx, sel.ray_last);
+        sel.stats->direct_pairs += std::max<int64_t>(0, r1 - r0) * (int64_t)nl;
+    }
     for (int64_t t0 = ty_lo; t0 <= ty_hi; t0 += max_rows_of_tiles) {
         const int64_t t1 = std::min(ty_hi + 1, t0 + max_rows_of_tiles);
         const unsigned nb = (unsigned)((t1 - t0) * ntx);
+        if (sel.stats) {
+            irs_status st = sel.stats->begin(s, 1);
+            if (st != IRS_OK) return st;
+            sel.stats->n_rays++;
+        }
         if (unit)
             hipLaunchKernelGGL(k_direct_f32<true>, dim3(nb), dim3(kThreads), 0, s, g, p->d_x,
                                p->d_y, p->d_m, p->d_cell_start, nl, ntx, t0, sel.row0, sel.row1,
@@ -336,6 +356,10 @@ irs_status launch_direct(irs_plan_s *p, const RaySel &sel)
                                sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2, sel.pixel,
                                sel.counts, sel.landed);
         IRS_HIP(hipGetLastError());
+        if (sel.stats) {
+            irs_status st = sel.stats->end(s);
+            if (st != IRS_OK) return st;
+        }
     }
     return IRS_OK;
 }

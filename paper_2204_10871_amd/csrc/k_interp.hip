@@ -311,6 +311,8 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
         dev_free(p->d_coef);
         p->d_coef = nullptr;
         p->coef_rows_cap = 0;
+        p->coef_c0 = -1;
+        p->coef_c1 = -2;
         if (hipMalloc(&p->d_coef, (size_t)(rows * row_bytes)) != hipSuccess) {
             (void)hipGetLastError();
             set_error("cannot allocate the level-2 coefficient band");
@@ -320,16 +322,43 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
     }
     const int64_t ntx = (g.nx + kWave - 1) / kWave;
     const int rows_per_block = kThreads / kWave;
+    CallStats *cs = sel.stats;
     for (int64_t c0 = cyA; c0 <= cyB; c0 += p->coef_rows_cap) {
         const int64_t c1 = std::min(cyB, c0 + p->coef_rows_cap - 1);
-        const unsigned nb2 = (unsigned)((c1 - c0 + 1) * g.n1x);
-        if (p->unit_mass)
-            hipLaunchKernelGGL(k_level2<true>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x, p->d_y,
-                               p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
-        else
-            hipLaunchKernelGGL(k_level2<false>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,
-                               p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
-        IRS_HIP(hipGetLastError());
+        if (!(p->coef_c0 <= c0 && c1 <= p->coef_c1)) {
+            // the band's level-2 coefficients are not resident: compute them
+            const unsigned nb2 = (unsigned)((c1 - c0 + 1) * g.n1x);
+            if (cs) {
+                irs_status st = cs->begin(s, 0);
+                if (st != IRS_OK) return st;
+                cs->n_level2++;
+                cs->level2_points += (c1 - c0 + 1) * row_pts;
+                for (int64_t cy = c0; cy <= c1; ++cy) {
+                    const int64_t yl = std::max<int64_t>(0, cy - 1), yh = std::min<int64_t>(g.n1y - 1, cy + 1);
+                    for (int64_t cx = 0; cx < g.n1x; ++cx) {
+                        const int64_t xl = std::max<int64_t>(0, cx - 1), xh = std::min<int64_t>(g.n1x - 1, cx + 1);
+                        int64_t near = 0;
+                        for (int64_t row = yl; row <= yh; ++row)
+                            near += p->h_cell_start[row * g.n1x + xh + 1] - p->h_cell_start[row * g.n1x + xl];
+                        cs->level2_pairs += q * q * (p->n_lens - near);
+                    }
+                }
+            }
+            if (p->unit_mass)
+                hipLaunchKernelGGL(k_level2<true>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,
+                                   p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
+            else
+                hipLaunchKernelGGL(k_level2<false>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,
+                                   p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
+            IRS_HIP(hipGetLastError());
+            if (cs) {
+                irs_status st = cs->end(s);
+                if (st != IRS_OK) return st;
+            }
+            p->coef_c0 = c0;
+            p->coef_c1 = c1;
+        }
+        const int32_t band0 = (int32_t)p->coef_c0;
         const int64_t jA = std::max(sel.row0, first_row_at(g, c0 * q));
         const int64_t jB = std::min(sel.row1, first_row_at(g, (c1 + 1) * q));
         if (jB <= jA) continue;
@@ -340,17 +369,26 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
             const unsigned nb3 = (unsigned)((t1 - t0) * ntx);
             const int64_t j0 = jA + t0 * rows_per_block;
             const int64_t j1 = std::min(jB, jA + t1 * rows_per_block);
+            if (cs) {
+                irs_status st = cs->begin(s, 1);
+                if (st != IRS_OK) return st;
+                cs->n_rays++;
+            }
             if (p->unit_mass)
                 hipLaunchKernelGGL(k_level3<true>, dim3(nb3), dim3(kThreads), 0, s, g, p->d_x,
-                                   p->d_y, p->d_m, p->d_cell_start, p->d_coef, (int32_t)c0, ntx,
+                                   p->d_y, p->d_m, p->d_cell_start, p->d_coef, band0, ntx,
                                    j0, j1, sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2,
                                    sel.pixel, sel.counts, sel.landed);
             else
                 hipLaunchKernelGGL(k_level3<false>, dim3(nb3), dim3(kThreads), 0, s, g, p->d_x,
-                                   p->d_y, p->d_m, p->d_cell_start, p->d_coef, (int32_t)c0, ntx,
+                                   p->d_y, p->d_m, p->d_cell_start, p->d_coef, band0, ntx,
                                    j0, j1, sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2,
                                    sel.pixel, sel.counts, sel.landed);
             IRS_HIP(hipGetLastError());
+            if (cs) {
+                irs_status st = cs->end(s);
+                if (st != IRS_OK) return st;
+            }
         }
     }
     return IRS_OK;

@@ -70,8 +70,10 @@ irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const 
     hipStream_t s = p->stream;
 
     IRS_HIP(hipMalloc(&p->d_cell_start, sizeof(int32_t) * (size_t)(ncell + 1)));
+    p->h_cell_start.assign((size_t)ncell + 1, 0);
     if (n == 0) {
         IRS_HIP(hipMemsetAsync(p->d_cell_start, 0, sizeof(int32_t) * (size_t)(ncell + 1), s));
+        IRS_HIP(hipStreamSynchronize(s));
         return IRS_OK;
     }
     const size_t nb = sizeof(double) * (size_t)n;
@@ -127,6 +129,8 @@ irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const 
         hipLaunchKernelGGL(k_cell_start, dim3(nbc), dim3(tb), 0, s, skey, n, ncell,
                            p->d_cell_start);
         IRS_TRY(hipGetLastError());
+        IRS_TRY(hipMemcpyAsync(p->h_cell_start.data(), p->d_cell_start,
+                               sizeof(int32_t) * (size_t)(ncell + 1), hipMemcpyDeviceToHost, s));
         IRS_TRY(hipStreamSynchronize(s));
     }
 done:

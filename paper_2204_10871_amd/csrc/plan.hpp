@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/irs.h"
 #include "device_common.hpp"
@@ -24,11 +25,13 @@ struct irs_plan_s {
     // increasing input order).  FP64 positions and masses.
     double *d_x = nullptr, *d_y = nullptr, *d_m = nullptr;   // d_m null when unit masses
     int32_t *d_cell_start = nullptr;                         // n1x*n1y + 1
+    std::vector<int32_t> h_cell_start;                       // host copy (work counts)
 
     // Level-2 coefficients of one band of level-1 rows: 10 doubles per point
     // (Re/Im of C0..C4), point (gx, gy) at ((gy - band_row0*q) * n1x*q + gx).
     double *d_coef = nullptr;
     int64_t coef_rows_cap = 0;   // level-1 rows the buffer holds
+    int64_t coef_c0 = -1, coef_c1 = -2;   // level-1 rows whose coefficients it holds now
 
     // Scratch for host-side outputs.
     uint32_t *d_counts = nullptr;  // npix^2, used when counts are on the host
@@ -61,7 +64,24 @@ irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const 
 // [row0, row1) and, when ray_first/ray_last are set, ray index r = j*nx + i
 // in [ray_first, ray_last).  Outputs: per-ray arrays indexed r - ray_first
 // (any may be null), or counts (null when per-ray outputs are wanted).
+// Work and (optionally) HIP-event timings accumulated over one API call.
+struct CallStats {
+    int64_t level2_points = 0, level2_pairs = 0, direct_pairs = 0;
+    int32_t n_level2 = 0, n_rays = 0;
+    double ms_level2 = 0.0, ms_rays = 0.0;
+    bool timed = false;
+    std::vector<hipEvent_t> ev;       // start/stop pairs, in launch order
+    std::vector<int> ev_kind;         // 0 = level-2, 1 = ray kernel
+    // Record the start event of a launch of kind k (no-op unless timed).
+    irs_status begin(hipStream_t s, int k);
+    irs_status end(hipStream_t s);
+    // Wait for the recorded events and sum their durations.
+    irs_status collect();
+    ~CallStats();
+};
+
 struct RaySel {
+    CallStats *stats;
     int64_t row0, row1;
     int64_t ray_first, ray_last;
     double *alpha1, *alpha2;
