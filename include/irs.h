@@ -70,6 +70,11 @@ enum { IRS_FP64 = 0,        /* every step in double precision                  *
 
 /* irs_params.flags */
 #define IRS_SHEET_OFF      (1ull << 0)  /* omit the negative mass sheet (point-lens tests) */
+#define IRS_LEVEL2_PAPER   (1ull << 1)  /* level-2 coefficients by direct summation of the
+                                           distant lenses at every level-2 point, as in
+                                           the paper, instead of through one local
+                                           expansion per level-1 cell (same values to
+                                           FP64 rounding; kept for comparison)          */
 /* per-call flags */
 #define IRS_OUT_ON_DEVICE  (1ull << 8)  /* output pointers are device pointers          */
 #define IRS_TIME_PHASES    (1ull << 9)  /* time each kernel launch with HIP events on
@@ -90,7 +95,7 @@ typedef struct {
     double   level2_ray_multiple; /* > 0: dx2 = this many ray spacings; both <= 0:   */
                                   /* dx2 = dx1/20 (flow chart, level-2 resolution)   */
     double   crit_eps;            /* <= 0: 1e-3                                        */
-    uint64_t flags;               /* IRS_SHEET_OFF                                     */
+    uint64_t flags;               /* IRS_SHEET_OFF, IRS_LEVEL2_PAPER                   */
 } irs_params;
 
 typedef struct {
@@ -123,8 +128,9 @@ typedef struct {
     /* work done by the call (interpolation: level-2 points computed and
        (point, distant lens) pairs summed; direct: ray-lens pairs)                   */
     int64_t level2_points;
-    int64_t level2_pairs;
+    int64_t level2_pairs;         /* (point, distant lens) pairs the paper's form sums */
     int64_t direct_pairs;
+    double  level2_flops;         /* algorithmic flops of the level-2 kernel used      */
     /* with IRS_TIME_PHASES: summed HIP-event durations of the launches          */
     int32_t n_level2_launches;    /* level-2 (far field) launches                     */
     int32_t n_ray_launches;       /* level-3 or direct-sum launches                   */

@@ -11,6 +11,7 @@ STATUS_NAMES = {0: "IRS_OK", 1: "IRS_E_INVALID", 2: "IRS_E_CRITICAL", 3: "IRS_E_
 IRS_DIRECT, IRS_INTERP = 0, 1
 IRS_FP64, IRS_FP32_KAHAN = 0, 1
 IRS_SHEET_OFF = 1 << 0
+IRS_LEVEL2_PAPER = 1 << 1
 IRS_OUT_ON_DEVICE = 1 << 8
 IRS_TIME_PHASES = 1 << 9
 
@@ -46,7 +47,8 @@ class MapStats(C.Structure):
     _fields_ = [("rays_shot", C.c_int64), ("rays_landed", C.c_int64), ("rays_off", C.c_int64),
                 ("n_lens", C.c_int64), ("kappa_star_eff", C.c_double), ("ms_total", C.c_double),
                 ("level2_points", C.c_int64), ("level2_pairs", C.c_int64),
-                ("direct_pairs", C.c_int64), ("n_level2_launches", C.c_int32),
+                ("direct_pairs", C.c_int64), ("level2_flops", C.c_double),
+                ("n_level2_launches", C.c_int32),
                 ("n_ray_launches", C.c_int32), ("ms_level2", C.c_double),
                 ("ms_rays", C.c_double)]
 

@@ -106,6 +106,7 @@ void release(irs_plan_s *p)
     dev_free(p->d_y);
     dev_free(p->d_m);
     dev_free(p->d_cell_start);
+    dev_free(p->d_cxy);
     dev_free(p->d_coef);
     dev_free(p->d_counts);
     dev_free(p->d_tmp);
@@ -348,6 +349,7 @@ static irs_status shoot(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t *
         stats->level2_points = cs.level2_points;
         stats->level2_pairs = cs.level2_pairs;
         stats->direct_pairs = cs.direct_pairs;
+        stats->level2_flops = cs.level2_flops;
         stats->n_level2_launches = cs.n_level2;
         stats->n_ray_launches = cs.n_rays;
         stats->ms_level2 = cs.ms_level2;

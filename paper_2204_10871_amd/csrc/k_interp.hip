@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <vector>
 
 #include "plan.hpp"
 
@@ -195,6 +197,189 @@ __global__ __launch_bounds__(kThreads) void k_level2(
     }
 }
 
+// -------------------------------------------------------------------------
+// Level 2 through one local expansion per level-1 cell.
+//
+// For a cell with centre zc the distant lenses split into the ring (inside the
+// (2R+1) x (2R+1) block of cells around it, outside the 3 x 3 block) and the
+// rest.  The rest are summed once per cell into the expansion
+//     sum_i m_i / (z - z_i) = (1/s) sum_{n<P} Lt_n ((z - zc)/s)^n,
+//     Lt_n = sum_i m_i (-1)^n (s/(zc - z_i))^(n+1),       s = cell scale,
+// which converges at every point of the cell with ratio <= rho = (half cell
+// diagonal)/((R + 1/2) * shortest cell side); the library picks P so that the
+// truncation stays below ~1e-15 relative.  Each level-2 point z0 then takes
+//     c_k = (1/s^(k+1)) sum_{n>=k} C(n,k) Lt_n ((z0 - zc)/s)^(n-k)
+// plus the ring lenses summed directly with the c_k formula.  The result is the
+// same c_k as the per-point sum over all distant lenses, to FP64 rounding.
+//
+// One workgroup = four cells of one level-1 row (one wave per cell).  Lens
+// tiles are staged in LDS once for the four waves; each lane takes four lenses
+// of a tile.  The expansions are reduced across lanes with shuffles.
+// -------------------------------------------------------------------------
+constexpr int kRing = 3;                       // R: expansion excludes the 7 x 7 block
+constexpr int kCellsPerBlock = kThreads / kWave;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <bool UNIT, int P>
+__global__ __launch_bounds__(kThreads) void k_level2_local(
+    DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
+    const double *__restrict__ lm, const uint32_t *__restrict__ lcxy,
+    const int32_t *__restrict__ cell_start, int32_t nl, int32_t cy0, int32_t nxb,
+    double *__restrict__ coef)
+{
+    __shared__ double s_x[kThreads], s_y[kThreads], s_m[UNIT ? 1 : kThreads];
+    __shared__ uint32_t s_c[kThreads];
+    __shared__ double s_L[kCellsPerBlock][P][2];
+
+    const int tid = threadIdx.x;
+    const int lane = tid % kWave, wave = tid / kWave;
+    const int32_t cy = cy0 + (int32_t)(blockIdx.x / (uint32_t)nxb);
+    const int32_t cx0 = (int32_t)(blockIdx.x % (uint32_t)nxb) * kCellsPerBlock;
+    const int32_t cx = cx0 + wave;                       // this wave's cell
+    const bool live = cx < g.n1x;
+    const double sc = fmax(g.w1, g.h1), isc = 1.0 / sc;
+    const double zcr = g.a1 + ((double)cx + 0.5) * g.w1;
+    const double zci = g.b1 + ((double)cy + 0.5) * g.h1;
+
+    // ---- phase A: expansion of the lenses outside the (2R+1)^2 block
+    double Lr[P], Li[P];
+#pragma unroll
+    for (int n = 0; n < P; ++n) Lr[n] = Li[n] = 0.0;
+    for (int32_t base = 0; base < nl; base += kThreads) {
+        __syncthreads();
+        if (base + tid < nl) {
+            s_x[tid] = lx[base + tid];
+            s_y[tid] = ly[base + tid];
+            if (!UNIT) s_m[tid] = lm[base + tid];
+            s_c[tid] = lcxy[base + tid];
+        }
+        __syncthreads();
+        const int cnt = min(kThreads, nl - base);
+#pragma unroll
+        for (int k = 0; k < kThreads / kWave; ++k) {
+            const int t = lane + k * kWave;
+            if (!live || t >= cnt) continue;
+            const uint32_t c = s_c[t];
+            const int32_t lcx = (int32_t)(c & 0xffffu), lcy = (int32_t)(c >> 16);
+            if (abs(lcx - cx) <= kRing && abs(lcy - cy) <= kRing) continue;
+            const double wr = (zcr - s_x[t]) * isc, wi = (zci - s_y[t]) * isc;
+            const double inv = 1.0 / (wr * wr + wi * wi);
+            const double ur = wr * inv, ui = -wi * inv;          // s/(zc - z_i)
+            const double M = UNIT ? 1.0 : s_m[t];
+            double tr = M * ur, ti = M * ui;                     // m u^(n+1) (-1)^n
+            const double vr = -ur, vi = -ui;
+#pragma unroll
+            for (int n = 0; n < P; ++n) {
+                Lr[n] += tr;
+                Li[n] += ti;
+                const double nr = tr * vr - ti * vi;
+                ti = tr * vi + ti * vr;
+                tr = nr;
+            }
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < P; ++n) {
+        const double r = wave_sum(Lr[n]), i = wave_sum(Li[n]);
+        if (lane == 0) {
+            s_L[wave][n][0] = r;
+            s_L[wave][n][1] = i;
+        }
+    }
+    __syncthreads();
+
+    // ---- phase B: the level-2 points of the four cells
+    const int q = g.q, npts = q * q;
+    const int64_t nxq = (int64_t)g.n1x * q;
+    for (int pp = tid; pp < kCellsPerBlock * npts; pp += kThreads) {
+        const int w = pp / npts, pt = pp % npts;
+        const int32_t ccx = cx0 + w;
+        if (ccx >= g.n1x) continue;
+        const int64_t gx = (int64_t)ccx * q + pt % q;
+        const int64_t gyl = pt / q;
+        const double x0 = level2_x(g, gx), y0 = level2_y(g, (int64_t)cy * q + gyl);
+        const double czr = g.a1 + ((double)ccx + 0.5) * g.w1;
+        const double dr = (x0 - czr) * isc, di = (y0 - zci) * isc;
+        // c_k = s^-(k+1) sum_n C(n,k) Lt_n d^(n-k), accumulated forward in n with
+        // C(n,k) by Pascal's rule and E[k] = d^(n-k) shifted along
+        double cr[5] = {0, 0, 0, 0, 0}, ci[5] = {0, 0, 0, 0, 0};
+        double b[5] = {1, 0, 0, 0, 0};
+        double er[5] = {1, 0, 0, 0, 0}, ei[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int n = 0; n < P; ++n) {
+            const double Lr_ = s_L[w][n][0], Li_ = s_L[w][n][1];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                cr[k] += b[k] * (Lr_ * er[k] - Li_ * ei[k]);
+                ci[k] += b[k] * (Lr_ * ei[k] + Li_ * er[k]);
+            }
+#pragma unroll
+            for (int k = 4; k >= 1; --k) b[k] += b[k - 1];
+#pragma unroll
+            for (int k = 4; k >= 1; --k) { er[k] = er[k - 1]; ei[k] = ei[k - 1]; }
+            const double nr = er[0] * dr - ei[0] * di;
+            ei[0] = er[0] * di + ei[0] * dr;
+            er[0] = nr;
+        }
+        cplx c[5];
+        double sk = isc;                                  // 1/s^(k+1)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            c[k] = {cr[k] * sk, ci[k] * sk};
+            sk *= isc;
+        }
+        // ring lenses: inside the (2R+1)^2 block, outside the 3 x 3 block
+        const int32_t yl = max(0, cy - kRing), yh = min(g.n1y - 1, cy + kRing);
+        for (int32_t row = yl; row <= yh; ++row) {
+            const bool mid = abs(row - cy) <= 1;
+            for (int seg = 0; seg < (mid ? 2 : 1); ++seg) {
+                int32_t xa, xb;
+                if (!mid) { xa = ccx - kRing; xb = ccx + kRing; }
+                else if (seg == 0) { xa = ccx - kRing; xb = ccx - 2; }
+                else { xa = ccx + 2; xb = ccx + kRing; }
+                xa = max(xa, 0);
+                xb = min(xb, g.n1x - 1);
+                if (xa > xb) continue;
+                const int32_t pb = cell_start[row * g.n1x + xa];
+                const int32_t pe = cell_start[row * g.n1x + xb + 1];
+                for (int32_t pl = pb; pl < pe; ++pl) {
+                    const double wr = x0 - lx[pl], wi = y0 - ly[pl];
+                    const double inv = 1.0 / (wr * wr + wi * wi);
+                    const cplx u = {wr * inv, -wi * inv};
+                    cplx t1 = UNIT ? u : cplx{lm[pl] * u.r, lm[pl] * u.i};
+                    c[0].r += t1.r; c[0].i += t1.i;
+                    cplx t2 = cmul(t1, u);
+                    c[1].r -= t2.r; c[1].i -= t2.i;
+                    cplx t3 = cmul(t2, u);
+                    c[2].r += t3.r; c[2].i += t3.i;
+                    cplx t4 = cmul(t3, u);
+                    c[3].r -= t4.r; c[3].i -= t4.i;
+                    cplx t5 = cmul(t4, u);
+                    c[4].r += t5.r; c[4].i += t5.i;
+                }
+            }
+        }
+        if (g.sheet && !corner_cell(g, ccx, cy)) {
+            cplx sh[5];
+            sheet_coeffs(g, x0, y0, sh);
+#pragma unroll
+            for (int o = 0; o < 5; ++o) { c[o].r += sh[o].r; c[o].i += sh[o].i; }
+        }
+        double *dst = coef + (((int64_t)(cy - cy0) * q + gyl) * nxq + gx) * 10;
+#pragma unroll
+        for (int o = 0; o < 5; ++o) {
+            dst[2 * o] = c[o].r;
+            dst[2 * o + 1] = c[o].i;
+        }
+    }
+}
+
 template <bool UNIT>
 __global__ __launch_bounds__(kThreads) void k_level3(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
@@ -290,6 +475,23 @@ int64_t level2_row_host(const DevGeom &g, int64_t j)
     return ((2 * j + 1) * (int64_t)g.n1y * g.q) / (2 * g.ny);
 }
 
+// Expansion order of the per-cell local expansion (0: sum at every point as
+// in the paper).  The expansion about a cell centre converges over the cell
+// with ratio rho = (half diagonal)/((R + 1/2) * shorter side); the truncation
+// of c_4 is about C(P,4) rho^(P-4)/(1-rho)^5, kept below 1e-14.
+int level2_order(const irs_plan_s *p)
+{
+    if (p->params.flags & IRS_LEVEL2_PAPER) return 0;
+    const DevGeom &g = p->dg;
+    const double rho = 0.5 * std::sqrt(g.w1 * g.w1 + g.h1 * g.h1) /
+                       ((kRing + 0.5) * std::min(g.w1, g.h1));
+    for (int P : {32, 48}) {
+        double c4 = (double)P * (P - 1) * (P - 2) * (P - 3) / 24.0;
+        if (c4 * std::pow(rho, P - 4) / std::pow(1.0 - rho, 5) < 1e-14) return P;
+    }
+    return 0;
+}
+
 }  // namespace
 
 irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
@@ -327,29 +529,57 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
         const int64_t c1 = std::min(cyB, c0 + p->coef_rows_cap - 1);
         if (!(p->coef_c0 <= c0 && c1 <= p->coef_c1)) {
             // the band's level-2 coefficients are not resident: compute them
-            const unsigned nb2 = (unsigned)((c1 - c0 + 1) * g.n1x);
+            const int P = level2_order(p);
             if (cs) {
                 irs_status st = cs->begin(s, 0);
                 if (st != IRS_OK) return st;
                 cs->n_level2++;
                 cs->level2_points += (c1 - c0 + 1) * row_pts;
-                for (int64_t cy = c0; cy <= c1; ++cy) {
-                    const int64_t yl = std::max<int64_t>(0, cy - 1), yh = std::min<int64_t>(g.n1y - 1, cy + 1);
+                const std::vector<int32_t> &hc = p->h_cell_start;
+                auto block = [&](int64_t cx, int64_t cy, int64_t r) {   // lenses in a (2r+1)^2 block
+                    const int64_t xl = std::max<int64_t>(0, cx - r), xh = std::min<int64_t>(g.n1x - 1, cx + r);
+                    int64_t n = 0;
+                    for (int64_t row = std::max<int64_t>(0, cy - r); row <= std::min<int64_t>(g.n1y - 1, cy + r); ++row)
+                        n += hc[row * g.n1x + xh + 1] - hc[row * g.n1x + xl];
+                    return n;
+                };
+                for (int64_t cy = c0; cy <= c1; ++cy)
                     for (int64_t cx = 0; cx < g.n1x; ++cx) {
-                        const int64_t xl = std::max<int64_t>(0, cx - 1), xh = std::min<int64_t>(g.n1x - 1, cx + 1);
-                        int64_t near = 0;
-                        for (int64_t row = yl; row <= yh; ++row)
-                            near += p->h_cell_start[row * g.n1x + xh + 1] - p->h_cell_start[row * g.n1x + xl];
-                        cs->level2_pairs += q * q * (p->n_lens - near);
+                        const int64_t b3 = block(cx, cy, 1);
+                        cs->level2_pairs += q * q * (p->n_lens - b3);
+                        if (P == 0) {
+                            cs->level2_flops += 44.0 * (double)(q * q * (p->n_lens - b3));
+                        } else {
+                            const int64_t b7 = block(cx, cy, kRing);
+                            cs->level2_flops += (double)(p->n_lens - b7) * (10.0 + 8.0 * P)
+                                              + (double)(q * q) * (44.0 * (double)(b7 - b3) + 60.0 * P);
+                        }
                     }
-                }
             }
-            if (p->unit_mass)
-                hipLaunchKernelGGL(k_level2<true>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,
-                                   p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
-            else
-                hipLaunchKernelGGL(k_level2<false>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,
-                                   p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
+            if (P == 0) {
+                const unsigned nb2 = (unsigned)((c1 - c0 + 1) * g.n1x);
+                if (p->unit_mass)
+                    hipLaunchKernelGGL(k_level2<true>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,
+                                       p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
+                else
+                    hipLaunchKernelGGL(k_level2<false>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,
+                                       p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
+            } else {
+                const int32_t nxb = (g.n1x + kCellsPerBlock - 1) / kCellsPerBlock;
+                const unsigned nb2 = (unsigned)((c1 - c0 + 1) * nxb);
+#define IRS_L2L(U, PP)                                                                        \
+    hipLaunchKernelGGL((k_level2_local<U, PP>), dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,      \
+                       p->d_y, p->d_m, p->d_cxy, p->d_cell_start, nl, (int32_t)c0, nxb,        \
+                       p->d_coef)
+                if (p->unit_mass) {
+                    if (P == 32) IRS_L2L(true, 32);
+                    else IRS_L2L(true, 48);
+                } else {
+                    if (P == 32) IRS_L2L(false, 32);
+                    else IRS_L2L(false, 48);
+                }
+#undef IRS_L2L
+            }
             IRS_HIP(hipGetLastError());
             if (cs) {
                 irs_status st = cs->end(s);

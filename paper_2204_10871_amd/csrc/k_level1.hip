@@ -28,10 +28,11 @@ __global__ void k_cell_keys(DevGeom g, const double *__restrict__ x,
     idx[i] = i;
 }
 
-__global__ void k_gather(const int32_t *__restrict__ perm, const double *__restrict__ x,
-                         const double *__restrict__ y, const double *__restrict__ m, int32_t n,
+__global__ void k_gather(const int32_t *__restrict__ perm, const int32_t *__restrict__ skey,
+                         const double *__restrict__ x, const double *__restrict__ y,
+                         const double *__restrict__ m, int32_t n, int32_t n1x,
                          double *__restrict__ sx, double *__restrict__ sy,
-                         double *__restrict__ sm)
+                         double *__restrict__ sm, uint32_t *__restrict__ cxy)
 {
     const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
@@ -39,6 +40,8 @@ __global__ void k_gather(const int32_t *__restrict__ perm, const double *__restr
     sx[p] = x[i];
     sy[p] = y[i];
     if (m) sm[p] = m[i];
+    const int32_t c = skey[p];
+    cxy[p] = ((uint32_t)(c / n1x) << 16) | (uint32_t)(c % n1x);
 }
 
 // cell_start[c] = number of sorted keys < c, for c in [0, ncell].
@@ -62,8 +65,8 @@ irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const 
 {
     const int32_t n = (int32_t)p->n_lens;
     const int64_t ncell64 = (int64_t)p->dg.n1x * p->dg.n1y;
-    if (ncell64 >= INT32_MAX) {
-        set_error("too many level-1 cells");
+    if (ncell64 >= INT32_MAX || p->dg.n1x > 65535 || p->dg.n1y > 65535) {
+        set_error("level-1 grid too large (at most 65535 cells per side)");
         return IRS_E_INVALID;
     }
     const int32_t ncell = (int32_t)ncell64;
@@ -80,6 +83,7 @@ irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const 
     IRS_HIP(hipMalloc(&p->d_x, nb));
     IRS_HIP(hipMalloc(&p->d_y, nb));
     if (hm) IRS_HIP(hipMalloc(&p->d_m, nb));
+    IRS_HIP(hipMalloc(&p->d_cxy, sizeof(uint32_t) * (size_t)n));
 
     double *ux = nullptr, *uy = nullptr, *um = nullptr;
     int32_t *key = nullptr, *skey = nullptr, *idx = nullptr, *perm = nullptr;
@@ -122,8 +126,8 @@ irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const 
         IRS_TRY(hipMalloc(&tmp, tmp_bytes));
         IRS_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key, skey, idx, perm, n, 0,
                                                    end_bit, s));
-        hipLaunchKernelGGL(k_gather, dim3(nbk), dim3(tb), 0, s, perm, ux, uy, um, n, p->d_x,
-                           p->d_y, p->d_m);
+        hipLaunchKernelGGL(k_gather, dim3(nbk), dim3(tb), 0, s, perm, skey, ux, uy, um, n,
+                           p->dg.n1x, p->d_x, p->d_y, p->d_m, p->d_cxy);
         IRS_TRY(hipGetLastError());
         const int nbc = (ncell + 1 + tb - 1) / tb;
         hipLaunchKernelGGL(k_cell_start, dim3(nbc), dim3(tb), 0, s, skey, n, ncell,

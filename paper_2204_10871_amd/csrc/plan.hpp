@@ -25,6 +25,7 @@ struct irs_plan_s {
     // increasing input order).  FP64 positions and masses.
     double *d_x = nullptr, *d_y = nullptr, *d_m = nullptr;   // d_m null when unit masses
     int32_t *d_cell_start = nullptr;                         // n1x*n1y + 1
+    uint32_t *d_cxy = nullptr;                               // per sorted lens: cy << 16 | cx
     std::vector<int32_t> h_cell_start;                       // host copy (work counts)
 
     // Level-2 coefficients of one band of level-1 rows: 10 doubles per point
@@ -67,6 +68,7 @@ irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const 
 // Work and (optionally) HIP-event timings accumulated over one API call.
 struct CallStats {
     int64_t level2_points = 0, level2_pairs = 0, direct_pairs = 0;
+    double level2_flops = 0.0;
     int32_t n_level2 = 0, n_rays = 0;
     double ms_level2 = 0.0, ms_rays = 0.0;
     bool timed = false;

@@ -186,3 +186,31 @@ def test_critical_and_invalid_plans(irs):
             pl.deflect_grid(pl.n_rays - 5, 10)
         with pytest.raises(irs.IrsError):
             pl.shoot_rows(-1, 3, np.zeros(16 * 16, np.uint32))
+
+
+@pytest.mark.parametrize("kind", ["square_cells", "oblong_cells"])
+def test_level2_local_expansion_equals_paper_form(irs, kind):
+    """The per-cell local expansion gives the same level-2 coefficients as the
+    per-point sum over all distant lenses (the paper's form), to FP64 rounding:
+    identical per-ray deflections to 1e-11 and identical maps."""
+    if kind == "square_cells":
+        c = Case(0.6, 0.0, 0.6, 14.0, 96, n_rays=400_000, mass="salpeter", seed=61)
+    else:   # I_y/dx1 just above 10: 191 x 11 cells of aspect ~1.1 (expansion order 48)
+        c = Case(0.45, 0.05, 0.45, 11.75, 64, n_rays=300_000, seed=62)
+    g = c.geo
+    say(f"level-2 forms {kind}: cells {g.n1x}x{g.n1y} w1={g.ix / g.n1x:.3f} h1={g.iy / g.n1y:.3f}")
+    import paper_2204_10871_amd as irs_mod
+    L = c.lenses
+    out = {}
+    for paper in (False, True):
+        p = irs_mod.make_params(**c.kw, method="interp", precision="fp64",
+                                level2_paper=paper, **c.p_extra)
+        with irs_mod.Plan(p, L.x, L.y, L.m) as pl:
+            a1, a2, px = pl.deflect_grid(0, pl.n_rays)
+            counts, st = pl.shoot_map()
+        out[paper] = (a1, a2, px, counts)
+    e = rel_err(out[False][0], out[False][1], out[True][0], out[True][1])
+    say(f"  max e_r local vs paper form {e.max():.3e}")
+    assert e.max() < 1e-11
+    assert np.mean(out[False][2] == out[True][2]) >= 1 - 1e-6
+    assert np.abs(out[False][3].astype(np.int64) - out[True][3]).sum() <= 2 * np.sum(out[False][2] != out[True][2])
