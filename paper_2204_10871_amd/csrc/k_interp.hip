@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <vector>
 
@@ -219,6 +220,17 @@ __global__ __launch_bounds__(kThreads) void k_level2(
 constexpr int kRing = 3;                       // R: expansion excludes the 7 x 7 block
 constexpr int kCellsPerBlock = kThreads / kWave;
 
+// 1/d for d > 0: hardware reciprocal estimate refined by two Newton steps
+// (error ~1 ulp; the IEEE division sequence is not needed here)
+__device__ __forceinline__ double rcp64(double d)
+{
+    double v = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, v, 1.0);
+    v = fma(v, e, v);
+    e = fma(-d, v, 1.0);
+    return fma(v, e, v);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -261,26 +273,43 @@ __global__ __launch_bounds__(kThreads) void k_level2_local(
         }
         __syncthreads();
         const int cnt = min(kThreads, nl - base);
+        // two lenses per lane at a time: two independent power chains
 #pragma unroll
-        for (int k = 0; k < kThreads / kWave; ++k) {
-            const int t = lane + k * kWave;
-            if (!live || t >= cnt) continue;
-            const uint32_t c = s_c[t];
-            const int32_t lcx = (int32_t)(c & 0xffffu), lcy = (int32_t)(c >> 16);
-            if (abs(lcx - cx) <= kRing && abs(lcy - cy) <= kRing) continue;
-            const double wr = (zcr - s_x[t]) * isc, wi = (zci - s_y[t]) * isc;
-            const double inv = 1.0 / (wr * wr + wi * wi);
-            const double ur = wr * inv, ui = -wi * inv;          // s/(zc - z_i)
-            const double M = UNIT ? 1.0 : s_m[t];
-            double tr = M * ur, ti = M * ui;                     // m u^(n+1) (-1)^n
-            const double vr = -ur, vi = -ui;
+        for (int k = 0; k < kThreads / kWave; k += 2) {
+            double tr[2], ti[2], vr[2], vi[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int t = lane + (k + e) * kWave;
+                bool use = live && t < cnt;
+                double X = zcr + sc, Y = zci, M = 0.0;   // harmless stand-in
+                if (use) {
+                    const uint32_t c = s_c[t];
+                    const int32_t lcx = (int32_t)(c & 0xffffu), lcy = (int32_t)(c >> 16);
+                    use = abs(lcx - cx) > kRing || abs(lcy - cy) > kRing;
+                    if (use) {
+                        X = s_x[t];
+                        Y = s_y[t];
+                        M = UNIT ? 1.0 : s_m[t];
+                    }
+                }
+                const double wr = (zcr - X) * isc, wi = (zci - Y) * isc;
+                const double inv = rcp64(wr * wr + wi * wi);
+                const double ur = wr * inv, ui = -wi * inv;       // s/(zc - z_i)
+                tr[e] = M * ur;                                   // m u^(n+1) (-1)^n
+                ti[e] = M * ui;
+                vr[e] = -ur;
+                vi[e] = -ui;
+            }
 #pragma unroll
             for (int n = 0; n < P; ++n) {
-                Lr[n] += tr;
-                Li[n] += ti;
-                const double nr = tr * vr - ti * vi;
-                ti = tr * vi + ti * vr;
-                tr = nr;
+                Lr[n] += tr[0] + tr[1];
+                Li[n] += ti[0] + ti[1];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const double nr = tr[e] * vr[e] - ti[e] * vi[e];
+                    ti[e] = tr[e] * vi[e] + ti[e] * vr[e];
+                    tr[e] = nr;
+                }
             }
         }
     }
@@ -380,6 +409,42 @@ __global__ __launch_bounds__(kThreads) void k_level2_local(
     }
 }
 
+// -------------------------------------------------------------------------
+// Level 3: one workgroup = a 64 x 32 tile of rays (lane = column, each wave 8
+// rows).  Every ray: Horner of its level-2 point's C_0..C_4, the sheet's
+// linear term (closed form in corner cells), the near lenses exactly, the
+// macro term, beta and the pixel.  Binning: the tile's rays land in a small
+// patch of the map, so the workgroup finds the bounding box of its landed
+// pixels, counts into an LDS histogram over that box (wave-aggregated LDS
+// adds) and flushes each non-empty bin with one global atomic; a box larger
+// than the LDS histogram falls back to wave-aggregated global atomics.
+// -------------------------------------------------------------------------
+constexpr int kL3Rows = 32;
+constexpr int kL3RowsPerWave = kL3Rows / (kThreads / kWave);
+constexpr int kHistCap = 8192;
+
+// floor(num / den) for 0 <= num < 2^53, den > 0, without 64-bit integer division
+__device__ __forceinline__ int64_t floor_div(int64_t num, int64_t den)
+{
+    int64_t v = (int64_t)((double)num / (double)den);
+    if (v * den > num) --v;
+    else if ((v + 1) * den <= num) ++v;
+    return v;
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
 template <bool UNIT>
 __global__ __launch_bounds__(kThreads) void k_level3(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
@@ -388,22 +453,35 @@ __global__ __launch_bounds__(kThreads) void k_level3(
     int64_t ray_first, int64_t ray_last, double *a1o, double *a2o, int64_t *pixo,
     uint32_t *counts, unsigned long long *landed)
 {
+    __shared__ uint32_t s_hist[kHistCap];
+    __shared__ int s_box[kThreads / kWave][4];
+
     const int tid = threadIdx.x;
     const int lane = tid % kWave, wave = tid / kWave;
     const int64_t tx = (int64_t)blockIdx.x % ntx;
     const int64_t ty = (int64_t)blockIdx.x / ntx;
     const int64_t i = tx * kWave + lane;
-    const int64_t j = jr0 + ty * (kThreads / kWave) + wave;
-    const int64_t r = j * g.nx + i;
-    const bool valid = i < g.nx && j < jr1 && r >= ray_first && r < ray_last;
-    double a1 = 0.0, a2 = 0.0;
-    int32_t pix = -1;
-    if (valid) {
-        const double t1 = ray_x(g, i), t2 = ray_y(g, j);
-        const int64_t gx = level2_col(g, i), gy = level2_row(g, j);
-        const int64_t cx = gx / g.q, cy = gy / g.q;
-        const double hr = t1 - level2_x(g, gx), hi = t2 - level2_y(g, gy);
-        const double *C = coef + (((gy - (int64_t)cy0 * g.q) * ((int64_t)g.n1x * g.q)) + gx) * 10;
+    const bool in_col = i < g.nx;
+    const int64_t nxq = (int64_t)g.n1x * g.q;
+    const int64_t gx = in_col ? floor_div((2 * i + 1) * nxq, 2 * g.nx) : 0;
+    const int64_t cx = gx / g.q;
+    const double t1 = ray_x(g, i);
+    const double hr = t1 - level2_x(g, gx);
+    const int64_t xl = cx > 0 ? cx - 1 : 0, xh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
+
+    int32_t pix[kL3RowsPerWave];
+#pragma unroll
+    for (int k = 0; k < kL3RowsPerWave; ++k) {
+        const int64_t j = jr0 + ty * kL3Rows + wave * kL3RowsPerWave + k;
+        const int64_t r = j * g.nx + i;
+        const bool valid = in_col && j < jr1 && r >= ray_first && r < ray_last;
+        pix[k] = -1;
+        if (!valid) continue;
+        const double t2 = ray_y(g, j);
+        const int64_t gy = floor_div((2 * j + 1) * (int64_t)g.n1y * g.q, 2 * g.ny);
+        const int64_t cy = gy / g.q;
+        const double hi = t2 - level2_y(g, gy);
+        const double *C = coef + ((gy - (int64_t)cy0 * g.q) * nxq + gx) * 10;
         // Horner: C0 + h (C1 + h (C2 + h (C3 + h C4)))
         cplx A = {C[8], C[9]};
 #pragma unroll
@@ -426,34 +504,86 @@ __global__ __launch_bounds__(kThreads) void k_level3(
         }
         // nearby lenses, exactly
         double n1 = 0.0, n2 = 0.0;
-        const int64_t xl = cx > 0 ? cx - 1 : 0, xh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
         const int64_t yl = cy > 0 ? cy - 1 : 0, yh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
         for (int64_t row = yl; row <= yh; ++row) {
             const int32_t pb = cell_start[row * g.n1x + xl];
             const int32_t pe = cell_start[row * g.n1x + xh + 1];
-            for (int32_t p = pb; p < pe; ++p) {
-                const double d1 = t1 - lx[p], d2 = t2 - ly[p];
+            for (int32_t q_ = pb; q_ < pe; ++q_) {
+                const double d1 = t1 - lx[q_], d2 = t2 - ly[q_];
                 const double rr = d1 * d1 + d2 * d2;
                 if (rr > 0.0) {
-                    const double w = (UNIT ? 1.0 : lm[p]) / rr;
+                    const double w = (UNIT ? 1.0 : lm[q_]) / rr;
                     n1 += w * d1;
                     n2 += w * d2;
                 }
             }
         }
-        a1 = g.kpg * t1 + n1 + A.r;          // conj(A) is the far + sheet deflection
-        a2 = g.kmg * t2 + n2 - A.i;
-        pix = pixel_of(g, t1 - a1, t2 - a2);
+        const double a1 = g.kpg * t1 + n1 + A.r;       // conj(A) is the far + sheet deflection
+        const double a2 = g.kmg * t2 + n2 - A.i;
+        pix[k] = pixel_of(g, t1 - a1, t2 - a2);
+        if (!counts) {
+            const int64_t o = r - ray_first;
+            if (a1o) a1o[o] = a1;
+            if (a2o) a2o[o] = a2;
+            if (pixo) pixo[o] = pix[k];
+        }
     }
-    if (counts) {
-        bin_wave(counts, pix);
-        const uint64_t got = __ballot(pix >= 0);
-        if (lane == 0 && got) atomicAdd(landed, (unsigned long long)__popcll(got));
-    } else if (valid) {
-        const int64_t o = r - ray_first;
-        if (a1o) a1o[o] = a1;
-        if (a2o) a2o[o] = a2;
-        if (pixo) pixo[o] = pix;
+    if (!counts) return;
+
+    // bounding box of the tile's landed pixels
+    int bx0 = INT_MAX, bx1 = -1, by0 = INT_MAX, by1 = -1, nland = 0;
+#pragma unroll
+    for (int k = 0; k < kL3RowsPerWave; ++k) {
+        if (pix[k] < 0) continue;
+        const int px = pix[k] % g.npix, py = pix[k] / g.npix;
+        bx0 = min(bx0, px); bx1 = max(bx1, px);
+        by0 = min(by0, py); by1 = max(by1, py);
+        ++nland;
+    }
+    bx0 = wave_min(bx0); bx1 = wave_max(bx1);
+    by0 = wave_min(by0); by1 = wave_max(by1);
+    unsigned long long wl = (unsigned long long)nland;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) wl += __shfl_xor(wl, o);
+    if (lane == 0) {
+        s_box[wave][0] = bx0; s_box[wave][1] = bx1;
+        s_box[wave][2] = by0; s_box[wave][3] = by1;
+        if (wl) atomicAdd(landed, wl);
+    }
+    __syncthreads();
+    bx0 = INT_MAX; bx1 = -1; by0 = INT_MAX; by1 = -1;
+#pragma unroll
+    for (int w = 0; w < kThreads / kWave; ++w) {
+        bx0 = min(bx0, s_box[w][0]); bx1 = max(bx1, s_box[w][1]);
+        by0 = min(by0, s_box[w][2]); by1 = max(by1, s_box[w][3]);
+    }
+    if (bx1 < 0) return;                                   // nothing landed (block-uniform)
+    const int bw = bx1 - bx0 + 1;
+    const int64_t area = (int64_t)bw * (by1 - by0 + 1);
+    if (area > kHistCap) {                                 // block-uniform fallback
+#pragma unroll
+        for (int k = 0; k < kL3RowsPerWave; ++k) bin_wave(counts, pix[k]);
+        return;
+    }
+    for (int b = tid; b < area; b += kThreads) s_hist[b] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kL3RowsPerWave; ++k) {
+        const int32_t lp = pix[k] < 0 ? -1
+                         : (pix[k] / g.npix - by0) * bw + (pix[k] % g.npix - bx0);
+        uint64_t todo = __ballot(lp >= 0);
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const int32_t v = __shfl(lp, leader);
+            const uint64_t same = __ballot(lp == v) & todo;
+            if (lane == leader) atomicAdd(&s_hist[v], (uint32_t)__popcll(same));
+            todo &= ~same;
+        }
+    }
+    __syncthreads();
+    for (int b = tid; b < area; b += kThreads) {
+        const uint32_t v = s_hist[b];
+        if (v) atomicAdd(&counts[(by0 + b / bw) * g.npix + bx0 + b % bw], v);
     }
 }
 
@@ -523,7 +653,7 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
         p->coef_rows_cap = rows;
     }
     const int64_t ntx = (g.nx + kWave - 1) / kWave;
-    const int rows_per_block = kThreads / kWave;
+    const int rows_per_block = kL3Rows;
     CallStats *cs = sel.stats;
     for (int64_t c0 = cyA; c0 <= cyB; c0 += p->coef_rows_cap) {
         const int64_t c1 = std::min(cyB, c0 + p->coef_rows_cap - 1);
