@@ -108,6 +108,7 @@ void release(irs_plan_s *p)
     dev_free(p->d_cell_start);
     dev_free(p->d_cxy);
     dev_free(p->d_coef);
+    dev_free(p->d_part);
     dev_free(p->d_counts);
     dev_free(p->d_tmp);
     dev_free(p->d_landed);

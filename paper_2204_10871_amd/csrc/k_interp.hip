@@ -219,6 +219,7 @@ __global__ __launch_bounds__(kThreads) void k_level2(
 // -------------------------------------------------------------------------
 constexpr int kRing = 3;                       // R: expansion excludes the 7 x 7 block
 constexpr int kCellsPerBlock = kThreads / kWave;
+constexpr int kChunkLens = 65536;              // lenses per partial expansion
 
 // 1/d for d > 0: hardware reciprocal estimate refined by two Newton steps
 // (error ~1 ulp; the IEEE division sequence is not needed here)
@@ -239,40 +240,41 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 template <bool UNIT, int P>
-__global__ __launch_bounds__(kThreads) void k_level2_local(
+__global__ __launch_bounds__(kThreads) void k_level2_expand(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
-    const double *__restrict__ lm, const uint32_t *__restrict__ lcxy,
-    const int32_t *__restrict__ cell_start, int32_t nl, int32_t cy0, int32_t nxb,
-    double *__restrict__ coef)
+    const double *__restrict__ lm, const uint32_t *__restrict__ lcxy, int32_t nl, int32_t cy0,
+    int32_t nxb, int32_t nchunk, int32_t chunk_len, double *__restrict__ part)
 {
     __shared__ double s_x[kThreads], s_y[kThreads], s_m[UNIT ? 1 : kThreads];
     __shared__ uint32_t s_c[kThreads];
-    __shared__ double s_L[kCellsPerBlock][P][2];
 
     const int tid = threadIdx.x;
     const int lane = tid % kWave, wave = tid / kWave;
-    const int32_t cy = cy0 + (int32_t)(blockIdx.x / (uint32_t)nxb);
-    const int32_t cx0 = (int32_t)(blockIdx.x % (uint32_t)nxb) * kCellsPerBlock;
-    const int32_t cx = cx0 + wave;                       // this wave's cell
+    const int32_t group = (int32_t)(blockIdx.x / (uint32_t)nchunk);
+    const int32_t chunk = (int32_t)(blockIdx.x % (uint32_t)nchunk);
+    const int32_t cy = cy0 + group / nxb;
+    const int32_t cx = (group % nxb) * kCellsPerBlock + wave;     // this wave's cell
     const bool live = cx < g.n1x;
     const double sc = fmax(g.w1, g.h1), isc = 1.0 / sc;
     const double zcr = g.a1 + ((double)cx + 0.5) * g.w1;
     const double zci = g.b1 + ((double)cy + 0.5) * g.h1;
+    const int32_t lo = chunk * chunk_len;
+    const int32_t hi = min(nl, lo + chunk_len);
 
-    // ---- phase A: expansion of the lenses outside the (2R+1)^2 block
+    // partial expansion of this chunk's lenses outside the (2R+1)^2 block
     double Lr[P], Li[P];
 #pragma unroll
     for (int n = 0; n < P; ++n) Lr[n] = Li[n] = 0.0;
-    for (int32_t base = 0; base < nl; base += kThreads) {
+    for (int32_t base = lo; base < hi; base += kThreads) {
         __syncthreads();
-        if (base + tid < nl) {
+        if (base + tid < hi) {
             s_x[tid] = lx[base + tid];
             s_y[tid] = ly[base + tid];
             if (!UNIT) s_m[tid] = lm[base + tid];
             s_c[tid] = lcxy[base + tid];
         }
         __syncthreads();
-        const int cnt = min(kThreads, nl - base);
+        const int cnt = min(kThreads, hi - base);
         // two lenses per lane at a time: two independent power chains
 #pragma unroll
         for (int k = 0; k < kThreads / kWave; k += 2) {
@@ -316,10 +318,36 @@ __global__ __launch_bounds__(kThreads) void k_level2_local(
 #pragma unroll
     for (int n = 0; n < P; ++n) {
         const double r = wave_sum(Lr[n]), i = wave_sum(Li[n]);
-        if (lane == 0) {
-            s_L[wave][n][0] = r;
-            s_L[wave][n][1] = i;
+        if (lane == 0 && live) {
+            double *dst = part + ((((int64_t)(cy - cy0) * g.n1x + cx) * nchunk + chunk) * P + n) * 2;
+            dst[0] = r;
+            dst[1] = i;
         }
+    }
+}
+
+template <bool UNIT, int P>
+__global__ __launch_bounds__(kThreads) void k_level2_points(
+    DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
+    const double *__restrict__ lm, const int32_t *__restrict__ cell_start, int32_t cy0,
+    int32_t nxb, int32_t nchunk, const double *__restrict__ part, double *__restrict__ coef)
+{
+    __shared__ double s_L[kCellsPerBlock][P][2];
+    const int tid = threadIdx.x;
+    const int32_t cy = cy0 + (int32_t)(blockIdx.x / (uint32_t)nxb);
+    const int32_t cx0 = (int32_t)(blockIdx.x % (uint32_t)nxb) * kCellsPerBlock;
+    const double sc = fmax(g.w1, g.h1), isc = 1.0 / sc;
+    const double zci = g.b1 + ((double)cy + 0.5) * g.h1;
+    // sum the chunks' partial expansions, in chunk order
+    for (int e = tid; e < kCellsPerBlock * P * 2; e += kThreads) {
+        const int w = e / (P * 2), n = (e / 2) % P, comp = e % 2;
+        const int32_t ccx = cx0 + w;
+        double acc = 0.0;
+        if (ccx < g.n1x) {
+            const double *src = part + (((int64_t)(cy - cy0) * g.n1x + ccx) * nchunk * P + n) * 2 + comp;
+            for (int k = 0; k < nchunk; ++k) acc += src[(int64_t)k * P * 2];
+        }
+        s_L[w][n][comp] = acc;
     }
     __syncthreads();
 
@@ -696,11 +724,32 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
                                        p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
             } else {
                 const int32_t nxb = (g.n1x + kCellsPerBlock - 1) / kCellsPerBlock;
-                const unsigned nb2 = (unsigned)((c1 - c0 + 1) * nxb);
+                // lenses are split into fixed chunks (a property of the plan, so
+                // results do not depend on how a map is cut into calls)
+                const int32_t nchunk = std::max<int32_t>(1, (nl + kChunkLens - 1) / kChunkLens);
+                const size_t need = (size_t)(c1 - c0 + 1) * g.n1x * nchunk * P * 2 * sizeof(double);
+                if (p->part_bytes < need) {
+                    dev_free(p->d_part);
+                    p->d_part = nullptr;
+                    p->part_bytes = 0;
+                    if (hipMalloc(&p->d_part, need) != hipSuccess) {
+                        (void)hipGetLastError();
+                        set_error("cannot allocate the level-2 partial expansions");
+                        return IRS_E_NOMEM;
+                    }
+                    p->part_bytes = need;
+                }
+                const unsigned nbA = (unsigned)((c1 - c0 + 1) * nxb * nchunk);
+                const unsigned nbB = (unsigned)((c1 - c0 + 1) * nxb);
 #define IRS_L2L(U, PP)                                                                        \
-    hipLaunchKernelGGL((k_level2_local<U, PP>), dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,      \
-                       p->d_y, p->d_m, p->d_cxy, p->d_cell_start, nl, (int32_t)c0, nxb,        \
-                       p->d_coef)
+    do {                                                                                      \
+        hipLaunchKernelGGL((k_level2_expand<U, PP>), dim3(nbA), dim3(kThreads), 0, s, g,      \
+                           p->d_x, p->d_y, p->d_m, p->d_cxy, nl, (int32_t)c0, nxb, nchunk,    \
+                           kChunkLens, p->d_part);                                            \
+        hipLaunchKernelGGL((k_level2_points<U, PP>), dim3(nbB), dim3(kThreads), 0, s, g,      \
+                           p->d_x, p->d_y, p->d_m, p->d_cell_start, (int32_t)c0, nxb, nchunk, \
+                           p->d_part, p->d_coef);                                             \
+    } while (0)
                 if (p->unit_mass) {
                     if (P == 32) IRS_L2L(true, 32);
                     else IRS_L2L(true, 48);

@@ -33,6 +33,8 @@ struct irs_plan_s {
     double *d_coef = nullptr;
     int64_t coef_rows_cap = 0;   // level-1 rows the buffer holds
     int64_t coef_c0 = -1, coef_c1 = -2;   // level-1 rows whose coefficients it holds now
+    double *d_part = nullptr;             // per-(cell, lens chunk) partial expansions
+    size_t part_bytes = 0;
 
     // Scratch for host-side outputs.
     uint32_t *d_counts = nullptr;  // npix^2, used when counts are on the host
