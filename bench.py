@@ -34,8 +34,24 @@ if ROOT not in sys.path:
 METRIC = "rays/sec and ray-lens interactions/sec at N_*=1e6; map rel-L1 vs FP64 oracle"
 FP64_PEAK = 78.6     # TFLOP/s, MI355X vector FP64
 FP32_PEAK = 157.3    # TFLOP/s, MI355X vector FP32 (packed)
-L2_FLOPS_PER_PAIR = 44   # (level-2 point, distant lens) pair, see the design doc
 DIRECT_FLOPS_PER_PAIR = 11
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "level2_expand_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2204_10871_amd", "csrc", "k_interp.hip")
+
+
+def _traffic(launches):
+    """HBM bytes per launch of the expansion kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when
+    there is none or the kernel source has changed since it was taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def log(msg):
@@ -52,6 +68,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--direct-rows", type=int, default=48)
+    ap.add_argument("--pmc-calibrate", action="store_true",
+                    help="run a plain 512 MiB device copy first (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -77,6 +95,14 @@ def main():
     log(f"plan: {G['nx']}x{G['ny']} rays, N*={n_star}, level-1 {G['n1x']}x{G['n1y']}, q={G['q']}")
     counts = torch.zeros(w.npix * w.npix, dtype=torch.int32, device="cuda:0")
 
+    if args.pmc_calibrate:
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy: 512 MiB read + 512 MiB written")
+
     c_mid = G["n1y"] // 2
     bands = [plan.level1_row_rays(c_mid + k) for k in range(args.warmup + args.steps)]
     for k in range(args.warmup):
@@ -92,7 +118,8 @@ def main():
         st = plan.shoot_rows(j0, j1 - j0, counts, time_phases=True)
         stats.append(st)
         log(f"step {k - args.warmup}: rows {j0}..{j1} rays {st['rays_shot']:.3e} "
-            f"level-2 {st['ms_level2']:.1f} ms, rays {st['ms_rays']:.1f} ms")
+            f"level-2 {st['ms_level2']:.2f} ms (expansion {st['ms_level2_expand']:.2f}), "
+            f"level-3 {st['ms_rays']:.2f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -100,14 +127,21 @@ def main():
     landed = sum(s["rays_landed"] for s in stats)
     value = rays / elapsed
     l2_pairs = sum(s["level2_pairs"] for s in stats)
+    ex_flops = sum(s["level2_expand_flops"] for s in stats)
+    ex_ms = sum(s["ms_level2_expand"] for s in stats)
     l2_ms = sum(s["ms_level2"] for s in stats)
-    l2_launches = sum(s["n_level2_launches"] for s in stats)
-    l2_achieved = L2_FLOPS_PER_PAIR * l2_pairs / (l2_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(l2_achieved, 3), "peak": FP64_PEAK,
-                "unit": "TFLOP/s", "frac": round(l2_achieved / FP64_PEAK, 4), "traffic": None,
-                "kernel": "k_level2 (FP64 far-field Taylor coefficients)",
-                "launches": l2_launches, "ms_per_launch": round(l2_ms / max(1, l2_launches), 3),
-                "flops_per_launch": L2_FLOPS_PER_PAIR * l2_pairs / max(1, l2_launches)}
+    l3_ms = sum(s["ms_rays"] for s in stats)
+    launches = sum(s["n_level2_launches"] for s in stats)
+    achieved = ex_flops / (ex_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK, 4),
+                "traffic": _traffic(launches),
+                "kernel": "k_level2_expand (FP64 per-cell local expansion of the distant lenses)",
+                "launches": launches, "ms_per_launch": round(ex_ms / max(1, launches), 3),
+                "flops_per_launch": ex_flops / max(1, launches)}
+    phases = {"level2_ms_per_step": l2_ms / args.steps, "level2_expand_ms_per_step": ex_ms / args.steps,
+              "level3_ms_per_step": l3_ms / args.steps,
+              "level2_all_kernels_tflops": sum(s["level2_flops"] for s in stats) / (l2_ms * 1e-3) / 1e12}
 
     result = {
         "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1,
@@ -120,10 +154,11 @@ def main():
                    "n_star": n_star, "rays_per_step": rays / args.steps,
                    "full_map_steps": G["n1y"], "method": "interp", "precision": "fp64"},
         "interactions_per_s": {"direct_equivalent": value * n_star,
-                               "level2_pairs_per_s": l2_pairs / elapsed},
+                               "level2_point_lens_pairs_per_s": l2_pairs / elapsed},
         "full_map_seconds_extrapolated": G["nx"] * G["ny"] / value,
         "landed_fraction": landed / rays,
         "roofline": roofline,
+        "phases": phases,
     }
 
     # ---- the oracle on a bounded sample of the last band (rays it sums one by one)

@@ -130,11 +130,13 @@ typedef struct {
     int64_t level2_points;
     int64_t level2_pairs;         /* (point, distant lens) pairs the paper's form sums */
     int64_t direct_pairs;
-    double  level2_flops;         /* algorithmic flops of the level-2 kernel used      */
+    double  level2_flops;         /* algorithmic flops of the level-2 kernels used     */
+    double  level2_expand_flops;  /* ... of which the per-cell expansion kernel        */
     /* with IRS_TIME_PHASES: summed HIP-event durations of the launches          */
     int32_t n_level2_launches;    /* level-2 (far field) launches                     */
     int32_t n_ray_launches;       /* level-3 or direct-sum launches                   */
-    double  ms_level2;
+    double  ms_level2;            /* all level-2 launches                             */
+    double  ms_level2_expand;     /* the per-cell expansion (or per-point sum) kernel  */
     double  ms_rays;
 } irs_map_stats;
 

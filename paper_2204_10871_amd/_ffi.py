@@ -48,9 +48,10 @@ class MapStats(C.Structure):
                 ("n_lens", C.c_int64), ("kappa_star_eff", C.c_double), ("ms_total", C.c_double),
                 ("level2_points", C.c_int64), ("level2_pairs", C.c_int64),
                 ("direct_pairs", C.c_int64), ("level2_flops", C.c_double),
+                ("level2_expand_flops", C.c_double),
                 ("n_level2_launches", C.c_int32),
                 ("n_ray_launches", C.c_int32), ("ms_level2", C.c_double),
-                ("ms_rays", C.c_double)]
+                ("ms_level2_expand", C.c_double), ("ms_rays", C.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -57,7 +57,8 @@ irs_status CallStats::collect()
         IRS_HIP(hipEventSynchronize(ev[2 * k + 1]));
         float ms = 0.0f;
         IRS_HIP(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
-        if (ev_kind[k] == 0) ms_level2 += ms;
+        if (ev_kind[k] == 0) { ms_level2 += ms; ms_level2_expand += ms; }
+        else if (ev_kind[k] == 2) ms_level2 += ms;
         else ms_rays += ms;
     }
     return IRS_OK;
@@ -351,6 +352,8 @@ static irs_status shoot(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t *
         stats->level2_pairs = cs.level2_pairs;
         stats->direct_pairs = cs.direct_pairs;
         stats->level2_flops = cs.level2_flops;
+        stats->level2_expand_flops = cs.level2_expand_flops;
+        stats->ms_level2_expand = cs.ms_level2_expand;
         stats->n_level2_launches = cs.n_level2;
         stats->n_ray_launches = cs.n_rays;
         stats->ms_level2 = cs.ms_level2;

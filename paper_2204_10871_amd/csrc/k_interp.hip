@@ -706,11 +706,14 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
                         const int64_t b3 = block(cx, cy, 1);
                         cs->level2_pairs += q * q * (p->n_lens - b3);
                         if (P == 0) {
-                            cs->level2_flops += 44.0 * (double)(q * q * (p->n_lens - b3));
+                            const double f = 44.0 * (double)(q * q * (p->n_lens - b3));
+                            cs->level2_flops += f;
+                            cs->level2_expand_flops += f;
                         } else {
                             const int64_t b7 = block(cx, cy, kRing);
-                            cs->level2_flops += (double)(p->n_lens - b7) * (10.0 + 8.0 * P)
-                                              + (double)(q * q) * (44.0 * (double)(b7 - b3) + 60.0 * P);
+                            const double fe = (double)(p->n_lens - b7) * (10.0 + 8.0 * P);
+                            cs->level2_expand_flops += fe;
+                            cs->level2_flops += fe + (double)(q * q) * (44.0 * (double)(b7 - b3) + 60.0 * P);
                         }
                     }
             }
@@ -746,10 +749,13 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
         hipLaunchKernelGGL((k_level2_expand<U, PP>), dim3(nbA), dim3(kThreads), 0, s, g,      \
                            p->d_x, p->d_y, p->d_m, p->d_cxy, nl, (int32_t)c0, nxb, nchunk,    \
                            kChunkLens, p->d_part);                                            \
+        if (cs && (st2 = cs->end(s)) != IRS_OK) return st2;                                  \
+        if (cs && (st2 = cs->begin(s, 2)) != IRS_OK) return st2;                             \
         hipLaunchKernelGGL((k_level2_points<U, PP>), dim3(nbB), dim3(kThreads), 0, s, g,      \
                            p->d_x, p->d_y, p->d_m, p->d_cell_start, (int32_t)c0, nxb, nchunk, \
                            p->d_part, p->d_coef);                                             \
     } while (0)
+                irs_status st2 = IRS_OK;
                 if (p->unit_mass) {
                     if (P == 32) IRS_L2L(true, 32);
                     else IRS_L2L(true, 48);

@@ -70,12 +70,12 @@ irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const 
 // Work and (optionally) HIP-event timings accumulated over one API call.
 struct CallStats {
     int64_t level2_points = 0, level2_pairs = 0, direct_pairs = 0;
-    double level2_flops = 0.0;
+    double level2_flops = 0.0, level2_expand_flops = 0.0;
     int32_t n_level2 = 0, n_rays = 0;
-    double ms_level2 = 0.0, ms_rays = 0.0;
+    double ms_level2 = 0.0, ms_level2_expand = 0.0, ms_rays = 0.0;
     bool timed = false;
     std::vector<hipEvent_t> ev;       // start/stop pairs, in launch order
-    std::vector<int> ev_kind;         // 0 = level-2, 1 = ray kernel
+    std::vector<int> ev_kind;         // 0 = level-2 expansion, 2 = level-2 points, 1 = rays
     // Record the start event of a launch of kind k (no-op unless timed).
     irs_status begin(hipStream_t s, int k);
     irs_status end(hipStream_t s);
