@@ -61,10 +61,20 @@ _lib = None
 
 
 def load():
-    """Load libirs.so, failing loudly when it has not been built."""
+    """Load libirs.so, failing loudly when it has not been built.
+
+    PyTorch wheels bundle their own HIP runtime under the same soname as
+    ROCm's (libamdhip64.so.7).  When PyTorch is installed it is imported
+    first, so the library binds to that runtime and both share one HIP
+    runtime (device pointers and streams can then be passed between them).
+    """
     global _lib
     if _lib is not None:
         return _lib
+    try:
+        import torch  # noqa: F401  (see docstring)
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library {LIB_PATH} is missing: build it first "
                            "(python -m paper_2204_10871_amd.build or __graft_entry__.build())")

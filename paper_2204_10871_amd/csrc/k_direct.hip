@@ -7,12 +7,12 @@
 // Two kernels:
 //   k_direct_f64  -- plain double precision, one ray per lane, lens tiles in LDS.
 //   k_direct_f32  -- the FP32 VALU-bound form: each workgroup owns a compact
-//                    64 x 16 tile of rays and works in coordinates relative to
-//                    the tile centre (rounded to FP32 from FP64 once per
-//                    lens and tile), lens tiles are staged in LDS and read as
-//                    broadcasts, four rays per lane share every LDS read, and
-//                    each ray's sum is compensated: 32 lenses are summed
-//                    plainly, then added with Kahan's correction.  The lenses
+//                    64 x 32 tile of rays; ray-lens offsets are rounded to
+//                    FP32 once from their FP64 values (d1 per column and
+//                    lens, d2 per row and lens through LDS), eight rays per
+//                    lane share every d1, and each ray's sum is compensated:
+//                    32 lenses are summed plainly, then added with Kahan's
+//                    correction.  The lenses
 //                    of the 3 x 3 level-1 cells around the ray are then
 //                    re-evaluated in FP64 and the difference to their FP32
 //                    terms is added (FP32 quantisation of a lens at distance d
@@ -113,20 +113,28 @@ __global__ __launch_bounds__(kThreads) void k_direct_f64(
 
 // -------------------------------------------------------------------------
 // FP32 with compensation
+//
+// Offsets are formed in FP64 and rounded to FP32 once: d1 = RN(theta1 - x_i)
+// per (column, lens), shared by the lane's 8 rays; d2 = RN(theta2 - y_i) per
+// (row, lens), computed once per workgroup into LDS and read by all 64
+// columns as broadcasts.  A single rounding of the exact offset is unbiased;
+// a tile-local frame (d1 = RN(xr - RN(x_i - o))) is not: its second rounding
+// carries the ray's offset identically into every lens of a binade, which
+// adds up coherently over 1e6 lenses.
 // -------------------------------------------------------------------------
 constexpr int kTX = kWave;            // ray columns per tile: one per lane
-constexpr int kRPT = 4;               // ray rows per lane
-constexpr int kTY = kRPT * kWaves;    // ray rows per tile
-constexpr int kLT = 512;              // lenses per LDS stage
+constexpr int kRPT = 8;               // ray rows per lane
+constexpr int kTY = kRPT * kWaves;    // ray rows per tile (32)
+constexpr int kLT = 256;              // lenses per LDS stage
 constexpr int kChunk = 32;            // lenses per uncompensated partial sum
 constexpr float kTiny = 1e-30f;       // keeps 1/r^2 finite for a lens on a ray
 
-// 1/r^2 for an FP32 offset: hardware reciprocal refined by one Newton step,
-// so that the result is (nearly) correctly rounded and unbiased.  A lens on
-// the ray gives r^2 = kTiny and a zero term (its offset is 0).
-__device__ __forceinline__ float inv_r2(float d1, float d2)
+// 1/r^2 from d1^2 (+ kTiny, precomputed) and d2: hardware reciprocal refined
+// by one Newton step, so the result is correctly rounded and unbiased.  A
+// lens on the ray gives r^2 = kTiny and a zero term (its offsets are 0).
+__device__ __forceinline__ float inv_r2(float d1sq, float d2)
 {
-    const float r2 = fmaf(d2, d2, fmaf(d1, d1, kTiny));
+    const float r2 = fmaf(d2, d2, d1sq);
     const float v = __builtin_amdgcn_rcpf(r2);
     const float e = fmaf(-r2, v, 1.0f);
     return fmaf(v, e, v);
@@ -148,29 +156,17 @@ __global__ __launch_bounds__(kThreads) void k_direct_f32(
     int64_t ray_last, double *a1o, double *a2o, int64_t *pixo, uint32_t *counts,
     unsigned long long *landed)
 {
-    __shared__ float4 s_x4[kLT / 4], s_y4[kLT / 4], s_m4[UNIT ? 1 : kLT / 4];
-    float *s_x = reinterpret_cast<float *>(s_x4);
-    float *s_y = reinterpret_cast<float *>(s_y4);
+    __shared__ double s_X[kLT], s_Y[kLT];
+    __shared__ float4 s_m4[UNIT ? 1 : kLT / 4];
+    __shared__ float4 s_d24[kTY][kLT / 4];          // d2 per (tile row, lens)
     float *s_m = reinterpret_cast<float *>(s_m4);
 
     const int tid = threadIdx.x;
     const int lane = tid % kWave, wave = tid / kWave;
     const int64_t tx = (int64_t)blockIdx.x % ntx;
     const int64_t ty = ty0 + (int64_t)blockIdx.x / ntx;
-
-    // tile origin (FP64) and this lane's rays in tile-local FP32 coordinates
-    const double ox = ray_x(g, tx * kTX + kTX / 2);
-    const double oy = ray_y(g, ty * kTY + kTY / 2);
     const int64_t i = tx * kTX + lane;
     const double t1 = ray_x(g, i);
-    const float xr = (float)(t1 - ox);
-    float yr[kRPT];
-    int64_t jrow[kRPT];
-#pragma unroll
-    for (int k = 0; k < kRPT; ++k) {
-        jrow[k] = ty * kTY + wave * kRPT + k;
-        yr[k] = (float)(ray_y(g, jrow[k]) - oy);
-    }
 
     float in1[kRPT], in2[kRPT], s1[kRPT], c1[kRPT], s2[kRPT], c2[kRPT];
 #pragma unroll
@@ -178,38 +174,46 @@ __global__ __launch_bounds__(kThreads) void k_direct_f32(
 
     for (int32_t base = 0; base < nl; base += kLT) {
         __syncthreads();
-        for (int t = tid; t < kLT; t += kThreads) {
-            const int32_t li = base + t;
+        {
+            const int32_t li = base + tid;
             if (li < nl) {
-                s_x[t] = (float)(lx[li] - ox);
-                s_y[t] = (float)(ly[li] - oy);
-                if (!UNIT) s_m[t] = (float)lm[li];
+                s_X[tid] = lx[li];
+                s_Y[tid] = ly[li];
+                if (!UNIT) s_m[tid] = (float)lm[li];
             }
         }
         __syncthreads();
         const int cnt = min(kLT, nl - base);
+        // d2 for every (tile row, lens) of the stage
+        for (int e = tid; e < kTY * kLT; e += kThreads) {
+            const int row = e / kLT, t = e % kLT;
+            if (t < cnt) {
+                const double t2r = ray_y(g, ty * kTY + row);
+                reinterpret_cast<float *>(s_d24[row])[t] = (float)(t2r - s_Y[t]);
+            }
+        }
+        __syncthreads();
         const int full = cnt - cnt % kChunk;
         for (int c = 0; c < full; c += kChunk) {
-#pragma unroll
+#pragma unroll 2
             for (int t = 0; t < kChunk; t += 4) {
-                const float4 X = s_x4[(c + t) / 4];
-                const float4 Y = s_y4[(c + t) / 4];
-                float4 M;
-                if (!UNIT) M = s_m4[(c + t) / 4];
-                const float xs[4] = {X.x, X.y, X.z, X.w};
-                const float ys[4] = {Y.x, Y.y, Y.z, Y.w};
-                float ms[4] = {1.0f, 1.0f, 1.0f, 1.0f};
-                if (!UNIT) { ms[0] = M.x; ms[1] = M.y; ms[2] = M.z; ms[3] = M.w; }
+                float d1[4], d1sq[4], ms[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const float d1 = xr - xs[u];
+                    d1[u] = (float)(t1 - s_X[c + t + u]);
+                    d1sq[u] = fmaf(d1[u], d1[u], kTiny);
+                    ms[u] = UNIT ? 1.0f : s_m[c + t + u];
+                }
 #pragma unroll
-                    for (int k = 0; k < kRPT; ++k) {
-                        const float d2 = yr[k] - ys[u];
-                        float w = inv_r2(d1, d2);
+                for (int k = 0; k < kRPT; ++k) {
+                    const float4 D = s_d24[wave * kRPT + k][(c + t) / 4];
+                    const float d2s[4] = {D.x, D.y, D.z, D.w};
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        float w = inv_r2(d1sq[u], d2s[u]);
                         if (!UNIT) w = ms[u] * w;
-                        in1[k] = fmaf(d1, w, in1[k]);
-                        in2[k] = fmaf(d2, w, in2[k]);
+                        in1[k] = fmaf(d1[u], w, in1[k]);
+                        in2[k] = fmaf(d2s[u], w, in2[k]);
                     }
                 }
             }
@@ -222,12 +226,13 @@ __global__ __launch_bounds__(kThreads) void k_direct_f32(
         }
         if (full < cnt) {
             for (int t = full; t < cnt; ++t) {
-                const float d1 = xr - s_x[t];
+                const float d1 = (float)(t1 - s_X[t]);
+                const float d1sq = fmaf(d1, d1, kTiny);
                 const float m = UNIT ? 1.0f : s_m[t];
 #pragma unroll
                 for (int k = 0; k < kRPT; ++k) {
-                    const float d2 = yr[k] - s_y[t];
-                    float w = inv_r2(d1, d2);
+                    const float d2 = reinterpret_cast<const float *>(s_d24[wave * kRPT + k])[t];
+                    float w = inv_r2(d1sq, d2);
                     if (!UNIT) w = m * w;
                     in1[k] = fmaf(d1, w, in1[k]);
                     in2[k] = fmaf(d2, w, in2[k]);
@@ -248,10 +253,10 @@ __global__ __launch_bounds__(kThreads) void k_direct_f32(
     const int64_t cxh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
 #pragma unroll
     for (int k = 0; k < kRPT; ++k) {
-        const int64_t j = jrow[k];
+        const int64_t j = ty * kTY + wave * kRPT + k;
         const int64_t r = j * g.nx + i;
         const bool valid = i < g.nx && j >= row0 && j < row1 && r >= ray_first && r < ray_last;
-        const double t2 = ray_y(g, j < g.ny ? j : g.ny - 1);
+        const double t2 = ray_y(g, j);
         double sum1 = (double)s1[k] - (double)c1[k];
         double sum2 = (double)s2[k] - (double)c2[k];
         if (valid) {
@@ -266,9 +271,9 @@ __global__ __launch_bounds__(kThreads) void k_direct_f32(
                     const double X = lx[pl], Y = ly[pl];
                     const double m64 = UNIT ? 1.0 : lm[pl];
                     // the FP32 term exactly as the main loop formed it
-                    const float d1f = xr - (float)(X - ox);
-                    const float d2f = yr[k] - (float)(Y - oy);
-                    float w = inv_r2(d1f, d2f);
+                    const float d1f = (float)(t1 - X);
+                    const float d2f = (float)(t2 - Y);
+                    float w = inv_r2(fmaf(d1f, d1f, kTiny), d2f);
                     if (!UNIT) w = (float)m64 * w;
                     // the FP64 term
                     const double e1 = t1 - X, e2 = t2 - Y;
