@@ -191,6 +191,13 @@ irs_status irs_shoot_rows(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t
 irs_status irs_shoot_map(irs_plan_t plan, uint32_t *counts, irs_map_stats *stats,
                          uint64_t flags);
 
+/*
+ * irs_plan_set_direct_variant -- FP32 direct tile shape of the plan (0, 1, 2 as
+ * in irs_batch_info.direct_variant; default 1).  Every shape gives the same
+ * results bit for bit; only the speed differs.  IRS_E_INVALID if out of range.
+ */
+irs_status irs_plan_set_direct_variant(irs_plan_t plan, int32_t variant);
+
 /* irs_plan_geometry -- the geometry the plan uses (n_lens = the plan's lens count). */
 irs_status irs_plan_geometry(irs_plan_t plan, irs_geometry_info *out);
 
@@ -199,6 +206,66 @@ void irs_free(irs_plan_t plan);
 
 /* irs_last_error -- message for the last failed call on this thread ("" if none). */
 const char *irs_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Batches of independent maps.                                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct irs_batch_s *irs_batch_t;   /* opaque, owned by the library */
+
+typedef struct {
+    int32_t n_maps;
+    int32_t method, precision;
+    int32_t direct_variant;       /* FP32 direct tile shape: 0 = 4 rays/lane x 512 lenses
+                                     per LDS stage, 1 = 8 x 256, 2 = 16 x 128          */
+    int32_t blocks_per_cu;        /* persistent workgroups per compute unit (direct)  */
+    int32_t band_rows;            /* level-1 rows per level-2 band (interpolation)    */
+    int32_t tuned;                /* 1 if the settings came from the autotuner         */
+    int32_t from_cache;           /* 1 if they were read from the tuning cache         */
+    int64_t work_items;           /* queue items of the persistent launch (direct)     */
+    double  tune_ms;              /* time the autotuner spent measuring                */
+} irs_batch_info;
+
+/*
+ * irs_batch_create -- group n plans (the motivation: the many maps needed to
+ * sample lens-model parameters, Sec. 4) into one batch.  All plans must share
+ * method, precision and device, and for the direct method the mass kind
+ * (unit or not).  The plans stay owned by the caller and must outlive the
+ * batch; the batch runs them on its own stream (hip_stream, or a new one if
+ * NULL).  Errors: IRS_E_INVALID, IRS_E_UNSUPPORTED, IRS_E_NOMEM, IRS_E_DEVICE.
+ */
+irs_status irs_batch_create(const irs_plan_t *plans, int32_t n, void *hip_stream,
+                            irs_batch_t *out);
+
+/*
+ * irs_batch_tune -- choose the batch's launch settings by measurement on this
+ * device: for the direct method the tile shape and the persistent grid size,
+ * timed on the heaviest map's first tiles; for the interpolation the band
+ * height, timed on one band of the heaviest map.  cache_path (or, if NULL,
+ * the IRS_TUNE_CACHE environment variable; neither: no cache) is a text file
+ * of "key = settings" lines keyed by method, precision, mass kind, lens-count
+ * and aspect buckets; a cached key is reused without measuring.  The chosen
+ * tile shape is also set on every plan of the batch.
+ */
+irs_status irs_batch_tune(irs_batch_t batch, const char *cache_path);
+
+/*
+ * irs_batch_run -- every map of the batch in one graph launch: for the direct
+ * method one persistent kernel drains a device queue of (map, ray tile)
+ * items ordered longest map first; for the interpolation the maps' band
+ * launches in sequence.  counts[k] is a DEVICE pointer to map k's
+ * npix_side^2 uint32 counts, overwritten.  The graph is captured on the first
+ * call and replayed while the counts pointers stay the same.  stats: n entries
+ * or NULL.  Results equal per-plan irs_shoot_map bit for bit.
+ */
+irs_status irs_batch_run(irs_batch_t batch, uint32_t *const *counts, irs_map_stats *stats,
+                         uint64_t flags);
+
+/* irs_batch_get_info -- the batch's current settings. */
+irs_status irs_batch_get_info(irs_batch_t batch, irs_batch_info *out);
+
+/* irs_batch_free -- release a batch (not its plans).  NULL is ignored. */
+void irs_batch_free(irs_batch_t batch);
 
 #ifdef __cplusplus
 }

@@ -13,7 +13,7 @@ from . import _ffi
 from ._ffi import (IRS_DIRECT, IRS_INTERP, IRS_FP64, IRS_FP32_KAHAN, IRS_SHEET_OFF,
                    IRS_OUT_ON_DEVICE, IRS_TIME_PHASES, EXPORTS, Params, GeometryInfo, MapStats)
 
-__all__ = ["IrsError", "make_params", "params_from_workload", "geometry", "Plan", "load",
+__all__ = ["IrsError", "make_params", "params_from_workload", "geometry", "Plan", "Batch", "load",
            "IRS_DIRECT", "IRS_INTERP", "IRS_FP64", "IRS_FP32_KAHAN", "EXPORTS"]
 
 load = _ffi.load
@@ -166,6 +166,11 @@ class Plan:
                    "irs_shoot_rows")
         return st.as_dict()
 
+    def set_direct_variant(self, v: int):
+        """FP32 direct tile shape (0, 1, 2); results are identical for all."""
+        _check(self._lib.irs_plan_set_direct_variant(self._h, int(v)),
+               "irs_plan_set_direct_variant")
+
     def level1_row_rays(self, c: int):
         """Ray rows [j0, j1) whose level-2 points lie in level-1 row c: ray row j
         sits in level-2 row floor((2j+1) n1y q / (2 ny))."""
@@ -182,3 +187,51 @@ class Plan:
                     lo = mid + 1
             return lo
         return first_at(c * g["q"]), first_at((c + 1) * g["q"])
+
+
+class Batch:
+    """Independent maps run together in one graph launch (see irs_batch_run)."""
+
+    def __init__(self, plans, stream=None):
+        lib = _ffi.load()
+        self._lib = lib
+        self.plans = list(plans)
+        arr = (C.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        h = C.c_void_p()
+        s = None if stream is None else C.c_void_p(int(stream))
+        _check(lib.irs_batch_create(arr, len(self.plans), s, C.byref(h)), "irs_batch_create")
+        self._h = h
+
+    def tune(self, cache_path=None):
+        _check(self._lib.irs_batch_tune(self._h, None if cache_path is None
+                                        else str(cache_path).encode()), "irs_batch_tune")
+        return self.info()
+
+    def info(self) -> dict:
+        out = _ffi.BatchInfo()
+        _check(self._lib.irs_batch_get_info(self._h, C.byref(out)), "irs_batch_get_info")
+        return out.as_dict()
+
+    def run(self, counts):
+        """counts: one device tensor (npix^2 32-bit ints) per plan, overwritten."""
+        ptrs = (C.c_void_p * len(counts))(*[t.data_ptr() for t in counts])
+        st = (MapStats * len(counts))()
+        _check(self._lib.irs_batch_run(self._h, ptrs, st, 0), "irs_batch_run")
+        return [s.as_dict() for s in st]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.irs_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -17,7 +17,9 @@ IRS_TIME_PHASES = 1 << 9
 
 # every function include/irs.h declares
 EXPORTS = ("irs_geometry", "irs_plan", "irs_deflect_grid", "irs_shoot_rows", "irs_shoot_map",
-           "irs_plan_geometry", "irs_free", "irs_last_error")
+           "irs_plan_set_direct_variant", "irs_plan_geometry", "irs_free", "irs_last_error",
+           "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info",
+           "irs_batch_free")
 
 
 class Params(C.Structure):
@@ -57,6 +59,16 @@ class MapStats(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class BatchInfo(C.Structure):
+    _fields_ = [("n_maps", C.c_int32), ("method", C.c_int32), ("precision", C.c_int32),
+                ("direct_variant", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("band_rows", C.c_int32), ("tuned", C.c_int32), ("from_cache", C.c_int32),
+                ("work_items", C.c_int64), ("tune_ms", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -86,12 +98,20 @@ def load():
     lib.irs_shoot_rows.argtypes = [vp, i64, i64, vp, P(MapStats), u64]
     lib.irs_shoot_map.argtypes = [vp, vp, P(MapStats), u64]
     lib.irs_plan_geometry.argtypes = [vp, P(GeometryInfo)]
+    lib.irs_plan_set_direct_variant.argtypes = [vp, C.c_int32]
+    lib.irs_batch_create.argtypes = [P(vp), C.c_int32, vp, P(vp)]
+    lib.irs_batch_tune.argtypes = [vp, C.c_char_p]
+    lib.irs_batch_run.argtypes = [vp, P(vp), P(MapStats), u64]
+    lib.irs_batch_get_info.argtypes = [vp, P(BatchInfo)]
+    lib.irs_batch_free.argtypes = [vp]
+    lib.irs_batch_free.restype = None
     lib.irs_free.argtypes = [vp]
     lib.irs_free.restype = None
     lib.irs_last_error.argtypes = []
     lib.irs_last_error.restype = C.c_char_p
     for name in ("irs_geometry", "irs_plan", "irs_deflect_grid", "irs_shoot_rows",
-                 "irs_shoot_map", "irs_plan_geometry"):
+                 "irs_shoot_map", "irs_plan_geometry", "irs_plan_set_direct_variant",
+                 "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -2,8 +2,8 @@
 
 Every translation unit under csrc/ is compiled by hipcc into _build/ and
 linked into paper_2204_10871_amd/libirs.so.  Packed FP32 instructions are
-disabled (-packed-fp32-ops); nothing else non-default is asked of the
-compiler.
+disabled (-packed-fp32-ops) and fma contraction is limited to single
+expressions (-ffp-contract=on).
 """
 import concurrent.futures as cf
 import os
@@ -26,6 +26,9 @@ def _hipcc():
 
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
+          # contract a*b+c into an fma only within one source expression (decided
+          # in the front end), so every kernel instantiation rounds alike
+          "-ffp-contract=on",
           f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(HERE, "..", "include")]

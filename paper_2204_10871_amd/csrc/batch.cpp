@@ -1,0 +1,516 @@
+// Batches of independent maps: one graph launch for all of them, with launch
+// settings chosen by measurement (the autotuner) and kept in a cache file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+
+using namespace irs;
+
+struct irs_batch_s {
+    std::vector<irs_plan_s *> plans;       // not owned
+    std::vector<int> order;                 // longest map first
+    int method = 0, precision = 0;
+    bool unit = true;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int n_cu = 1;
+    int variant = 1, bpc = 4, band_rows = 4;
+    bool tuned = false, from_cache = false;
+    double tune_ms = 0.0;
+    // device tables of the direct queue
+    DirectArgs *d_maps = nullptr;
+    int64_t *d_item_start = nullptr;
+    unsigned long long *d_cursor = nullptr;   // [0] cursor, [1..n] landed per map
+    int64_t items = 0;
+    // captured graph
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint32_t *> graph_counts;
+    int graph_variant = -1, graph_bpc = -1, graph_band_rows = -1;
+};
+
+namespace {
+
+void drop_graph(irs_batch_s *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    b->graph_counts.clear();
+}
+
+double map_cost(const irs_plan_s *p)
+{
+    const double rays = (double)p->dg.nx * (double)p->dg.ny;
+    if (p->params.method == IRS_DIRECT) return rays * (double)std::max<int64_t>(1, p->n_lens);
+    const double l2 = (double)p->dg.n1x * p->dg.n1y * (double)std::max<int64_t>(1, p->n_lens);
+    return rays * 40.0 + l2 * 300.0;
+}
+
+// Tables of the direct queue for the current variant: maps in LPT order.
+irs_status build_direct_tables(irs_batch_s *b, uint32_t *const *counts)
+{
+    const int n = (int)b->plans.size();
+    std::vector<DirectArgs> maps(n);
+    std::vector<int64_t> start(n + 1, 0);
+    for (int k = 0; k < n; ++k) {
+        const int m = b->order[k];
+        irs_plan_s *p = b->plans[m];
+        maps[k] = direct_args_full(p, b->variant, counts ? counts[m] : nullptr,
+                                   b->d_cursor + 1 + m);
+        start[k + 1] = start[k] + direct_items(p, b->variant);
+    }
+    b->items = start[n];
+    IRS_HIP(hipMemcpyAsync(b->d_maps, maps.data(), sizeof(DirectArgs) * n,
+                           hipMemcpyHostToDevice, b->stream));
+    IRS_HIP(hipMemcpyAsync(b->d_item_start, start.data(), sizeof(int64_t) * (n + 1),
+                           hipMemcpyHostToDevice, b->stream));
+    IRS_HIP(hipStreamSynchronize(b->stream));
+    return IRS_OK;
+}
+
+// Enqueue the whole batch on b->stream (capturable: kernels only).
+irs_status enqueue_all(irs_batch_s *b, uint32_t *const *counts)
+{
+    const int n = (int)b->plans.size();
+    irs_status st = launch_zero(b->stream, b->d_cursor, 2 * (size_t)(n + 1));
+    if (st != IRS_OK) return st;
+    for (int m = 0; m < n; ++m) {
+        const irs_plan_s *p = b->plans[m];
+        st = launch_zero(b->stream, counts[m], (size_t)p->geo.npix * (size_t)p->geo.npix);
+        if (st != IRS_OK) return st;
+    }
+    if (b->method == IRS_DIRECT)
+        return launch_direct_queue(b->stream, b->precision, b->unit, b->variant, b->d_maps,
+                                   b->d_item_start, n, b->d_cursor, b->bpc * b->n_cu);
+    for (int k = 0; k < n; ++k) {
+        const int m = b->order[k];
+        irs_plan_s *p = b->plans[m];
+        RaySel sel{};
+        sel.stats = nullptr;
+        sel.row0 = 0;
+        sel.row1 = p->dg.ny;
+        sel.ray_first = 0;
+        sel.ray_last = p->dg.nx * p->dg.ny;
+        sel.counts = counts[m];
+        sel.landed = b->d_cursor + 1 + m;
+        hipStream_t saved = p->stream;
+        p->stream = b->stream;
+        st = launch_interp(p, sel);
+        p->stream = saved;
+        if (st != IRS_OK) return st;
+    }
+    return IRS_OK;
+}
+
+irs_status prepare_interp(irs_batch_s *b)
+{
+    for (irs_plan_s *p : b->plans) {
+        if (b->band_rows > 0) {
+            const int64_t row_bytes = (int64_t)p->dg.n1x * p->dg.q * p->dg.q * 10 * 8;
+            p->coef_budget = (int64_t)b->band_rows * row_bytes;
+        }
+        irs_status st = interp_prepare(p);
+        if (st != IRS_OK) return st;
+    }
+    return IRS_OK;
+}
+
+std::string tune_key(const irs_batch_s *b)
+{
+    const irs_plan_s *p = b->plans[b->order[0]];
+    const double aspect = std::max(p->geo.info.ix, p->geo.info.iy) /
+                          std::min(p->geo.info.ix, p->geo.info.iy);
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s %s %s n%d a%d",
+                  b->method == IRS_DIRECT ? "direct" : "interp",
+                  b->precision == IRS_FP64 ? "fp64" : "fp32", b->unit ? "unit" : "mass",
+                  (int)std::lround(std::log2((double)std::max<int64_t>(1, p->n_lens))),
+                  (int)std::lround(std::log2(aspect)));
+    return buf;
+}
+
+bool cache_lookup(const std::string &path, const std::string &key, std::string &val)
+{
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        const size_t eq = line.find(" = ");
+        if (eq != std::string::npos && line.substr(0, eq) == key) {
+            val = line.substr(eq + 3);
+            found = true;                    // the last entry for a key wins
+        }
+    }
+    return found;
+}
+
+void cache_store(const std::string &path, const std::string &key, const std::string &val)
+{
+    std::ofstream f(path, std::ios::app);
+    if (f) f << key << " = " << val << "\n";
+}
+
+// time one configuration of the heaviest map (events on the batch stream)
+irs_status time_direct(irs_batch_s *b, int variant, int bpc, uint32_t *scratch, double &ms)
+{
+    irs_plan_s *p = b->plans[b->order[0]];
+    DirectArgs a = direct_args_full(p, variant, scratch, b->d_cursor + 1);
+    const int64_t items = direct_items(p, variant);
+    const int64_t sample = std::min<int64_t>(items, (int64_t)4 * 8 * b->n_cu);
+    int64_t start[2] = {0, sample};
+    IRS_HIP(hipMemcpyAsync(b->d_maps, &a, sizeof a, hipMemcpyHostToDevice, b->stream));
+    IRS_HIP(hipMemcpyAsync(b->d_item_start, start, sizeof start, hipMemcpyHostToDevice, b->stream));
+    hipEvent_t e0, e1;
+    IRS_HIP(hipEventCreate(&e0));
+    IRS_HIP(hipEventCreate(&e1));
+    irs_status st = IRS_OK;
+    ms = 0.0;
+    for (int rep = 0; rep < 2 && st == IRS_OK; ++rep) {     // first run warms up
+        st = launch_zero(b->stream, b->d_cursor, 2);
+        if (st == IRS_OK) st = (hipEventRecord(e0, b->stream) == hipSuccess) ? IRS_OK : IRS_E_DEVICE;
+        if (st == IRS_OK)
+            st = launch_direct_queue(b->stream, b->precision, b->unit, variant, b->d_maps,
+                                     b->d_item_start, 1, b->d_cursor, bpc * b->n_cu);
+        if (st == IRS_OK && hipEventRecord(e1, b->stream) != hipSuccess) st = IRS_E_DEVICE;
+        if (st == IRS_OK && hipEventSynchronize(e1) != hipSuccess) st = IRS_E_DEVICE;
+        float f = 0.0f;
+        if (st == IRS_OK) (void)hipEventElapsedTime(&f, e0, e1);
+        ms = (double)f * (double)items / (double)sample;     // whole-map estimate
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != IRS_OK) set_error("autotuner: timing launch failed");
+    return st;
+}
+
+irs_status time_interp(irs_batch_s *b, int rows, uint32_t *scratch, double &ms)
+{
+    irs_plan_s *p = b->plans[b->order[0]];
+    const int64_t row_bytes = (int64_t)p->dg.n1x * p->dg.q * p->dg.q * 10 * 8;
+    p->coef_budget = (int64_t)rows * row_bytes;
+    irs_status st = interp_prepare(p);
+    if (st != IRS_OK) return st;
+    const int64_t c1 = std::min<int64_t>(p->dg.n1y, rows) ;
+    // rays of the first c1 level-1 rows
+    int64_t j1 = 0;
+    {
+        const int64_t M = (int64_t)p->dg.n1y * p->dg.q;
+        int64_t lo = 0, hi = p->dg.ny;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (((2 * mid + 1) * M) / (2 * p->dg.ny) >= c1 * p->dg.q) hi = mid;
+            else lo = mid + 1;
+        }
+        j1 = lo;
+    }
+    hipEvent_t e0, e1;
+    IRS_HIP(hipEventCreate(&e0));
+    IRS_HIP(hipEventCreate(&e1));
+    hipStream_t saved = p->stream;
+    p->stream = b->stream;
+    ms = 0.0;
+    for (int rep = 0; rep < 2 && st == IRS_OK; ++rep) {
+        p->coef_c0 = -1;
+        p->coef_c1 = -2;
+        RaySel sel{};
+        sel.row0 = 0;
+        sel.row1 = std::max<int64_t>(1, j1);
+        sel.ray_first = 0;
+        sel.ray_last = p->dg.nx * p->dg.ny;
+        sel.counts = scratch;
+        sel.landed = b->d_cursor + 1;
+        if (hipEventRecord(e0, b->stream) != hipSuccess) st = IRS_E_DEVICE;
+        if (st == IRS_OK) st = launch_interp(p, sel);
+        if (st == IRS_OK && hipEventRecord(e1, b->stream) != hipSuccess) st = IRS_E_DEVICE;
+        if (st == IRS_OK && hipEventSynchronize(e1) != hipSuccess) st = IRS_E_DEVICE;
+        float f = 0.0f;
+        if (st == IRS_OK) (void)hipEventElapsedTime(&f, e0, e1);
+        ms = (double)f * (double)p->dg.ny / (double)std::max<int64_t>(1, j1);
+    }
+    p->stream = saved;
+    p->coef_c0 = -1;
+    p->coef_c1 = -2;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+irs_status irs_batch_create(const irs_plan_t *plans, int32_t n, void *hip_stream,
+                            irs_batch_t *out)
+{
+    if (out) *out = nullptr;
+    if (!plans || !out || n <= 0) {
+        set_error("irs_batch_create: NULL argument or empty batch");
+        return IRS_E_INVALID;
+    }
+    for (int k = 0; k < n; ++k)
+        if (!plans[k]) {
+            set_error("irs_batch_create: NULL plan");
+            return IRS_E_INVALID;
+        }
+    const irs_plan_s *p0 = plans[0];
+    for (int k = 1; k < n; ++k) {
+        const irs_plan_s *p = plans[k];
+        if (p->params.method != p0->params.method || p->params.precision != p0->params.precision ||
+            p->device != p0->device ||
+            (p0->params.method == IRS_DIRECT && p->unit_mass != p0->unit_mass)) {
+            set_error("irs_batch_create: plans differ in method, precision, device or mass kind");
+            return IRS_E_UNSUPPORTED;
+        }
+    }
+    irs_batch_s *b = new (std::nothrow) irs_batch_s();
+    if (!b) {
+        set_error("irs_batch_create: host allocation failed");
+        return IRS_E_NOMEM;
+    }
+    b->plans.assign(plans, plans + n);
+    b->method = p0->params.method;
+    b->precision = p0->params.precision;
+    b->unit = p0->unit_mass;
+    b->variant = p0->direct_variant;
+    b->order.resize(n);
+    for (int k = 0; k < n; ++k) b->order[k] = k;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+        return map_cost(b->plans[x]) > map_cost(b->plans[y]);
+    });
+    irs_status st = IRS_OK;
+    hipError_t e = hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount,
+                                         p0->device);
+    if (e == hipSuccess && hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else if (e == hipSuccess) {
+        e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        b->own_stream = (e == hipSuccess);
+    }
+    if (e == hipSuccess) e = hipMalloc(&b->d_maps, sizeof(DirectArgs) * n);
+    if (e == hipSuccess) e = hipMalloc(&b->d_item_start, sizeof(int64_t) * (n + 1));
+    if (e == hipSuccess) e = hipMalloc(&b->d_cursor, sizeof(unsigned long long) * (n + 1));
+    if (e != hipSuccess) st = hip_fail(e, "irs_batch_create");
+    if (st != IRS_OK) {
+        irs_batch_free(b);
+        return st;
+    }
+    *out = b;
+    set_error("");
+    return IRS_OK;
+}
+
+irs_status irs_batch_tune(irs_batch_t b, const char *cache_path)
+{
+    if (!b) {
+        set_error("irs_batch_tune: NULL batch");
+        return IRS_E_INVALID;
+    }
+    std::string path = cache_path ? cache_path : "";
+    if (path.empty()) {
+        const char *env = std::getenv("IRS_TUNE_CACHE");
+        if (env) path = env;
+    }
+    const std::string key = tune_key(b);
+    std::string val;
+    if (!path.empty() && cache_lookup(path, key, val)) {
+        int v = -1, bpc = -1, rows = -1;
+        if (std::sscanf(val.c_str(), "variant=%d bpc=%d band_rows=%d", &v, &bpc, &rows) == 3 &&
+            v >= 0 && v < kDirectVariants && bpc > 0 && rows >= 0) {
+            b->variant = v;
+            b->bpc = bpc;
+            b->band_rows = rows;
+            b->tuned = b->from_cache = true;
+            for (irs_plan_s *p : b->plans) p->direct_variant = v;
+            drop_graph(b);
+            return IRS_OK;
+        }
+    }
+    irs_plan_s *heavy = b->plans[b->order[0]];
+    const size_t map_bytes = sizeof(uint32_t) * (size_t)heavy->geo.npix * (size_t)heavy->geo.npix;
+    uint32_t *scratch = nullptr;
+    IRS_HIP(hipMalloc(&scratch, map_bytes));
+    auto t0 = std::chrono::steady_clock::now();
+    irs_status st = IRS_OK;
+    double best = 1e300;
+    if (b->method == IRS_DIRECT && b->precision == IRS_FP32_KAHAN) {
+        for (int v = 0; v < kDirectVariants && st == IRS_OK; ++v)
+            for (int bpc : {2, 4, 8}) {
+                double ms = 0.0;
+                st = time_direct(b, v, bpc, scratch, ms);
+                if (st != IRS_OK) break;
+                if (ms < best) {
+                    best = ms;
+                    b->variant = v;
+                    b->bpc = bpc;
+                }
+            }
+    } else if (b->method == IRS_DIRECT) {
+        for (int bpc : {2, 4, 8}) {
+            double ms = 0.0;
+            st = time_direct(b, 0, bpc, scratch, ms);
+            if (st != IRS_OK) break;
+            if (ms < best) {
+                best = ms;
+                b->bpc = bpc;
+            }
+        }
+    } else {
+        const int64_t n1y = heavy->dg.n1y;
+        for (int rows : {1, 4, 16}) {
+            if (rows > n1y && rows != 1) break;
+            double ms = 0.0;
+            st = time_interp(b, rows, scratch, ms);
+            if (st != IRS_OK) break;
+            if (ms < best) {
+                best = ms;
+                b->band_rows = rows;
+            }
+        }
+    }
+    dev_free(scratch);
+    if (st != IRS_OK) return st;
+    b->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    b->tuned = true;
+    b->from_cache = false;
+    for (irs_plan_s *p : b->plans) p->direct_variant = b->variant;
+    drop_graph(b);
+    if (!path.empty()) {
+        char buf[96];
+        std::snprintf(buf, sizeof buf, "variant=%d bpc=%d band_rows=%d", b->variant, b->bpc,
+                      b->band_rows);
+        cache_store(path, key, buf);
+    }
+    set_error("");
+    return IRS_OK;
+}
+
+irs_status irs_batch_run(irs_batch_t b, uint32_t *const *counts, irs_map_stats *stats,
+                         uint64_t flags)
+{
+    (void)flags;
+    if (!b || !counts) {
+        set_error("irs_batch_run: NULL argument");
+        return IRS_E_INVALID;
+    }
+    const int n = (int)b->plans.size();
+    for (int k = 0; k < n; ++k)
+        if (!counts[k]) {
+            set_error("irs_batch_run: NULL counts pointer");
+            return IRS_E_INVALID;
+        }
+    const bool same = b->exec && b->graph_variant == b->variant && b->graph_bpc == b->bpc &&
+                      b->graph_band_rows == b->band_rows &&
+                      std::equal(b->graph_counts.begin(), b->graph_counts.end(), counts);
+    irs_status st = IRS_OK;
+    if (!same) {
+        drop_graph(b);
+        if (b->method == IRS_DIRECT) st = build_direct_tables(b, counts);
+        else st = prepare_interp(b);
+        if (st != IRS_OK) return st;
+        hipGraph_t graph = nullptr;
+        IRS_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        st = enqueue_all(b, counts);
+        hipError_t e = hipStreamEndCapture(b->stream, &graph);
+        if (st != IRS_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            b->exec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        b->graph_counts.assign(counts, counts + n);
+        b->graph_variant = b->variant;
+        b->graph_bpc = b->bpc;
+        b->graph_band_rows = b->band_rows;
+    }
+    hipEvent_t e0, e1;
+    IRS_HIP(hipEventCreate(&e0));
+    IRS_HIP(hipEventCreate(&e1));
+    (void)hipEventRecord(e0, b->stream);
+    hipError_t e = hipGraphLaunch(b->exec, b->stream);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return hip_fail(e, "hipGraphLaunch");
+    }
+    (void)hipEventRecord(e1, b->stream);
+    std::vector<unsigned long long> landed(n + 1);
+    e = hipMemcpyAsync(landed.data(), b->d_cursor, sizeof(unsigned long long) * (n + 1),
+                       hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "irs_batch_run");
+    for (irs_plan_s *p : b->plans) {        // a replay leaves no band the host knows of
+        p->coef_c0 = -1;
+        p->coef_c1 = -2;
+    }
+    if (stats) {
+        for (int m = 0; m < n; ++m) {
+            const irs_plan_s *p = b->plans[m];
+            irs_map_stats &s = stats[m];
+            std::memset(&s, 0, sizeof s);
+            s.rays_shot = p->dg.nx * p->dg.ny;
+            s.rays_landed = (int64_t)landed[1 + m];
+            s.rays_off = s.rays_shot - s.rays_landed;
+            s.n_lens = p->n_lens;
+            s.kappa_star_eff = p->kappa_star_eff;
+            s.ms_total = ms;                      // the whole batch's graph launch
+            if (p->params.method == IRS_DIRECT) s.direct_pairs = s.rays_shot * p->n_lens;
+        }
+    }
+    set_error("");
+    return IRS_OK;
+}
+
+irs_status irs_batch_get_info(irs_batch_t b, irs_batch_info *out)
+{
+    if (!b || !out) {
+        set_error("irs_batch_get_info: NULL argument");
+        return IRS_E_INVALID;
+    }
+    out->n_maps = (int32_t)b->plans.size();
+    out->method = b->method;
+    out->precision = b->precision;
+    out->direct_variant = b->variant;
+    out->blocks_per_cu = b->bpc;
+    out->band_rows = b->band_rows;
+    out->tuned = b->tuned ? 1 : 0;
+    out->from_cache = b->from_cache ? 1 : 0;
+    int64_t items = 0;
+    for (const irs_plan_s *p : b->plans) items += direct_items(p, b->variant);
+    out->work_items = b->method == IRS_DIRECT ? items : 0;
+    out->tune_ms = b->tune_ms;
+    return IRS_OK;
+}
+
+void irs_batch_free(irs_batch_t b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    dev_free(b->d_maps);
+    dev_free(b->d_item_start);
+    dev_free(b->d_cursor);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+}  // extern "C"

@@ -239,6 +239,16 @@ irs_status irs_plan(const irs_params *params, int64_t n_lens, const double *x, c
     return IRS_OK;
 }
 
+irs_status irs_plan_set_direct_variant(irs_plan_t plan, int32_t variant)
+{
+    if (!plan || variant < 0 || variant >= kDirectVariants) {
+        set_error("irs_plan_set_direct_variant: NULL plan or variant out of range");
+        return IRS_E_INVALID;
+    }
+    plan->direct_variant = variant;
+    return IRS_OK;
+}
+
 irs_status irs_plan_geometry(irs_plan_t plan, irs_geometry_info *out)
 {
     if (!plan || !out) {

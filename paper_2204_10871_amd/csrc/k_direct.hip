@@ -111,6 +111,61 @@ __global__ __launch_bounds__(kThreads) void k_direct_f64(
     emit(valid, r - out_base, a1, a2, pix, a1o, a2o, pixo, counts, landed);
 }
 
+// Persistent FP64 form for batches: item = 256 consecutive rays of a map.
+template <bool UNIT>
+__global__ __launch_bounds__(kThreads) void k_direct_f64_queue(
+    const DirectArgs *__restrict__ maps, const int64_t *__restrict__ item_start, int32_t nmaps,
+    unsigned long long *cursor)
+{
+    __shared__ double s_x[kLens64], s_y[kLens64], s_m[UNIT ? 1 : kLens64];
+    __shared__ long long s_item;
+    const int tid = threadIdx.x;
+    const int64_t total = item_start[nmaps];
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_item = (long long)atomicAdd(cursor, 1ull);
+        __syncthreads();
+        const int64_t item = s_item;
+        if (item >= total) break;                    // every workgroup reaches this
+        int lo = 0, hi = nmaps - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (item_start[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const DirectArgs &a = maps[lo];
+        const DevGeom &g = a.g;
+        const int64_t r = (item - item_start[lo]) * kThreads + tid;
+        const bool valid = r < g.nx * g.ny;
+        const int64_t rr = valid ? r : 0;
+        const double t1 = ray_x(g, rr % g.nx), t2 = ray_y(g, rr / g.nx);
+        double s1 = 0.0, s2 = 0.0;
+        for (int32_t base = 0; base < a.nl; base += kLens64) {
+            __syncthreads();
+            if (base + tid < a.nl) {
+                s_x[tid] = a.lx[base + tid];
+                s_y[tid] = a.ly[base + tid];
+                if (!UNIT) s_m[tid] = a.lm[base + tid];
+            }
+            __syncthreads();
+            const int cnt = min(kLens64, a.nl - base);
+            for (int t = 0; t < cnt; ++t) {
+                const double d1 = t1 - s_x[t], d2 = t2 - s_y[t];
+                const double r2 = d1 * d1 + d2 * d2;
+                if (r2 > 0.0) {
+                    const double w = (UNIT ? 1.0 : s_m[t]) / r2;
+                    s1 += w * d1;
+                    s2 += w * d2;
+                }
+            }
+        }
+        double a1, a2;
+        int32_t pix;
+        assemble(g, t1, t2, s1, s2, a1, a2, pix);
+        emit(valid, 0, a1, a2, pix, nullptr, nullptr, nullptr, a.counts, a.landed);
+    }
+}
+
 // -------------------------------------------------------------------------
 // FP32 with compensation
 //
@@ -123,9 +178,6 @@ __global__ __launch_bounds__(kThreads) void k_direct_f64(
 // adds up coherently over 1e6 lenses.
 // -------------------------------------------------------------------------
 constexpr int kTX = kWave;            // ray columns per tile: one per lane
-constexpr int kRPT = 8;               // ray rows per lane
-constexpr int kTY = kRPT * kWaves;    // ray rows per tile (32)
-constexpr int kLT = 256;              // lenses per LDS stage
 constexpr int kChunk = 32;            // lenses per uncompensated partial sum
 constexpr float kTiny = 1e-30f;       // keeps 1/r^2 finite for a lens on a ray
 
@@ -148,148 +200,194 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float x)
     s = t;
 }
 
-template <bool UNIT>
-__global__ __launch_bounds__(kThreads) void k_direct_f32(
-    DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
-    const double *__restrict__ lm, const int32_t *__restrict__ cell_start, int32_t nl,
-    int64_t ntx, int64_t ty0, int64_t row0, int64_t row1, int64_t ray_first,
-    int64_t ray_last, double *a1o, double *a2o, int64_t *pixo, uint32_t *counts,
-    unsigned long long *landed)
-{
-    __shared__ double s_X[kLT], s_Y[kLT];
-    __shared__ float4 s_m4[UNIT ? 1 : kLT / 4];
-    __shared__ float4 s_d24[kTY][kLT / 4];          // d2 per (tile row, lens)
-    float *s_m = reinterpret_cast<float *>(s_m4);
+}  // namespace
 
-    const int tid = threadIdx.x;
-    const int lane = tid % kWave, wave = tid / kWave;
-    const int64_t tx = (int64_t)blockIdx.x % ntx;
-    const int64_t ty = ty0 + (int64_t)blockIdx.x / ntx;
-    const int64_t i = tx * kTX + lane;
-    const double t1 = ray_x(g, i);
+// The FP32 tile: RPT ray rows per lane (RPT * 4 rows per tile), LT lenses per
+// LDS stage.  Every shape computes each ray with the same operations in the
+// same order (LT is a multiple of kChunk), so all shapes give identical bits.
+template <bool UNIT, int RPT, int LT>
+struct DirectTile {
+    static constexpr int TY = RPT * kWaves;
+    struct Smem {
+        double X[LT], Y[LT];
+        float4 m4[UNIT ? 1 : LT / 4];
+        float4 d24[TY][LT / 4];          // d2 per (tile row, lens)
+    };
 
-    float in1[kRPT], in2[kRPT], s1[kRPT], c1[kRPT], s2[kRPT], c2[kRPT];
+    __device__ static void run(Smem &sm, const DirectArgs &a, int64_t tx, int64_t ty)
+    {
+        const DevGeom &g = a.g;
+        float *s_m = reinterpret_cast<float *>(sm.m4);
+        const int tid = threadIdx.x;
+        const int lane = tid % kWave, wave = tid / kWave;
+        const int64_t i = tx * kTX + lane;
+        const double t1 = ray_x(g, i);
+        const int32_t nl = a.nl;
+
+        float in1[RPT], in2[RPT], s1[RPT], c1[RPT], s2[RPT], c2[RPT];
 #pragma unroll
-    for (int k = 0; k < kRPT; ++k) in1[k] = in2[k] = s1[k] = c1[k] = s2[k] = c2[k] = 0.0f;
+        for (int k = 0; k < RPT; ++k) in1[k] = in2[k] = s1[k] = c1[k] = s2[k] = c2[k] = 0.0f;
 
-    for (int32_t base = 0; base < nl; base += kLT) {
-        __syncthreads();
-        {
-            const int32_t li = base + tid;
-            if (li < nl) {
-                s_X[tid] = lx[li];
-                s_Y[tid] = ly[li];
-                if (!UNIT) s_m[tid] = (float)lm[li];
-            }
-        }
-        __syncthreads();
-        const int cnt = min(kLT, nl - base);
-        // d2 for every (tile row, lens) of the stage
-        for (int e = tid; e < kTY * kLT; e += kThreads) {
-            const int row = e / kLT, t = e % kLT;
-            if (t < cnt) {
-                const double t2r = ray_y(g, ty * kTY + row);
-                reinterpret_cast<float *>(s_d24[row])[t] = (float)(t2r - s_Y[t]);
-            }
-        }
-        __syncthreads();
-        const int full = cnt - cnt % kChunk;
-        for (int c = 0; c < full; c += kChunk) {
-#pragma unroll 2
-            for (int t = 0; t < kChunk; t += 4) {
-                float d1[4], d1sq[4], ms[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    d1[u] = (float)(t1 - s_X[c + t + u]);
-                    d1sq[u] = fmaf(d1[u], d1[u], kTiny);
-                    ms[u] = UNIT ? 1.0f : s_m[c + t + u];
+        for (int32_t base = 0; base < nl; base += LT) {
+            __syncthreads();
+            for (int t = tid; t < LT; t += kThreads) {
+                const int32_t li = base + t;
+                if (li < nl) {
+                    sm.X[t] = a.lx[li];
+                    sm.Y[t] = a.ly[li];
+                    if (!UNIT) s_m[t] = (float)a.lm[li];
                 }
-#pragma unroll
-                for (int k = 0; k < kRPT; ++k) {
-                    const float4 D = s_d24[wave * kRPT + k][(c + t) / 4];
-                    const float d2s[4] = {D.x, D.y, D.z, D.w};
+            }
+            __syncthreads();
+            const int cnt = min(LT, nl - base);
+            for (int e = tid; e < TY * LT; e += kThreads) {
+                const int row = e / LT, t = e % LT;
+                if (t < cnt) {
+                    const double t2r = ray_y(g, ty * TY + row);
+                    reinterpret_cast<float *>(sm.d24[row])[t] = (float)(t2r - sm.Y[t]);
+                }
+            }
+            __syncthreads();
+            const int full = cnt - cnt % kChunk;
+            for (int c = 0; c < full; c += kChunk) {
+#pragma unroll 2
+                for (int t = 0; t < kChunk; t += 4) {
+                    float d1[4], d1sq[4], ms[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        float w = inv_r2(d1sq[u], d2s[u]);
-                        if (!UNIT) w = ms[u] * w;
-                        in1[k] = fmaf(d1[u], w, in1[k]);
-                        in2[k] = fmaf(d2s[u], w, in2[k]);
+                        d1[u] = (float)(t1 - sm.X[c + t + u]);
+                        d1sq[u] = fmaf(d1[u], d1[u], kTiny);
+                        ms[u] = UNIT ? 1.0f : s_m[c + t + u];
+                    }
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) {
+                        const float4 D = sm.d24[wave * RPT + k][(c + t) / 4];
+                        const float d2s[4] = {D.x, D.y, D.z, D.w};
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            float w = inv_r2(d1sq[u], d2s[u]);
+                            if (!UNIT) w = ms[u] * w;
+                            in1[k] = fmaf(d1[u], w, in1[k]);
+                            in2[k] = fmaf(d2s[u], w, in2[k]);
+                        }
                     }
                 }
-            }
 #pragma unroll
-            for (int k = 0; k < kRPT; ++k) {
-                kahan_add(s1[k], c1[k], in1[k]);
-                kahan_add(s2[k], c2[k], in2[k]);
-                in1[k] = in2[k] = 0.0f;
-            }
-        }
-        if (full < cnt) {
-            for (int t = full; t < cnt; ++t) {
-                const float d1 = (float)(t1 - s_X[t]);
-                const float d1sq = fmaf(d1, d1, kTiny);
-                const float m = UNIT ? 1.0f : s_m[t];
-#pragma unroll
-                for (int k = 0; k < kRPT; ++k) {
-                    const float d2 = reinterpret_cast<const float *>(s_d24[wave * kRPT + k])[t];
-                    float w = inv_r2(d1sq, d2);
-                    if (!UNIT) w = m * w;
-                    in1[k] = fmaf(d1, w, in1[k]);
-                    in2[k] = fmaf(d2, w, in2[k]);
+                for (int k = 0; k < RPT; ++k) {
+                    kahan_add(s1[k], c1[k], in1[k]);
+                    kahan_add(s2[k], c2[k], in2[k]);
+                    in1[k] = in2[k] = 0.0f;
                 }
             }
+            if (full < cnt) {
+                for (int t = full; t < cnt; ++t) {
+                    const float d1 = (float)(t1 - sm.X[t]);
+                    const float d1sq = fmaf(d1, d1, kTiny);
+                    const float m = UNIT ? 1.0f : s_m[t];
 #pragma unroll
-            for (int k = 0; k < kRPT; ++k) {
-                kahan_add(s1[k], c1[k], in1[k]);
-                kahan_add(s2[k], c2[k], in2[k]);
-                in1[k] = in2[k] = 0.0f;
+                    for (int k = 0; k < RPT; ++k) {
+                        const float d2 = reinterpret_cast<const float *>(sm.d24[wave * RPT + k])[t];
+                        float w = inv_r2(d1sq, d2);
+                        if (!UNIT) w = m * w;
+                        in1[k] = fmaf(d1, w, in1[k]);
+                        in2[k] = fmaf(d2, w, in2[k]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) {
+                    kahan_add(s1[k], c1[k], in1[k]);
+                    kahan_add(s2[k], c2[k], in2[k]);
+                    in1[k] = in2[k] = 0.0f;
+                }
             }
+        }
+
+        // FP64 near-lens residual, assembly and output, ray by ray
+        const int64_t cx = ((2 * i + 1) * (int64_t)g.n1x) / (2 * g.nx);
+        const int64_t cxl = cx > 0 ? cx - 1 : 0;
+        const int64_t cxh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int64_t j = ty * TY + wave * RPT + k;
+            const int64_t r = j * g.nx + i;
+            const bool valid = i < g.nx && j >= a.row0 && j < a.row1 && r >= a.ray_first &&
+                               r < a.ray_last;
+            const double t2 = ray_y(g, j);
+            double sum1 = (double)s1[k] - (double)c1[k];
+            double sum2 = (double)s2[k] - (double)c2[k];
+            if (valid) {
+                const int64_t cy = ((2 * j + 1) * (int64_t)g.n1y) / (2 * g.ny);
+                const int64_t cyl = cy > 0 ? cy - 1 : 0;
+                const int64_t cyh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
+                double r1 = 0.0, r2s = 0.0;
+                for (int64_t row = cyl; row <= cyh; ++row) {
+                    const int32_t pb = a.cell_start[row * g.n1x + cxl];
+                    const int32_t pe = a.cell_start[row * g.n1x + cxh + 1];
+                    for (int32_t pl = pb; pl < pe; ++pl) {
+                        const double X = a.lx[pl], Y = a.ly[pl];
+                        const double m64 = UNIT ? 1.0 : a.lm[pl];
+                        // the FP32 term exactly as the main loop formed it
+                        const float d1f = (float)(t1 - X);
+                        const float d2f = (float)(t2 - Y);
+                        float w = inv_r2(fmaf(d1f, d1f, kTiny), d2f);
+                        if (!UNIT) w = (float)m64 * w;
+                        // the FP64 term
+                        const double e1 = t1 - X, e2 = t2 - Y;
+                        const double rr2 = e1 * e1 + e2 * e2;
+                        const double w64 = rr2 > 0.0 ? m64 / rr2 : 0.0;
+                        r1 += w64 * e1 - (double)d1f * (double)w;
+                        r2s += w64 * e2 - (double)d2f * (double)w;
+                    }
+                }
+                sum1 += r1;
+                sum2 += r2s;
+            }
+            double a1, a2;
+            int32_t pix;
+            assemble(g, t1, t2, sum1, sum2, a1, a2, pix);
+            emit(valid, r - a.ray_first, a1, a2, pix, a.a1o, a.a2o, a.pixo, a.counts, a.landed);
         }
     }
+};
 
-    // FP64 near-lens residual, assembly and output, ray by ray
-    const int64_t cx = ((2 * i + 1) * (int64_t)g.n1x) / (2 * g.nx);
-    const int64_t cxl = cx > 0 ? cx - 1 : 0;
-    const int64_t cxh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
-#pragma unroll
-    for (int k = 0; k < kRPT; ++k) {
-        const int64_t j = ty * kTY + wave * kRPT + k;
-        const int64_t r = j * g.nx + i;
-        const bool valid = i < g.nx && j >= row0 && j < row1 && r >= ray_first && r < ray_last;
-        const double t2 = ray_y(g, j);
-        double sum1 = (double)s1[k] - (double)c1[k];
-        double sum2 = (double)s2[k] - (double)c2[k];
-        if (valid) {
-            const int64_t cy = ((2 * j + 1) * (int64_t)g.n1y) / (2 * g.ny);
-            const int64_t cyl = cy > 0 ? cy - 1 : 0;
-            const int64_t cyh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
-            double r1 = 0.0, r2s = 0.0;
-            for (int64_t row = cyl; row <= cyh; ++row) {
-                const int32_t pb = cell_start[row * g.n1x + cxl];
-                const int32_t pe = cell_start[row * g.n1x + cxh + 1];
-                for (int32_t pl = pb; pl < pe; ++pl) {
-                    const double X = lx[pl], Y = ly[pl];
-                    const double m64 = UNIT ? 1.0 : lm[pl];
-                    // the FP32 term exactly as the main loop formed it
-                    const float d1f = (float)(t1 - X);
-                    const float d2f = (float)(t2 - Y);
-                    float w = inv_r2(fmaf(d1f, d1f, kTiny), d2f);
-                    if (!UNIT) w = (float)m64 * w;
-                    // the FP64 term
-                    const double e1 = t1 - X, e2 = t2 - Y;
-                    const double rr2 = e1 * e1 + e2 * e2;
-                    const double w64 = rr2 > 0.0 ? m64 / rr2 : 0.0;
-                    r1 += w64 * e1 - (double)d1f * (double)w;
-                    r2s += w64 * e2 - (double)d2f * (double)w;
-                }
-            }
-            sum1 += r1;
-            sum2 += r2s;
+namespace {
+
+template <bool UNIT, int RPT, int LT>
+__global__ __launch_bounds__(kThreads) void k_direct_f32(DirectArgs a, int64_t ntx, int64_t ty0)
+{
+    using T = DirectTile<UNIT, RPT, LT>;
+    __shared__ typename T::Smem sm;
+    T::run(sm, a, (int64_t)blockIdx.x % ntx, ty0 + (int64_t)blockIdx.x / ntx);
+}
+
+// Persistent form for batches: workgroups pull (map, tile) items from a
+// device queue until it is empty.  Items are numbered map by map in the
+// order the host chose (longest-processing-time first); item_start[m] is the
+// first item of map m and item_start[nmaps] the total.
+template <bool UNIT, int RPT, int LT>
+__global__ __launch_bounds__(kThreads) void k_direct_f32_queue(
+    const DirectArgs *__restrict__ maps, const int64_t *__restrict__ item_start, int32_t nmaps,
+    unsigned long long *cursor)
+{
+    using T = DirectTile<UNIT, RPT, LT>;
+    __shared__ typename T::Smem sm;
+    __shared__ long long s_item;
+    const int64_t total = item_start[nmaps];
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = (long long)atomicAdd(cursor, 1ull);
+        __syncthreads();
+        const int64_t item = s_item;
+        if (item >= total) break;                    // every workgroup reaches this
+        int lo = 0, hi = nmaps - 1;                  // map m with item_start[m] <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (item_start[mid] <= item) lo = mid;
+            else hi = mid - 1;
         }
-        double a1, a2;
-        int32_t pix;
-        assemble(g, t1, t2, sum1, sum2, a1, a2, pix);
-        emit(valid, r - ray_first, a1, a2, pix, a1o, a2o, pixo, counts, landed);
+        const DirectArgs &a = maps[lo];
+        const int64_t t = item - item_start[lo];
+        T::run(sm, a, t % a.ntx, a.ty0 + t / a.ntx);
     }
 }
 
@@ -333,15 +431,34 @@ irs_status launch_direct(irs_plan_s *p, const RaySel &sel)
         return IRS_OK;
     }
 
+    const int v = p->direct_variant;
+    const int64_t TY = direct_variant_rows(v);
     const int64_t ntx = (g.nx + kTX - 1) / kTX;
-    const int64_t ty_lo = sel.row0 / kTY;
-    const int64_t ty_hi = (sel.row1 - 1) / kTY;          // inclusive
+    const int64_t ty_lo = sel.row0 / TY;
+    const int64_t ty_hi = (sel.row1 - 1) / TY;          // inclusive
     const int64_t max_rows_of_tiles = std::max<int64_t>(1, ((int64_t)1 << 22) / ntx);
     if (sel.stats) {
         const int64_t r0 = std::max(sel.row0 * g.nx, sel.ray_first);
         const int64_t r1 = std::min(sel.row1 * g.nx, sel.ray_last);
         sel.stats->direct_pairs += std::max<int64_t>(0, r1 - r0) * (int64_t)nl;
     }
+    DirectArgs a{};
+    a.g = g;
+    a.lx = p->d_x;
+    a.ly = p->d_y;
+    a.lm = p->d_m;
+    a.cell_start = p->d_cell_start;
+    a.nl = nl;
+    a.ntx = ntx;
+    a.row0 = sel.row0;
+    a.row1 = sel.row1;
+    a.ray_first = sel.ray_first;
+    a.ray_last = sel.ray_last;
+    a.a1o = sel.alpha1;
+    a.a2o = sel.alpha2;
+    a.pixo = sel.pixel;
+    a.counts = sel.counts;
+    a.landed = sel.landed;
     for (int64_t t0 = ty_lo; t0 <= ty_hi; t0 += max_rows_of_tiles) {
         const int64_t t1 = std::min(ty_hi + 1, t0 + max_rows_of_tiles);
         const unsigned nb = (unsigned)((t1 - t0) * ntx);
@@ -350,22 +467,106 @@ irs_status launch_direct(irs_plan_s *p, const RaySel &sel)
             if (st != IRS_OK) return st;
             sel.stats->n_rays++;
         }
-        if (unit)
-            hipLaunchKernelGGL(k_direct_f32<true>, dim3(nb), dim3(kThreads), 0, s, g, p->d_x,
-                               p->d_y, p->d_m, p->d_cell_start, nl, ntx, t0, sel.row0, sel.row1,
-                               sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2, sel.pixel,
-                               sel.counts, sel.landed);
-        else
-            hipLaunchKernelGGL(k_direct_f32<false>, dim3(nb), dim3(kThreads), 0, s, g, p->d_x,
-                               p->d_y, p->d_m, p->d_cell_start, nl, ntx, t0, sel.row0, sel.row1,
-                               sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2, sel.pixel,
-                               sel.counts, sel.landed);
+#define IRS_DF32(U, R, L) hipLaunchKernelGGL((k_direct_f32<U, R, L>), dim3(nb), dim3(kThreads), 0, s, a, ntx, t0)
+        if (unit) {
+            if (v == 0) IRS_DF32(true, 4, 512);
+            else if (v == 1) IRS_DF32(true, 8, 256);
+            else IRS_DF32(true, 16, 128);
+        } else {
+            if (v == 0) IRS_DF32(false, 4, 512);
+            else if (v == 1) IRS_DF32(false, 8, 256);
+            else IRS_DF32(false, 16, 128);
+        }
+#undef IRS_DF32
         IRS_HIP(hipGetLastError());
         if (sel.stats) {
             irs_status st = sel.stats->end(s);
             if (st != IRS_OK) return st;
         }
     }
+    return IRS_OK;
+}
+
+int direct_variant_rows(int v) { return (v == 0 ? 4 : v == 1 ? 8 : 16) * kWaves; }
+
+const char *direct_variant_name(int v)
+{
+    return v == 0 ? "rpt4_lt512" : v == 1 ? "rpt8_lt256" : "rpt16_lt128";
+}
+
+int64_t direct_items(const irs_plan_s *p, int variant)
+{
+    const DevGeom &g = p->dg;
+    if (p->params.precision == IRS_FP64) return (g.nx * g.ny + kThreads - 1) / kThreads;
+    const int64_t TY = direct_variant_rows(variant);
+    return ((g.nx + kTX - 1) / kTX) * ((g.ny + TY - 1) / TY);
+}
+
+DirectArgs direct_args_full(const irs_plan_s *p, int variant, uint32_t *counts,
+                            unsigned long long *landed)
+{
+    DirectArgs a{};
+    a.g = p->dg;
+    a.lx = p->d_x;
+    a.ly = p->d_y;
+    a.lm = p->d_m;
+    a.cell_start = p->d_cell_start;
+    a.nl = (int32_t)p->n_lens;
+    a.ntx = (p->dg.nx + kTX - 1) / kTX;
+    a.ty0 = 0;
+    a.row0 = 0;
+    a.row1 = p->dg.ny;
+    a.ray_first = 0;
+    a.ray_last = p->dg.nx * p->dg.ny;
+    a.counts = counts;
+    a.landed = landed;
+    (void)variant;
+    return a;
+}
+
+irs_status launch_direct_queue(hipStream_t s, int precision, bool unit, int v,
+                               const DirectArgs *maps, const int64_t *item_start,
+                               int32_t nmaps, unsigned long long *cursor, int blocks)
+{
+    if (precision == IRS_FP64) {
+        if (unit)
+            hipLaunchKernelGGL(k_direct_f64_queue<true>, dim3(blocks), dim3(kThreads), 0, s,
+                               maps, item_start, nmaps, cursor);
+        else
+            hipLaunchKernelGGL(k_direct_f64_queue<false>, dim3(blocks), dim3(kThreads), 0, s,
+                               maps, item_start, nmaps, cursor);
+    } else {
+#define IRS_DQ(U, R, L) hipLaunchKernelGGL((k_direct_f32_queue<U, R, L>), dim3(blocks), dim3(kThreads), 0, s, maps, item_start, nmaps, cursor)
+        if (unit) {
+            if (v == 0) IRS_DQ(true, 4, 512);
+            else if (v == 1) IRS_DQ(true, 8, 256);
+            else IRS_DQ(true, 16, 128);
+        } else {
+            if (v == 0) IRS_DQ(false, 4, 512);
+            else if (v == 1) IRS_DQ(false, 8, 256);
+            else IRS_DQ(false, 16, 128);
+        }
+#undef IRS_DQ
+    }
+    IRS_HIP(hipGetLastError());
+    return IRS_OK;
+}
+
+namespace {
+__global__ void k_zero(uint32_t *__restrict__ p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+}  // namespace
+
+irs_status launch_zero(hipStream_t s, void *ptr, size_t n_words)
+{
+    if (n_words == 0) return IRS_OK;
+    const size_t blocks = std::min<size_t>((n_words + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t *)ptr, n_words);
+    IRS_HIP(hipGetLastError());
     return IRS_OK;
 }
 

@@ -652,6 +652,63 @@ int level2_order(const irs_plan_s *p)
 
 }  // namespace
 
+namespace {
+
+int64_t level2_row_bytes(const irs_plan_s *p)
+{
+    return (int64_t)p->dg.n1x * p->dg.q * p->dg.q * 10 * (int64_t)sizeof(double);
+}
+
+// level-1 rows per band: as many as fit in the plan's coefficient budget
+int64_t band_rows(const irs_plan_s *p)
+{
+    return std::min<int64_t>(p->dg.n1y, std::max<int64_t>(1, p->coef_budget / level2_row_bytes(p)));
+}
+
+// coefficient and partial-expansion buffers for bands of `rows` level-1 rows
+irs_status ensure_bands(irs_plan_s *p, int64_t rows)
+{
+    if (p->coef_rows_cap < rows) {
+        dev_free(p->d_coef);
+        p->d_coef = nullptr;
+        p->coef_rows_cap = 0;
+        p->coef_c0 = -1;
+        p->coef_c1 = -2;
+        if (hipMalloc(&p->d_coef, (size_t)(rows * level2_row_bytes(p))) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("cannot allocate the level-2 coefficient band");
+            return IRS_E_NOMEM;
+        }
+        p->coef_rows_cap = rows;
+    }
+    const int P = level2_order(p);
+    if (P > 0) {
+        const int32_t nchunk = std::max<int32_t>(1, (int32_t)((p->n_lens + kChunkLens - 1) / kChunkLens));
+        const size_t need = (size_t)p->coef_rows_cap * p->dg.n1x * nchunk * P * 2 * sizeof(double);
+        if (p->part_bytes < need) {
+            dev_free(p->d_part);
+            p->d_part = nullptr;
+            p->part_bytes = 0;
+            if (hipMalloc(&p->d_part, need) != hipSuccess) {
+                (void)hipGetLastError();
+                set_error("cannot allocate the level-2 partial expansions");
+                return IRS_E_NOMEM;
+            }
+            p->part_bytes = need;
+        }
+    }
+    return IRS_OK;
+}
+
+}  // namespace
+
+irs_status interp_prepare(irs_plan_s *p)
+{
+    p->coef_c0 = -1;                 // nothing resident that a replay could rely on
+    p->coef_c1 = -2;
+    return ensure_bands(p, band_rows(p));
+}
+
 irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
 {
     const DevGeom &g = p->dg;
@@ -660,26 +717,11 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
     if (sel.row1 <= sel.row0) return IRS_OK;
     const int64_t q = g.q;
     const int64_t row_pts = (int64_t)g.n1x * q * q;            // level-2 points per level-1 row
-    const int64_t row_bytes = row_pts * 10 * (int64_t)sizeof(double);
     const int64_t cyA = level2_row_host(g, sel.row0) / q;
     const int64_t cyB = level2_row_host(g, sel.row1 - 1) / q;  // inclusive
     const int64_t want = cyB - cyA + 1;
-    // band buffer: as many level-1 rows as fit in 2 GiB (at least one)
-    const int64_t fit = std::max<int64_t>(1, ((int64_t)2 << 30) / row_bytes);
-    const int64_t rows = std::min(fit, want);
-    if (p->coef_rows_cap < rows) {
-        dev_free(p->d_coef);
-        p->d_coef = nullptr;
-        p->coef_rows_cap = 0;
-        p->coef_c0 = -1;
-        p->coef_c1 = -2;
-        if (hipMalloc(&p->d_coef, (size_t)(rows * row_bytes)) != hipSuccess) {
-            (void)hipGetLastError();
-            set_error("cannot allocate the level-2 coefficient band");
-            return IRS_E_NOMEM;
-        }
-        p->coef_rows_cap = rows;
-    }
+    irs_status st0 = ensure_bands(p, std::min(band_rows(p), want));
+    if (st0 != IRS_OK) return st0;
     const int64_t ntx = (g.nx + kWave - 1) / kWave;
     const int rows_per_block = kL3Rows;
     CallStats *cs = sel.stats;
@@ -730,18 +772,6 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
                 // lenses are split into fixed chunks (a property of the plan, so
                 // results do not depend on how a map is cut into calls)
                 const int32_t nchunk = std::max<int32_t>(1, (nl + kChunkLens - 1) / kChunkLens);
-                const size_t need = (size_t)(c1 - c0 + 1) * g.n1x * nchunk * P * 2 * sizeof(double);
-                if (p->part_bytes < need) {
-                    dev_free(p->d_part);
-                    p->d_part = nullptr;
-                    p->part_bytes = 0;
-                    if (hipMalloc(&p->d_part, need) != hipSuccess) {
-                        (void)hipGetLastError();
-                        set_error("cannot allocate the level-2 partial expansions");
-                        return IRS_E_NOMEM;
-                    }
-                    p->part_bytes = need;
-                }
                 const unsigned nbA = (unsigned)((c1 - c0 + 1) * nxb * nchunk);
                 const unsigned nbB = (unsigned)((c1 - c0 + 1) * nxb);
 #define IRS_L2L(U, PP)                                                                        \

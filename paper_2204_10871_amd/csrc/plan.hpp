@@ -11,6 +11,24 @@
 #include "device_common.hpp"
 #include "geometry.hpp"
 
+// Arguments of the direct-sum tile routines (one map).
+namespace irs {
+struct DirectArgs {
+    DevGeom g;
+    const double *lx, *ly, *lm;          // sorted lenses (lm null: unit masses)
+    const int32_t *cell_start;
+    int32_t nl;
+    int32_t pad_;
+    int64_t ntx, ty0;                    // tiles per row; first tile row (queue kernels)
+    int64_t row0, row1;                  // ray rows computed
+    int64_t ray_first, ray_last;         // ray index range computed
+    double *a1o, *a2o;                   // per-ray outputs (indexed r - ray_first) or
+    int64_t *pixo;                       //   ... null
+    uint32_t *counts;                    // map counts (null: per-ray outputs)
+    unsigned long long *landed;          // rays binned
+};
+}  // namespace irs
+
 struct irs_plan_s {
     irs_params params;
     irs::HostGeometry geo;
@@ -20,6 +38,8 @@ struct irs_plan_s {
     int64_t n_lens = 0;
     bool unit_mass = true;
     double kappa_star_eff = 0.0;
+    int direct_variant = 1;              // FP32 direct tile shape (see k_direct.hip)
+    int64_t coef_budget = (int64_t)2 << 30;   // bytes for one band of level-2 coefficients
 
     // Lenses packed into level-1 cells (row-major cell order; inside a cell in
     // increasing input order).  FP64 positions and masses.
@@ -96,5 +116,25 @@ struct RaySel {
 
 irs_status launch_direct(irs_plan_s *p, const RaySel &sel);
 irs_status launch_interp(irs_plan_s *p, const RaySel &sel);
+
+// FP32 direct tile shapes: rays per lane x lenses per LDS stage.
+constexpr int kDirectVariants = 3;
+int direct_variant_rows(int v);          // ray rows per tile of shape v
+const char *direct_variant_name(int v);
+
+// Batched direct sums: one persistent launch over every map's tiles.
+// maps: device table; item_start: device prefix of tiles per map; cursor:
+// device counter, zero before the launch.  blocks: persistent grid size.
+irs_status launch_direct_queue(hipStream_t s, int precision, bool unit, int variant,
+                               const DirectArgs *maps, const int64_t *item_start,
+                               int32_t nmaps, unsigned long long *cursor, int blocks);
+// Tiles (FP32) or 256-ray groups (FP64) of a whole map, and its DirectArgs.
+int64_t direct_items(const irs_plan_s *p, int variant);
+DirectArgs direct_args_full(const irs_plan_s *p, int variant, uint32_t *counts,
+                            unsigned long long *landed);
+// Level-2 buffers sized for whole-map bands, allocated now (before a capture).
+irs_status interp_prepare(irs_plan_s *p);
+// Fill kernel (graph-safe zeroing): n 32-bit words.
+irs_status launch_zero(hipStream_t s, void *ptr, size_t n_words);
 
 }  // namespace irs

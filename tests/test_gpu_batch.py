@@ -1,0 +1,127 @@
+"""Batches of independent maps (one graph launch) against the same maps shot
+one plan at a time, the autotuner's cache, and graph replays."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def irs():
+    import paper_2204_10871_amd as irs
+    irs.load()
+    return irs
+
+
+def _maps(irs, n, method, precision, seed=3, npix=64, n_rays=150_000):
+    """n uneven maps: kappa_*, gamma, kappa_c and lens counts drawn like the
+    batched workload, shrunk to test size."""
+    rng = np.random.default_rng(seed)
+    plans = []
+    while len(plans) < n:
+        ks, g = rng.uniform(0.1, 0.8, 2)
+        kc = float(rng.choice([0.0, 0.2]))
+        k = ks + kc
+        if min(abs(1 - k - g), abs(1 - k + g)) < 0.05:
+            continue
+        n_star = int(10 ** rng.uniform(1.5, 3.3))
+        S = orc.source_side_for_lens_count(ks, kc, g, n_star)
+        if S < 2.0:
+            continue
+        p = irs.make_params(ks, kc, g, S, npix, n_rays=n_rays + 977 * len(plans),
+                            method=method, precision=precision)
+        g0 = irs.geometry(p, 0)
+        L = synth.uniform_lenses(g0["n_stars_expected"],
+                                 (g0["a1"], g0["a2"], g0["b1"], g0["b2"]), 1000 + len(plans))
+        plans.append(irs.Plan(p, L.x, L.y, L.m))
+    return plans
+
+
+@pytest.mark.parametrize("method,precision", [("direct", "fp64"), ("direct", "fp32"),
+                                              ("interp", "fp64")])
+def test_batch_equals_single_plans(irs, method, precision):
+    import torch
+    plans = _maps(irs, 7, method, precision)
+    singles = [p.shoot_map()[0].ravel().astype(np.int64) for p in plans]
+    counts = [torch.empty(p.params.npix_side ** 2, dtype=torch.int32, device="cuda:0")
+              for p in plans]
+    with irs.Batch(plans) as b:
+        info = b.tune()
+        say(f"{method}/{precision}: tuned {info}")
+        st = b.run(counts)
+        for k, p in enumerate(plans):
+            got = counts[k].cpu().numpy().astype(np.int64)
+            assert np.array_equal(got, singles[k]), f"map {k} differs"
+            assert st[k]["rays_landed"] == int(singles[k].sum())
+    for p in plans:
+        p.close()
+
+
+def test_direct_fp32_tile_shapes_identical(irs):
+    plans = _maps(irs, 2, "direct", "fp32", seed=5)
+    for p in plans:
+        maps = []
+        for v in range(3):
+            p.set_direct_variant(v)
+            a1, a2, px = p.deflect_grid(0, p.n_rays)
+            maps.append((a1, a2, px))
+        for v in (1, 2):
+            assert np.array_equal(maps[0][0], maps[v][0]) and np.array_equal(maps[0][2], maps[v][2])
+        p.close()
+
+
+def test_graph_replays_with_eager_work_between(irs):
+    """Replay the captured graph several times with the program's own eager GPU
+    work and synchronisations in between; every replay equals the eager maps."""
+    import torch
+    plans = _maps(irs, 4, "interp", "fp64", seed=9)
+    singles = [p.shoot_map()[0].ravel().astype(np.int64) for p in plans]
+    counts = [torch.empty(p.params.npix_side ** 2, dtype=torch.int32, device="cuda:0")
+              for p in plans]
+    with irs.Batch(plans) as b:
+        for rep in range(4):
+            b.run(counts)
+            for k in range(len(plans)):
+                assert np.array_equal(counts[k].cpu().numpy().astype(np.int64), singles[k]), rep
+            x = torch.randn(1 << 20, device="cuda:0")
+            (x * 2).sum().item()                      # eager work between replays
+            torch.cuda.synchronize()
+            counts[0].fill_(7)                        # the graph must overwrite this
+    for p in plans:
+        p.close()
+
+
+def test_tuning_cache_roundtrip(irs, tmp_path):
+    plans = _maps(irs, 3, "direct", "fp32", seed=11)
+    cache = tmp_path / "tune.txt"
+    with irs.Batch(plans) as b:
+        first = b.tune(cache)
+    assert first["tuned"] == 1 and first["from_cache"] == 0 and cache.exists()
+    text = cache.read_text()
+    assert "direct fp32 unit" in text
+    with irs.Batch(plans) as b:
+        second = b.tune(cache)
+    assert second["from_cache"] == 1
+    assert (second["direct_variant"], second["blocks_per_cu"]) == \
+        (first["direct_variant"], first["blocks_per_cu"])
+    for p in plans:
+        p.close()
+
+
+def test_batch_rejects_mixed_plans(irs):
+    a = _maps(irs, 1, "direct", "fp32", seed=13)[0]
+    b = _maps(irs, 1, "interp", "fp64", seed=13)[0]
+    with pytest.raises(irs.IrsError) as e:
+        irs.Batch([a, b])
+    assert e.value.status == 5
+    a.close()
+    b.close()
