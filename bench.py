@@ -58,6 +58,49 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def bench_batch(irs, synth, torch, stream):
+    """The 64-map batch (kappa_*, gamma ~ U[0.1, 0.8], kappa_c in {0, 0.2},
+    N_* = 10^U[3, 5], 1024^2..4096^2 px, 100 rays/px), interpolated: one tuned
+    graph launch vs the same maps launched one after another."""
+    draws = synth.configs.batch_draws()
+    plans, counts = [], []
+    t0 = time.perf_counter()
+    for d in draws:
+        S = irs.source_side_for_n_star(d.kappa_star, d.kappa_c, d.gamma, d.n_star_target)
+        p = irs.make_params(d.kappa_star, d.kappa_c, d.gamma, S, d.npix,
+                            rays_per_pixel=d.rays_per_pixel, method="interp", precision="fp64")
+        g = irs.geometry(p, 0)
+        L = synth.uniform_lenses(g["n_stars_expected"], (g["a1"], g["a2"], g["b1"], g["b2"]),
+                                 d.seed)
+        plans.append(irs.Plan(p, L.x, L.y, L.m, stream=stream.cuda_stream))
+        counts.append(torch.empty(d.npix * d.npix, dtype=torch.int32, device="cuda:0"))
+    rays = sum(p.n_rays for p in plans)
+    log(f"batch: {len(plans)} maps, {rays:.3e} rays, set up in {time.perf_counter() - t0:.1f} s")
+    with irs.Batch(plans) as b:
+        info = b.tune()
+        b.run(counts)                                      # capture + first replay
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        b.run(counts)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - tb
+    batched = [c.clone() for c in counts]
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for p, c in zip(plans, counts):
+        c.zero_()
+        p.shoot_rows(0, p.geometry["ny"], c)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - ts
+    same = all(torch.equal(a, c) for a, c in zip(batched, counts))
+    for p in plans:
+        p.close()
+    log(f"batch: graph {tb:.2f} s, one by one {ts:.2f} s, identical {same}")
+    return {"maps": len(plans), "rays": rays, "method": "interp", "precision": "fp64",
+            "batched_rays_per_s": rays / tb, "sequential_rays_per_s": rays / ts,
+            "speedup": ts / tb, "identical_to_sequential": same, "tuned": info}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,7 +110,9 @@ def main():
                     help="rays of the oracle sample (each sums all 1e6 lenses)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
-    ap.add_argument("--direct-rows", type=int, default=48)
+    ap.add_argument("--direct-rows", type=int, default=64)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-map batch measurement")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="run a plain 512 MiB device copy first (scale for HBM counters)")
     args = ap.parse_args()
@@ -199,11 +244,13 @@ def main():
     if not args.no_direct:
         pd = irs.params_from_workload(w, method="direct", precision="fp32")
         with irs.Plan(pd, L.x, L.y, L.m, stream=stream.cuda_stream) as dplan:
-            r0 = (G["ny"] // 2) // 16 * 16
-            dplan.shoot_rows(r0, 16, counts)             # warm-up tile row
+            # whole tile rows (64 is a multiple of every tile height)
+            r0 = (G["ny"] // 2) // 64 * 64
+            rows = max(64, (args.direct_rows + 63) // 64 * 64)
+            dplan.deflect_grid(r0 * G["nx"], 64)          # warm-up: one tile
             torch.cuda.synchronize()
             td = time.perf_counter()
-            st = dplan.shoot_rows(r0 + 16, args.direct_rows, counts, time_phases=True)
+            st = dplan.shoot_rows(r0, rows, counts, time_phases=True)
             torch.cuda.synchronize()
             td = time.perf_counter() - td
         pairs = st["direct_pairs"]
@@ -216,6 +263,8 @@ def main():
         log(f"direct fp32: {pairs / td:.3e} pairs/s, {tf:.1f} TFLOP/s")
 
     plan.close()
+    if not args.no_batch:
+        result["batch"] = bench_batch(irs, synth, torch, stream)
     print(json.dumps(result), flush=True)
 
 

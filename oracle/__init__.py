@@ -8,14 +8,16 @@ with the HIP library (paper_2204_10871_amd) and does not import it.
                   grid, level-1/2/3 resolutions, pixel areas).
   irs_oracle.c -- O-1 (direct definition of Eq. 6 + Appendix A + binning) and
                   O-2 (the three-level-grid interpolation, step by step).
-  mlp.py       -- FP64 reference of the learned interpolant's network.
+  learned.py   -- FP64 reference of the learned far-field interpolant (network,
+                  base interpolant, local data); orc_far_point gives its exact
+                  samples.
 
 Parity status of each function is listed in its docstring ("pinned by ...").
 """
 from .geometry import Geometry, geometry, CriticalLineError, source_side_for_lens_count
 from .core import (build, load, sheet_I, alpha_points, shoot_direct, level1,
-                   level2, level2_grid, shoot_interp, sheet_taylor, setup_of)
+                   level2, level2_grid, shoot_interp, sheet_taylor, setup_of, far_point)
 
 __all__ = ["Geometry", "geometry", "CriticalLineError", "source_side_for_lens_count",
            "build", "load", "sheet_I", "alpha_points", "shoot_direct", "level1",
-           "level2", "level2_grid", "shoot_interp", "sheet_taylor", "setup_of"]
+           "level2", "level2_grid", "shoot_interp", "sheet_taylor", "setup_of", "far_point"]

@@ -57,6 +57,8 @@ def load():
         lib.orc_shoot_interp.argtypes = [P(_Setup), i64, vp, vp, vp, vp, vp, vp, i64, i64, vp,
                                          vp, vp, vp, vp, vp, C.c_int]
         lib.orc_sheet_taylor_xy.argtypes = [P(_Setup), d, d, vp]
+        lib.orc_far_point.argtypes = [P(_Setup), i64, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp,
+                                      vp, C.c_int]
         _lib = lib
         return lib
 
@@ -201,3 +203,27 @@ def sheet_taylor(g: Geometry, z0: complex):
     out = np.empty(10)
     lib.orc_sheet_taylor_xy(C.byref(s), float(z0.real), float(z0.imag), _ptr(out))
     return out[0::2] + 1j * out[1::2]
+
+
+def far_point(g: Geometry, lenses, cell_start, perm, cx, cy, x, y, threads=0):
+    """Analytic far field A and its derivative A' of cell (cx[k], cy[k]) at the
+    points (x[k], y[k]) (orc_far_point).  Returns complex arrays (A, dA).
+
+    Pinned by: the direct definition (O-1) at the same points, since
+    conj(alpha - macro - near) = A - kappa_* conj(z) outside the corner cells,
+    and by central differences of A for A'."""
+    lib = load()
+    s = setup_of(g)
+    cx = np.ascontiguousarray(cx, dtype=np.int64)
+    cy = np.ascontiguousarray(cy, dtype=np.int64)
+    x, y = _f64(x), _f64(y)
+    n = cx.size
+    out = np.zeros(4 * n)
+    lx, ly, lm = _f64(lenses.x), _f64(lenses.y), _f64(lenses.m)
+    cs = np.ascontiguousarray(cell_start, dtype=np.int64)
+    pm = np.ascontiguousarray(perm, dtype=np.int64)
+    lib.orc_far_point(C.byref(s), lenses.n, _ptr(lx), _ptr(ly), _ptr(lm),
+                      _ptr(cs), _ptr(pm), n, _ptr(cx), _ptr(cy), _ptr(x), _ptr(y), _ptr(out),
+                      threads)
+    o = out.reshape(n, 4)
+    return o[:, 0] + 1j * o[:, 1], o[:, 2] + 1j * o[:, 3]

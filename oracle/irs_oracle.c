@@ -450,3 +450,57 @@ void orc_sheet_taylor_xy(const orc_setup *s, double x, double y, double *out)
         out[2 * k + 1] = cimag(g[k]);
     }
 }
+
+/* ------------------------------------------------------------------------- */
+/* Far field at arbitrary points (the learned interpolant's exact samples).    */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Analytic far field of cell (cx, cy) at points z = x + i y, by the plain
+ * definition: the distant lenses (outside the 3 x 3 block around the cell)
+ * give A(z) = sum m_i / (z - z_i) and A'(z) = -sum m_i / (z - z_i)^2; outside
+ * the four corner cells the analytic part of the sheet is added,
+ * -kappa_star G(z) and -kappa_star G'(z), with G(z) = F(z) - conj(z) (the sheet's
+ * remaining term -kappa_star conj(z) is the ray's own, exactly linear).  So
+ * conj(alpha_far + alpha_sheet)(z) = A(z) - kappa_star conj(z) in non-corner
+ * cells and A(z) - kappa_star F(z) in corner cells.
+ * out[4k..4k+3] = Re A, Im A, Re A', Im A'.
+ */
+void orc_far_point(const orc_setup *s, int64_t nl, const double *lx, const double *ly,
+                   const double *lm, const int64_t *cell_start, const int64_t *perm,
+                   int64_t npts, const int64_t *pcx, const int64_t *pcy, const double *px,
+                   const double *py, double *out, int nthreads)
+{
+    (void)nl;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t k = 0; k < npts; ++k) {
+        const double complex z = px[k] + I * py[k];
+        const int64_t cx = pcx[k], cy = pcy[k];
+        double complex A = 0.0, dA = 0.0;
+        for (int64_t lcy = 0; lcy < s->n1y; ++lcy)
+            for (int64_t lcx = 0; lcx < s->n1x; ++lcx) {
+                if (is_near(cx, cy, lcx, lcy)) continue;
+                const int64_t cell = lcy * s->n1x + lcx;
+                for (int64_t p = cell_start[cell]; p < cell_start[cell + 1]; ++p) {
+                    const int64_t i = perm[p];
+                    const double m = lm ? lm[i] : 1.0;
+                    const double complex w = z - (lx[i] + I * ly[i]);
+                    A += m / w;
+                    dA -= m / (w * w);
+                }
+            }
+        if (s->sheet && !is_corner_cell(s, cx, cy)) {
+            double complex g[5];
+            orc_sheet_taylor(s, z, g);
+            A -= s->kappa_star * (g[0] - conj(z));
+            dA -= s->kappa_star * g[1];
+        }
+        out[4 * k] = creal(A);
+        out[4 * k + 1] = cimag(A);
+        out[4 * k + 2] = creal(dA);
+        out[4 * k + 3] = cimag(dA);
+    }
+}

@@ -68,6 +68,24 @@ def geometry(params: Params, n_lens: int = 0) -> dict:
     return out.as_dict()
 
 
+def source_side_for_n_star(kappa_star, kappa_c, gamma, n_star, **kw) -> float:
+    """Source side S whose rectangle holds n_star lenses by the lens-count rule
+    (irs_geometry's n_stars_expected), found by bisection on S."""
+    lo, hi = 1e-3, 1.0
+    while geometry(make_params(kappa_star, kappa_c, gamma, hi, 16, n_rays=1, **kw))[
+            "n_stars_expected"] < n_star:
+        hi *= 2.0
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        n = geometry(make_params(kappa_star, kappa_c, gamma, mid, 16, n_rays=1, **kw))[
+            "n_stars_expected"]
+        if n < n_star:
+            lo = mid
+        else:
+            hi = mid
+    return hi
+
+
 def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
 

@@ -217,6 +217,12 @@ struct DirectTile {
     __device__ static void run(Smem &sm, const DirectArgs &a, int64_t tx, int64_t ty)
     {
         const DevGeom &g = a.g;
+        {
+            // skip a tile none of whose rays is asked for (block-uniform)
+            const int64_t jA = max(ty * TY, a.row0), jB = min(ty * TY + TY - 1, a.row1 - 1);
+            const int64_t iA = tx * kTX, iB = min(tx * kTX + kTX - 1, g.nx - 1);
+            if (jA > jB || jB * g.nx + iB < a.ray_first || jA * g.nx + iA >= a.ray_last) return;
+        }
         float *s_m = reinterpret_cast<float *>(sm.m4);
         const int tid = threadIdx.x;
         const int lane = tid % kWave, wave = tid / kWave;
