@@ -11,7 +11,7 @@
  *   2. optionally the three-level-grid interpolation: lenses packed into
  *      level-1 cells, distant lenses and the sheet summed with Taylor
  *      coefficients up to fourth order at level-2 points, nearby lenses summed
- *      exactly for every level-3 ray (Sec. 2.3 and the flow chart of Sec. 2.4);
+ *      exactly for every level-3 ray (Sec. 2.4 and its flow chart);
  *   3. binning of the mapped rays beta = theta - alpha (Eq. 4) into
  *      source-plane pixel counts N_ij, with Mag_ij = N_ij S_I / S_S
  *      (flow chart, "Calculate the magnification of each pixel").
@@ -59,7 +59,9 @@ typedef enum {
 
 /* irs_params.method */
 enum { IRS_DIRECT = 0,      /* sum over every lens for every ray (Eq. 6)       */
-       IRS_INTERP = 1 };    /* three-level-grid interpolation (Sec. 2.3)       */
+       IRS_INTERP = 1,      /* three-level-grid interpolation (Sec. 2.4)       */
+       IRS_LEARNED = 2 };   /* Sec. 2.4's split with a learned interpolant of the
+                               distant field on a coarse grid (see irs_learn)  */
 
 /* irs_params.precision */
 enum { IRS_FP64 = 0,        /* every step in double precision                  */
@@ -89,7 +91,7 @@ typedef struct {
     double   rays_per_pixel;      /* N_av; used when n_rays <= 0                      */
     int64_t  n_rays;              /* > 0: total ray count instead of N_av * N_pix     */
     double   border;              /* < 0: P = 10 sqrt(kappa_*); >= 0: explicit P      */
-    int32_t  method;              /* IRS_DIRECT or IRS_INTERP                          */
+    int32_t  method;              /* IRS_DIRECT, IRS_INTERP or IRS_LEARNED             */
     int32_t  precision;           /* IRS_FP64 or IRS_FP32_KAHAN                        */
     double   level2_spacing;      /* > 0: explicit level-2 spacing dx2                */
     double   level2_ray_multiple; /* > 0: dx2 = this many ray spacings; both <= 0:   */
@@ -138,6 +140,9 @@ typedef struct {
     double  ms_level2;            /* all level-2 launches                             */
     double  ms_level2_expand;     /* the per-cell expansion (or per-point sum) kernel  */
     double  ms_rays;
+    int32_t learned;              /* IRS_LEARNED plans: 1 if the network was used,    */
+                                  /* 0 if the grid-interpolation fallback was          */
+    int32_t pad_;
 } irs_map_stats;
 
 /*
@@ -266,6 +271,139 @@ irs_status irs_batch_get_info(irs_batch_t batch, irs_batch_info *out);
 
 /* irs_batch_free -- release a batch (not its plans).  NULL is ignored. */
 void irs_batch_free(irs_batch_t batch);
+
+/* ------------------------------------------------------------------------ */
+/* Learned interpolant of the distant-lens field (method IRS_LEARNED).       */
+/* ------------------------------------------------------------------------ */
+/*
+ * The interpolation of Sec. 2.4 sums the nearby lenses (3 x 3 level-1 cells)
+ * exactly and takes the distant lenses and the sheet from a fourth-order
+ * Taylor series about the ray's level-2 point.  IRS_LEARNED keeps that split
+ * and replaces the Taylor series by a learned interpolant on a coarser grid.
+ * Every level-1 cell is cut into coarse x coarse squares; at their corners the
+ * plan computes, in FP64, the cell's distant field A(z) (distant lenses plus
+ * the analytic part of the sheet, outside the four corner cells) and A'(z).
+ * For a ray at z in a square with corners z_c, offset h in [0,1]^2:
+ *   I(z)  = sum_c w_c(h) (A_c + A'_c (z - z_c))       bilinear weights w_c,
+ *   D     = (delta_c, eps_c) / sigma, delta_c = (A'_c - mean A') s,
+ *           eps_c = A_c - mean A - mean A' (z_c - mean z_c), s = mean side,
+ *           sigma = max |delta_c|, |eps_c|,
+ *   A(z) ~= I(z) + sigma sum_k L_k(h) D_k,   k = 0..7,
+ * with L(h) in C^8 from a Fourier-feature MLP: features sin and cos of
+ * 2 pi f_j . (h - 1/2) for 64 frequencies f_j, four hidden ReLU layers of 128,
+ * 16 outputs (L_k = y_2k + i y_2k+1).  Weights and activations are BF16 on the
+ * matrix cores with FP32 accumulation.  The network is trained on the GPU
+ * (Adam, FP32 master weights) on exact samples of A that the plan computes,
+ * then validated on samples from other rows; if it misses the tolerance the
+ * plan shoots with the grid interpolation of IRS_INTERP instead (fallback).
+ * The paper has no learned part; this is the library's extension of Sec. 2.4.
+ *
+ * Parameter vector: IRS_LEARN_NPARAMS FP32 numbers W1 (128 x 128, row-major,
+ * row = output unit), b1 (128), W2, b2, W3, b3, W4, b4, W5 (16 x 128), b5 (16).
+ * Frequencies: IRS_LEARN_NFREQ x 2 FP32, row j = (f_jx, f_jy).
+ */
+#define IRS_LEARN_NFREQ    64
+#define IRS_LEARN_NPARAMS  68112
+#define IRS_LEARN_FIELDS   24   /* floats per sample record (irs_learn_samples) */
+
+typedef struct {
+    int32_t  coarse;        /* squares per level-1 cell side, 1..32              */
+    int32_t  train_rows;    /* level-1 rows the training samples come from,      */
+                            /* spread evenly over the map                        */
+    int64_t  n_samples;     /* training samples                                  */
+    int64_t  n_val;         /* validation samples, from rows between those       */
+    int32_t  batch;         /* samples per Adam step, multiple of 256            */
+    int32_t  steps;         /* Adam steps                                         */
+    float    lr, lr_final;  /* learning rate, cosine decay from lr to lr_final    */
+    float    beta1, beta2, adam_eps;
+    int32_t  pad_;
+    uint64_t seed;          /* sample positions and initial weights               */
+    double   tol_mean;      /* fallback if validation mean |error| exceeds this;  */
+                            /* <= 0: 2.5e-5 dpix                                  */
+    double   tol_p9999;     /* ... or its 99.99th percentile; <= 0: 2.5e-3 dpix   */
+} irs_learn_params;
+
+typedef struct {
+    int64_t n_samples, n_val, steps;
+    double  loss_first, loss_last;      /* mean training loss of the first and last
+                                           5% of the steps (normalised units)    */
+    double  val_mean_abs, val_p9999_abs, val_max_abs;    /* |learned - A|, theta_E */
+    double  base_mean_abs, base_p9999_abs, base_max_abs; /* |I - A|: same grid,
+                                                            no network            */
+    double  tol_mean, tol_p9999;
+    int32_t fallback;       /* 1: tolerance missed; the plan uses grid interpolation */
+    int32_t coarse;
+    double  ms_samples, ms_train, ms_validate;
+    int64_t corner_bytes_per_row;       /* learned table per level-1 row          */
+    int64_t coef_bytes_per_row;         /* grid-interpolation table per row       */
+} irs_learn_report;
+
+/* irs_learn_defaults -- default training settings (coarse 4, 2e6 samples over 8
+   rows, 2e5 validation samples, batch 8192, 3000 steps, lr 2e-3 -> 2e-5). */
+irs_status irs_learn_defaults(irs_learn_params *out);
+
+/*
+ * irs_learn -- generate exact samples, train the network and validate it on an
+ * IRS_LEARNED plan.  freqs: IRS_LEARN_NFREQ x 2 host floats; theta0: initial
+ * parameters (host, IRS_LEARN_NPARAMS) or NULL for a seeded He initialisation.
+ * report may be NULL.  Afterwards the plan's shooting calls use the network,
+ * or the grid interpolation if report->fallback is 1.
+ * Errors: IRS_E_INVALID (not an IRS_LEARNED plan, settings out of range),
+ * IRS_E_UNSUPPORTED (IRS_LEVEL2_PAPER plans), IRS_E_NOMEM, IRS_E_DEVICE.
+ */
+irs_status irs_learn(irs_plan_t plan, const irs_learn_params *lp, const float *freqs,
+                     const float *theta0, irs_learn_report *report);
+
+/*
+ * irs_learn_set -- install a network (for example one saved with irs_learn_get)
+ * on an IRS_LEARNED plan, validate it as irs_learn does (lp: NULL for the
+ * defaults; only coarse, n_val, train_rows, seed and the tolerances are read)
+ * and decide the fallback.  Host arrays as for irs_learn.
+ */
+irs_status irs_learn_set(irs_plan_t plan, const irs_learn_params *lp, const float *freqs,
+                         const float *theta, irs_learn_report *report);
+
+/* irs_learn_get -- the plan's network: frequencies, parameters (host) and coarse.
+   IRS_E_INVALID if the plan has none. */
+irs_status irs_learn_get(irs_plan_t plan, float *freqs, float *theta, int32_t *coarse);
+
+/*
+ * irs_learn_corners -- the corner table of level-1 rows [row0, row0 + nrows):
+ * out (host, FP64) [((r - row0) n1x + cx) (coarse+1)^2 + b (coarse+1) + a] x 4
+ * = Re A, Im A, Re A', Im A' at corner (a, b) of cell (cx, r), corner position
+ * (a1 + (cx coarse + a) sx, b1 + (r coarse + b) sy), sx = I_x/(n1x coarse),
+ * sy = I_y/(n1y coarse).  For checking the learned path.
+ */
+irs_status irs_learn_corners(irs_plan_t plan, int32_t coarse, int64_t row0, int64_t nrows,
+                             double *out);
+
+/*
+ * irs_learn_samples -- the exact samples irs_learn trains on: per_cell samples
+ * in every cell of level-1 rows [row0, row0 + nrows), positions from a
+ * counter-based generator (seed, sample index).  out: DEVICE floats, field f of
+ * sample k at out[f n + k], n = nrows n1x per_cell; fields 0-1 h, 2-17 D
+ * (Re, Im of D_0..D_7), 18-19 T = (A - I)/sigma, 20 sigma, 21 cx, 22 cy,
+ * 23 square b coarse + a.
+ */
+irs_status irs_learn_samples(irs_plan_t plan, int32_t coarse, int64_t row0, int64_t nrows,
+                             int32_t per_cell, uint64_t seed, float *out);
+
+/*
+ * irs_mlp_forward -- the network's outputs y (DEVICE, 16 x n: y[o n + k]) at
+ * offsets h (DEVICE, 2 x n: hx row then hy row), with the inference kernel.
+ * freqs, theta: host arrays as above.  hip_stream: NULL for the default stream.
+ */
+irs_status irs_mlp_forward(int64_t n, const float *freqs, const float *theta,
+                           const float *h, float *y, void *hip_stream);
+
+/*
+ * irs_mlp_loss_grad -- training loss (1/n) sum |sum_k L_k D_k - T|^2 over the n
+ * sample records (DEVICE, IRS_LEARN_FIELDS x n as irs_learn_samples writes)
+ * and its gradient (host, IRS_LEARN_NPARAMS floats) from the training kernels.
+ */
+irs_status irs_mlp_loss_grad(int64_t n, const float *freqs, const float *theta,
+                             const float *samples, double *loss, float *grad,
+                             void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -200,7 +200,7 @@ void orc_shoot_direct(const orc_setup *s, int64_t nl, const double *lx,
 }
 
 /* ------------------------------------------------------------------------- */
-/* O-2: the three-level-grid interpolation, step by step (Sec. 2.3 and 2.4).   */
+/* O-2: the three-level-grid interpolation, step by step (Sec. 2.4).           */
 /* ------------------------------------------------------------------------- */
 
 /* Level-1 cell of a lens: the rectangle is tiled by n1x x n1y cells. */
@@ -269,8 +269,20 @@ void orc_sheet_taylor(const orc_setup *s, double complex z0, double complex *g)
     double t1 = creal(z0), t2 = cimag(z0), I1, I2;
     orc_sheet_I(s->a1, s->a2, s->b1, s->b2, 1, &t1, &t2, &I1, &I2);
     g[0] = (I1 - I * I2) / M_PI;
+    /* Log(z - c) with its cut pointing away from the rectangle: up from the
+     * top corners (argument in (-3 pi/2, pi/2]), down from the bottom ones
+     * (argument in (-pi/2, 3 pi/2]).  Inside the rectangle this is the
+     * principal Log; on and just outside the edges (points a rounding step
+     * outside) it continues the interior values instead of jumping by 2 pi
+     * where the principal cut runs along the top and bottom edges. */
     double complex sum_log = 0.0;
-    for (int k = 0; k < 4; ++k) sum_log += sg[k] * clog(z0 - c[k]);
+    for (int k = 0; k < 4; ++k) {
+        const double u = creal(z0) - creal(c[k]), v = cimag(z0) - cimag(c[k]);
+        double th = atan2(v, u);
+        if (k >= 2 && th > 0.5 * M_PI) th -= 2.0 * M_PI;
+        if (k < 2 && th < -0.5 * M_PI) th += 2.0 * M_PI;
+        sum_log += sg[k] * (0.5 * log(u * u + v * v) + I * th);
+    }
     g[1] = 1.0 - (I / M_PI) * sum_log;
     static const double fact[5] = { 1.0, 1.0, 2.0, 6.0, 24.0 };
     for (int n = 2; n <= 4; ++n) {

@@ -161,3 +161,59 @@ def learned_value(theta, freqs, zc, Ac, dAc, sx, sy, h, z):
     """I(z) + sigma sum_k L_k(h) D_k."""
     D, sigma = local_data(zc, Ac, dAc, sx, sy)
     return base_interp(zc, Ac, dAc, h, z) + sigma * predict(theta, freqs, h, D)
+
+
+# ---------------------------------------------------------------------------
+# Rays with the learned interpolant (reference for the GPU path)
+# ---------------------------------------------------------------------------
+
+def _pixel(g, b1, b2):
+    """Source pixel of beta (row-major, -1 off the map), as in O-1."""
+    dpix = g.source_side / g.npix
+    ix = np.floor((b1 + 0.5 * g.source_side) / dpix)
+    iy = np.floor((b2 + 0.5 * g.source_side) / dpix)
+    ok = (ix >= 0) & (ix < g.npix) & (iy >= 0) & (iy < g.npix)
+    return np.where(ok, iy * g.npix + ix, -1).astype(np.int64)
+
+
+def ray_squares(g, qc, ray_ids):
+    """Ray positions, cells and squares: the coarse grid splits [a1, a2] into
+    n1x*qc columns and the ray sits at the centre of its ray cell, so its
+    column is floor((i + 1/2) n1x qc / nx), in integers."""
+    r = np.asarray(ray_ids, dtype=np.int64)
+    i, j = r % g.nx, r // g.nx
+    gxc = ((2 * i + 1) * g.n1x * qc) // (2 * g.nx)
+    gyc = ((2 * j + 1) * g.n1y * qc) // (2 * g.ny)
+    t1 = g.a1 + (i + 0.5) * ((g.a2 - g.a1) / g.nx)
+    t2 = g.b1 + (j + 0.5) * ((g.b2 - g.b1) / g.ny)
+    return t1, t2, gxc, gyc
+
+
+def learned_rays(g, lenses, cell_start, perm, qc, freqs, theta, ray_ids, threads=0):
+    """alpha1, alpha2 and pixel of rays under the learned interpolant, with the
+    network in FP64.  The near lenses, the macro term and the non-analytic part
+    of the sheet are those of the direct definition, so
+        alpha_learned = alpha_O1 + conj(A_learned(z) - A(z)),
+    A the exact distant field of the ray's cell (orc_far_point)."""
+    from .core import alpha_points, far_point
+    t1, t2, gxc, gyc = ray_squares(g, qc, ray_ids)
+    cx, cy = gxc // qc, gyc // qc
+    sx = (g.a2 - g.a1) / (g.n1x * qc)
+    sy = (g.b2 - g.b1) / (g.n1y * qc)
+    X0, X1 = g.a1 + gxc * sx, g.a1 + (gxc + 1) * sx
+    Y0, Y1 = g.b1 + gyc * sy, g.b1 + (gyc + 1) * sy
+    n = t1.size
+    px = np.stack([X0, X1, X0, X1], axis=1).ravel()
+    py = np.stack([Y0, Y0, Y1, Y1], axis=1).ravel()
+    Ac, dAc = far_point(g, lenses, cell_start, perm, np.repeat(cx, 4), np.repeat(cy, 4), px, py,
+                        threads)
+    Ac, dAc = Ac.reshape(n, 4), dAc.reshape(n, 4)
+    zc = (px + 1j * py).reshape(n, 4)
+    A, _ = far_point(g, lenses, cell_start, perm, cx, cy, t1, t2, threads)
+    h = np.stack([(t1 - X0) / sx, (t2 - Y0) / sy], axis=1)
+    Al = learned_value(theta, freqs, zc, Ac, dAc, sx, sy, h, t1 + 1j * t2)
+    a1, a2, _ = alpha_points(g, lenses, t1, t2)
+    d = Al - A
+    a1 = a1 + d.real
+    a2 = a2 - d.imag
+    return a1, a2, _pixel(g, t1 - a1, t2 - a2)

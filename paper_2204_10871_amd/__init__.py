@@ -10,15 +10,19 @@ import ctypes as C
 import numpy as np
 
 from . import _ffi
-from ._ffi import (IRS_DIRECT, IRS_INTERP, IRS_FP64, IRS_FP32_KAHAN, IRS_SHEET_OFF,
-                   IRS_OUT_ON_DEVICE, IRS_TIME_PHASES, EXPORTS, Params, GeometryInfo, MapStats)
+from ._ffi import (IRS_DIRECT, IRS_INTERP, IRS_LEARNED, IRS_FP64, IRS_FP32_KAHAN, IRS_SHEET_OFF,
+                   IRS_OUT_ON_DEVICE, IRS_TIME_PHASES, IRS_LEARN_NFREQ, IRS_LEARN_NPARAMS,
+                   IRS_LEARN_FIELDS, EXPORTS, Params, GeometryInfo, MapStats, LearnParams,
+                   LearnReport)
 
 __all__ = ["IrsError", "make_params", "params_from_workload", "geometry", "Plan", "Batch", "load",
-           "IRS_DIRECT", "IRS_INTERP", "IRS_FP64", "IRS_FP32_KAHAN", "EXPORTS"]
+           "learn_params", "mlp_forward", "mlp_loss_grad", "IRS_DIRECT", "IRS_INTERP",
+           "IRS_LEARNED", "IRS_FP64", "IRS_FP32_KAHAN", "IRS_LEARN_NPARAMS", "IRS_LEARN_FIELDS",
+           "EXPORTS"]
 
 load = _ffi.load
 
-_METHODS = {"direct": IRS_DIRECT, "interp": IRS_INTERP}
+_METHODS = {"direct": IRS_DIRECT, "interp": IRS_INTERP, "learned": IRS_LEARNED}
 _PRECISIONS = {"fp64": IRS_FP64, "fp32": IRS_FP32_KAHAN, "fp32_kahan": IRS_FP32_KAHAN}
 
 
@@ -96,6 +100,49 @@ def _vp(a):
 
 def _dev_ptr(t):
     return C.c_void_p(t.data_ptr())
+
+
+def learn_params(**over) -> LearnParams:
+    """Training settings: the library's defaults with keyword overrides."""
+    lib = _ffi.load()
+    lp = LearnParams()
+    _check(lib.irs_learn_defaults(C.byref(lp)), "irs_learn_defaults")
+    for k, v in over.items():
+        if not hasattr(lp, k):
+            raise KeyError(k)
+        setattr(lp, k, v)
+    return lp
+
+
+def _f32(a, n):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.size != n:
+        raise ValueError(f"expected {n} float32 values, got {a.size}")
+    return a
+
+
+def mlp_forward(freqs, theta, h, y, stream=None):
+    """Network outputs into y (device tensor, 16 x n float32) for offsets h
+    (device tensor, 2 x n float32: hx row, then hy row)."""
+    lib = _ffi.load()
+    n = h.shape[-1]
+    fr, th = _f32(freqs, 2 * IRS_LEARN_NFREQ), _f32(theta, IRS_LEARN_NPARAMS)
+    s = None if stream is None else C.c_void_p(int(stream))
+    _check(lib.irs_mlp_forward(int(n), _vp(fr), _vp(th), _dev_ptr(h), _dev_ptr(y), s),
+           "irs_mlp_forward")
+
+
+def mlp_loss_grad(freqs, theta, samples, n, stream=None):
+    """(loss, gradient float32 [IRS_LEARN_NPARAMS]) of the training kernels over
+    n sample records (device tensor, IRS_LEARN_FIELDS x n float32)."""
+    lib = _ffi.load()
+    fr, th = _f32(freqs, 2 * IRS_LEARN_NFREQ), _f32(theta, IRS_LEARN_NPARAMS)
+    g = np.empty(IRS_LEARN_NPARAMS, np.float32)
+    loss = C.c_double()
+    s = None if stream is None else C.c_void_p(int(stream))
+    _check(lib.irs_mlp_loss_grad(int(n), _vp(fr), _vp(th), _dev_ptr(samples), C.byref(loss),
+                                 _vp(g), s), "irs_mlp_loss_grad")
+    return loss.value, g
 
 
 class Plan:
@@ -183,6 +230,52 @@ class Plan:
                                             C.byref(st), fl | IRS_OUT_ON_DEVICE),
                    "irs_shoot_rows")
         return st.as_dict()
+
+    # ---- learned interpolant (method "learned")
+    def learn(self, freqs, lp: LearnParams = None, theta0=None) -> dict:
+        """Train and validate the network (irs_learn); returns the report."""
+        lp = lp if lp is not None else learn_params()
+        fr = _f32(freqs, 2 * IRS_LEARN_NFREQ)
+        th = None if theta0 is None else _f32(theta0, IRS_LEARN_NPARAMS)
+        rep = LearnReport()
+        _check(self._lib.irs_learn(self._h, C.byref(lp), _vp(fr), _vp(th), C.byref(rep)),
+               "irs_learn")
+        return rep.as_dict()
+
+    def learn_set(self, freqs, theta, lp: LearnParams = None) -> dict:
+        """Install a network and validate it (irs_learn_set); returns the report."""
+        lp = lp if lp is not None else learn_params()
+        fr, th = _f32(freqs, 2 * IRS_LEARN_NFREQ), _f32(theta, IRS_LEARN_NPARAMS)
+        rep = LearnReport()
+        _check(self._lib.irs_learn_set(self._h, C.byref(lp), _vp(fr), _vp(th), C.byref(rep)),
+               "irs_learn_set")
+        return rep.as_dict()
+
+    def learn_get(self):
+        """(frequencies (64, 2), parameters, coarse) of the plan's network."""
+        fr = np.empty(2 * IRS_LEARN_NFREQ, np.float32)
+        th = np.empty(IRS_LEARN_NPARAMS, np.float32)
+        qc = C.c_int32()
+        _check(self._lib.irs_learn_get(self._h, _vp(fr), _vp(th), C.byref(qc)), "irs_learn_get")
+        return fr.reshape(IRS_LEARN_NFREQ, 2), th, qc.value
+
+    def learn_corners(self, coarse: int, row0: int, nrows: int) -> np.ndarray:
+        """Corner table of level-1 rows [row0, row0+nrows): complex (A, A') arrays
+        shaped (nrows, n1x, coarse+1, coarse+1)."""
+        g = self.geometry
+        q1 = coarse + 1
+        out = np.empty(nrows * g["n1x"] * q1 * q1 * 4)
+        _check(self._lib.irs_learn_corners(self._h, int(coarse), int(row0), int(nrows), _vp(out)),
+               "irs_learn_corners")
+        o = out.reshape(nrows, g["n1x"], q1, q1, 4)
+        return o[..., 0] + 1j * o[..., 1], o[..., 2] + 1j * o[..., 3]
+
+    def learn_samples(self, coarse: int, row0: int, nrows: int, per_cell: int, seed: int, out):
+        """Exact samples into a device tensor of IRS_LEARN_FIELDS x n float32,
+        n = nrows * n1x * per_cell."""
+        _check(self._lib.irs_learn_samples(self._h, int(coarse), int(row0), int(nrows),
+                                           int(per_cell), int(seed), _dev_ptr(out)),
+               "irs_learn_samples")
 
     def set_direct_variant(self, v: int):
         """FP32 direct tile shape (0, 1, 2); results are identical for all."""

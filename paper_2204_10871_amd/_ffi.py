@@ -8,18 +8,22 @@ LIB_PATH = os.path.join(HERE, "libirs.so")
 IRS_OK, IRS_E_INVALID, IRS_E_CRITICAL, IRS_E_NOMEM, IRS_E_DEVICE, IRS_E_UNSUPPORTED = range(6)
 STATUS_NAMES = {0: "IRS_OK", 1: "IRS_E_INVALID", 2: "IRS_E_CRITICAL", 3: "IRS_E_NOMEM",
                 4: "IRS_E_DEVICE", 5: "IRS_E_UNSUPPORTED"}
-IRS_DIRECT, IRS_INTERP = 0, 1
+IRS_DIRECT, IRS_INTERP, IRS_LEARNED = 0, 1, 2
 IRS_FP64, IRS_FP32_KAHAN = 0, 1
 IRS_SHEET_OFF = 1 << 0
 IRS_LEVEL2_PAPER = 1 << 1
 IRS_OUT_ON_DEVICE = 1 << 8
 IRS_TIME_PHASES = 1 << 9
+IRS_LEARN_NFREQ = 64
+IRS_LEARN_NPARAMS = 68112
+IRS_LEARN_FIELDS = 24
 
 # every function include/irs.h declares
 EXPORTS = ("irs_geometry", "irs_plan", "irs_deflect_grid", "irs_shoot_rows", "irs_shoot_map",
            "irs_plan_set_direct_variant", "irs_plan_geometry", "irs_free", "irs_last_error",
            "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info",
-           "irs_batch_free")
+           "irs_batch_free", "irs_learn_defaults", "irs_learn", "irs_learn_set", "irs_learn_get",
+           "irs_learn_corners", "irs_learn_samples", "irs_mlp_forward", "irs_mlp_loss_grad")
 
 
 class Params(C.Structure):
@@ -53,7 +57,8 @@ class MapStats(C.Structure):
                 ("level2_expand_flops", C.c_double),
                 ("n_level2_launches", C.c_int32),
                 ("n_ray_launches", C.c_int32), ("ms_level2", C.c_double),
-                ("ms_level2_expand", C.c_double), ("ms_rays", C.c_double)]
+                ("ms_level2_expand", C.c_double), ("ms_rays", C.c_double),
+                ("learned", C.c_int32), ("pad_", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -64,6 +69,32 @@ class BatchInfo(C.Structure):
                 ("direct_variant", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("band_rows", C.c_int32), ("tuned", C.c_int32), ("from_cache", C.c_int32),
                 ("work_items", C.c_int64), ("tune_ms", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class LearnParams(C.Structure):
+    _fields_ = [("coarse", C.c_int32), ("train_rows", C.c_int32), ("n_samples", C.c_int64),
+                ("n_val", C.c_int64), ("batch", C.c_int32), ("steps", C.c_int32),
+                ("lr", C.c_float), ("lr_final", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("adam_eps", C.c_float), ("pad_", C.c_int32),
+                ("seed", C.c_uint64), ("tol_mean", C.c_double), ("tol_p9999", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad_"}
+
+
+class LearnReport(C.Structure):
+    _fields_ = [("n_samples", C.c_int64), ("n_val", C.c_int64), ("steps", C.c_int64),
+                ("loss_first", C.c_double), ("loss_last", C.c_double),
+                ("val_mean_abs", C.c_double), ("val_p9999_abs", C.c_double),
+                ("val_max_abs", C.c_double), ("base_mean_abs", C.c_double),
+                ("base_p9999_abs", C.c_double), ("base_max_abs", C.c_double),
+                ("tol_mean", C.c_double), ("tol_p9999", C.c_double), ("fallback", C.c_int32),
+                ("coarse", C.c_int32), ("ms_samples", C.c_double), ("ms_train", C.c_double),
+                ("ms_validate", C.c_double), ("corner_bytes_per_row", C.c_int64),
+                ("coef_bytes_per_row", C.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -105,13 +136,24 @@ def load():
     lib.irs_batch_get_info.argtypes = [vp, P(BatchInfo)]
     lib.irs_batch_free.argtypes = [vp]
     lib.irs_batch_free.restype = None
+    i32 = C.c_int32
+    lib.irs_learn_defaults.argtypes = [P(LearnParams)]
+    lib.irs_learn.argtypes = [vp, P(LearnParams), vp, vp, P(LearnReport)]
+    lib.irs_learn_set.argtypes = [vp, P(LearnParams), vp, vp, P(LearnReport)]
+    lib.irs_learn_get.argtypes = [vp, vp, vp, P(i32)]
+    lib.irs_learn_corners.argtypes = [vp, i32, i64, i64, vp]
+    lib.irs_learn_samples.argtypes = [vp, i32, i64, i64, i32, u64, vp]
+    lib.irs_mlp_forward.argtypes = [i64, vp, vp, vp, vp, vp]
+    lib.irs_mlp_loss_grad.argtypes = [i64, vp, vp, vp, P(C.c_double), vp, vp]
     lib.irs_free.argtypes = [vp]
     lib.irs_free.restype = None
     lib.irs_last_error.argtypes = []
     lib.irs_last_error.restype = C.c_char_p
     for name in ("irs_geometry", "irs_plan", "irs_deflect_grid", "irs_shoot_rows",
                  "irs_shoot_map", "irs_plan_geometry", "irs_plan_set_direct_variant",
-                 "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info"):
+                 "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info",
+                 "irs_learn_defaults", "irs_learn", "irs_learn_set", "irs_learn_get",
+                 "irs_learn_corners", "irs_learn_samples", "irs_mlp_forward", "irs_mlp_loss_grad"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -264,6 +264,10 @@ irs_status irs_batch_create(const irs_plan_t *plans, int32_t n, void *hip_stream
             return IRS_E_INVALID;
         }
     const irs_plan_s *p0 = plans[0];
+    if (p0->params.method != IRS_DIRECT && p0->params.method != IRS_INTERP) {
+        set_error("irs_batch_create: batches take IRS_DIRECT or IRS_INTERP plans");
+        return IRS_E_UNSUPPORTED;
+    }
     for (int k = 1; k < n; ++k) {
         const irs_plan_s *p = plans[k];
         if (p->params.method != p0->params.method || p->params.precision != p0->params.precision ||

@@ -113,6 +113,7 @@ void release(irs_plan_s *p)
     dev_free(p->d_counts);
     dev_free(p->d_tmp);
     dev_free(p->d_landed);
+    learn_release(p);
     delete p;
 }
 
@@ -130,6 +131,7 @@ irs_status ensure_tmp(irs_plan_s *p, size_t bytes)
 irs_status run(irs_plan_s *p, const RaySel &sel)
 {
     if (p->params.method == IRS_DIRECT) return launch_direct(p, sel);
+    if (p->params.method == IRS_LEARNED) return launch_learned(p, sel);
     return launch_interp(p, sel);
 }
 
@@ -374,6 +376,7 @@ static irs_status shoot(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t *
         stats->n_lens = plan->n_lens;
         stats->kappa_star_eff = plan->kappa_star_eff;
         stats->ms_total = ms;
+        stats->learned = (plan->params.method == IRS_LEARNED && plan->learn_ok) ? 1 : 0;
     }
     set_error("");
     return IRS_OK;

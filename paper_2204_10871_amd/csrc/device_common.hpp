@@ -60,6 +60,20 @@ __device__ __forceinline__ int64_t level2_row(const DevGeom &g, int64_t j)
 //   I2 = sum sign * [ u/2 ln(u^2+v^2) + v atan(u/v) ]
 // (p atan(q/p) and p ln(.) are taken as 0 where p = 0).  The negative sheet's
 // deflection is -(kappa_*/pi) (I1, I2).
+// Argument of w = u + i v for the sheet's Log(z - c_k), with the cut pointing
+// away from the rectangle: up from a top corner (result in (-3 pi/2, pi/2]),
+// down from a bottom corner (in (-pi/2, 3 pi/2]).  Inside the rectangle this
+// is the principal argument; points on an edge, or a rounding step outside
+// it, continue the interior values instead of crossing the principal cut,
+// which runs along the top and bottom edges.
+__device__ __forceinline__ double log_arg(double u, double v, bool top)
+{
+    double th = atan2(v, u);
+    if (top && th > 0.5 * M_PI) th -= 2.0 * M_PI;
+    if (!top && th < -0.5 * M_PI) th += 2.0 * M_PI;
+    return th;
+}
+
 __device__ __forceinline__ void sheet_unit(const DevGeom &g, double t1, double t2,
                                            double &I1, double &I2)
 {

@@ -34,8 +34,8 @@ irs_status derive_geometry(const irs_params &p, int64_t n_lens, HostGeometry &ou
         err = "n_lens must be in [0, 2^31)";
         return IRS_E_INVALID;
     }
-    if (p.method != IRS_DIRECT && p.method != IRS_INTERP) {
-        err = "method must be IRS_DIRECT or IRS_INTERP";
+    if (p.method != IRS_DIRECT && p.method != IRS_INTERP && p.method != IRS_LEARNED) {
+        err = "method must be IRS_DIRECT, IRS_INTERP or IRS_LEARNED";
         return IRS_E_UNSUPPORTED;
     }
     if (p.precision != IRS_FP64 && p.precision != IRS_FP32_KAHAN) {

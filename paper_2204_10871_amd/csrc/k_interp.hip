@@ -1,4 +1,4 @@
-// Three-level-grid interpolation (Sec. 2.3 and the flow chart of Sec. 2.4).
+// Three-level-grid interpolation (Sec. 2.4 and its flow chart).
 //
 // Level 1: lenses are packed into n1x x n1y cells (k_level1.hip).  For a ray
 // or level-2 point in cell (cx, cy) the lenses of the 3 x 3 block of cells
@@ -32,7 +32,7 @@
 #include <cmath>
 #include <vector>
 
-#include "plan.hpp"
+#include "level2.hpp"
 
 namespace irs {
 
@@ -86,7 +86,7 @@ __device__ void sheet_coeffs(const DevGeom &g, double x0, double y0, cplx out[5]
         const double u = x0 - a, v = y0 - b;
         const double d2 = u * u + v * v;
         lr += sgn * 0.5 * log(d2);
-        li += sgn * atan2(v, u);
+        li += sgn * log_arg(u, v, c >= 2);
         const cplx w = {u / d2, -v / d2};        // 1/(z0 - c)
         const cplx w2 = cmul(w, w), w3 = cmul(w2, w);
         y2.r += sgn * w.r;          y2.i += sgn * w.i;            // n = 2: +0!/(z-c)
@@ -217,9 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_level2(
 // tiles are staged in LDS once for the four waves; each lane takes four lenses
 // of a tile.  The expansions are reduced across lanes with shuffles.
 // -------------------------------------------------------------------------
-constexpr int kRing = 3;                       // R: expansion excludes the 7 x 7 block
 constexpr int kCellsPerBlock = kThreads / kWave;
-constexpr int kChunkLens = 65536;              // lenses per partial expansion
 
 // 1/d for d > 0: hardware reciprocal estimate refined by two Newton steps
 // (error ~1 ulp; the IEEE division sequence is not needed here)
@@ -633,6 +631,8 @@ int64_t level2_row_host(const DevGeom &g, int64_t j)
     return ((2 * j + 1) * (int64_t)g.n1y * g.q) / (2 * g.ny);
 }
 
+}  // namespace
+
 // Expansion order of the per-cell local expansion (0: sum at every point as
 // in the paper).  The expansion about a cell centre converges over the cell
 // with ratio rho = (half diagonal)/((R + 1/2) * shorter side); the truncation
@@ -650,8 +650,6 @@ int level2_order(const irs_plan_s *p)
     return 0;
 }
 
-}  // namespace
-
 namespace {
 
 int64_t level2_row_bytes(const irs_plan_s *p)
@@ -663,6 +661,26 @@ int64_t level2_row_bytes(const irs_plan_s *p)
 int64_t band_rows(const irs_plan_s *p)
 {
     return std::min<int64_t>(p->dg.n1y, std::max<int64_t>(1, p->coef_budget / level2_row_bytes(p)));
+}
+
+// partial-expansion buffer for `rows` level-1 rows
+irs_status ensure_part(irs_plan_s *p, int64_t rows)
+{
+    const int P = level2_order(p);
+    if (P <= 0) return IRS_OK;
+    const size_t need = (size_t)rows * p->dg.n1x * level2_chunks(p) * P * 2 * sizeof(double);
+    if (p->part_bytes < need) {
+        dev_free(p->d_part);
+        p->d_part = nullptr;
+        p->part_bytes = 0;
+        if (hipMalloc(&p->d_part, need) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("cannot allocate the level-2 partial expansions");
+            return IRS_E_NOMEM;
+        }
+        p->part_bytes = need;
+    }
+    return IRS_OK;
 }
 
 // coefficient and partial-expansion buffers for bands of `rows` level-1 rows
@@ -681,26 +699,40 @@ irs_status ensure_bands(irs_plan_s *p, int64_t rows)
         }
         p->coef_rows_cap = rows;
     }
-    const int P = level2_order(p);
-    if (P > 0) {
-        const int32_t nchunk = std::max<int32_t>(1, (int32_t)((p->n_lens + kChunkLens - 1) / kChunkLens));
-        const size_t need = (size_t)p->coef_rows_cap * p->dg.n1x * nchunk * P * 2 * sizeof(double);
-        if (p->part_bytes < need) {
-            dev_free(p->d_part);
-            p->d_part = nullptr;
-            p->part_bytes = 0;
-            if (hipMalloc(&p->d_part, need) != hipSuccess) {
-                (void)hipGetLastError();
-                set_error("cannot allocate the level-2 partial expansions");
-                return IRS_E_NOMEM;
-            }
-            p->part_bytes = need;
-        }
-    }
-    return IRS_OK;
+    return ensure_part(p, p->coef_rows_cap);
 }
 
 }  // namespace
+
+irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1)
+{
+    const int P = level2_order(p);
+    if (P <= 0) {
+        set_error("the per-cell expansion is not used by this plan");
+        return IRS_E_UNSUPPORTED;
+    }
+    irs_status st = ensure_part(p, c1 - c0 + 1);
+    if (st != IRS_OK) return st;
+    const DevGeom &g = p->dg;
+    const int32_t nl = (int32_t)p->n_lens;
+    const int32_t nxb = (g.n1x + kCellsPerBlock - 1) / kCellsPerBlock;
+    const int32_t nchunk = level2_chunks(p);
+    const unsigned nb = (unsigned)((c1 - c0 + 1) * nxb * nchunk);
+#define IRS_L2E(U, PP)                                                                    \
+    hipLaunchKernelGGL((k_level2_expand<U, PP>), dim3(nb), dim3(kThreads), 0, p->stream, g, \
+                       p->d_x, p->d_y, p->d_m, p->d_cxy, nl, (int32_t)c0, nxb, nchunk,   \
+                       kChunkLens, p->d_part)
+    if (p->unit_mass) {
+        if (P == 32) IRS_L2E(true, 32);
+        else IRS_L2E(true, 48);
+    } else {
+        if (P == 32) IRS_L2E(false, 32);
+        else IRS_L2E(false, 48);
+    }
+#undef IRS_L2E
+    IRS_HIP(hipGetLastError());
+    return IRS_OK;
+}
 
 irs_status interp_prepare(irs_plan_s *p)
 {

@@ -56,6 +56,18 @@ struct irs_plan_s {
     double *d_part = nullptr;             // per-(cell, lens chunk) partial expansions
     size_t part_bytes = 0;
 
+    // Learned interpolant (IRS_LEARNED): network, validation verdict and the
+    // corner table of one band of level-1 rows (4 doubles per corner:
+    // Re A, Im A, Re A', Im A'; (qc + 1)^2 corners per cell).
+    int learn_qc = 0;                     // squares per cell side; 0: no network
+    bool learn_ok = false;                // validated; false: grid fallback
+    float *d_theta = nullptr;             // FP32 parameters
+    float *d_freqs = nullptr;             // 64 x 2
+    void *d_wfwd = nullptr;               // BF16 forward fragments
+    double *d_corner = nullptr;
+    int64_t corner_rows_cap = 0;
+    int64_t corner_c0 = -1, corner_c1 = -2;
+
     // Scratch for host-side outputs.
     uint32_t *d_counts = nullptr;  // npix^2, used when counts are on the host
     unsigned long long *d_landed = nullptr;   // rays binned by the current call
@@ -116,6 +128,8 @@ struct RaySel {
 
 irs_status launch_direct(irs_plan_s *p, const RaySel &sel);
 irs_status launch_interp(irs_plan_s *p, const RaySel &sel);
+irs_status launch_learned(irs_plan_s *p, const RaySel &sel);
+void learn_release(irs_plan_s *p);
 
 // FP32 direct tile shapes: rays per lane x lenses per LDS stage.
 constexpr int kDirectVariants = 3;

@@ -88,3 +88,20 @@ def test_plan_rejects_bad_lenses_before_device(irs):
     with pytest.raises(irs.IrsError) as e:
         irs.Plan(p, np.array([0.0]), np.array([0.0]), m=np.array([-1.0]))
     assert e.value.status == 1
+
+
+def test_learned_entry_points_reject_bad_arguments(irs):
+    """Argument checks of the learned interpolant's entry points (no device work)."""
+    import ctypes as C
+    from paper_2204_10871_amd import _ffi
+    lib = irs.load()
+    lp = irs.learn_params()
+    assert lp.coarse == 4 and lp.batch % 256 == 0
+    rep = _ffi.LearnReport()
+    assert lib.irs_learn(None, C.byref(lp), None, None, C.byref(rep)) == 1
+    assert lib.irs_learn_set(None, None, None, None, None) == 1
+    assert lib.irs_learn_get(None, None, None, None) == 1
+    assert lib.irs_learn_corners(None, 3, 0, 1, None) == 1
+    assert lib.irs_learn_samples(None, 3, 0, 1, 1, 0, None) == 1
+    assert lib.irs_mlp_forward(-1, None, None, None, None, None) == 1
+    assert lib.irs_mlp_loss_grad(0, None, None, None, None, None, None) == 1

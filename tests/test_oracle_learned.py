@@ -198,3 +198,22 @@ def test_far_point_derivative_and_analyticity(far_case):
     scale = np.max(np.abs(dA))
     assert np.max(np.abs(Ax - dA)) < 1e-7 * scale
     assert np.max(np.abs(Ay - 1j * dA)) < 1e-7 * scale
+
+
+def test_far_point_continuous_on_the_edges(far_case):
+    """Corner points of the top and bottom cell rows lie on the rectangle's
+    edges (or a rounding step outside).  The field there must continue the
+    interior values: the principal Log's cut runs along those edges, so it
+    is taken pointing away from the rectangle instead."""
+    g, L, cs, perm = far_case
+    cx = np.arange(1, g.n1x - 1)
+    x = g.a1 + (cx + 0.37) * (g.a2 - g.a1) / g.n1x
+    for cy, yb, sgn in ((g.n1y - 1, g.b2, -1.0), (0, g.b1, 1.0)):
+        cyv = np.full_like(cx, cy)
+        A_e, dA_e = orc.far_point(g, L, cs, perm, cx, cyv, x, np.full(x.size, yb))
+        A_o, dA_o = orc.far_point(g, L, cs, perm, cx, cyv, x, np.full(x.size, yb - sgn * 1e-12))
+        A_i, dA_i = orc.far_point(g, L, cs, perm, cx, cyv, x, np.full(x.size, yb + sgn * 1e-7))
+        scale = np.max(np.abs(dA_i))
+        assert np.max(np.abs(dA_e - dA_i)) < 1e-5 * scale
+        assert np.max(np.abs(dA_o - dA_i)) < 1e-5 * scale
+        assert np.max(np.abs(A_e - A_i)) < 1e-5 * max(1.0, np.max(np.abs(A_i)))
