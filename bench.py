@@ -58,6 +58,90 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def bench_learned(irs, synth, torch, stream, args, result):
+    """The learned interpolant on its workload (kappa_* = gamma = 0.5,
+    kappa_c = 0.05, N_* = 1e6 unit lenses, 8192^2 px, 100 rays/px): training,
+    validation, three level-1 row bands timed against the grid interpolation
+    on the same bands, and a ray sample judged by the oracle's direct sum."""
+    import numpy as np
+    import oracle as orc
+    w = synth.configs.CFG5
+    pL = irs.params_from_workload(w, method="learned", precision="fp64")
+    pI = irs.params_from_workload(w, method="interp", precision="fp64")
+    g0 = irs.geometry(pL, 0)
+    L = synth.uniform_lenses(g0["n_stars_expected"], (g0["a1"], g0["a2"], g0["b1"], g0["b2"]),
+                             w.seed)
+    out = {"workload": "kappa*=0.5 kappa_c=0.05 gamma=0.5, N*=1e6 unit, S=532.16, 8192^2 px, "
+                       "N_av=100 (6.7e9 rays)", "n_star": L.n}
+    npix = w.npix
+    counts = torch.zeros(npix * npix, dtype=torch.int32, device="cuda:0")
+    with irs.Plan(pL, L.x, L.y, L.m, stream=stream.cuda_stream) as pl, \
+            irs.Plan(pI, L.x, L.y, L.m, stream=stream.cuda_stream) as pi:
+        G = pl.geometry
+        t0 = time.perf_counter()
+        rep = pl.learn(synth.network.fourier_frequencies(7), irs.learn_params())
+        out["learn_seconds"] = time.perf_counter() - t0
+        out["report"] = rep
+        log(f"learned: trained in {out['learn_seconds']:.1f} s, val mean |err| "
+            f"{rep['val_mean_abs']:.2e} (grid alone {rep['base_mean_abs']:.2e}, tol "
+            f"{rep['tol_mean']:.2e}), fallback {rep['fallback']}")
+        c_mid = G["n1y"] // 2
+        bands = [pl.level1_row_rays(c) for c in (c_mid, c_mid + 1, c_mid + 2)]
+        warm = pl.level1_row_rays(c_mid - 1)
+        res = {}
+        for name, plan in (("learned", pl), ("interp", pi)):
+            plan.shoot_rows(warm[0], warm[1] - warm[0], counts)
+            torch.cuda.synchronize()
+            ms, ms2, ms3, rays = 0.0, 0.0, 0.0, 0
+            for j0, j1 in bands:
+                st = plan.shoot_rows(j0, j1 - j0, counts, time_phases=True)
+                ms += st["ms_total"]
+                ms2 += st["ms_level2"]
+                ms3 += st["ms_rays"]
+                rays += st["rays_shot"]
+            res[name] = {"ms_per_band": ms / len(bands), "ms_level2_per_band": ms2 / len(bands),
+                         "ms_rays_per_band": ms3 / len(bands), "rays_per_s": rays / (ms * 1e-3),
+                         "full_map_seconds": ms / len(bands) * 1e-3 * G["n1y"]}
+            log(f"{name}: {ms / len(bands):.2f} ms/band (level-2 {ms2 / len(bands):.2f}, "
+                f"rays {ms3 / len(bands):.2f}), {rays / (ms * 1e-3):.3e} rays/s")
+        out.update(res)
+        # judge: the direct definition on a ray sample of the first band
+        og = orc.geometry(w.kappa_star, w.kappa_c, w.gamma, w.source_side, w.npix,
+                          rays_per_pixel=w.rays_per_pixel, n_lens=L.n)
+        j0, j1 = bands[0]
+        rng = np.random.default_rng(11)
+        nsamp = max(256, args.cpu_sample // 4)
+        ids = np.sort(rng.choice((j1 - j0) * G["nx"], nsamp, replace=False)) + j0 * G["nx"]
+        threads = min(16, os.cpu_count() or 1)
+        ref = orc.shoot_direct(og, L, ray_ids=ids, threads=threads, want_counts=False)
+        for name, plan in (("learned", pl), ("interp", pi)):
+            n = (j1 - j0) * G["nx"]
+            a1 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+            a2 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+            px = torch.empty(n, dtype=torch.int64, device="cuda:0")
+            plan.deflect_grid_device(j0 * G["nx"], n, a1, a2, px)
+            sel = torch.as_tensor(ids - j0 * G["nx"], device="cuda:0")
+            g1, g2, gp = a1[sel].cpu().numpy(), a2[sel].cpu().numpy(), px[sel].cpu().numpy()
+            d = np.hypot(g1 - ref["alpha1"], g2 - ref["alpha2"])
+            rel = d / np.hypot(ref["alpha1"], ref["alpha2"])
+            mis = int(np.sum(gp != ref["pix"]))
+            out[name]["judge"] = {"rays": int(nsamp), "max_abs_alpha_err": float(d.max()),
+                                  "mean_abs_alpha_err": float(d.mean()),
+                                  "max_rel_alpha_err": float(rel.max()),
+                                  "pixel_mismatches": mis}
+            log(f"{name} vs direct on {nsamp} rays: max |d alpha| {d.max():.2e}, "
+                f"pixel mismatches {mis}")
+        direct = result.get("direct_fp32", {}).get("interactions_per_s")
+        if direct:
+            t_direct = G["nx"] * G["ny"] * L.n / direct
+            out["direct_fp32_full_map_seconds_estimated"] = t_direct
+            for name in ("learned", "interp"):
+                out[name]["speedup_over_direct"] = t_direct / out[name]["full_map_seconds"]
+        out["coefficient_bytes_per_level1_row"] = {"learned": rep["corner_bytes_per_row"],
+                                                   "interp": rep["coef_bytes_per_row"]}
+    return out
+
+
 def bench_batch(irs, synth, torch, stream):
     """The 64-map batch (kappa_*, gamma ~ U[0.1, 0.8], kappa_c in {0, 0.2},
     N_* = 10^U[3, 5], 1024^2..4096^2 px, 100 rays/px), interpolated: one tuned
@@ -113,12 +197,14 @@ def main():
     ap.add_argument("--direct-rows", type=int, default=64)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-map batch measurement")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-interpolant measurement (N_* = 1e6, 8192^2 px)")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="run a plain 512 MiB device copy first (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md, 'How the path would shard'); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -263,6 +349,8 @@ def main():
         log(f"direct fp32: {pairs / td:.3e} pairs/s, {tf:.1f} TFLOP/s")
 
     plan.close()
+    if not args.no_learned:
+        result["learned"] = bench_learned(irs, synth, torch, stream, args, result)
     if not args.no_batch:
         result["batch"] = bench_batch(irs, synth, torch, stream)
     print(json.dumps(result), flush=True)

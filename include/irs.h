@@ -338,8 +338,8 @@ typedef struct {
     int64_t coef_bytes_per_row;         /* grid-interpolation table per row       */
 } irs_learn_report;
 
-/* irs_learn_defaults -- default training settings (coarse 4, 2e6 samples over 8
-   rows, 2e5 validation samples, batch 8192, 3000 steps, lr 2e-3 -> 2e-5). */
+/* irs_learn_defaults -- default training settings (coarse 16, 2e6 samples over 8
+   rows, 2e5 validation samples, batch 8192, 6000 steps, lr 2e-3 -> 2e-5). */
 irs_status irs_learn_defaults(irs_learn_params *out);
 
 /*

@@ -1372,12 +1372,12 @@ irs_status irs_learn_defaults(irs_learn_params *out)
         return IRS_E_INVALID;
     }
     irs_learn_params d{};
-    d.coarse = 4;
+    d.coarse = 16;
     d.train_rows = 8;
     d.n_samples = 2000000;
     d.n_val = 200000;
     d.batch = 8192;
-    d.steps = 3000;
+    d.steps = 6000;
     d.lr = 2e-3f;
     d.lr_final = 2e-5f;
     d.beta1 = 0.9f;

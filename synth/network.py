@@ -16,9 +16,10 @@ def normals(seed: int, stream: int, n: int) -> np.ndarray:
     return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u[1::2])
 
 
-def fourier_frequencies(seed: int = 31, scale: float = 1.0) -> np.ndarray:
+def fourier_frequencies(seed: int = 31, scale: float = 0.25) -> np.ndarray:
     """(64, 2) float32 frequencies, each component normal with std `scale`
-    (cycles per unit of the in-square offset)."""
+    (cycles per unit of the in-square offset; the interpolation weights are
+    smooth over a square, so low frequencies serve best)."""
     return (normals(seed, 11, 2 * N_FREQ) * scale).reshape(N_FREQ, 2).astype(np.float32)
 
 

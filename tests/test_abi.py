@@ -96,7 +96,7 @@ def test_learned_entry_points_reject_bad_arguments(irs):
     from paper_2204_10871_amd import _ffi
     lib = irs.load()
     lp = irs.learn_params()
-    assert lp.coarse == 4 and lp.batch % 256 == 0
+    assert 1 <= lp.coarse <= 32 and lp.batch % 256 == 0 and lp.steps > 0
     rep = _ffi.LearnReport()
     assert lib.irs_learn(None, C.byref(lp), None, None, C.byref(rep)) == 1
     assert lib.irs_learn_set(None, None, None, None, None) == 1

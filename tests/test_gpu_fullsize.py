@@ -107,3 +107,19 @@ def test_4096_map_bands(irs, which):
                 j0 = pl.geometry["ny"] // 2 // 16 * 16
                 j1 = j0 + 16
             _band_check(irs, pl, j0, j1, og, L, 1500, tol)
+
+
+def test_1e6_lens_learned_band(irs):
+    """The learned interpolant at its full-size workload (kappa_* = gamma = 0.5,
+    kappa_c = 0.05, 1e6 unit lenses, 8192^2 px, 100 rays/px): trained with the
+    default settings, then one level-1 row band checked as above."""
+    w = synth.configs.CFG5
+    p, L, og = _workload(irs, w, "learned", "fp64")
+    with irs.Plan(p, L.x, L.y, L.m) as pl:
+        rep = pl.learn(synth.network.fourier_frequencies(7), irs.learn_params())
+        say(f"learned 1e6: val mean {rep['val_mean_abs']:.2e} (grid alone {rep['base_mean_abs']:.2e},"
+            f" tol {rep['tol_mean']:.2e}), p99.99 {rep['val_p9999_abs']:.2e}, "
+            f"fallback {rep['fallback']}, train {rep['ms_train']:.0f} ms")
+        assert rep["fallback"] == 0
+        j0, j1 = pl.level1_row_rays(pl.geometry["n1y"] // 2 + 1)
+        _band_check(irs, pl, j0, j1, og, L, 1500, 1e-4)

@@ -170,8 +170,8 @@ def test_samples_match_oracle(irs):
     assert eD < 1e-6 and eT < 1e-5 * max(1.0, np.abs(T).max()) and es < 1e-6
 
 
-LEARN_SMALL = dict(coarse=3, train_rows=6, n_samples=200_000, n_val=50_000, batch=4096,
-                   steps=1500, lr=2e-3, lr_final=2e-5)
+LEARN_SMALL = dict(coarse=12, train_rows=6, n_samples=500_000, n_val=50_000, batch=8192,
+                   steps=3000, lr=2e-3, lr_final=2e-5)
 
 
 @pytest.fixture(scope="module")
@@ -179,7 +179,7 @@ def trained(irs):
     """A small learned plan, trained once for the tests below."""
     p, L, og = _plan(irs, S=10.0, npix=96, n_rays=400_000)
     pl = irs.Plan(p, L.x, L.y, L.m)
-    fr = synth.network.fourier_frequencies(7, 1.0)
+    fr = synth.network.fourier_frequencies(7)
     rep = pl.learn(fr, irs.learn_params(**LEARN_SMALL))
     say("training report: " + ", ".join(f"{k}={v:.4g}" if isinstance(v, float) else f"{k}={v}"
                                        for k, v in rep.items()))
@@ -188,12 +188,15 @@ def trained(irs):
 
 
 def test_training_reduces_loss_and_beats_base(trained):
+    """The gain: on the same coarse grid (12 x 12 squares per level-1 cell,
+    169 exact corner values against the paper's 400 level-2 points) the grid
+    alone misses the tolerance many times over; with the network it meets it."""
     pl, p, L, og, rep = trained
-    assert rep["loss_last"] < 0.1 * rep["loss_first"]
-    # the gain: on the same coarse grid the network's interpolant is much
-    # closer to the exact distant field than the grid alone
-    assert rep["val_mean_abs"] < 0.2 * rep["base_mean_abs"]
-    assert rep["val_p9999_abs"] < rep["base_p9999_abs"]
+    assert rep["loss_last"] < 0.01 * rep["loss_first"]
+    assert rep["val_mean_abs"] < 0.05 * rep["base_mean_abs"]
+    assert rep["val_p9999_abs"] < 0.05 * rep["base_p9999_abs"]
+    assert rep["base_mean_abs"] > 10 * rep["tol_mean"]
+    assert rep["fallback"] == 0
 
 
 def test_learned_rays_match_oracle_and_direct(irs, trained):
