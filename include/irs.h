@@ -143,6 +143,8 @@ typedef struct {
     int32_t learned;              /* IRS_LEARNED plans: 1 if the network was used,    */
                                   /* 0 if the grid-interpolation fallback was          */
     int32_t pad_;
+    double  ray_flops;            /* algorithmic FP64 flops of the level-3 launches   */
+                                  /* (interpolation; 46 per ray + 10 per near lens)   */
 } irs_map_stats;
 
 /*

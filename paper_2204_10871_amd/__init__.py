@@ -215,6 +215,14 @@ class Plan:
         _check(self._lib.irs_shoot_map(self._h, _vp(counts), C.byref(st), fl), "irs_shoot_map")
         return counts.reshape(npix, npix), st.as_dict()
 
+    def shoot_map_device(self, counts, time_phases=False):
+        """Full map into a device tensor of npix^2 32-bit integers (overwritten).
+        Returns the stats dict."""
+        st = MapStats()
+        fl = IRS_OUT_ON_DEVICE | (IRS_TIME_PHASES if time_phases else 0)
+        _check(self._lib.irs_shoot_map(self._h, _dev_ptr(counts), C.byref(st), fl), "irs_shoot_map")
+        return st.as_dict()
+
     def shoot_rows(self, row0: int, nrows: int, counts, time_phases=False):
         """Add rows [row0, row0+nrows) into counts: a host uint32 array or a
         device tensor of npix^2 32-bit integers.  Returns the stats dict."""

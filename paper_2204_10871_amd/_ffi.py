@@ -58,7 +58,7 @@ class MapStats(C.Structure):
                 ("n_level2_launches", C.c_int32),
                 ("n_ray_launches", C.c_int32), ("ms_level2", C.c_double),
                 ("ms_level2_expand", C.c_double), ("ms_rays", C.c_double),
-                ("learned", C.c_int32), ("pad_", C.c_int32)]
+                ("learned", C.c_int32), ("pad_", C.c_int32), ("ray_flops", C.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "plan.hpp"
+#include "level2.hpp"
 
 namespace irs {
 
@@ -110,6 +110,8 @@ void release(irs_plan_s *p)
     dev_free(p->d_cxy);
     dev_free(p->d_coef);
     dev_free(p->d_part);
+    dev_free(p->d_super);
+    dev_free(p->d_super_part);
     dev_free(p->d_counts);
     dev_free(p->d_tmp);
     dev_free(p->d_landed);
@@ -370,6 +372,7 @@ static irs_status shoot(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t *
         stats->n_ray_launches = cs.n_rays;
         stats->ms_level2 = cs.ms_level2;
         stats->ms_rays = cs.ms_rays;
+        stats->ray_flops = cs.ray_flops;
         stats->rays_shot = nrows * g.nx;
         stats->rays_landed = (int64_t)landed;
         stats->rays_off = stats->rays_shot - stats->rays_landed;
@@ -395,6 +398,7 @@ irs_status irs_shoot_map(irs_plan_t plan, uint32_t *counts, irs_map_stats *stats
         set_error("irs_shoot_map: NULL plan");
         return IRS_E_INVALID;
     }
+    level2_reset(plan);          // a whole map computes every far-field expansion itself
     return shoot(plan, 0, plan->geo.info.ny, counts, stats, flags, true, "irs_shoot_map");
 }
 

@@ -324,6 +324,270 @@ __global__ __launch_bounds__(kThreads) void k_level2_expand(
     }
 }
 
+// -------------------------------------------------------------------------
+// Two-level distant field.  The distant lenses of a cell (outside its 7 x 7
+// block) are those outside the (2 R_S + 1)^2 block of super cells around the
+// cell's super cell (K_S x K_S level-1 cells each) plus those inside that
+// block but outside the 7 x 7 block.  The former are summed once per super
+// cell into an expansion of order PS about its centre zS, scale sS:
+//     (1/sS) sum_n E_n u^n,  u = (z - zS)/sS,
+//     E_n = sum_i m_i (-1)^n (sS/(zS - z_i))^(n+1),
+// which converges over the super cell with ratio rho_S = (super half
+// diagonal)/((R_S + 1/2) K_S * shortest cell side).  It is translated to each
+// of its cells (re-expansion about the cell centre: with d = (zc - zS)/sS,
+//     Lt_k += (s/sS)^(k+1) sum_{n>=k} C(n,k) E_n d^(n-k)),
+// and the latter, at most (2 R_S + 1)^2 K_S^2 cells of lenses, are summed into
+// Lt per cell directly.  The cell expansion is the same series as summing all
+// distant lenses into it, to FP64 rounding; the work per cell drops from N_*
+// lenses to about (2 R_S + 1)^2 K_S^2 lenses plus N_* / K_S^2.
+// -------------------------------------------------------------------------
+constexpr int kSuperK = 8;                     // level-1 cells per super-cell side
+constexpr int kSuperR = 2;                     // R_S
+
+__device__ __forceinline__ void super_centre(const DevGeom &g, int32_t X, int32_t Y, double &zr,
+                                             double &zi, double &sS)
+{
+    zr = g.a1 + ((double)(kSuperK * X) + 0.5 * kSuperK) * g.w1;
+    zi = g.b1 + ((double)(kSuperK * Y) + 0.5 * kSuperK) * g.h1;
+    sS = kSuperK * fmax(g.w1, g.h1);
+}
+
+// partial super expansions: one wave per super cell, four per workgroup,
+// lenses of one chunk; part[(((Y nSx + X) nchunk + chunk) PS + n) 2 + c]
+template <bool UNIT, int PS>
+__global__ __launch_bounds__(kThreads) void k_super_expand(
+    DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
+    const double *__restrict__ lm, const uint32_t *__restrict__ lcxy, int32_t nl, int32_t Y0,
+    int32_t nSx, int32_t nSxb, int32_t nchunk, int32_t chunk_len, double *__restrict__ part)
+{
+    __shared__ double s_x[kThreads], s_y[kThreads], s_m[UNIT ? 1 : kThreads];
+    __shared__ uint32_t s_c[kThreads];
+    const int tid = threadIdx.x;
+    const int lane = tid % kWave, wave = tid / kWave;
+    const int32_t group = (int32_t)(blockIdx.x / (uint32_t)nchunk);
+    const int32_t chunk = (int32_t)(blockIdx.x % (uint32_t)nchunk);
+    const int32_t Y = Y0 + group / nSxb;
+    const int32_t X = (group % nSxb) * kCellsPerBlock + wave;
+    const bool live = X < nSx;
+    double zr, zi, sS;
+    super_centre(g, X, Y, zr, zi, sS);
+    const double isc = 1.0 / sS;
+    const int32_t lo = chunk * chunk_len;
+    const int32_t hi = min(nl, lo + chunk_len);
+    double Lr[PS], Li[PS];
+#pragma unroll
+    for (int n = 0; n < PS; ++n) Lr[n] = Li[n] = 0.0;
+    for (int32_t base = lo; base < hi; base += kThreads) {
+        __syncthreads();
+        if (base + tid < hi) {
+            s_x[tid] = lx[base + tid];
+            s_y[tid] = ly[base + tid];
+            if (!UNIT) s_m[tid] = lm[base + tid];
+            s_c[tid] = lcxy[base + tid];
+        }
+        __syncthreads();
+        const int cnt = min(kThreads, hi - base);
+#pragma unroll
+        for (int k = 0; k < kThreads / kWave; k += 2) {
+            double tr[2], ti[2], vr[2], vi[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int t = lane + (k + e) * kWave;
+                bool use = live && t < cnt;
+                double Xl = zr + sS, Yl = zi, M = 0.0;     // harmless stand-in
+                if (use) {
+                    const uint32_t c = s_c[t];
+                    const int32_t sx = (int32_t)(c & 0xffffu) / kSuperK, sy = (int32_t)(c >> 16) / kSuperK;
+                    use = abs(sx - X) > kSuperR || abs(sy - Y) > kSuperR;
+                    if (use) {
+                        Xl = s_x[t];
+                        Yl = s_y[t];
+                        M = UNIT ? 1.0 : s_m[t];
+                    }
+                }
+                const double wr = (zr - Xl) * isc, wi = (zi - Yl) * isc;
+                const double inv = rcp64(wr * wr + wi * wi);
+                const double ur = wr * inv, ui = -wi * inv;
+                tr[e] = M * ur;
+                ti[e] = M * ui;
+                vr[e] = -ur;
+                vi[e] = -ui;
+            }
+#pragma unroll
+            for (int n = 0; n < PS; ++n) {
+                Lr[n] += tr[0] + tr[1];
+                Li[n] += ti[0] + ti[1];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const double nr = tr[e] * vr[e] - ti[e] * vi[e];
+                    ti[e] = tr[e] * vi[e] + ti[e] * vr[e];
+                    tr[e] = nr;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < PS; ++n) {
+        const double r = wave_sum(Lr[n]), i = wave_sum(Li[n]);
+        if (lane == 0 && live) {
+            double *dst = part + ((((int64_t)(Y - Y0) * nSx + X) * nchunk + chunk) * PS + n) * 2;
+            dst[0] = r;
+            dst[1] = i;
+        }
+    }
+}
+
+// chunk partials summed in chunk order into the super table
+__global__ __launch_bounds__(kThreads) void k_super_reduce(const double *__restrict__ part, int64_t n_out,
+                                                           int32_t nchunk, int32_t PS,
+                                                           double *__restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= n_out) return;
+    const int64_t cellterm = e / 2, comp = e % 2;
+    const int64_t cell = cellterm / PS, n = cellterm % PS;
+    const double *src = part + ((cell * nchunk) * PS + n) * 2 + comp;
+    double acc = 0.0;
+    for (int k = 0; k < nchunk; ++k) acc += src[(int64_t)k * PS * 2];
+    out[e] = acc;
+}
+
+// Cell expansions of level-1 rows from c0: the super expansion translated to
+// the cell plus the lenses of the super block outside the cell's 7 x 7 block.
+// One wave per cell, four cells (of one super cell) per workgroup.
+// out[(((cy - c0) n1x + cx) P + n) 2 + c]
+constexpr int kSuperRows = (2 * kSuperR + 1) * kSuperK;    // cell rows of a super block
+
+template <bool UNIT, int P, int PS>
+__global__ __launch_bounds__(kThreads) void k_level2_near(
+    DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
+    const double *__restrict__ lm, const uint32_t *__restrict__ lcxy,
+    const int32_t *__restrict__ cell_start, const double *__restrict__ super, int32_t nSx,
+    int32_t c0, int32_t nxb, double *__restrict__ out)
+{
+    __shared__ double s_x[kThreads], s_y[kThreads], s_m[UNIT ? 1 : kThreads];
+    __shared__ uint32_t s_c[kThreads];
+    __shared__ double s_E[PS][2];
+    __shared__ int32_t s_pb[kSuperRows], s_off[kSuperRows + 1];
+    const int tid = threadIdx.x;
+    const int lane = tid % kWave, wave = tid / kWave;
+    const int32_t cy = c0 + (int32_t)(blockIdx.x / (uint32_t)nxb);
+    const int32_t cx0 = (int32_t)(blockIdx.x % (uint32_t)nxb) * kCellsPerBlock;
+    const int32_t cx = cx0 + wave;
+    const bool live = cx < g.n1x;
+    const int32_t X = cx0 / kSuperK, Y = cy / kSuperK;
+    // the super expansion and the lens ranges of the super block, row by row
+    for (int e = tid; e < PS * 2; e += kThreads) s_E[e / 2][e % 2] = super[((int64_t)Y * nSx + X) * PS * 2 + e];
+    const int32_t ya = max(0, (Y - kSuperR) * kSuperK), yb = min(g.n1y, (Y + kSuperR + 1) * kSuperK);
+    const int32_t xa = max(0, (X - kSuperR) * kSuperK), xb = min(g.n1x, (X + kSuperR + 1) * kSuperK);
+    const int nrow = yb - ya;
+    if (tid < nrow) {
+        const int32_t row = ya + tid;
+        s_pb[tid] = cell_start[row * g.n1x + xa];
+        s_off[tid + 1] = cell_start[row * g.n1x + xb] - cell_start[row * g.n1x + xa];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        s_off[0] = 0;
+        for (int r = 0; r < nrow; ++r) s_off[r + 1] += s_off[r];
+    }
+    __syncthreads();
+    const int32_t total = s_off[nrow];
+
+    const double sc = fmax(g.w1, g.h1), isc = 1.0 / sc;
+    const double zcr = g.a1 + ((double)cx + 0.5) * g.w1;
+    const double zci = g.b1 + ((double)cy + 0.5) * g.h1;
+
+    double Lr[P], Li[P];
+#pragma unroll
+    for (int n = 0; n < P; ++n) Lr[n] = Li[n] = 0.0;
+    for (int32_t base = 0; base < total; base += kThreads) {
+        __syncthreads();
+        if (base + tid < total) {
+            const int32_t gi = base + tid;
+            int r = 0;
+            while (s_off[r + 1] <= gi) ++r;            // row of this lens (at most 40 rows)
+            const int32_t li = s_pb[r] + (gi - s_off[r]);
+            s_x[tid] = lx[li];
+            s_y[tid] = ly[li];
+            if (!UNIT) s_m[tid] = lm[li];
+            s_c[tid] = lcxy[li];
+        }
+        __syncthreads();
+        const int cnt = min(kThreads, total - base);
+#pragma unroll
+        for (int k = 0; k < kThreads / kWave; k += 2) {
+            double tr[2], ti[2], vr[2], vi[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int t = lane + (k + e) * kWave;
+                bool use = live && t < cnt;
+                double Xl = zcr + sc, Yl = zci, M = 0.0;   // harmless stand-in
+                if (use) {
+                    const uint32_t c = s_c[t];
+                    const int32_t lcx = (int32_t)(c & 0xffffu), lcy = (int32_t)(c >> 16);
+                    use = abs(lcx - cx) > kRing || abs(lcy - cy) > kRing;
+                    if (use) {
+                        Xl = s_x[t];
+                        Yl = s_y[t];
+                        M = UNIT ? 1.0 : s_m[t];
+                    }
+                }
+                const double wr = (zcr - Xl) * isc, wi = (zci - Yl) * isc;
+                const double inv = rcp64(wr * wr + wi * wi);
+                const double ur = wr * inv, ui = -wi * inv;
+                tr[e] = M * ur;
+                ti[e] = M * ui;
+                vr[e] = -ur;
+                vi[e] = -ui;
+            }
+#pragma unroll
+            for (int n = 0; n < P; ++n) {
+                Lr[n] += tr[0] + tr[1];
+                Li[n] += ti[0] + ti[1];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const double nr = tr[e] * vr[e] - ti[e] * vi[e];
+                    ti[e] = tr[e] * vi[e] + ti[e] * vr[e];
+                    tr[e] = nr;
+                }
+            }
+        }
+    }
+    // translation of the super expansion: lane k < P computes term k
+    double Tr = 0.0, Ti = 0.0;
+    {
+        double zSr, zSi, sS;
+        super_centre(g, X, Y, zSr, zSi, sS);
+        const double dr = (zcr - zSr) / sS, di = (zci - zSi) / sS;
+        const int k = lane;
+        if (k < P) {
+            double pr = 1.0, pi = 0.0;        // d^(n-k)
+            double cb = 1.0;                  // C(n, k)
+            for (int n = k; n < PS; ++n) {
+                Tr += cb * (s_E[n][0] * pr - s_E[n][1] * pi);
+                Ti += cb * (s_E[n][0] * pi + s_E[n][1] * pr);
+                const double nr = pr * dr - pi * di;
+                pi = pr * di + pi * dr;
+                pr = nr;
+                cb = cb * (double)(n + 1) / (double)(n + 1 - k);
+            }
+            const double f = pow(sc / sS, (double)(k + 1));
+            Tr *= f;
+            Ti *= f;
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < P; ++n) {
+        const double r = wave_sum(Lr[n]) + __shfl(Tr, n), i = wave_sum(Li[n]) + __shfl(Ti, n);
+        if (lane == 0 && live) {
+            double *dst = out + ((((int64_t)(cy - c0) * g.n1x + cx)) * P + n) * 2;
+            dst[0] = r;
+            dst[1] = i;
+        }
+    }
+}
+
 template <bool UNIT, int P>
 __global__ __launch_bounds__(kThreads) void k_level2_points(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
@@ -538,7 +802,7 @@ __global__ __launch_bounds__(kThreads) void k_level3(
                 const double d1 = t1 - lx[q_], d2 = t2 - ly[q_];
                 const double rr = d1 * d1 + d2 * d2;
                 if (rr > 0.0) {
-                    const double w = (UNIT ? 1.0 : lm[q_]) / rr;
+                    const double w = (UNIT ? 1.0 : lm[q_]) * rcp64(rr);
                     n1 += w * d1;
                     n2 += w * d2;
                 }
@@ -704,7 +968,137 @@ irs_status ensure_bands(irs_plan_s *p, int64_t rows)
 
 }  // namespace
 
-irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1)
+int super_order(const irs_plan_s *p)
+{
+    if (level2_order(p) == 0) return 0;
+    const DevGeom &g = p->dg;
+    const double rho = 0.5 * kSuperK * std::sqrt(g.w1 * g.w1 + g.h1 * g.h1) /
+                       ((kSuperR + 0.5) * kSuperK * std::min(g.w1, g.h1));
+    for (int P : {32, 48}) {
+        double c4 = (double)P * (P - 1) * (P - 2) * (P - 3) / 24.0;
+        if (c4 * std::pow(rho, P - 4) / std::pow(1.0 - rho, 5) < 1e-14) return P;
+    }
+    return 0;
+}
+
+int32_t level2_chunks(const irs_plan_s *p)
+{
+    if (super_order(p) > 0) return 1;
+    return p->n_lens > 0 ? (int32_t)((p->n_lens + kChunkLens - 1) / kChunkLens) : 1;
+}
+
+void level2_reset(irs_plan_s *p) { std::fill(p->super_ok.begin(), p->super_ok.end(), 0); }
+
+namespace {
+
+int32_t super_nx(const DevGeom &g) { return (g.n1x + kSuperK - 1) / kSuperK; }
+int32_t super_ny(const DevGeom &g) { return (g.n1y + kSuperK - 1) / kSuperK; }
+int32_t lens_chunks(const irs_plan_s *p)
+{
+    return p->n_lens > 0 ? (int32_t)((p->n_lens + kChunkLens - 1) / kChunkLens) : 1;
+}
+
+irs_status ensure_super_buffers(irs_plan_s *p, int64_t rows)
+{
+    const DevGeom &g = p->dg;
+    const int PS = super_order(p);
+    const int32_t nSx = super_nx(g), nSy = super_ny(g);
+    if (!p->d_super) {
+        if (hipMalloc(&p->d_super, sizeof(double) * (size_t)nSy * nSx * PS * 2) != hipSuccess) {
+            (void)hipGetLastError();
+            p->d_super = nullptr;
+            set_error("cannot allocate the super-cell expansions");
+            return IRS_E_NOMEM;
+        }
+        p->super_ok.assign((size_t)nSy, 0);
+    }
+    const size_t need = sizeof(double) * (size_t)rows * nSx * lens_chunks(p) * PS * 2;
+    if (p->super_part_bytes < need) {
+        dev_free(p->d_super_part);
+        p->d_super_part = nullptr;
+        p->super_part_bytes = 0;
+        if (hipMalloc(&p->d_super_part, need) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("cannot allocate the super-cell partial expansions");
+            return IRS_E_NOMEM;
+        }
+        p->super_part_bytes = need;
+    }
+    return IRS_OK;
+}
+
+// lenses of the cell block [xa, xb) x [ya, yb) (clipped), from the host copy
+int64_t lenses_in(const irs_plan_s *p, int64_t xa, int64_t xb, int64_t ya, int64_t yb)
+{
+    const DevGeom &g = p->dg;
+    xa = std::max<int64_t>(0, xa);
+    xb = std::min<int64_t>(g.n1x, xb);
+    ya = std::max<int64_t>(0, ya);
+    yb = std::min<int64_t>(g.n1y, yb);
+    if (xa >= xb || ya >= yb) return 0;
+    const std::vector<int32_t> &hc = p->h_cell_start;
+    int64_t n = 0;
+    for (int64_t row = ya; row < yb; ++row) n += hc[row * g.n1x + xb] - hc[row * g.n1x + xa];
+    return n;
+}
+
+// super rows [Ya, Yb] that are not cached, in runs of consecutive rows
+irs_status ensure_super_rows(irs_plan_s *p, int64_t Ya, int64_t Yb, double *flops)
+{
+    const DevGeom &g = p->dg;
+    const int PS = super_order(p);
+    const int32_t nSx = super_nx(g);
+    const int32_t nSxb = (nSx + kCellsPerBlock - 1) / kCellsPerBlock;
+    const int32_t nchunk = lens_chunks(p);
+    const int32_t nl = (int32_t)p->n_lens;
+    irs_status st = ensure_super_buffers(p, 1);
+    if (st != IRS_OK) return st;
+    for (int64_t y0 = Ya; y0 <= Yb;) {
+        if (p->super_ok[y0]) { ++y0; continue; }
+        int64_t y1 = y0;
+        while (y1 + 1 <= Yb && !p->super_ok[y1 + 1]) ++y1;
+        if ((st = ensure_super_buffers(p, y1 - y0 + 1)) != IRS_OK) return st;
+        const unsigned nb = (unsigned)((y1 - y0 + 1) * nSxb * nchunk);
+#define IRS_SE(U, PP)                                                                          \
+    hipLaunchKernelGGL((k_super_expand<U, PP>), dim3(nb), dim3(kThreads), 0, p->stream, g,      \
+                       p->d_x, p->d_y, p->d_m, p->d_cxy, nl, (int32_t)y0, nSx, nSxb, nchunk,  \
+                       kChunkLens, p->d_super_part)
+        if (p->unit_mass) {
+            if (PS == 32) IRS_SE(true, 32);
+            else IRS_SE(true, 48);
+        } else {
+            if (PS == 32) IRS_SE(false, 32);
+            else IRS_SE(false, 48);
+        }
+#undef IRS_SE
+        const int64_t n_out = (y1 - y0 + 1) * nSx * PS * 2;
+        hipLaunchKernelGGL(k_super_reduce, dim3((unsigned)((n_out + kThreads - 1) / kThreads)),
+                           dim3(kThreads), 0, p->stream, p->d_super_part, n_out, nchunk, PS,
+                           p->d_super + y0 * nSx * PS * 2);
+        IRS_HIP(hipGetLastError());
+        if (flops)
+            for (int64_t Y = y0; Y <= y1; ++Y)
+                for (int32_t X = 0; X < nSx; ++X) {
+                    const int64_t inside = lenses_in(p, (X - kSuperR) * kSuperK, (X + kSuperR + 1) * kSuperK,
+                                                     (Y - kSuperR) * kSuperK, (Y + kSuperR + 1) * kSuperK);
+                    *flops += (double)(p->n_lens - inside) * (10.0 + 8.0 * PS);
+                }
+        for (int64_t Y = y0; Y <= y1; ++Y) p->super_ok[Y] = 1;
+        y0 = y1 + 1;
+    }
+    return IRS_OK;
+}
+
+}  // namespace
+
+irs_status level2_prepare(irs_plan_s *p)
+{
+    level2_reset(p);
+    if (super_order(p) <= 0) return IRS_OK;
+    return ensure_super_buffers(p, super_ny(p->dg));
+}
+
+irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *flops)
 {
     const int P = level2_order(p);
     if (P <= 0) {
@@ -716,21 +1110,58 @@ irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1)
     const DevGeom &g = p->dg;
     const int32_t nl = (int32_t)p->n_lens;
     const int32_t nxb = (g.n1x + kCellsPerBlock - 1) / kCellsPerBlock;
-    const int32_t nchunk = level2_chunks(p);
-    const unsigned nb = (unsigned)((c1 - c0 + 1) * nxb * nchunk);
+    const int PS = super_order(p);
+    if (PS == 0) {
+        // one level: every cell sums all its distant lenses, in lens chunks
+        const int32_t nchunk = level2_chunks(p);
+        const unsigned nb = (unsigned)((c1 - c0 + 1) * nxb * nchunk);
 #define IRS_L2E(U, PP)                                                                    \
     hipLaunchKernelGGL((k_level2_expand<U, PP>), dim3(nb), dim3(kThreads), 0, p->stream, g, \
                        p->d_x, p->d_y, p->d_m, p->d_cxy, nl, (int32_t)c0, nxb, nchunk,   \
                        kChunkLens, p->d_part)
-    if (p->unit_mass) {
-        if (P == 32) IRS_L2E(true, 32);
-        else IRS_L2E(true, 48);
-    } else {
-        if (P == 32) IRS_L2E(false, 32);
-        else IRS_L2E(false, 48);
-    }
+        if (p->unit_mass) {
+            if (P == 32) IRS_L2E(true, 32);
+            else IRS_L2E(true, 48);
+        } else {
+            if (P == 32) IRS_L2E(false, 32);
+            else IRS_L2E(false, 48);
+        }
 #undef IRS_L2E
+        IRS_HIP(hipGetLastError());
+        if (flops)
+            for (int64_t cy = c0; cy <= c1; ++cy)
+                for (int64_t cx = 0; cx < g.n1x; ++cx)
+                    *flops += (double)(p->n_lens - lenses_in(p, cx - kRing, cx + kRing + 1, cy - kRing,
+                                                              cy + kRing + 1)) * (10.0 + 8.0 * P);
+        return IRS_OK;
+    }
+    if ((st = ensure_super_rows(p, c0 / kSuperK, c1 / kSuperK, flops)) != IRS_OK) return st;
+    const int32_t nSx = super_nx(g);
+    const unsigned nb = (unsigned)((c1 - c0 + 1) * nxb);
+#define IRS_LN(U, PP, QS)                                                                         \
+    hipLaunchKernelGGL((k_level2_near<U, PP, QS>), dim3(nb), dim3(kThreads), 0, p->stream, g,      \
+                       p->d_x, p->d_y, p->d_m, p->d_cxy, p->d_cell_start, p->d_super, nSx,       \
+                       (int32_t)c0, nxb, p->d_part)
+    if (p->unit_mass) {
+        if (P == 32) { if (PS == 32) IRS_LN(true, 32, 32); else IRS_LN(true, 32, 48); }
+        else { if (PS == 32) IRS_LN(true, 48, 32); else IRS_LN(true, 48, 48); }
+    } else {
+        if (P == 32) { if (PS == 32) IRS_LN(false, 32, 32); else IRS_LN(false, 32, 48); }
+        else { if (PS == 32) IRS_LN(false, 48, 32); else IRS_LN(false, 48, 48); }
+    }
+#undef IRS_LN
     IRS_HIP(hipGetLastError());
+    if (flops)
+        for (int64_t cy = c0; cy <= c1; ++cy) {
+            const int64_t Y = cy / kSuperK;
+            for (int64_t cx = 0; cx < g.n1x; ++cx) {
+                const int64_t X = cx / kSuperK;
+                const int64_t ring = lenses_in(p, (X - kSuperR) * kSuperK, (X + kSuperR + 1) * kSuperK,
+                                               (Y - kSuperR) * kSuperK, (Y + kSuperR + 1) * kSuperK) -
+                                     lenses_in(p, cx - kRing, cx + kRing + 1, cy - kRing, cy + kRing + 1);
+                *flops += (double)ring * (10.0 + 8.0 * P) + 8.0 * PS * P;
+            }
+        }
     return IRS_OK;
 }
 
@@ -738,7 +1169,41 @@ irs_status interp_prepare(irs_plan_s *p)
 {
     p->coef_c0 = -1;                 // nothing resident that a replay could rely on
     p->coef_c1 = -2;
-    return ensure_bands(p, band_rows(p));
+    irs_status st = ensure_bands(p, band_rows(p));
+    if (st != IRS_OK) return st;
+    return level2_prepare(p);
+}
+
+// Algorithmic FP64 flops of the level-3 rays of rows [j0, j1): per ray 46
+// (Horner of C_0..C_4: 32, sheet 2, macro term 6, beta 2, pixel 4) plus 10 per
+// nearby lens (offsets 2, r^2 3, m/r^2 1, products 2, sums 2).
+double level3_flops(irs_plan_s *p, int64_t j0, int64_t j1)
+{
+    const DevGeom &g = p->dg;
+    if (j1 <= j0) return 0.0;
+    std::vector<int64_t> &cols = p->h_cell_cols;
+    if ((int64_t)cols.size() != g.n1x) {                    // ray columns of each cell column
+        cols.assign(g.n1x, 0);
+        for (int64_t cx = 0, i = 0; cx < g.n1x; ++cx)
+            while (i < g.nx && ((2 * i + 1) * (int64_t)g.n1x) / (2 * g.nx) == cx) { ++cols[cx]; ++i; }
+    }
+    double f = 0.0;
+    for (int64_t j = j0; j < j1;) {
+        const int64_t cy = ((2 * j + 1) * (int64_t)g.n1y) / (2 * g.ny);
+        int64_t jn = j;
+        while (jn < j1 && ((2 * jn + 1) * (int64_t)g.n1y) / (2 * g.ny) == cy) ++jn;
+        double row = 0.0;
+        for (int64_t cx = 0; cx < g.n1x; ++cx) {
+            const int64_t xl = std::max<int64_t>(0, cx - 1), xh = std::min<int64_t>(g.n1x - 1, cx + 1);
+            int64_t nn = 0;
+            for (int64_t r = std::max<int64_t>(0, cy - 1); r <= std::min<int64_t>(g.n1y - 1, cy + 1); ++r)
+                nn += p->h_cell_start[r * g.n1x + xh + 1] - p->h_cell_start[r * g.n1x + xl];
+            row += (double)cols[cx] * (46.0 + 10.0 * (double)nn);
+        }
+        f += row * (double)(jn - j);
+        j = jn;
+    }
+    return f;
 }
 
 irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
@@ -785,9 +1250,7 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
                             cs->level2_expand_flops += f;
                         } else {
                             const int64_t b7 = block(cx, cy, kRing);
-                            const double fe = (double)(p->n_lens - b7) * (10.0 + 8.0 * P);
-                            cs->level2_expand_flops += fe;
-                            cs->level2_flops += fe + (double)(q * q) * (44.0 * (double)(b7 - b3) + 60.0 * P);
+                            cs->level2_flops += (double)(q * q) * (44.0 * (double)(b7 - b3) + 60.0 * P);
                         }
                     }
             }
@@ -801,16 +1264,19 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
                                        p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
             } else {
                 const int32_t nxb = (g.n1x + kCellsPerBlock - 1) / kCellsPerBlock;
-                // lenses are split into fixed chunks (a property of the plan, so
-                // results do not depend on how a map is cut into calls)
-                const int32_t nchunk = std::max<int32_t>(1, (nl + kChunkLens - 1) / kChunkLens);
-                const unsigned nbA = (unsigned)((c1 - c0 + 1) * nxb * nchunk);
+                // lens chunks (one level) are a property of the plan, so results
+                // do not depend on how a map is cut into calls
+                const int32_t nchunk = level2_chunks(p);
                 const unsigned nbB = (unsigned)((c1 - c0 + 1) * nxb);
+                double fl = 0.0;
+                irs_status st3 = launch_level2_expand(p, c0, c1, cs ? &fl : nullptr);
+                if (st3 != IRS_OK) return st3;
+                if (cs) {
+                    cs->level2_expand_flops += fl;
+                    cs->level2_flops += fl;
+                }
 #define IRS_L2L(U, PP)                                                                        \
     do {                                                                                      \
-        hipLaunchKernelGGL((k_level2_expand<U, PP>), dim3(nbA), dim3(kThreads), 0, s, g,      \
-                           p->d_x, p->d_y, p->d_m, p->d_cxy, nl, (int32_t)c0, nxb, nchunk,    \
-                           kChunkLens, p->d_part);                                            \
         if (cs && (st2 = cs->end(s)) != IRS_OK) return st2;                                  \
         if (cs && (st2 = cs->begin(s, 2)) != IRS_OK) return st2;                             \
         hipLaunchKernelGGL((k_level2_points<U, PP>), dim3(nbB), dim3(kThreads), 0, s, g,      \
@@ -850,6 +1316,7 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
                 irs_status st = cs->begin(s, 1);
                 if (st != IRS_OK) return st;
                 cs->n_rays++;
+                cs->ray_flops += level3_flops(p, std::max(j0, sel.row0), std::min(j1, sel.row1));
             }
             if (p->unit_mass)
                 hipLaunchKernelGGL(k_level3<true>, dim3(nb3), dim3(kThreads), 0, s, g, p->d_x,

@@ -47,14 +47,21 @@ struct irs_plan_s {
     int32_t *d_cell_start = nullptr;                         // n1x*n1y + 1
     uint32_t *d_cxy = nullptr;                               // per sorted lens: cy << 16 | cx
     std::vector<int32_t> h_cell_start;                       // host copy (work counts)
+    std::vector<int64_t> h_cell_cols;                        // ray columns per cell column
 
     // Level-2 coefficients of one band of level-1 rows: 10 doubles per point
     // (Re/Im of C0..C4), point (gx, gy) at ((gy - band_row0*q) * n1x*q + gx).
     double *d_coef = nullptr;
     int64_t coef_rows_cap = 0;   // level-1 rows the buffer holds
     int64_t coef_c0 = -1, coef_c1 = -2;   // level-1 rows whose coefficients it holds now
-    double *d_part = nullptr;             // per-(cell, lens chunk) partial expansions
+    double *d_part = nullptr;             // per-cell expansions (or per-chunk partials)
     size_t part_bytes = 0;
+    // Two-level distant field: expansions of the super cells, kept while the
+    // plan lives (its lenses never change); super_ok[Y]: row Y is computed.
+    double *d_super = nullptr;
+    std::vector<char> super_ok;
+    double *d_super_part = nullptr;       // per-(super cell, lens chunk) partials
+    size_t super_part_bytes = 0;
 
     // Learned interpolant (IRS_LEARNED): network, validation verdict and the
     // corner table of one band of level-1 rows (4 doubles per corner:
@@ -102,7 +109,7 @@ irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const 
 // Work and (optionally) HIP-event timings accumulated over one API call.
 struct CallStats {
     int64_t level2_points = 0, level2_pairs = 0, direct_pairs = 0;
-    double level2_flops = 0.0, level2_expand_flops = 0.0;
+    double level2_flops = 0.0, level2_expand_flops = 0.0, ray_flops = 0.0;
     int32_t n_level2 = 0, n_rays = 0;
     double ms_level2 = 0.0, ms_level2_expand = 0.0, ms_rays = 0.0;
     bool timed = false;
