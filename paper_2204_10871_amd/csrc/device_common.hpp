@@ -21,6 +21,7 @@ struct DevGeom {
     int32_t pad_;
     double w1, h1;              // level-1 cell sides (I_x/n1x, I_y/n1y)
     double w2, h2;              // level-2 subcell sides (w1/q, h1/q)
+    double inv_dpix;            // npix/S
 };
 
 constexpr int kWave = 64;
@@ -94,6 +95,32 @@ __device__ __forceinline__ void sheet_unit(const DevGeom &g, double t1, double t
     }
     I1 = s1;
     I2 = s2;
+}
+
+// floor((b + S/2) / dpix) with the quotient rounded as an IEEE division: the
+// product by 1/dpix is within 1e-9 of that quotient for |quotient| < 1e6, so
+// its floor is the same unless it lies that close to an integer, where the
+// division itself decides.
+__device__ __forceinline__ double pixel_floor(const DevGeom &g, double b)
+{
+    const double xs = b + g.half_side;
+    const double q = xs * g.inv_dpix;
+    const double f = floor(q);
+    if (q - f < 1e-9 || f + 1.0 - q < 1e-9 || !(fabs(q) < 1e6)) return floor(xs / g.dpix);
+    return f;
+}
+
+// Source pixel column and row of beta; false (and -1, -1) off the map.
+__device__ __forceinline__ bool pixel_xy(const DevGeom &g, double b1, double b2, int32_t &ix,
+                                         int32_t &iy)
+{
+    const double fx = pixel_floor(g, b1);
+    const double fy = pixel_floor(g, b2);
+    const double n = (double)g.npix;
+    const bool in = fx >= 0.0 && fx < n && fy >= 0.0 && fy < n;
+    ix = in ? (int32_t)fx : -1;
+    iy = in ? (int32_t)fy : -1;
+    return in;
 }
 
 // Source pixel of beta, -1 off the map.

@@ -737,41 +737,56 @@ __device__ __forceinline__ int wave_max(int v)
 
 template <bool UNIT>
 __global__ __launch_bounds__(kThreads) void k_level3(
-    DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
-    const double *__restrict__ lm, const int32_t *__restrict__ cell_start,
+    DevGeom g, const double2 *__restrict__ lxy, const double *__restrict__ lm,
+    const int32_t *__restrict__ cell_start,
     const double *__restrict__ coef, int32_t cy0, int64_t ntx, int64_t jr0, int64_t jr1,
     int64_t ray_first, int64_t ray_last, double *a1o, double *a2o, int64_t *pixo,
     uint32_t *counts, unsigned long long *landed)
 {
     __shared__ uint32_t s_hist[kHistCap];
     __shared__ int s_box[kThreads / kWave][4];
+    // per ray row of the tile: theta_2, offset from its level-2 row, level-2
+    // row within the band, level-1 row (computed once per row, not per ray)
+    __shared__ double s_t2[kL3Rows], s_hi[kL3Rows];
+    __shared__ int32_t s_gyl[kL3Rows], s_cy[kL3Rows];
 
     const int tid = threadIdx.x;
     const int lane = tid % kWave, wave = tid / kWave;
     const int64_t tx = (int64_t)blockIdx.x % ntx;
     const int64_t ty = (int64_t)blockIdx.x / ntx;
+    const int64_t jb = jr0 + ty * kL3Rows;
+    if (tid < kL3Rows) {
+        const int64_t j = jb + tid;
+        const int64_t gy = floor_div((2 * j + 1) * (int64_t)g.n1y * g.q, 2 * g.ny);
+        const double t2 = ray_y(g, j);
+        s_t2[tid] = t2;
+        s_hi[tid] = t2 - level2_y(g, gy);
+        s_gyl[tid] = (int32_t)(gy - (int64_t)cy0 * g.q);
+        s_cy[tid] = (int32_t)gy / g.q;
+    }
     const int64_t i = tx * kWave + lane;
     const bool in_col = i < g.nx;
     const int64_t nxq = (int64_t)g.n1x * g.q;
     const int64_t gx = in_col ? floor_div((2 * i + 1) * nxq, 2 * g.nx) : 0;
-    const int64_t cx = gx / g.q;
+    const int32_t cx = (int32_t)gx / g.q;
     const double t1 = ray_x(g, i);
     const double hr = t1 - level2_x(g, gx);
-    const int64_t xl = cx > 0 ? cx - 1 : 0, xh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
+    const int32_t xl = cx > 0 ? cx - 1 : 0, xh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
+    __syncthreads();
 
-    int32_t pix[kL3RowsPerWave];
+    int32_t pxs[kL3RowsPerWave], pys[kL3RowsPerWave];
 #pragma unroll
     for (int k = 0; k < kL3RowsPerWave; ++k) {
-        const int64_t j = jr0 + ty * kL3Rows + wave * kL3RowsPerWave + k;
+        const int rl = wave * kL3RowsPerWave + k;
+        const int64_t j = jb + rl;
         const int64_t r = j * g.nx + i;
         const bool valid = in_col && j < jr1 && r >= ray_first && r < ray_last;
-        pix[k] = -1;
+        pxs[k] = -1;
+        pys[k] = -1;
         if (!valid) continue;
-        const double t2 = ray_y(g, j);
-        const int64_t gy = floor_div((2 * j + 1) * (int64_t)g.n1y * g.q, 2 * g.ny);
-        const int64_t cy = gy / g.q;
-        const double hi = t2 - level2_y(g, gy);
-        const double *C = coef + ((gy - (int64_t)cy0 * g.q) * nxq + gx) * 10;
+        const double t2 = s_t2[rl], hi = s_hi[rl];
+        const int32_t cy = s_cy[rl];
+        const double *C = coef + ((int64_t)s_gyl[rl] * nxq + gx) * 10;
         // Horner: C0 + h (C1 + h (C2 + h (C3 + h C4)))
         cplx A = {C[8], C[9]};
 #pragma unroll
@@ -792,30 +807,30 @@ __global__ __launch_bounds__(kThreads) void k_level3(
                 A.i += g.kappa_star * hi;
             }
         }
-        // nearby lenses, exactly
+        // nearby lenses, exactly (a lens exactly on the ray adds nothing)
         double n1 = 0.0, n2 = 0.0;
-        const int64_t yl = cy > 0 ? cy - 1 : 0, yh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
-        for (int64_t row = yl; row <= yh; ++row) {
+        const int32_t yl = cy > 0 ? cy - 1 : 0, yh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
+        for (int32_t row = yl; row <= yh; ++row) {
             const int32_t pb = cell_start[row * g.n1x + xl];
             const int32_t pe = cell_start[row * g.n1x + xh + 1];
             for (int32_t q_ = pb; q_ < pe; ++q_) {
-                const double d1 = t1 - lx[q_], d2 = t2 - ly[q_];
+                const double2 z = lxy[q_];
+                const double d1 = t1 - z.x, d2 = t2 - z.y;
                 const double rr = d1 * d1 + d2 * d2;
-                if (rr > 0.0) {
-                    const double w = (UNIT ? 1.0 : lm[q_]) * rcp64(rr);
-                    n1 += w * d1;
-                    n2 += w * d2;
-                }
+                double w = (UNIT ? 1.0 : lm[q_]) * rcp64(rr);
+                w = rr > 0.0 ? w : 0.0;
+                n1 += w * d1;
+                n2 += w * d2;
             }
         }
         const double a1 = g.kpg * t1 + n1 + A.r;       // conj(A) is the far + sheet deflection
         const double a2 = g.kmg * t2 + n2 - A.i;
-        pix[k] = pixel_of(g, t1 - a1, t2 - a2);
+        pixel_xy(g, t1 - a1, t2 - a2, pxs[k], pys[k]);
         if (!counts) {
             const int64_t o = r - ray_first;
             if (a1o) a1o[o] = a1;
             if (a2o) a2o[o] = a2;
-            if (pixo) pixo[o] = pix[k];
+            if (pixo) pixo[o] = pxs[k] < 0 ? -1 : (int64_t)pys[k] * g.npix + pxs[k];
         }
     }
     if (!counts) return;
@@ -824,10 +839,9 @@ __global__ __launch_bounds__(kThreads) void k_level3(
     int bx0 = INT_MAX, bx1 = -1, by0 = INT_MAX, by1 = -1, nland = 0;
 #pragma unroll
     for (int k = 0; k < kL3RowsPerWave; ++k) {
-        if (pix[k] < 0) continue;
-        const int px = pix[k] % g.npix, py = pix[k] / g.npix;
-        bx0 = min(bx0, px); bx1 = max(bx1, px);
-        by0 = min(by0, py); by1 = max(by1, py);
+        if (pxs[k] < 0) continue;
+        bx0 = min(bx0, pxs[k]); bx1 = max(bx1, pxs[k]);
+        by0 = min(by0, pys[k]); by1 = max(by1, pys[k]);
         ++nland;
     }
     bx0 = wave_min(bx0); bx1 = wave_max(bx1);
@@ -852,15 +866,16 @@ __global__ __launch_bounds__(kThreads) void k_level3(
     const int64_t area = (int64_t)bw * (by1 - by0 + 1);
     if (area > kHistCap) {                                 // block-uniform fallback
 #pragma unroll
-        for (int k = 0; k < kL3RowsPerWave; ++k) bin_wave(counts, pix[k]);
+        for (int k = 0; k < kL3RowsPerWave; ++k)
+            bin_wave(counts, pxs[k] < 0 ? -1 : pys[k] * g.npix + pxs[k]);
         return;
     }
     for (int b = tid; b < area; b += kThreads) s_hist[b] = 0u;
     __syncthreads();
+    // wave-aggregated LDS adds: lanes with the same bin are merged by ballot
 #pragma unroll
     for (int k = 0; k < kL3RowsPerWave; ++k) {
-        const int32_t lp = pix[k] < 0 ? -1
-                         : (pix[k] / g.npix - by0) * bw + (pix[k] % g.npix - bx0);
+        const int32_t lp = pxs[k] < 0 ? -1 : (pys[k] - by0) * bw + (pxs[k] - bx0);
         uint64_t todo = __ballot(lp >= 0);
         while (todo) {
             const int leader = __ffsll((unsigned long long)todo) - 1;
@@ -871,9 +886,16 @@ __global__ __launch_bounds__(kThreads) void k_level3(
         }
     }
     __syncthreads();
+    // flush: bin b is (row b / bw, column b % bw) of the box; the quotient
+    // from a float estimate, corrected to the exact integer
+    const float inv_bw = 1.0f / (float)bw;
     for (int b = tid; b < area; b += kThreads) {
         const uint32_t v = s_hist[b];
-        if (v) atomicAdd(&counts[(by0 + b / bw) * g.npix + bx0 + b % bw], v);
+        if (!v) continue;
+        int row = (int)((float)b * inv_bw);
+        if (row * bw > b) --row;
+        else if ((row + 1) * bw <= b) ++row;
+        atomicAdd(&counts[(by0 + row) * g.npix + bx0 + (b - row * bw)], v);
     }
 }
 
@@ -1319,13 +1341,13 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
                 cs->ray_flops += level3_flops(p, std::max(j0, sel.row0), std::min(j1, sel.row1));
             }
             if (p->unit_mass)
-                hipLaunchKernelGGL(k_level3<true>, dim3(nb3), dim3(kThreads), 0, s, g, p->d_x,
-                                   p->d_y, p->d_m, p->d_cell_start, p->d_coef, band0, ntx,
+                hipLaunchKernelGGL(k_level3<true>, dim3(nb3), dim3(kThreads), 0, s, g,
+                                   (const double2 *)p->d_xy, p->d_m, p->d_cell_start, p->d_coef, band0, ntx,
                                    j0, j1, sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2,
                                    sel.pixel, sel.counts, sel.landed);
             else
-                hipLaunchKernelGGL(k_level3<false>, dim3(nb3), dim3(kThreads), 0, s, g, p->d_x,
-                                   p->d_y, p->d_m, p->d_cell_start, p->d_coef, band0, ntx,
+                hipLaunchKernelGGL(k_level3<false>, dim3(nb3), dim3(kThreads), 0, s, g,
+                                   (const double2 *)p->d_xy, p->d_m, p->d_cell_start, p->d_coef, band0, ntx,
                                    j0, j1, sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2,
                                    sel.pixel, sel.counts, sel.landed);
             IRS_HIP(hipGetLastError());

@@ -32,13 +32,15 @@ __global__ void k_gather(const int32_t *__restrict__ perm, const int32_t *__rest
                          const double *__restrict__ x, const double *__restrict__ y,
                          const double *__restrict__ m, int32_t n, int32_t n1x,
                          double *__restrict__ sx, double *__restrict__ sy,
-                         double *__restrict__ sm, uint32_t *__restrict__ cxy)
+                         double *__restrict__ sm, uint32_t *__restrict__ cxy,
+                         double2 *__restrict__ sxy)
 {
     const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int32_t i = perm[p];
     sx[p] = x[i];
     sy[p] = y[i];
+    sxy[p] = make_double2(x[i], y[i]);
     if (m) sm[p] = m[i];
     const int32_t c = skey[p];
     cxy[p] = ((uint32_t)(c / n1x) << 16) | (uint32_t)(c % n1x);
@@ -84,6 +86,7 @@ irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const 
     IRS_HIP(hipMalloc(&p->d_y, nb));
     if (hm) IRS_HIP(hipMalloc(&p->d_m, nb));
     IRS_HIP(hipMalloc(&p->d_cxy, sizeof(uint32_t) * (size_t)n));
+    IRS_HIP(hipMalloc(&p->d_xy, 2 * nb));
 
     double *ux = nullptr, *uy = nullptr, *um = nullptr;
     int32_t *key = nullptr, *skey = nullptr, *idx = nullptr, *perm = nullptr;
@@ -127,7 +130,7 @@ irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const 
         IRS_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key, skey, idx, perm, n, 0,
                                                    end_bit, s));
         hipLaunchKernelGGL(k_gather, dim3(nbk), dim3(tb), 0, s, perm, skey, ux, uy, um, n,
-                           p->dg.n1x, p->d_x, p->d_y, p->d_m, p->d_cxy);
+                           p->dg.n1x, p->d_x, p->d_y, p->d_m, p->d_cxy, (double2 *)p->d_xy);
         IRS_TRY(hipGetLastError());
         const int nbc = (ncell + 1 + tb - 1) / tb;
         hipLaunchKernelGGL(k_cell_start, dim3(nbc), dim3(tb), 0, s, skey, n, ncell,
