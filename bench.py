@@ -139,6 +139,71 @@ def bench_learned(irs, synth, torch, stream, args, result):
     return out
 
 
+def rms_by_rays(test, ref, s_test, s_ref, nbins=300):
+    """Pixel-by-pixel relative error of the magnification (N S_I / S_S) of a
+    map against a reference, RMS in logarithmic bins of the map's rays per
+    pixel (Sec. 3.2).  Returns (bin centres, RMS, pixels per bin)."""
+    import numpy as np
+    t = test.astype(np.float64).ravel()
+    r = ref.astype(np.float64).ravel()
+    ok = (t > 0) & (r > 0)
+    t, r = t[ok], r[ok]
+    err = (t * s_test) / (r * s_ref) - 1.0
+    edges = np.logspace(np.log10(t.min()), np.log10(t.max() + 1), nbins + 1)
+    idx = np.clip(np.digitize(t, edges) - 1, 0, nbins - 1)
+    n = np.bincount(idx, minlength=nbins)
+    ss = np.bincount(idx, weights=err * err, minlength=nbins)
+    sn = np.bincount(idx, weights=t, minlength=nbins)
+    keep = n >= 20
+    return sn[keep] / n[keep], np.sqrt(ss[keep] / n[keep]), n[keep]
+
+
+def bench_accuracy(irs, synth, torch, stream):
+    """Accuracy against the number of rays (Sec. 3.2): kappa = kappa_* = 0.652,
+    gamma = 0, 1024^2 px, equal masses, S = 50 Einstein radii of a solar mass
+    with <M> = 0.1 solar masses (158.1 in units of the mean mass); maps of
+    (10240 k)^2 rays, k = 1..7, against a 4e10-ray map of the same lenses; RMS
+    relative magnification error in 300 logarithmic bins of rays per pixel and
+    the slope of log RMS against log rays per pixel."""
+    import numpy as np
+    S = 50.0 / math.sqrt(0.1)
+    npix = 1024
+    p0 = irs.make_params(0.652, 0.0, 0.0, S, npix, n_rays=1, method="interp", precision="fp64")
+    g0 = irs.geometry(p0, 0)
+    L = synth.uniform_lenses(g0["n_stars_expected"], (g0["a1"], g0["a2"], g0["b1"], g0["b2"]),
+                             synth.configs.SEED_BASE + 8)
+    counts = torch.zeros(npix * npix, dtype=torch.int32, device="cuda:0")
+
+    def shoot(n_rays):
+        p = irs.make_params(0.652, 0.0, 0.0, S, npix, n_rays=n_rays, method="interp",
+                            precision="fp64")
+        with irs.Plan(p, L.x, L.y, L.m, stream=stream.cuda_stream) as pl:
+            st = pl.shoot_map_device(counts)
+            g = pl.geometry
+        torch.cuda.synchronize()
+        return counts.cpu().numpy().reshape(npix, npix).copy(), g["s_img"], st
+
+    t0 = time.perf_counter()
+    ref, s_ref, st_ref = shoot(200_000 ** 2)
+    out = {"workload": "kappa=kappa_*=0.652, gamma=0, S=158.1 (mean-mass units), 1024^2 px, "
+                       "equal masses, interpolated path", "n_star": L.n,
+           "reference_rays": st_ref["rays_shot"], "maps": []}
+    slopes = []
+    for k in range(1, 8):
+        m, s_img, st = shoot((10240 * k) ** 2)
+        x, rms, n = rms_by_rays(m, ref, s_img, s_ref)
+        sel = (x > 10) & (n >= 100)
+        slope = float(np.polyfit(np.log10(x[sel]), np.log10(rms[sel]), 1)[0]) if sel.sum() > 3 else None
+        slopes.append(slope)
+        out["maps"].append({"rays": st["rays_shot"], "mean_rays_per_pixel": float(m.mean()),
+                            "slope": slope, "rms_at_median": float(np.median(rms))})
+        log(f"accuracy: {st['rays_shot']:.3e} rays, slope {slope:.3f}, median RMS {np.median(rms):.3e}")
+    good = [s for s in slopes if s is not None]
+    out["slope_mean"] = float(np.mean(good)) if good else None
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
 def bench_batch(irs, synth, torch, stream):
     """The 64-map batch (kappa_*, gamma ~ U[0.1, 0.8], kappa_c in {0, 0.2},
     N_* = 10^U[3, 5], 1024^2..4096^2 px, 100 rays/px), interpolated: one tuned
@@ -169,8 +234,7 @@ def bench_batch(irs, synth, torch, stream):
     torch.cuda.synchronize()
     ts = time.perf_counter()
     for p, c in zip(plans, counts):
-        c.zero_()
-        p.shoot_rows(0, p.geometry["ny"], c)
+        p.shoot_map_device(c)            # computes every expansion, as the graph does
     torch.cuda.synchronize()
     ts = time.perf_counter() - ts
     same = all(torch.equal(a, c) for a, c in zip(batched, counts))
@@ -197,6 +261,8 @@ def main():
     ap.add_argument("--direct-rows", type=int, default=64)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-map batch measurement")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the accuracy-versus-rays experiment (Sec. 3.2)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-interpolant measurement (N_* = 1e6, 8192^2 px)")
     ap.add_argument("--pmc-calibrate", action="store_true",
@@ -364,6 +430,8 @@ def main():
         log(f"direct fp32: {pairs / td:.3e} pairs/s, {tf:.1f} TFLOP/s")
 
     plan.close()
+    if not args.no_accuracy:
+        result["accuracy_vs_rays"] = bench_accuracy(irs, synth, torch, stream)
     if not args.no_learned:
         result["learned"] = bench_learned(irs, synth, torch, stream, args, result)
     if not args.no_batch:

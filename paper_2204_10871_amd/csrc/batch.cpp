@@ -34,6 +34,10 @@ struct irs_batch_s {
     int64_t *d_item_start = nullptr;
     unsigned long long *d_cursor = nullptr;   // [0] cursor, [1..n] landed per map
     int64_t items = 0;
+    // interpolated batches: parallel branches of the graph (default priority)
+    std::vector<hipStream_t> lanes;
+    std::vector<hipEvent_t> lane_done;
+    hipEvent_t fork = nullptr;
     // captured graph
     hipGraphExec_t exec = nullptr;
     std::vector<uint32_t *> graph_counts;
@@ -41,6 +45,8 @@ struct irs_batch_s {
 };
 
 namespace {
+
+constexpr int kLanes = 4;                  // parallel branches of an interpolated batch
 
 void drop_graph(irs_batch_s *b)
 {
@@ -93,9 +99,17 @@ irs_status enqueue_all(irs_batch_s *b, uint32_t *const *counts)
     if (b->method == IRS_DIRECT)
         return launch_direct_queue(b->stream, b->precision, b->unit, b->variant, b->d_maps,
                                    b->d_item_start, n, b->d_cursor, b->bpc * b->n_cu);
+    // the maps run on parallel branches (fork from the batch stream, join back);
+    // longest first, each onto the branch with the least work so far
+    const int nl = (int)b->lanes.size();
+    IRS_HIP(hipEventRecord(b->fork, b->stream));
+    for (int l = 0; l < nl; ++l) IRS_HIP(hipStreamWaitEvent(b->lanes[l], b->fork, 0));
+    std::vector<double> load(nl, 0.0);
     for (int k = 0; k < n; ++k) {
         const int m = b->order[k];
         irs_plan_s *p = b->plans[m];
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[l] += map_cost(p);
         RaySel sel{};
         sel.stats = nullptr;
         sel.row0 = 0;
@@ -105,10 +119,14 @@ irs_status enqueue_all(irs_batch_s *b, uint32_t *const *counts)
         sel.counts = counts[m];
         sel.landed = b->d_cursor + 1 + m;
         hipStream_t saved = p->stream;
-        p->stream = b->stream;
+        p->stream = b->lanes[l];
         st = launch_interp(p, sel);
         p->stream = saved;
         if (st != IRS_OK) return st;
+    }
+    for (int l = 0; l < nl; ++l) {
+        IRS_HIP(hipEventRecord(b->lane_done[l], b->lanes[l]));
+        IRS_HIP(hipStreamWaitEvent(b->stream, b->lane_done[l], 0));
     }
     return IRS_OK;
 }
@@ -300,6 +318,18 @@ irs_status irs_batch_create(const irs_plan_t *plans, int32_t n, void *hip_stream
     } else if (e == hipSuccess) {
         e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
         b->own_stream = (e == hipSuccess);
+    }
+    if (e == hipSuccess && b->method != IRS_DIRECT) {
+        const int nl = std::min(n, kLanes);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        for (int l = 0; l < nl && e == hipSuccess; ++l) {
+            hipStream_t ls = nullptr;
+            hipEvent_t le = nullptr;
+            e = hipStreamCreateWithFlags(&ls, hipStreamNonBlocking);
+            if (e == hipSuccess) b->lanes.push_back(ls);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&le, hipEventDisableTiming);
+            if (e == hipSuccess) b->lane_done.push_back(le);
+        }
     }
     if (e == hipSuccess) e = hipMalloc(&b->d_maps, sizeof(DirectArgs) * n);
     if (e == hipSuccess) e = hipMalloc(&b->d_item_start, sizeof(int64_t) * (n + 1));
@@ -513,6 +543,12 @@ void irs_batch_free(irs_batch_t b)
     dev_free(b->d_maps);
     dev_free(b->d_item_start);
     dev_free(b->d_cursor);
+    for (hipStream_t ls : b->lanes) {
+        (void)hipStreamSynchronize(ls);
+        (void)hipStreamDestroy(ls);
+    }
+    for (hipEvent_t le : b->lane_done) (void)hipEventDestroy(le);
+    if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
