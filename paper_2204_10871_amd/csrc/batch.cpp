@@ -32,7 +32,8 @@ struct irs_batch_s {
     // device tables of the direct queue
     DirectArgs *d_maps = nullptr;
     int64_t *d_item_start = nullptr;
-    unsigned long long *d_cursor = nullptr;   // [0] cursor, [1..n] landed per map
+    unsigned long long *d_cursor = nullptr;   // [0] cursor, then kLandedSlots landed
+                                              // counters per map
     int64_t items = 0;
     // interpolated batches: parallel branches of the graph (default priority)
     std::vector<hipStream_t> lanes;
@@ -73,7 +74,7 @@ irs_status build_direct_tables(irs_batch_s *b, uint32_t *const *counts)
         const int m = b->order[k];
         irs_plan_s *p = b->plans[m];
         maps[k] = direct_args_full(p, b->variant, counts ? counts[m] : nullptr,
-                                   b->d_cursor + 1 + m);
+                                   b->d_cursor + 1 + (size_t)m * kLandedSlots);
         start[k + 1] = start[k] + direct_items(p, b->variant);
     }
     b->items = start[n];
@@ -89,7 +90,7 @@ irs_status build_direct_tables(irs_batch_s *b, uint32_t *const *counts)
 irs_status enqueue_all(irs_batch_s *b, uint32_t *const *counts)
 {
     const int n = (int)b->plans.size();
-    irs_status st = launch_zero(b->stream, b->d_cursor, 2 * (size_t)(n + 1));
+    irs_status st = launch_zero(b->stream, b->d_cursor, 2 * (1 + (size_t)n * kLandedSlots));
     if (st != IRS_OK) return st;
     for (int m = 0; m < n; ++m) {
         const irs_plan_s *p = b->plans[m];
@@ -117,7 +118,7 @@ irs_status enqueue_all(irs_batch_s *b, uint32_t *const *counts)
         sel.ray_first = 0;
         sel.ray_last = p->dg.nx * p->dg.ny;
         sel.counts = counts[m];
-        sel.landed = b->d_cursor + 1 + m;
+        sel.landed = b->d_cursor + 1 + (size_t)m * kLandedSlots;
         hipStream_t saved = p->stream;
         p->stream = b->lanes[l];
         st = launch_interp(p, sel);
@@ -195,7 +196,7 @@ irs_status time_direct(irs_batch_s *b, int variant, int bpc, uint32_t *scratch, 
     irs_status st = IRS_OK;
     ms = 0.0;
     for (int rep = 0; rep < 2 && st == IRS_OK; ++rep) {     // first run warms up
-        st = launch_zero(b->stream, b->d_cursor, 2);
+        st = launch_zero(b->stream, b->d_cursor, 2 * (1 + (size_t)kLandedSlots));
         if (st == IRS_OK) st = (hipEventRecord(e0, b->stream) == hipSuccess) ? IRS_OK : IRS_E_DEVICE;
         if (st == IRS_OK)
             st = launch_direct_queue(b->stream, b->precision, b->unit, variant, b->d_maps,
@@ -333,7 +334,8 @@ irs_status irs_batch_create(const irs_plan_t *plans, int32_t n, void *hip_stream
     }
     if (e == hipSuccess) e = hipMalloc(&b->d_maps, sizeof(DirectArgs) * n);
     if (e == hipSuccess) e = hipMalloc(&b->d_item_start, sizeof(int64_t) * (n + 1));
-    if (e == hipSuccess) e = hipMalloc(&b->d_cursor, sizeof(unsigned long long) * (n + 1));
+    if (e == hipSuccess)
+        e = hipMalloc(&b->d_cursor, sizeof(unsigned long long) * (1 + (size_t)n * kLandedSlots));
     if (e != hipSuccess) st = hip_fail(e, "irs_batch_create");
     if (st != IRS_OK) {
         irs_batch_free(b);
@@ -483,8 +485,8 @@ irs_status irs_batch_run(irs_batch_t b, uint32_t *const *counts, irs_map_stats *
         return hip_fail(e, "hipGraphLaunch");
     }
     (void)hipEventRecord(e1, b->stream);
-    std::vector<unsigned long long> landed(n + 1);
-    e = hipMemcpyAsync(landed.data(), b->d_cursor, sizeof(unsigned long long) * (n + 1),
+    std::vector<unsigned long long> landed(1 + (size_t)n * kLandedSlots);
+    e = hipMemcpyAsync(landed.data(), b->d_cursor, sizeof(unsigned long long) * landed.size(),
                        hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     float ms = 0.0f;
@@ -502,7 +504,9 @@ irs_status irs_batch_run(irs_batch_t b, uint32_t *const *counts, irs_map_stats *
             irs_map_stats &s = stats[m];
             std::memset(&s, 0, sizeof s);
             s.rays_shot = p->dg.nx * p->dg.ny;
-            s.rays_landed = (int64_t)landed[1 + m];
+            unsigned long long lm = 0;
+            for (int k = 0; k < kLandedSlots; ++k) lm += landed[1 + (size_t)m * kLandedSlots + k];
+            s.rays_landed = (int64_t)lm;
             s.rays_off = s.rays_shot - s.rays_landed;
             s.n_lens = p->n_lens;
             s.kappa_star_eff = p->kappa_star_eff;

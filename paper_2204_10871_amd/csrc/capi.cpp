@@ -229,7 +229,7 @@ irs_status irs_plan(const irs_params *params, int64_t n_lens, const double *x, c
         release(p);
         return st;
     }
-    e = hipMalloc(&p->d_landed, sizeof(unsigned long long));
+    e = hipMalloc(&p->d_landed, sizeof(unsigned long long) * kLandedSlots);
     if (e != hipSuccess) {
         st = hip_fail(e, "hipMalloc");
         release(p);
@@ -336,7 +336,7 @@ static irs_status shoot(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t *
         dst = plan->d_counts;
     }
     if (!on_dev || overwrite) IRS_HIP(hipMemsetAsync(dst, 0, map_bytes, s));
-    IRS_HIP(hipMemsetAsync(plan->d_landed, 0, sizeof(unsigned long long), s));
+    IRS_HIP(hipMemsetAsync(plan->d_landed, 0, sizeof(unsigned long long) * kLandedSlots, s));
     CallStats cs;
     cs.timed = (flags & IRS_TIME_PHASES) != 0;
     RaySel sel{};
@@ -349,8 +349,8 @@ static irs_status shoot(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t *
     sel.landed = plan->d_landed;
     irs_status st = run(plan, sel);
     if (st != IRS_OK) return st;
-    unsigned long long landed = 0;
-    IRS_HIP(hipMemcpyAsync(&landed, plan->d_landed, sizeof landed, hipMemcpyDeviceToHost, s));
+    unsigned long long slots[kLandedSlots];
+    IRS_HIP(hipMemcpyAsync(slots, plan->d_landed, sizeof slots, hipMemcpyDeviceToHost, s));
     if (!on_dev) {
         std::vector<uint32_t> tmp((size_t)plan->geo.npix * (size_t)plan->geo.npix);
         IRS_HIP(hipMemcpyAsync(tmp.data(), dst, map_bytes, hipMemcpyDeviceToHost, s));
@@ -360,6 +360,8 @@ static irs_status shoot(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t *
             for (size_t k = 0; k < tmp.size(); ++k) counts[k] += tmp[k];
     }
     IRS_HIP(hipStreamSynchronize(s));
+    unsigned long long landed = 0;
+    for (unsigned long long v : slots) landed += v;
     const double ms = timer.stop();
     st = cs.collect();
     if (st != IRS_OK) return st;

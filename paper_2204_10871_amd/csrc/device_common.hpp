@@ -133,6 +133,16 @@ __device__ __forceinline__ int32_t pixel_of(const DevGeom &g, double b1, double 
     return (int32_t)fy * g.npix + (int32_t)fx;
 }
 
+// Rays binned by a call are counted in kLandedSlots counters (a workgroup adds
+// to slot blockIdx mod kLandedSlots; the host sums them): one counter shared by
+// every workgroup serialises its atomics in one L2 channel.
+constexpr int kLandedSlots = 256;
+
+__device__ __forceinline__ void landed_add(unsigned long long *landed, unsigned long long v)
+{
+    atomicAdd(landed + (blockIdx.x & (kLandedSlots - 1)), v);
+}
+
 // Wavefront-aggregated histogram update: lanes hitting the same pixel are
 // merged (ballot on the leader's pixel) and one lane issues a single atomic
 // with the group's count.  Must be called by every lane of the wave

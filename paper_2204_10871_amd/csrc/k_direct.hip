@@ -59,7 +59,7 @@ __device__ __forceinline__ void emit(bool valid, int64_t out_idx, double a1, dou
         const int32_t pv = valid ? pix : -1;
         bin_wave(counts, pv);
         const uint64_t got = __ballot(pv >= 0);
-        if (__lane_id() == 0 && got) atomicAdd(landed, (unsigned long long)__popcll(got));
+        if (__lane_id() == 0 && got) landed_add(landed, (unsigned long long)__popcll(got));
     } else if (valid) {
         if (a1o) a1o[out_idx] = a1;
         if (a2o) a2o[out_idx] = a2;

@@ -722,6 +722,20 @@ __device__ __forceinline__ int64_t floor_div(int64_t num, int64_t den)
     return v;
 }
 
+// One nearby lens's term for the ray at (t1, t2): m (d1, d2)/|d|^2, d the
+// offset; a lens exactly on the ray adds nothing.  Explicit fused operations,
+// so every caller rounds the same way.
+__device__ __forceinline__ void near_term(double t1, double t2, double2 z, double m, double &n1,
+                                          double &n2)
+{
+    const double d1 = t1 - z.x, d2 = t2 - z.y;
+    const double rr = fma(d1, d1, d2 * d2);
+    double w = m * rcp64(rr);
+    w = rr > 0.0 ? w : 0.0;
+    n1 = fma(w, d1, n1);
+    n2 = fma(w, d2, n2);
+}
+
 __device__ __forceinline__ int wave_min(int v)
 {
 #pragma unroll
@@ -744,7 +758,7 @@ __global__ __launch_bounds__(kThreads) void k_level3(
     uint32_t *counts, unsigned long long *landed)
 {
     __shared__ uint32_t s_hist[kHistCap];
-    __shared__ int s_box[kThreads / kWave][4];
+    __shared__ int s_box[kThreads / kWave][5];
     // per ray row of the tile: theta_2, offset from its level-2 row, level-2
     // row within the band, level-1 row (computed once per row, not per ray)
     __shared__ double s_t2[kL3Rows], s_hi[kL3Rows];
@@ -774,10 +788,57 @@ __global__ __launch_bounds__(kThreads) void k_level3(
     const int32_t xl = cx > 0 ? cx - 1 : 0, xh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
     __syncthreads();
 
-    int32_t pxs[kL3RowsPerWave], pys[kL3RowsPerWave];
+    // nearby lenses, exactly.  A lane's rays are kL3RowsPerWave consecutive
+    // rows of one column; they nearly always share their level-1 cell row (a
+    // cell spans hundreds of ray rows), so one pass over the lenses serves
+    // them all; otherwise each ray takes its own pass.  Both add the same
+    // terms in the same order with the same operations.
+    constexpr int R = kL3RowsPerWave;
+    const int rl0 = wave * R;
+    double n1s[R], n2s[R];
 #pragma unroll
-    for (int k = 0; k < kL3RowsPerWave; ++k) {
-        const int rl = wave * kL3RowsPerWave + k;
+    for (int k = 0; k < R; ++k) n1s[k] = n2s[k] = 0.0;
+    if (in_col && jb + rl0 < jr1) {                       // wave-uniform rows
+        bool shared = true;
+#pragma unroll
+        for (int k = 1; k < R; ++k) shared = shared && s_cy[rl0 + k] == s_cy[rl0];
+        if (shared) {
+            double t2s[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) t2s[k] = s_t2[rl0 + k];
+            const int32_t cy = s_cy[rl0];
+            const int32_t yl = cy > 0 ? cy - 1 : 0, yh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
+            for (int32_t row = yl; row <= yh; ++row) {
+                const int32_t pb = cell_start[row * g.n1x + xl];
+                const int32_t pe = cell_start[row * g.n1x + xh + 1];
+                for (int32_t q_ = pb; q_ < pe; ++q_) {
+                    const double2 z = lxy[q_];
+                    const double m = UNIT ? 1.0 : lm[q_];
+#pragma unroll
+                    for (int k = 0; k < R; ++k) near_term(t1, t2s[k], z, m, n1s[k], n2s[k]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                if (jb + rl0 + k >= jr1) continue;
+                const double t2 = s_t2[rl0 + k];
+                const int32_t cy = s_cy[rl0 + k];
+                const int32_t yl = cy > 0 ? cy - 1 : 0, yh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
+                for (int32_t row = yl; row <= yh; ++row) {
+                    const int32_t pb = cell_start[row * g.n1x + xl];
+                    const int32_t pe = cell_start[row * g.n1x + xh + 1];
+                    for (int32_t q_ = pb; q_ < pe; ++q_)
+                        near_term(t1, t2, lxy[q_], UNIT ? 1.0 : lm[q_], n1s[k], n2s[k]);
+                }
+            }
+        }
+    }
+
+    int32_t pxs[R], pys[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int rl = rl0 + k;
         const int64_t j = jb + rl;
         const int64_t r = j * g.nx + i;
         const bool valid = in_col && j < jr1 && r >= ray_first && r < ray_last;
@@ -807,24 +868,8 @@ __global__ __launch_bounds__(kThreads) void k_level3(
                 A.i += g.kappa_star * hi;
             }
         }
-        // nearby lenses, exactly (a lens exactly on the ray adds nothing)
-        double n1 = 0.0, n2 = 0.0;
-        const int32_t yl = cy > 0 ? cy - 1 : 0, yh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
-        for (int32_t row = yl; row <= yh; ++row) {
-            const int32_t pb = cell_start[row * g.n1x + xl];
-            const int32_t pe = cell_start[row * g.n1x + xh + 1];
-            for (int32_t q_ = pb; q_ < pe; ++q_) {
-                const double2 z = lxy[q_];
-                const double d1 = t1 - z.x, d2 = t2 - z.y;
-                const double rr = d1 * d1 + d2 * d2;
-                double w = (UNIT ? 1.0 : lm[q_]) * rcp64(rr);
-                w = rr > 0.0 ? w : 0.0;
-                n1 += w * d1;
-                n2 += w * d2;
-            }
-        }
-        const double a1 = g.kpg * t1 + n1 + A.r;       // conj(A) is the far + sheet deflection
-        const double a2 = g.kmg * t2 + n2 - A.i;
+        const double a1 = g.kpg * t1 + n1s[k] + A.r;   // conj(A) is the far + sheet deflection
+        const double a2 = g.kmg * t2 + n2s[k] - A.i;
         pixel_xy(g, t1 - a1, t2 - a2, pxs[k], pys[k]);
         if (!counts) {
             const int64_t o = r - ray_first;
@@ -852,15 +897,18 @@ __global__ __launch_bounds__(kThreads) void k_level3(
     if (lane == 0) {
         s_box[wave][0] = bx0; s_box[wave][1] = bx1;
         s_box[wave][2] = by0; s_box[wave][3] = by1;
-        if (wl) atomicAdd(landed, wl);
+        s_box[wave][4] = (int)wl;
     }
     __syncthreads();
     bx0 = INT_MAX; bx1 = -1; by0 = INT_MAX; by1 = -1;
+    int nblock = 0;
 #pragma unroll
     for (int w = 0; w < kThreads / kWave; ++w) {
         bx0 = min(bx0, s_box[w][0]); bx1 = max(bx1, s_box[w][1]);
         by0 = min(by0, s_box[w][2]); by1 = max(by1, s_box[w][3]);
+        nblock += s_box[w][4];
     }
+    if (tid == 0 && nblock) landed_add(landed, (unsigned long long)nblock);
     if (bx1 < 0) return;                                   // nothing landed (block-uniform)
     const int bw = bx1 - bx0 + 1;
     const int64_t area = (int64_t)bw * (by1 - by0 + 1);

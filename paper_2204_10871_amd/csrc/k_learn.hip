@@ -927,7 +927,7 @@ __global__ __launch_bounds__(kL3Threads) void k_level3_learned(
             nland += __popcll(__ballot(pix >= 0));
         }
     }
-    if (counts && lane == 0 && nland) atomicAdd(landed, nland);
+    if (counts && lane == 0 && nland) landed_add(landed, nland);
 }
 
 int device_cus()
