@@ -920,18 +920,23 @@ __global__ __launch_bounds__(kThreads) void k_level3(
     }
     for (int b = tid; b < area; b += kThreads) s_hist[b] = 0u;
     __syncthreads();
-    // wave-aggregated LDS adds: lanes with the same bin are merged by ballot
+    // LDS adds by runs: a lane's rays are consecutive rows of one column and
+    // mostly land in one pixel, so each run of equal bins is added once
+    {
+        int32_t cur = -1;
+        uint32_t run = 0;
 #pragma unroll
-    for (int k = 0; k < kL3RowsPerWave; ++k) {
-        const int32_t lp = pxs[k] < 0 ? -1 : (pys[k] - by0) * bw + (pxs[k] - bx0);
-        uint64_t todo = __ballot(lp >= 0);
-        while (todo) {
-            const int leader = __ffsll((unsigned long long)todo) - 1;
-            const int32_t v = __shfl(lp, leader);
-            const uint64_t same = __ballot(lp == v) & todo;
-            if (lane == leader) atomicAdd(&s_hist[v], (uint32_t)__popcll(same));
-            todo &= ~same;
+        for (int k = 0; k < kL3RowsPerWave; ++k) {
+            const int32_t lp = pxs[k] < 0 ? -1 : (pys[k] - by0) * bw + (pxs[k] - bx0);
+            if (lp == cur) {
+                ++run;
+                continue;
+            }
+            if (cur >= 0) atomicAdd(&s_hist[cur], run);
+            cur = lp;
+            run = 1;
         }
+        if (cur >= 0) atomicAdd(&s_hist[cur], run);
     }
     __syncthreads();
     // flush: bin b is (row b / bw, column b % bw) of the box; the quotient
