@@ -725,15 +725,61 @@ __device__ __forceinline__ int64_t floor_div(int64_t num, int64_t den)
 // One nearby lens's term for the ray at (t1, t2): m (d1, d2)/|d|^2, d the
 // offset; a lens exactly on the ray adds nothing.  Explicit fused operations,
 // so every caller rounds the same way.
-__device__ __forceinline__ void near_term(double t1, double t2, double2 z, double m, double &n1,
-                                          double &n2)
+// Term of one nearby lens for a ray at (t1, t2): m (d1, d2)/(d1^2 + d2^2),
+// d = theta - z, with d1 and d1s = d1^2 + kNearTiny taken once per lens for
+// all rays of a column.  The quotient m/rr is the hardware reciprocal
+// estimate v times m, corrected once (w = y + v (m - rr y)), which squares
+// the estimate's relative error.  kNearTiny (far below the square of any
+// lens-ray distance that occurs) keeps rr > 0 where a lens sits exactly on
+// a ray, whose term is then exactly 0 because d = 0; it changes no other rr.
+constexpr double kNearTiny = 1e-300;
+
+__device__ __forceinline__ void near_term(double d1, double d1s, double t2, double zy, double m,
+                                          double &n1, double &n2)
 {
-    const double d1 = t1 - z.x, d2 = t2 - z.y;
-    const double rr = fma(d1, d1, d2 * d2);
-    double w = m * rcp64(rr);
-    w = rr > 0.0 ? w : 0.0;
+    const double d2 = t2 - zy;
+    const double rr = fma(d2, d2, d1s);
+    const double v = __builtin_amdgcn_rcp(rr);
+    const double y = m * v;
+    const double w = fma(v, fma(-rr, y, m), y);
     n1 = fma(w, d1, n1);
     n2 = fma(w, d2, n2);
+}
+
+// Nearby lenses of RR rays in one column (t1) and RR rows (t2s) that share
+// the level-1 cell row cy: the lenses of cells (xl..xh, cy-1..cy+1).  The
+// loop is the same for the whole wave: it runs over the lenses of cells
+// cl..ch (every lane's xl..xh lies inside, cl/ch/cy wave-uniform, so lens
+// data come through scalar loads); where the wave's lanes lie in more than
+// one cell column (straddle), a lane gives the lenses outside its own xl..xh
+// mass 0, which adds exact zeros.  Lenses are taken in their sorted order.
+template <bool UNIT, int RR>
+__device__ __forceinline__ void near_pass(const DevGeom &g, const double2 *__restrict__ lxy,
+                                          const double *__restrict__ lm,
+                                          const int32_t *__restrict__ cell_start, int32_t cy,
+                                          int32_t cl, int32_t ch, bool straddle, int32_t xl,
+                                          int32_t xh, double t1, const double *t2s, double *n1s,
+                                          double *n2s)
+{
+    const int32_t yl = cy > 0 ? cy - 1 : 0, yh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
+    for (int32_t row = yl; row <= yh; ++row) {
+        const int32_t pb = cell_start[row * g.n1x + cl];
+        const int32_t pe = cell_start[row * g.n1x + ch + 1];
+        int32_t lpb = pb, lpe = pe;
+        if (straddle) {
+            lpb = cell_start[row * g.n1x + xl];
+            lpe = cell_start[row * g.n1x + xh + 1];
+        }
+        for (int32_t q_ = pb; q_ < pe; ++q_) {
+            const double2 z = lxy[q_];
+            double m = UNIT ? 1.0 : lm[q_];
+            if (straddle) m = (q_ >= lpb && q_ < lpe) ? m : 0.0;
+            const double d1 = t1 - z.x;
+            const double d1s = fma(d1, d1, kNearTiny);
+#pragma unroll
+            for (int k = 0; k < RR; ++k) near_term(d1, d1s, t2s[k], z.y, m, n1s[k], n2s[k]);
+        }
+    }
 }
 
 __device__ __forceinline__ int wave_min(int v)
@@ -795,42 +841,33 @@ __global__ __launch_bounds__(kThreads) void k_level3(
     // terms in the same order with the same operations.
     constexpr int R = kL3RowsPerWave;
     const int rl0 = wave * R;
-    double n1s[R], n2s[R];
+    double n1s[R], n2s[R], t2s[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) n1s[k] = n2s[k] = 0.0;
-    if (in_col && jb + rl0 < jr1) {                       // wave-uniform rows
+    for (int k = 0; k < R; ++k) {
+        n1s[k] = n2s[k] = 0.0;
+        t2s[k] = s_t2[rl0 + k];
+    }
+    if (jb + rl0 < jr1) {                                 // wave-uniform rows
+        // level-1 columns of the wave's first and last ray (lane 0 always
+        // holds a ray column)
+        const int32_t cxa = __builtin_amdgcn_readfirstlane(cx);
+        const int32_t cxb = __builtin_amdgcn_readfirstlane(wave_max(in_col ? cx : cxa));
+        const int32_t cl = cxa > 0 ? cxa - 1 : 0, ch = cxb < g.n1x - 1 ? cxb + 1 : g.n1x - 1;
+        const bool straddle = cxa != cxb;
+        const int32_t cy0r = __builtin_amdgcn_readfirstlane(s_cy[rl0]);
         bool shared = true;
 #pragma unroll
-        for (int k = 1; k < R; ++k) shared = shared && s_cy[rl0 + k] == s_cy[rl0];
+        for (int k = 1; k < R; ++k) shared = shared && s_cy[rl0 + k] == cy0r;
         if (shared) {
-            double t2s[R];
-#pragma unroll
-            for (int k = 0; k < R; ++k) t2s[k] = s_t2[rl0 + k];
-            const int32_t cy = s_cy[rl0];
-            const int32_t yl = cy > 0 ? cy - 1 : 0, yh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
-            for (int32_t row = yl; row <= yh; ++row) {
-                const int32_t pb = cell_start[row * g.n1x + xl];
-                const int32_t pe = cell_start[row * g.n1x + xh + 1];
-                for (int32_t q_ = pb; q_ < pe; ++q_) {
-                    const double2 z = lxy[q_];
-                    const double m = UNIT ? 1.0 : lm[q_];
-#pragma unroll
-                    for (int k = 0; k < R; ++k) near_term(t1, t2s[k], z, m, n1s[k], n2s[k]);
-                }
-            }
+            near_pass<UNIT, R>(g, lxy, lm, cell_start, cy0r, cl, ch, straddle, xl, xh, t1, t2s,
+                               n1s, n2s);
         } else {
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 if (jb + rl0 + k >= jr1) continue;
-                const double t2 = s_t2[rl0 + k];
-                const int32_t cy = s_cy[rl0 + k];
-                const int32_t yl = cy > 0 ? cy - 1 : 0, yh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
-                for (int32_t row = yl; row <= yh; ++row) {
-                    const int32_t pb = cell_start[row * g.n1x + xl];
-                    const int32_t pe = cell_start[row * g.n1x + xh + 1];
-                    for (int32_t q_ = pb; q_ < pe; ++q_)
-                        near_term(t1, t2, lxy[q_], UNIT ? 1.0 : lm[q_], n1s[k], n2s[k]);
-                }
+                const int32_t cyk = __builtin_amdgcn_readfirstlane(s_cy[rl0 + k]);
+                near_pass<UNIT, 1>(g, lxy, lm, cell_start, cyk, cl, ch, straddle, xl, xh, t1,
+                                   &t2s[k], &n1s[k], &n2s[k]);
             }
         }
     }
