@@ -89,6 +89,7 @@ DevGeom make_dev_geom(const HostGeometry &hg)
     d.half_side = 0.5 * hg.source_side;
     d.dpix = g.dpix;
     d.inv_dpix = 1.0 / g.dpix;
+    d.sheet_f = -hg.kappa_star / M_PI;
     d.npix = (int32_t)hg.npix;
     d.sheet = hg.sheet ? 1 : 0;
     d.n1x = (int32_t)g.n1x;
@@ -110,6 +111,7 @@ void release(irs_plan_s *p)
     dev_free(p->d_cell_start);
     dev_free(p->d_cxy);
     dev_free(p->d_xy);
+    dev_free(p->d_rows);
     dev_free(p->d_coef);
     dev_free(p->d_part);
     dev_free(p->d_super);

@@ -703,15 +703,28 @@ __global__ __launch_bounds__(kThreads) void k_level2_points(
 // Level 3: one workgroup = a 64 x 32 tile of rays (lane = column, each wave 8
 // rows).  Every ray: Horner of its level-2 point's C_0..C_4, the sheet's
 // linear term (closed form in corner cells), the near lenses exactly, the
-// macro term, beta and the pixel.  Binning: the tile's rays land in a small
-// patch of the map, so the workgroup finds the bounding box of its landed
-// pixels, counts into an LDS histogram over that box (wave-aggregated LDS
-// adds) and flushes each non-empty bin with one global atomic; a box larger
-// than the LDS histogram falls back to wave-aggregated global atomics.
+// macro term, beta and the pixel.  What depends on the ray row only (theta_2,
+// its level-2 and level-1 rows, the offset from the level-2 row) comes from a
+// per-plan row table through scalar loads, so a wave's rows cost no vector
+// work; a lane's rows share their level-2 point's coefficients until the
+// level-2 row changes.  Binning: the tile's rays land in a small patch of the
+// map, so the workgroup finds the bounding box of its landed pixels, counts
+// into an LDS histogram over that box and flushes each non-empty bin with one
+// global atomic; a box larger than the LDS histogram falls back to
+// wave-aggregated global atomics.
 // -------------------------------------------------------------------------
 constexpr int kL3Rows = 32;
 constexpr int kL3RowsPerWave = kL3Rows / (kThreads / kWave);
 constexpr int kHistCap = 8192;
+
+// One ray row of the plan's ray grid, as the level-3 kernel reads it.
+struct alignas(32) RowInfo {
+    double t2;        // theta_2 of the row
+    double hi;        // t2 minus the y of its level-2 row
+    int32_t gy;       // level-2 row
+    int32_t cy;       // level-1 row
+    int64_t base;     // index of the row's first ray (j nx)
+};
 
 // floor(num / den) for 0 <= num < 2^53, den > 0, without 64-bit integer division
 __device__ __forceinline__ int64_t floor_div(int64_t num, int64_t den)
@@ -722,9 +735,6 @@ __device__ __forceinline__ int64_t floor_div(int64_t num, int64_t den)
     return v;
 }
 
-// One nearby lens's term for the ray at (t1, t2): m (d1, d2)/|d|^2, d the
-// offset; a lens exactly on the ray adds nothing.  Explicit fused operations,
-// so every caller rounds the same way.
 // Term of one nearby lens for a ray at (t1, t2): m (d1, d2)/(d1^2 + d2^2),
 // d = theta - z, with d1 and d1s = d1^2 + kNearTiny taken once per lens for
 // all rays of a column.  The quotient m/rr is the hardware reciprocal
@@ -795,35 +805,41 @@ __device__ __forceinline__ int wave_max(int v)
     return v;
 }
 
+__global__ __launch_bounds__(kThreads) void k_row_table(DevGeom g, RowInfo *rows)
+{
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (j >= g.ny) return;
+    const int64_t gy = floor_div((2 * j + 1) * (int64_t)g.n1y * g.q, 2 * g.ny);
+    RowInfo r;
+    r.t2 = ray_y(g, j);
+    r.hi = r.t2 - level2_y(g, gy);
+    r.gy = (int32_t)gy;
+    r.cy = (int32_t)(gy / g.q);
+    r.base = j * g.nx;
+    rows[j] = r;
+}
+
 template <bool UNIT>
-__global__ __launch_bounds__(kThreads) void k_level3(
+__global__ __launch_bounds__(kThreads, 4) void k_level3(
     DevGeom g, const double2 *__restrict__ lxy, const double *__restrict__ lm,
-    const int32_t *__restrict__ cell_start,
+    const int32_t *__restrict__ cell_start, const RowInfo *__restrict__ rows,
     const double *__restrict__ coef, int32_t cy0, int64_t ntx, int64_t jr0, int64_t jr1,
     int64_t ray_first, int64_t ray_last, double *a1o, double *a2o, int64_t *pixo,
     uint32_t *counts, unsigned long long *landed)
 {
     __shared__ uint32_t s_hist[kHistCap];
     __shared__ int s_box[kThreads / kWave][5];
-    // per ray row of the tile: theta_2, offset from its level-2 row, level-2
-    // row within the band, level-1 row (computed once per row, not per ray)
-    __shared__ double s_t2[kL3Rows], s_hi[kL3Rows];
-    __shared__ int32_t s_gyl[kL3Rows], s_cy[kL3Rows];
+    __shared__ double s_t2[kL3Rows];
 
     const int tid = threadIdx.x;
-    const int lane = tid % kWave, wave = tid / kWave;
+    const int lane = tid % kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int64_t tx = (int64_t)blockIdx.x % ntx;
     const int64_t ty = (int64_t)blockIdx.x / ntx;
+    constexpr int R = kL3RowsPerWave;
     const int64_t jb = jr0 + ty * kL3Rows;
-    if (tid < kL3Rows) {
-        const int64_t j = jb + tid;
-        const int64_t gy = floor_div((2 * j + 1) * (int64_t)g.n1y * g.q, 2 * g.ny);
-        const double t2 = ray_y(g, j);
-        s_t2[tid] = t2;
-        s_hi[tid] = t2 - level2_y(g, gy);
-        s_gyl[tid] = (int32_t)(gy - (int64_t)cy0 * g.q);
-        s_cy[tid] = (int32_t)gy / g.q;
-    }
+    const int64_t jw = jb + wave * R;                    // the wave's first row
+    if (tid < kL3Rows) s_t2[tid] = rows[min(jb + tid, jr1 - 1)].t2;
     const int64_t i = tx * kWave + lane;
     const bool in_col = i < g.nx;
     const int64_t nxq = (int64_t)g.n1x * g.q;
@@ -832,74 +848,92 @@ __global__ __launch_bounds__(kThreads) void k_level3(
     const double t1 = ray_x(g, i);
     const double hr = t1 - level2_x(g, gx);
     const int32_t xl = cx > 0 ? cx - 1 : 0, xh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
-    __syncthreads();
+    const uint32_t coff = (uint32_t)gx * 10u * (uint32_t)sizeof(double);   // lane's point in a row
 
-    // nearby lenses, exactly.  A lane's rays are kL3RowsPerWave consecutive
-    // rows of one column; they nearly always share their level-1 cell row (a
-    // cell spans hundreds of ray rows), so one pass over the lenses serves
-    // them all; otherwise each ray takes its own pass.  Both add the same
-    // terms in the same order with the same operations.
-    constexpr int R = kL3RowsPerWave;
-    const int rl0 = wave * R;
+    // the wave's rows (rows past jr1 repeat the last one and bin nothing)
+    const RowInfo *rw = rows + min(jw, jr1 - 1);
+    const int nr = (int)min<int64_t>(R, jr1 - jw);       // rows of the wave inside [jr0, jr1)
+    auto row = [&](int k) -> const RowInfo & { return rw[k < nr ? k : (nr > 0 ? nr - 1 : 0)]; };
+
+    // nearby lenses, exactly.  A lane's rays are R consecutive rows of one
+    // column; they nearly always share their level-1 cell row (a cell spans
+    // hundreds of ray rows), so one pass over the lenses serves them all;
+    // otherwise each ray takes its own pass.  Both add the same terms in the
+    // same order with the same operations.
+    __syncthreads();
     double n1s[R], n2s[R], t2s[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         n1s[k] = n2s[k] = 0.0;
-        t2s[k] = s_t2[rl0 + k];
+        t2s[k] = s_t2[wave * R + k];     // row(k).t2, in a vector register
     }
-    if (jb + rl0 < jr1) {                                 // wave-uniform rows
+    if (nr > 0) {                                         // wave-uniform rows
         // level-1 columns of the wave's first and last ray (lane 0 always
         // holds a ray column)
         const int32_t cxa = __builtin_amdgcn_readfirstlane(cx);
         const int32_t cxb = __builtin_amdgcn_readfirstlane(wave_max(in_col ? cx : cxa));
         const int32_t cl = cxa > 0 ? cxa - 1 : 0, ch = cxb < g.n1x - 1 ? cxb + 1 : g.n1x - 1;
         const bool straddle = cxa != cxb;
-        const int32_t cy0r = __builtin_amdgcn_readfirstlane(s_cy[rl0]);
-        bool shared = true;
-#pragma unroll
-        for (int k = 1; k < R; ++k) shared = shared && s_cy[rl0 + k] == cy0r;
-        if (shared) {
+        const int32_t cy0r = row(0).cy;
+        if (row(R - 1).cy == cy0r) {                      // rows sorted: all share cy0r
             near_pass<UNIT, R>(g, lxy, lm, cell_start, cy0r, cl, ch, straddle, xl, xh, t1, t2s,
                                n1s, n2s);
         } else {
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                if (jb + rl0 + k >= jr1) continue;
-                const int32_t cyk = __builtin_amdgcn_readfirstlane(s_cy[rl0 + k]);
-                near_pass<UNIT, 1>(g, lxy, lm, cell_start, cyk, cl, ch, straddle, xl, xh, t1,
-                                   &t2s[k], &n1s[k], &n2s[k]);
+                if (k >= nr) continue;
+                near_pass<UNIT, 1>(g, lxy, lm, cell_start, row(k).cy, cl, ch, straddle, xl, xh,
+                                   t1, &t2s[k], &n1s[k], &n2s[k]);
             }
         }
     }
 
+    // coefficients of a lane's level-2 point in band row gy
+    auto coef_row = [&](int32_t gy) {
+        return (const double2 *)((const char *)(coef + (int64_t)(gy - cy0 * g.q) * nxq * 10) + coff);
+    };
+    double2 C[5];
+    int32_t cgy = row(0).gy;
+    {
+        const double2 *cp = coef_row(cgy);
+#pragma unroll
+        for (int e = 0; e < 5; ++e) C[e] = cp[e];
+    }
+
+    const int32_t i32 = (int32_t)i;
     int32_t pxs[R], pys[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        const int rl = rl0 + k;
-        const int64_t j = jb + rl;
-        const int64_t r = j * g.nx + i;
-        const bool valid = in_col && j < jr1 && r >= ray_first && r < ray_last;
+        // columns of row j inside [ray_first, ray_last), as a lane window
+        const int64_t lo = ray_first - row(k).base, hi_ = ray_last - row(k).base;
+        const int32_t wlo = (int32_t)(lo < 0 ? 0 : (lo > g.nx ? g.nx : lo));
+        const int32_t whi = (int32_t)(hi_ < 0 ? 0 : (hi_ > g.nx ? g.nx : hi_));
+        const bool valid = k < nr && i32 >= wlo && i32 < whi;
         pxs[k] = -1;
         pys[k] = -1;
         if (!valid) continue;
-        const double t2 = s_t2[rl], hi = s_hi[rl];
-        const int32_t cy = s_cy[rl];
-        const double *C = coef + ((int64_t)s_gyl[rl] * nxq + gx) * 10;
+        if (row(k).gy != cgy) {                            // wave-uniform: next level-2 row
+            const double2 *cp = coef_row(row(k).gy);
+#pragma unroll
+            for (int e = 0; e < 5; ++e) C[e] = cp[e];
+            cgy = row(k).gy;
+        }
+        const double t2 = row(k).t2, hi = row(k).hi;
+        const int32_t cy = row(k).cy;
         // Horner: C0 + h (C1 + h (C2 + h (C3 + h C4)))
-        cplx A = {C[8], C[9]};
+        cplx A = {C[4].x, C[4].y};
 #pragma unroll
         for (int o = 3; o >= 0; --o) {
             A = cmul(A, cplx{hr, hi});
-            A.r += C[2 * o];
-            A.i += C[2 * o + 1];
+            A.r += C[o].x;
+            A.i += C[o].y;
         }
         if (g.sheet) {
             if (corner_cell(g, cx, cy)) {
                 double I1, I2;
                 sheet_unit(g, t1, t2, I1, I2);
-                const double f = -g.kappa_star / M_PI;
-                A.r += f * I1;
-                A.i -= f * I2;
+                A.r += g.sheet_f * I1;
+                A.i -= g.sheet_f * I2;
             } else {
                 A.r -= g.kappa_star * hr;     // -kappa_* conj(h)
                 A.i += g.kappa_star * hi;
@@ -909,7 +943,7 @@ __global__ __launch_bounds__(kThreads) void k_level3(
         const double a2 = g.kmg * t2 + n2s[k] - A.i;
         pixel_xy(g, t1 - a1, t2 - a2, pxs[k], pys[k]);
         if (!counts) {
-            const int64_t o = r - ray_first;
+            const int64_t o = row(k).base + i - ray_first;
             if (a1o) a1o[o] = a1;
             if (a2o) a2o[o] = a2;
             if (pixo) pixo[o] = pxs[k] < 0 ? -1 : (int64_t)pys[k] * g.npix + pxs[k];
@@ -1277,11 +1311,28 @@ irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *f
     return IRS_OK;
 }
 
+// The level-3 row table (geometry only, built once per plan; the build waits
+// for its kernel, so work on other streams may read the table at once).
+irs_status ensure_rows(irs_plan_s *p)
+{
+    if (p->d_rows) return IRS_OK;
+    const DevGeom &g = p->dg;
+    IRS_HIP(hipMalloc(&p->d_rows, (size_t)g.ny * sizeof(RowInfo)));
+    const unsigned nb = (unsigned)((g.ny + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_row_table, dim3(nb), dim3(kThreads), 0, p->stream, g,
+                       (RowInfo *)p->d_rows);
+    IRS_HIP(hipGetLastError());
+    IRS_HIP(hipStreamSynchronize(p->stream));
+    return IRS_OK;
+}
+
 irs_status interp_prepare(irs_plan_s *p)
 {
     p->coef_c0 = -1;                 // nothing resident that a replay could rely on
     p->coef_c1 = -2;
-    irs_status st = ensure_bands(p, band_rows(p));
+    irs_status st = ensure_rows(p);
+    if (st != IRS_OK) return st;
+    st = ensure_bands(p, band_rows(p));
     if (st != IRS_OK) return st;
     return level2_prepare(p);
 }
@@ -1329,7 +1380,9 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
     const int64_t cyA = level2_row_host(g, sel.row0) / q;
     const int64_t cyB = level2_row_host(g, sel.row1 - 1) / q;  // inclusive
     const int64_t want = cyB - cyA + 1;
-    irs_status st0 = ensure_bands(p, std::min(band_rows(p), want));
+    irs_status st0 = ensure_rows(p);
+    if (st0 != IRS_OK) return st0;
+    st0 = ensure_bands(p, std::min(band_rows(p), want));
     if (st0 != IRS_OK) return st0;
     const int64_t ntx = (g.nx + kWave - 1) / kWave;
     const int rows_per_block = kL3Rows;
@@ -1432,12 +1485,14 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
             }
             if (p->unit_mass)
                 hipLaunchKernelGGL(k_level3<true>, dim3(nb3), dim3(kThreads), 0, s, g,
-                                   (const double2 *)p->d_xy, p->d_m, p->d_cell_start, p->d_coef, band0, ntx,
+                                   (const double2 *)p->d_xy, p->d_m, p->d_cell_start,
+                                   (const RowInfo *)p->d_rows, p->d_coef, band0, ntx,
                                    j0, j1, sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2,
                                    sel.pixel, sel.counts, sel.landed);
             else
                 hipLaunchKernelGGL(k_level3<false>, dim3(nb3), dim3(kThreads), 0, s, g,
-                                   (const double2 *)p->d_xy, p->d_m, p->d_cell_start, p->d_coef, band0, ntx,
+                                   (const double2 *)p->d_xy, p->d_m, p->d_cell_start,
+                                   (const RowInfo *)p->d_rows, p->d_coef, band0, ntx,
                                    j0, j1, sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2,
                                    sel.pixel, sel.counts, sel.landed);
             IRS_HIP(hipGetLastError());
