@@ -901,14 +901,21 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
     }
 
     const int32_t i32 = (int32_t)i;
+    // rows whose rays all lie in [ray_first, ray_last) need no per-ray test
+    const bool full = nr > 0 && row(0).base >= ray_first && row(nr - 1).base + g.nx <= ray_last;
     int32_t pxs[R], pys[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        // columns of row j inside [ray_first, ray_last), as a lane window
-        const int64_t lo = ray_first - row(k).base, hi_ = ray_last - row(k).base;
-        const int32_t wlo = (int32_t)(lo < 0 ? 0 : (lo > g.nx ? g.nx : lo));
-        const int32_t whi = (int32_t)(hi_ < 0 ? 0 : (hi_ > g.nx ? g.nx : hi_));
-        const bool valid = k < nr && i32 >= wlo && i32 < whi;
+        bool valid;
+        if (full) {
+            valid = k < nr && in_col;
+        } else {
+            // columns of row k inside [ray_first, ray_last), as a lane window
+            const int64_t lo = ray_first - row(k).base, hi_ = ray_last - row(k).base;
+            const int32_t wlo = (int32_t)(lo < 0 ? 0 : (lo > g.nx ? g.nx : lo));
+            const int32_t whi = (int32_t)(hi_ < 0 ? 0 : (hi_ > g.nx ? g.nx : hi_));
+            valid = k < nr && i32 >= wlo && i32 < whi;
+        }
         pxs[k] = -1;
         pys[k] = -1;
         if (!valid) continue;
