@@ -710,8 +710,8 @@ __global__ __launch_bounds__(kThreads) void k_level2_points(
 // level-2 row changes.  Binning: the tile's rays land in a small patch of the
 // map, so the workgroup finds the bounding box of its landed pixels, counts
 // into an LDS histogram over that box and flushes each non-empty bin with one
-// global atomic; a box larger than the LDS histogram falls back to
-// wave-aggregated global atomics.
+// global atomic; a box larger than the LDS histogram (rays scattered, as near
+// a lens) falls back to one global add per run of equal pixels in a lane.
 // -------------------------------------------------------------------------
 constexpr int kL3Rows = 32;
 constexpr int kL3RowsPerWave = kL3Rows / (kThreads / kWave);
@@ -819,7 +819,9 @@ __global__ __launch_bounds__(kThreads) void k_row_table(DevGeom g, RowInfo *rows
     rows[j] = r;
 }
 
-template <bool UNIT>
+// BIN: count rays into `counts` (a1o, a2o, pixo unused); otherwise write the
+// per-ray outputs (counts, landed unused).
+template <bool UNIT, bool BIN>
 __global__ __launch_bounds__(kThreads, 4) void k_level3(
     DevGeom g, const double2 *__restrict__ lxy, const double *__restrict__ lm,
     const int32_t *__restrict__ cell_start, const RowInfo *__restrict__ rows,
@@ -949,14 +951,14 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
         const double a1 = g.kpg * t1 + n1s[k] + A.r;   // conj(A) is the far + sheet deflection
         const double a2 = g.kmg * t2 + n2s[k] - A.i;
         pixel_xy(g, t1 - a1, t2 - a2, pxs[k], pys[k]);
-        if (!counts) {
+        if (!BIN) {
             const int64_t o = row(k).base + i - ray_first;
             if (a1o) a1o[o] = a1;
             if (a2o) a2o[o] = a2;
             if (pixo) pixo[o] = pxs[k] < 0 ? -1 : (int64_t)pys[k] * g.npix + pxs[k];
         }
     }
-    if (!counts) return;
+    if (!BIN) return;
 
     // bounding box of the tile's landed pixels
     int bx0 = INT_MAX, bx1 = -1, by0 = INT_MAX, by1 = -1, nland = 0;
@@ -990,10 +992,23 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
     if (bx1 < 0) return;                                   // nothing landed (block-uniform)
     const int bw = bx1 - bx0 + 1;
     const int64_t area = (int64_t)bw * (by1 - by0 + 1);
-    if (area > kHistCap) {                                 // block-uniform fallback
+    if (area > kHistCap) {
+        // block-uniform fallback (rays scattered, as near a lens): global
+        // adds by runs of equal pixels down a lane's rows
+        int32_t cur = -1;
+        uint32_t run = 0;
 #pragma unroll
-        for (int k = 0; k < kL3RowsPerWave; ++k)
-            bin_wave(counts, pxs[k] < 0 ? -1 : pys[k] * g.npix + pxs[k]);
+        for (int k = 0; k < kL3RowsPerWave; ++k) {
+            const int32_t pix = pxs[k] < 0 ? -1 : pys[k] * g.npix + pxs[k];
+            if (pix == cur) {
+                ++run;
+                continue;
+            }
+            if (cur >= 0) atomicAdd(&counts[cur], run);
+            cur = pix;
+            run = 1;
+        }
+        if (cur >= 0) atomicAdd(&counts[cur], run);
         return;
     }
     for (int b = tid; b < area; b += kThreads) s_hist[b] = 0u;
@@ -1490,18 +1505,21 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
                 cs->n_rays++;
                 cs->ray_flops += level3_flops(p, std::max(j0, sel.row0), std::min(j1, sel.row1));
             }
-            if (p->unit_mass)
-                hipLaunchKernelGGL(k_level3<true>, dim3(nb3), dim3(kThreads), 0, s, g,
-                                   (const double2 *)p->d_xy, p->d_m, p->d_cell_start,
-                                   (const RowInfo *)p->d_rows, p->d_coef, band0, ntx,
-                                   j0, j1, sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2,
-                                   sel.pixel, sel.counts, sel.landed);
-            else
-                hipLaunchKernelGGL(k_level3<false>, dim3(nb3), dim3(kThreads), 0, s, g,
-                                   (const double2 *)p->d_xy, p->d_m, p->d_cell_start,
-                                   (const RowInfo *)p->d_rows, p->d_coef, band0, ntx,
-                                   j0, j1, sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2,
-                                   sel.pixel, sel.counts, sel.landed);
+#define IRS_L3(U, B)                                                                          \
+    hipLaunchKernelGGL((k_level3<U, B>), dim3(nb3), dim3(kThreads), 0, s, g,                  \
+                       (const double2 *)p->d_xy, p->d_m, p->d_cell_start,                     \
+                       (const RowInfo *)p->d_rows, p->d_coef, band0, ntx, j0, j1,             \
+                       sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2, sel.pixel,         \
+                       sel.counts, sel.landed)
+            const bool bin = sel.counts != nullptr;
+            if (p->unit_mass) {
+                if (bin) IRS_L3(true, true);
+                else IRS_L3(true, false);
+            } else {
+                if (bin) IRS_L3(false, true);
+                else IRS_L3(false, false);
+            }
+#undef IRS_L3
             IRS_HIP(hipGetLastError());
             if (cs) {
                 irs_status st = cs->end(s);
