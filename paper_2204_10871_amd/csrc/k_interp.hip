@@ -339,17 +339,19 @@ __global__ __launch_bounds__(kThreads) void k_level2_expand(
 // and the latter, at most (2 R_S + 1)^2 K_S^2 cells of lenses, are summed into
 // Lt per cell directly.  The cell expansion is the same series as summing all
 // distant lenses into it, to FP64 rounding; the work per cell drops from N_*
-// lenses to about (2 R_S + 1)^2 K_S^2 lenses plus N_* / K_S^2.
+// lenses to about (2 R_S + 1)^2 K_S^2 lenses plus N_* / K_S^2, and K_S is
+// chosen per plan to balance the two (super_side).
 // -------------------------------------------------------------------------
-constexpr int kSuperK = 8;                     // level-1 cells per super-cell side
 constexpr int kSuperR = 2;                     // R_S
+constexpr int kSuperKMax = 32;                 // largest super-cell side (cells)
 
-__device__ __forceinline__ void super_centre(const DevGeom &g, int32_t X, int32_t Y, double &zr,
-                                             double &zi, double &sS)
+// centre and scale of super cell (X, Y) of side ks cells
+__device__ __forceinline__ void super_centre(const DevGeom &g, int32_t X, int32_t Y, int32_t ks,
+                                             double &zr, double &zi, double &sS)
 {
-    zr = g.a1 + ((double)(kSuperK * X) + 0.5 * kSuperK) * g.w1;
-    zi = g.b1 + ((double)(kSuperK * Y) + 0.5 * kSuperK) * g.h1;
-    sS = kSuperK * fmax(g.w1, g.h1);
+    zr = g.a1 + ((double)(ks * X) + 0.5 * ks) * g.w1;
+    zi = g.b1 + ((double)(ks * Y) + 0.5 * ks) * g.h1;
+    sS = ks * fmax(g.w1, g.h1);
 }
 
 // partial super expansions: one wave per super cell, four per workgroup,
@@ -358,7 +360,8 @@ template <bool UNIT, int PS>
 __global__ __launch_bounds__(kThreads) void k_super_expand(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
     const double *__restrict__ lm, const uint32_t *__restrict__ lcxy, int32_t nl, int32_t Y0,
-    int32_t nSx, int32_t nSxb, int32_t nchunk, int32_t chunk_len, double *__restrict__ part)
+    int32_t nSx, int32_t nSxb, int32_t nchunk, int32_t chunk_len, int32_t ks,
+    double *__restrict__ part)
 {
     __shared__ double s_x[kThreads], s_y[kThreads], s_m[UNIT ? 1 : kThreads];
     __shared__ uint32_t s_c[kThreads];
@@ -370,7 +373,7 @@ __global__ __launch_bounds__(kThreads) void k_super_expand(
     const int32_t X = (group % nSxb) * kCellsPerBlock + wave;
     const bool live = X < nSx;
     double zr, zi, sS;
-    super_centre(g, X, Y, zr, zi, sS);
+    super_centre(g, X, Y, ks, zr, zi, sS);
     const double isc = 1.0 / sS;
     const int32_t lo = chunk * chunk_len;
     const int32_t hi = min(nl, lo + chunk_len);
@@ -397,7 +400,7 @@ __global__ __launch_bounds__(kThreads) void k_super_expand(
                 double Xl = zr + sS, Yl = zi, M = 0.0;     // harmless stand-in
                 if (use) {
                     const uint32_t c = s_c[t];
-                    const int32_t sx = (int32_t)(c & 0xffffu) / kSuperK, sy = (int32_t)(c >> 16) / kSuperK;
+                    const int32_t sx = (int32_t)(c & 0xffffu) / ks, sy = (int32_t)(c >> 16) / ks;
                     use = abs(sx - X) > kSuperR || abs(sy - Y) > kSuperR;
                     if (use) {
                         Xl = s_x[t];
@@ -456,14 +459,14 @@ __global__ __launch_bounds__(kThreads) void k_super_reduce(const double *__restr
 // the cell plus the lenses of the super block outside the cell's 7 x 7 block.
 // One wave per cell, four cells (of one super cell) per workgroup.
 // out[(((cy - c0) n1x + cx) P + n) 2 + c]
-constexpr int kSuperRows = (2 * kSuperR + 1) * kSuperK;    // cell rows of a super block
+constexpr int kSuperRows = (2 * kSuperR + 1) * kSuperKMax; // cell rows of a super block, at most
 
 template <bool UNIT, int P, int PS>
 __global__ __launch_bounds__(kThreads) void k_level2_near(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
     const double *__restrict__ lm, const uint32_t *__restrict__ lcxy,
     const int32_t *__restrict__ cell_start, const double *__restrict__ super, int32_t nSx,
-    int32_t c0, int32_t nxb, double *__restrict__ out)
+    int32_t c0, int32_t nxb, int32_t ks, double *__restrict__ out)
 {
     __shared__ double s_x[kThreads], s_y[kThreads], s_m[UNIT ? 1 : kThreads];
     __shared__ uint32_t s_c[kThreads];
@@ -475,11 +478,11 @@ __global__ __launch_bounds__(kThreads) void k_level2_near(
     const int32_t cx0 = (int32_t)(blockIdx.x % (uint32_t)nxb) * kCellsPerBlock;
     const int32_t cx = cx0 + wave;
     const bool live = cx < g.n1x;
-    const int32_t X = cx0 / kSuperK, Y = cy / kSuperK;
+    const int32_t X = cx0 / ks, Y = cy / ks;             // ks is a multiple of kCellsPerBlock
     // the super expansion and the lens ranges of the super block, row by row
     for (int e = tid; e < PS * 2; e += kThreads) s_E[e / 2][e % 2] = super[((int64_t)Y * nSx + X) * PS * 2 + e];
-    const int32_t ya = max(0, (Y - kSuperR) * kSuperK), yb = min(g.n1y, (Y + kSuperR + 1) * kSuperK);
-    const int32_t xa = max(0, (X - kSuperR) * kSuperK), xb = min(g.n1x, (X + kSuperR + 1) * kSuperK);
+    const int32_t ya = max(0, (Y - kSuperR) * ks), yb = min(g.n1y, (Y + kSuperR + 1) * ks);
+    const int32_t xa = max(0, (X - kSuperR) * ks), xb = min(g.n1x, (X + kSuperR + 1) * ks);
     const int nrow = yb - ya;
     if (tid < nrow) {
         const int32_t row = ya + tid;
@@ -505,8 +508,12 @@ __global__ __launch_bounds__(kThreads) void k_level2_near(
         __syncthreads();
         if (base + tid < total) {
             const int32_t gi = base + tid;
-            int r = 0;
-            while (s_off[r + 1] <= gi) ++r;            // row of this lens (at most 40 rows)
+            int r = 0, rh = nrow - 1;                  // row of this lens: s_off[r] <= gi < s_off[r + 1]
+            while (r < rh) {
+                const int mid = (r + rh + 1) >> 1;
+                if (s_off[mid] <= gi) r = mid;
+                else rh = mid - 1;
+            }
             const int32_t li = s_pb[r] + (gi - s_off[r]);
             s_x[tid] = lx[li];
             s_y[tid] = ly[li];
@@ -558,7 +565,7 @@ __global__ __launch_bounds__(kThreads) void k_level2_near(
     double Tr = 0.0, Ti = 0.0;
     {
         double zSr, zSi, sS;
-        super_centre(g, X, Y, zSr, zSi, sS);
+        super_centre(g, X, Y, ks, zSr, zSi, sS);
         const double dr = (zcr - zSr) / sS, di = (zci - zSi) / sS;
         const int k = lane;
         if (k < P) {
@@ -1140,8 +1147,10 @@ int super_order(const irs_plan_s *p)
 {
     if (level2_order(p) == 0) return 0;
     const DevGeom &g = p->dg;
-    const double rho = 0.5 * kSuperK * std::sqrt(g.w1 * g.w1 + g.h1 * g.h1) /
-                       ((kSuperR + 0.5) * kSuperK * std::min(g.w1, g.h1));
+    // the super block's half-diagonal over the distance to the nearest
+    // excluded lens: independent of the super-cell side
+    const double rho = 0.5 * std::sqrt(g.w1 * g.w1 + g.h1 * g.h1) /
+                       ((kSuperR + 0.5) * std::min(g.w1, g.h1));
     for (int P : {32, 48}) {
         double c4 = (double)P * (P - 1) * (P - 2) * (P - 3) / 24.0;
         if (c4 * std::pow(rho, P - 4) / std::pow(1.0 - rho, 5) < 1e-14) return P;
@@ -1157,10 +1166,37 @@ int32_t level2_chunks(const irs_plan_s *p)
 
 void level2_reset(irs_plan_s *p) { std::fill(p->super_ok.begin(), p->super_ok.end(), 0); }
 
+// Super-cell side K (cells, a multiple of kCellsPerBlock), once per plan.
+// The super expansions cost about N_* (n1x n1y / K^2) PS terms, the
+// per-cell sums over the super block about n1x n1y min(N_*, nu (2 R_S + 1)^2
+// K^2) P terms (nu = lenses per cell); K in {4, 8, 16, 32} with the smaller
+// total.  The accuracy of either series does not depend on K.
+int32_t super_side(irs_plan_s *p)
+{
+    if (p->super_k > 0) return p->super_k;
+    const DevGeom &g = p->dg;
+    const double cells = (double)g.n1x * (double)g.n1y, nl = (double)p->n_lens;
+    const double nu = cells > 0.0 ? nl / cells : 0.0;
+    const double PS = std::max(1, super_order(p)), P = std::max(1, level2_order(p));
+    int32_t best = 8;
+    double best_cost = -1.0;
+    for (int32_t K : {4, 8, 16, 32}) {
+        const double nS = std::ceil(g.n1x / (double)K) * std::ceil(g.n1y / (double)K);
+        const double block = (double)(2 * kSuperR + 1) * K;
+        const double cost = nl * nS * PS + cells * std::min(nl, nu * block * block) * P;
+        if (best_cost < 0.0 || cost < best_cost) {
+            best_cost = cost;
+            best = K;
+        }
+    }
+    p->super_k = best;
+    return best;
+}
+
 namespace {
 
-int32_t super_nx(const DevGeom &g) { return (g.n1x + kSuperK - 1) / kSuperK; }
-int32_t super_ny(const DevGeom &g) { return (g.n1y + kSuperK - 1) / kSuperK; }
+int32_t super_nx(irs_plan_s *p) { const int32_t k = super_side(p); return (p->dg.n1x + k - 1) / k; }
+int32_t super_ny(irs_plan_s *p) { const int32_t k = super_side(p); return (p->dg.n1y + k - 1) / k; }
 int32_t lens_chunks(const irs_plan_s *p)
 {
     return p->n_lens > 0 ? (int32_t)((p->n_lens + kChunkLens - 1) / kChunkLens) : 1;
@@ -1170,7 +1206,7 @@ irs_status ensure_super_buffers(irs_plan_s *p, int64_t rows)
 {
     const DevGeom &g = p->dg;
     const int PS = super_order(p);
-    const int32_t nSx = super_nx(g), nSy = super_ny(g);
+    const int32_t nSx = super_nx(p), nSy = super_ny(p);
     if (!p->d_super) {
         if (hipMalloc(&p->d_super, sizeof(double) * (size_t)nSy * nSx * PS * 2) != hipSuccess) {
             (void)hipGetLastError();
@@ -1215,7 +1251,8 @@ irs_status ensure_super_rows(irs_plan_s *p, int64_t Ya, int64_t Yb, double *flop
 {
     const DevGeom &g = p->dg;
     const int PS = super_order(p);
-    const int32_t nSx = super_nx(g);
+    const int32_t ks = super_side(p);
+    const int32_t nSx = super_nx(p);
     const int32_t nSxb = (nSx + kCellsPerBlock - 1) / kCellsPerBlock;
     const int32_t nchunk = lens_chunks(p);
     const int32_t nl = (int32_t)p->n_lens;
@@ -1230,7 +1267,7 @@ irs_status ensure_super_rows(irs_plan_s *p, int64_t Ya, int64_t Yb, double *flop
 #define IRS_SE(U, PP)                                                                          \
     hipLaunchKernelGGL((k_super_expand<U, PP>), dim3(nb), dim3(kThreads), 0, p->stream, g,      \
                        p->d_x, p->d_y, p->d_m, p->d_cxy, nl, (int32_t)y0, nSx, nSxb, nchunk,  \
-                       kChunkLens, p->d_super_part)
+                       kChunkLens, ks, p->d_super_part)
         if (p->unit_mass) {
             if (PS == 32) IRS_SE(true, 32);
             else IRS_SE(true, 48);
@@ -1247,8 +1284,8 @@ irs_status ensure_super_rows(irs_plan_s *p, int64_t Ya, int64_t Yb, double *flop
         if (flops)
             for (int64_t Y = y0; Y <= y1; ++Y)
                 for (int32_t X = 0; X < nSx; ++X) {
-                    const int64_t inside = lenses_in(p, (X - kSuperR) * kSuperK, (X + kSuperR + 1) * kSuperK,
-                                                     (Y - kSuperR) * kSuperK, (Y + kSuperR + 1) * kSuperK);
+                    const int64_t inside = lenses_in(p, (X - kSuperR) * ks, (X + kSuperR + 1) * ks,
+                                                     (Y - kSuperR) * ks, (Y + kSuperR + 1) * ks);
                     *flops += (double)(p->n_lens - inside) * (10.0 + 8.0 * PS);
                 }
         for (int64_t Y = y0; Y <= y1; ++Y) p->super_ok[Y] = 1;
@@ -1263,7 +1300,7 @@ irs_status level2_prepare(irs_plan_s *p)
 {
     level2_reset(p);
     if (super_order(p) <= 0) return IRS_OK;
-    return ensure_super_buffers(p, super_ny(p->dg));
+    return ensure_super_buffers(p, super_ny(p));
 }
 
 irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *flops)
@@ -1303,13 +1340,14 @@ irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *f
                                                               cy + kRing + 1)) * (10.0 + 8.0 * P);
         return IRS_OK;
     }
-    if ((st = ensure_super_rows(p, c0 / kSuperK, c1 / kSuperK, flops)) != IRS_OK) return st;
-    const int32_t nSx = super_nx(g);
+    const int32_t ks = super_side(p);
+    if ((st = ensure_super_rows(p, c0 / ks, c1 / ks, flops)) != IRS_OK) return st;
+    const int32_t nSx = super_nx(p);
     const unsigned nb = (unsigned)((c1 - c0 + 1) * nxb);
 #define IRS_LN(U, PP, QS)                                                                         \
     hipLaunchKernelGGL((k_level2_near<U, PP, QS>), dim3(nb), dim3(kThreads), 0, p->stream, g,      \
                        p->d_x, p->d_y, p->d_m, p->d_cxy, p->d_cell_start, p->d_super, nSx,       \
-                       (int32_t)c0, nxb, p->d_part)
+                       (int32_t)c0, nxb, ks, p->d_part)
     if (p->unit_mass) {
         if (P == 32) { if (PS == 32) IRS_LN(true, 32, 32); else IRS_LN(true, 32, 48); }
         else { if (PS == 32) IRS_LN(true, 48, 32); else IRS_LN(true, 48, 48); }
@@ -1321,11 +1359,11 @@ irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *f
     IRS_HIP(hipGetLastError());
     if (flops)
         for (int64_t cy = c0; cy <= c1; ++cy) {
-            const int64_t Y = cy / kSuperK;
+            const int64_t Y = cy / ks;
             for (int64_t cx = 0; cx < g.n1x; ++cx) {
-                const int64_t X = cx / kSuperK;
-                const int64_t ring = lenses_in(p, (X - kSuperR) * kSuperK, (X + kSuperR + 1) * kSuperK,
-                                               (Y - kSuperR) * kSuperK, (Y + kSuperR + 1) * kSuperK) -
+                const int64_t X = cx / ks;
+                const int64_t ring = lenses_in(p, (X - kSuperR) * ks, (X + kSuperR + 1) * ks,
+                                               (Y - kSuperR) * ks, (Y + kSuperR + 1) * ks) -
                                      lenses_in(p, cx - kRing, cx + kRing + 1, cy - kRing, cy + kRing + 1);
                 *flops += (double)ring * (10.0 + 8.0 * P) + 8.0 * PS * P;
             }

@@ -52,6 +52,7 @@ struct irs_plan_s {
 
     // Level-2 coefficients of one band of level-1 rows: 10 doubles per point
     // (Re/Im of C0..C4), point (gx, gy) at ((gy - band_row0*q) * n1x*q + gx).
+    int32_t super_k = 0;                  // super-cell side (cells), chosen once per plan
     void *d_rows = nullptr;               // level-3 row table (ny entries of 32 B)
     double *d_coef = nullptr;
     int64_t coef_rows_cap = 0;   // level-1 rows the buffer holds
