@@ -62,18 +62,16 @@ constexpr int kBias = 4 * kHd + kNO;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__host__ __device__ inline uint16_t f2bf(float x)
-{
-    // round to nearest even (finite inputs)
-    uint32_t u;
-    __builtin_memcpy(&u, &x, 4);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16 rounded to nearest even (the hardware conversion)
+__device__ inline uint16_t f2bf(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+// two values in one word, a in the low half (one packed conversion)
 __device__ inline uint32_t pack2(float a, float b)
 {
-    return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16);
+    const bf16x2 v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 __device__ inline f32x16 mfma(const uint4 &a, const uint4 &b, const f32x16 &c)
