@@ -204,6 +204,124 @@ def bench_accuracy(irs, synth, torch, stream):
     return out
 
 
+def _ray_thetas(g, torch, r0, n):
+    """theta of rays r0 .. r0+n-1 of a plan (row-major grid, rays at cell centres)."""
+    r = torch.arange(r0, r0 + n, dtype=torch.int64, device="cuda:0")
+    i, j = r % g["nx"], r // g["nx"]
+    return (g["a1"] + (i.double() + 0.5) * g["ray_dx"], g["b1"] + (j.double() + 0.5) * g["ray_dy"])
+
+
+def border_coverage(irs, synth, torch, stream, kappa_star, kappa_c, gamma, S, npix,
+                    rays_per_pixel, seed, big=3.0, mass="unit", chunk=1 << 24):
+    """The protective border's ray coverage (Sec. 2.3): with border P = 10
+    sqrt(kappa_*) the shooting rectangle holds a fraction of the rays that
+    reach the target map; the rest start beyond it.  A plan with border big*P
+    and the same ray spacing and lens density stands in for the unbounded
+    plane: coverage = (its map-landing rays that start inside the border-P
+    rectangle) / (all its map-landing rays).  FP64 direct sum."""
+    P = 10.0 * math.sqrt(kappa_star)
+    g_in = irs.geometry(irs.make_params(kappa_star, kappa_c, gamma, S, npix,
+                                        rays_per_pixel=rays_per_pixel), 0)
+    dx3 = g_in["dx3"]
+    g0 = irs.geometry(irs.make_params(kappa_star, kappa_c, gamma, S, npix, n_rays=1,
+                                      border=big * P), 0)
+    n_big = int(round((g0["a2"] - g0["a1"]) * (g0["b2"] - g0["b1"]) / (dx3 * dx3)))
+    p = irs.make_params(kappa_star, kappa_c, gamma, S, npix, n_rays=n_big, border=big * P,
+                        method="direct", precision="fp64")
+    g = irs.geometry(p, 0)
+    L = synth.uniform_lenses(g["n_stars_expected"], (g["a1"], g["a2"], g["b1"], g["b2"]), seed,
+                             mass=mass)
+    total = g["nx"] * g["ny"]
+    px = torch.empty(min(chunk, total), dtype=torch.int64, device="cuda:0")
+    landed = inner = 0
+    t0 = time.perf_counter()
+    with irs.Plan(p, L.x, L.y, L.m, stream=stream.cuda_stream) as pl:
+        for r0 in range(0, total, chunk):
+            n = min(chunk, total - r0)
+            pl.deflect_grid_device(r0, n, None, None, px[:n])
+            t1, t2 = _ray_thetas(g, torch, r0, n)
+            hit = px[:n] >= 0
+            ins = (t1 >= g_in["a1"]) & (t1 < g_in["a2"]) & (t2 >= g_in["b1"]) & (t2 < g_in["b2"])
+            landed += int(hit.sum())
+            inner += int((hit & ins).sum())
+    torch.cuda.synchronize()
+    return {"kappa_star": kappa_star, "kappa_c": kappa_c, "gamma": gamma, "source_side": S,
+            "npix": npix, "border": P, "outer_border": big * P, "n_star_outer": L.n,
+            "rays_outer": total, "landed": landed, "landed_from_inside": inner,
+            "coverage": inner / landed if landed else None,
+            "seconds": time.perf_counter() - t0}
+
+
+def perturbation_u(irs, synth, torch, stream, n_star, realizations, spacing, seed0,
+                   kappa_star=0.5, central=0.5):
+    """|phi|/phi_0 of the stars' deflection perturbation (deflection of n_star
+    unit masses plus the negative sheet, i.e. alpha minus the macro term
+    kappa_* theta at kappa_c = gamma = 0), sampled on a grid of spacing
+    `spacing` over the central `central` fraction (per side) of a square lens
+    plane holding exactly n_star lenses at density kappa_*; `realizations`
+    independent lens draws.  FP64 direct sum.  Returns a host array."""
+    import numpy as np
+    side = math.sqrt(math.pi * n_star / kappa_star)
+    S = side * (1.0 - kappa_star)                     # border 0: the plane is S/(1 - kappa_*)
+    n_rays = int(round((side / spacing) ** 2))
+    p = irs.make_params(kappa_star, 0.0, 0.0, S, 64, n_rays=n_rays, border=0.0,
+                        method="direct", precision="fp64")
+    g = irs.geometry(p, 0)
+    total = g["nx"] * g["ny"]
+    a1 = torch.empty(total, dtype=torch.float64, device="cuda:0")
+    a2 = torch.empty_like(a1)
+    t1, t2 = _ray_thetas(g, torch, 0, total)
+    half = 0.5 * central * side
+    sel = (t1.abs() <= half) & (t2.abs() <= half)
+    out = []
+    for r in range(realizations):
+        L = synth.uniform_lenses(n_star, (g["a1"], g["a2"], g["b1"], g["b2"]), seed0 + r)
+        with irs.Plan(p, L.x, L.y, L.m, stream=stream.cuda_stream) as pl:
+            pl.deflect_grid_device(0, total, a1, a2, None)
+            u = torch.sqrt((a1 - kappa_star * t1) ** 2 + (a2 - kappa_star * t2) ** 2)[sel]
+            out.append((u / math.sqrt(kappa_star)).cpu().numpy())
+    return np.concatenate(out)
+
+
+def bench_border(irs, synth, torch, stream):
+    """Protective border and deflection-perturbation density (Sec. 2.3): the
+    coverage of the 10 sqrt(kappa_*) border on three lens-plane shapes, and the
+    measured density of |phi|/phi_0 against the closed forms with c = 3.05
+    (Katz et al.) and c = 1.454 (the paper's modified form): Kolmogorov-Smirnov
+    distance of the radial CDFs."""
+    import numpy as np
+    from oracle import border as ob
+    t0 = time.perf_counter()
+    out = {"coverage": [], "perturbation": []}
+    for (ks, kc, gm, S, npix, rpp, seed) in ((0.3, 0.0, 0.3, 10.0, 256, 64.0, 901),
+                                             (0.45, 0.05, 0.45, 25.0, 1024, 4.0, 902),
+                                             (0.6, 0.0, 0.6, 50.0, 512, 16.0, 903)):
+        c = border_coverage(irs, synth, torch, stream, ks, kc, gm, S, npix, rpp, seed)
+        out["coverage"].append(c)
+        log(f"border: kappa_*={ks} kappa_c={kc} gamma={gm} S={S}: coverage {c['coverage']:.5f} "
+            f"({c['landed']:.3e} landed rays, {c['n_star_outer']} lenses)")
+    ugrid = np.concatenate([np.linspace(0.05, 8.0, 160), np.geomspace(8.2, 40.0, 24)])
+    # ~900 samples per draw (a 30 x 30 grid over the central half); the field's
+    # long-range part is shared by a draw's samples, so the draws, not the
+    # samples, set the statistical weight
+    for n, reals in ((100, 400), (1000, 300), (10000, 200), (100000, 100), (1000000, 40)):
+        spacing = math.sqrt(math.pi * n / 0.5) * 0.5 / 30.0
+        u = np.sort(perturbation_u(irs, synth, torch, stream, n, reals, spacing, 1000 * n))
+        Femp = np.searchsorted(u, ugrid, side="right") / u.size
+        rec = {"n_star": n, "realizations": reals, "samples": int(u.size), "spacing": spacing,
+               "median": float(np.median(u)), "p98": float(np.quantile(u, 0.98))}
+        for name, cc in (("katz", ob.KATZ_C), ("modified", ob.MODIFIED_C)):
+            F = ob.radial_cdf(ugrid, n, cc)
+            rec[f"ks_{name}"] = float(np.max(np.abs(Femp - F)))
+            rec[f"median_{name}"] = float(ugrid[np.searchsorted(F, 0.5)])
+        out["perturbation"].append(rec)
+        log(f"border: N={n}: {u.size} samples, median |phi|/phi0 {rec['median']:.3f} "
+            f"(Katz {rec['median_katz']:.3f}, modified {rec['median_modified']:.3f}), "
+            f"KS distance Katz {rec['ks_katz']:.4f}, modified {rec['ks_modified']:.4f}")
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
 def bench_batch(irs, synth, torch, stream):
     """The 64-map batch (kappa_*, gamma ~ U[0.1, 0.8], kappa_c in {0, 0.2},
     N_* = 10^U[3, 5], 1024^2..4096^2 px, 100 rays/px), interpolated: one tuned
@@ -263,6 +381,8 @@ def main():
                     help="skip the 64-map batch measurement")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the accuracy-versus-rays experiment (Sec. 3.2)")
+    ap.add_argument("--no-border", action="store_true",
+                    help="skip the protective-border coverage and perturbation-density section")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-interpolant measurement (N_* = 1e6, 8192^2 px)")
     ap.add_argument("--pmc-calibrate", action="store_true",
@@ -436,6 +556,8 @@ def main():
         result["learned"] = bench_learned(irs, synth, torch, stream, args, result)
     if not args.no_batch:
         result["batch"] = bench_batch(irs, synth, torch, stream)
+    if not args.no_border:
+        result["border"] = bench_border(irs, synth, torch, stream)
     print(json.dumps(result), flush=True)
 
 

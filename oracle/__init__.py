@@ -8,6 +8,8 @@ with the HIP library (paper_2204_10871_amd) and does not import it.
                   grid, level-1/2/3 resolutions, pixel areas).
   irs_oracle.c -- O-1 (direct definition of Eq. 6 + Appendix A + binning) and
                   O-2 (the three-level-grid interpolation, step by step).
+  border.py    -- the deflection-perturbation density behind the protective
+                  border (Sec. 2.3, Eqs. 10-11), by direct integration.
   learned.py   -- FP64 reference of the learned far-field interpolant (network,
                   base interpolant, local data); orc_far_point gives its exact
                   samples.
