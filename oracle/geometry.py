@@ -10,7 +10,7 @@ Rules (each line cites the step it follows):
   dx2 = dx1 / 20                                               (level-2 resolution)
   Mag_ij = N_ij S_I / S_S                                      (magnification step)
 
-Readings where the paper is silent (each listed in the design notes):
+Readings where the paper is silent:
   - the rectangle is centred at the origin;
   - the ray grid has nx = round(I_x/dx3), ny = round(I_y/dx3) columns/rows,
     rays at cell centres, so S_I = (I_x/nx)(I_y/ny);
