@@ -322,6 +322,52 @@ def bench_border(irs, synth, torch, stream):
     return out
 
 
+def bench_circle(irs, synth, torch, stream):
+    """Circular against rectangular lens plane (Sec. 2.2): lenses needed for
+    the paper's workloads (the circle circumscribes the image rectangle), and
+    whole FP64 direct-sum maps of the kappa_* = gamma = 0.45, kappa_c = 0.05
+    shape (aspect 19) with each plane."""
+    out = {"lens_counts": []}
+    for w in (synth.configs.CFG1, synth.configs.CFG2, synth.configs.CFG3, synth.configs.CFG5):
+        kw = dict(kappa_star=w.kappa_star, kappa_c=w.kappa_c, gamma=w.gamma,
+                  source_side=w.source_side, npix=w.npix, rays_per_pixel=w.rays_per_pixel,
+                  n_rays=w.n_rays)
+        gr = irs.geometry(irs.make_params(**kw), 0)
+        gc = irs.geometry(irs.make_params(circle=True, **kw), 0)
+        out["lens_counts"].append({"workload": w.name, "aspect": gr["ix"] / gr["iy"],
+                                   "rectangle": gr["n_stars_expected"],
+                                   "circle": gc["n_stars_expected"],
+                                   "ratio": gc["n_stars_expected"] / gr["n_stars_expected"]})
+        log(f"circle: {w.name}: {gr['n_stars_expected']} lenses (rectangle) against "
+            f"{gc['n_stars_expected']} (circle), x{gc['n_stars_expected'] / gr['n_stars_expected']:.2f}")
+    npix = 1024
+    counts = torch.zeros(npix * npix, dtype=torch.int32, device="cuda:0")
+    timing = {}
+    for circle in (False, True):
+        p = irs.make_params(0.45, 0.05, 0.45, 25.0, npix, rays_per_pixel=4.0, circle=circle,
+                            method="direct", precision="fp64")
+        g = irs.geometry(p, 0)
+        if circle:
+            L = synth.disc_lenses(g["n_stars_expected"], g["lens_radius"], 905)
+        else:
+            L = synth.uniform_lenses(g["n_stars_expected"], (g["a1"], g["a2"], g["b1"], g["b2"]), 905)
+        with irs.Plan(p, L.x, L.y, L.m, stream=stream.cuda_stream) as pl:
+            pl.shoot_map_device(counts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = pl.shoot_map_device(counts)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+        key = "circle" if circle else "rectangle"
+        timing[key] = {"lenses": L.n, "rays": st["rays_shot"], "landed": st["rays_landed"],
+                       "seconds": sec, "pairs_per_s": st["rays_shot"] * L.n / sec}
+        log(f"circle: {key} plane, {L.n} lenses, {st['rays_shot']:.3e} rays: {sec * 1e3:.1f} ms "
+            f"({st['rays_shot'] * L.n / sec:.3e} pairs/s)")
+    timing["time_ratio"] = timing["circle"]["seconds"] / timing["rectangle"]["seconds"]
+    out["fp64_direct_aspect19"] = timing
+    return out
+
+
 def bench_batch(irs, synth, torch, stream):
     """The 64-map batch (kappa_*, gamma ~ U[0.1, 0.8], kappa_c in {0, 0.2},
     N_* = 10^U[3, 5], 1024^2..4096^2 px, 100 rays/px), interpolated: one tuned
@@ -381,6 +427,8 @@ def main():
                     help="skip the 64-map batch measurement")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the accuracy-versus-rays experiment (Sec. 3.2)")
+    ap.add_argument("--no-circle", action="store_true",
+                    help="skip the circular-against-rectangular lens plane section")
     ap.add_argument("--no-border", action="store_true",
                     help="skip the protective-border coverage and perturbation-density section")
     ap.add_argument("--no-learned", action="store_true",
@@ -558,6 +606,8 @@ def main():
         result["batch"] = bench_batch(irs, synth, torch, stream)
     if not args.no_border:
         result["border"] = bench_border(irs, synth, torch, stream)
+    if not args.no_circle:
+        result["circle"] = bench_circle(irs, synth, torch, stream)
     print(json.dumps(result), flush=True)
 
 

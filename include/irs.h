@@ -77,6 +77,15 @@ enum { IRS_FP64 = 0,        /* every step in double precision                  *
                                            the paper, instead of through one local
                                            expansion per level-1 cell (same values to
                                            FP64 rounding; kept for comparison)          */
+#define IRS_CIRCLE         (1ull << 2)  /* circular lens plane (Sec. 2.1): the lenses fill
+                                           the image rectangle's circumscribed circle,
+                                           radius R = sqrt(I_x^2 + I_y^2)/2, and the
+                                           negative sheet deflects by -kappa_* theta
+                                           (Eq. 9) instead of the rectangle's Appendix A
+                                           forms; n_stars_expected = round(kappa_* R^2).
+                                           The caller's lenses should lie in the circle.
+                                           Direct method in FP64 only (otherwise
+                                           IRS_E_UNSUPPORTED from irs_geometry/irs_plan) */
 /* per-call flags */
 #define IRS_OUT_ON_DEVICE  (1ull << 8)  /* output pointers are device pointers          */
 #define IRS_TIME_PHASES    (1ull << 9)  /* time each kernel launch with HIP events on
@@ -97,7 +106,7 @@ typedef struct {
     double   level2_ray_multiple; /* > 0: dx2 = this many ray spacings; both <= 0:   */
                                   /* dx2 = dx1/20 (flow chart, level-2 resolution)   */
     double   crit_eps;            /* <= 0: 1e-3                                        */
-    uint64_t flags;               /* IRS_SHEET_OFF, IRS_LEVEL2_PAPER                   */
+    uint64_t flags;               /* IRS_SHEET_OFF, IRS_LEVEL2_PAPER, IRS_CIRCLE       */
 } irs_params;
 
 typedef struct {
@@ -117,7 +126,9 @@ typedef struct {
     double  dpix;                 /* S / npix_side                                     */
     double  s_img, s_src;         /* S_I = ray_dx * ray_dy, S_S = dpix^2               */
     double  mu_th;                /* 1/((1-kappa)^2 - gamma^2)                          */
-    int64_t n_stars_expected;     /* round(kappa_* I_x I_y / pi)                       */
+    int64_t n_stars_expected;     /* round(kappa_* I_x I_y / pi); IRS_CIRCLE:
+                                     round(kappa_* lens_radius^2)                    */
+    double  lens_radius;          /* IRS_CIRCLE: sqrt(I_x^2 + I_y^2)/2; else 0        */
 } irs_geometry_info;
 
 typedef struct {

@@ -73,7 +73,8 @@ def _f64(a):
 
 def setup_of(g: Geometry) -> _Setup:
     return _Setup(g.kappa_star, g.kappa, g.gamma, g.a1, g.a2, g.b1, g.b2, g.nx, g.ny,
-                  g.source_side, g.npix, 1 if g.sheet else 0, g.n1x, g.n1y, g.q)
+                  g.source_side, g.npix, (2 if g.circle else 1) if g.sheet else 0, g.n1x,
+                  g.n1y, g.q)
 
 
 def sheet_I(rect, x, y):

@@ -79,26 +79,36 @@ class Geometry:
         return (self.a1, self.a2, self.b1, self.b2)
 
     @property
+    def lens_radius(self) -> float:
+        """Circular lens plane: radius of the image rectangle's circumscribed
+        circle (Sec. 2.2); 0 for the rectangle."""
+        return 0.5 * math.hypot(self.ix, self.iy) if self.circle else 0.0
+
+    @property
     def n_stars_expected(self) -> int:
-        """Lens count that fills the rectangle at density kappa_* with unit mean
+        """Lens count that fills the lens plane at density kappa_* with unit mean
         mass: the sheet of Appendix A has A = kappa_*/pi per unit area, i.e.
-        kappa_* I_x I_y / pi Einstein masses."""
+        kappa_* I_x I_y / pi Einstein masses (kappa_* R^2 for the circle)."""
+        if self.circle:
+            return _round_half_up(self.kappa_star * self.lens_radius ** 2)
         return _round_half_up(self.kappa_star * self.ix * self.iy / math.pi)
 
     l2_spacing_arg: float = 0.0        # explicit level-2 spacing, 0 = rule
     l2_ray_multiple_arg: float = 0.0   # level-2 spacing in ray spacings, 0 = rule
+    circle: bool = False               # circular lens plane, sheet -kappa_* theta (Eq. 9)
 
     def with_lens_count(self, n_lens: int) -> "Geometry":
         """Same inputs, geometry re-derived for n_lens lenses (dx1 depends on N_*)."""
         return geometry(self.kappa_star, self.kappa_c, self.gamma, self.source_side,
                         self.npix, n_rays=self.n_rays_target, border=self.border,
                         n_lens=n_lens, level2_spacing=self.l2_spacing_arg,
-                        level2_ray_multiple=self.l2_ray_multiple_arg, sheet=self.sheet)
+                        level2_ray_multiple=self.l2_ray_multiple_arg, sheet=self.sheet,
+                        circle=self.circle)
 
 
 def geometry(kappa_star, kappa_c, gamma, source_side, npix, rays_per_pixel=None,
              n_rays=None, border=None, n_lens=0, level2_spacing=None,
-             level2_ray_multiple=None, crit_eps=1e-3, sheet=True) -> Geometry:
+             level2_ray_multiple=None, crit_eps=1e-3, sheet=True, circle=False) -> Geometry:
     kappa = kappa_star + kappa_c
     lam1 = 1.0 - kappa - gamma
     lam2 = 1.0 - kappa + gamma
@@ -133,7 +143,7 @@ def geometry(kappa_star, kappa_c, gamma, source_side, npix, rays_per_pixel=None,
                  dx1=dx1, n1x=n1x, n1y=n1y, dx2=dx2, q=q, dpix=dpix, s_img=s_img,
                  s_src=dpix * dpix, mu_th=1.0 / (lam1 * lam2), sheet=bool(sheet),
                  l2_spacing_arg=float(level2_spacing or 0.0),
-                 l2_ray_multiple_arg=float(level2_ray_multiple or 0.0))
+                 l2_ray_multiple_arg=float(level2_ray_multiple or 0.0), circle=bool(circle))
     return g
 
 

@@ -39,7 +39,9 @@ typedef struct {
     int64_t nx, ny;      /* regular ray grid, rays at cell centres              */
     double source_side;  /* S_scale: side of the source map, theta_E units      */
     int64_t npix;        /* pixels per side of the source map                   */
-    int64_t sheet;       /* 1: include the negative mass sheet; 0: omit it      */
+    int64_t sheet;       /* 1: the rectangle's negative mass sheet (Appendix A);
+                            2: a circular lens plane's, -kappa_star theta (Eq. 9);
+                            0: omit it                                           */
     /* level-1 / level-2 grids (interpolation only) */
     int64_t n1x, n1y;    /* level-1 cells tiling the rectangle                  */
     int64_t q;           /* level-2 points per level-1 cell side                */
@@ -111,8 +113,9 @@ static void ray_theta(const orc_setup *s, int64_t r, double *t1, double *t2)
  *                           + alpha_{-kappa_star}(theta),
  * where alpha_{-kappa_star} = -(kappa_star/pi) (I1, I2) is the NEGATIVE sheet that
  * cancels the stars' mean density (the closed forms of Appendix A describe a
- * positive sheet; the sign is flipped here).  A lens exactly at theta
- * contributes nothing and is counted as singular.
+ * positive sheet; the sign is flipped here).  On a circular lens plane that
+ * contains theta the same sheet deflects by -kappa_star theta (Eq. 9).  A lens
+ * exactly at theta contributes nothing and is counted as singular.
  */
 static void alpha_direct(const orc_setup *s, int64_t nl, const double *lx,
                          const double *ly, const double *lm, double t1,
@@ -128,7 +131,10 @@ static void alpha_direct(const orc_setup *s, int64_t nl, const double *lx,
         sy += m * d2 / r2;
     }
     double shx = 0.0, shy = 0.0;
-    if (s->sheet) {
+    if (s->sheet == 2) {
+        shx = -s->kappa_star * t1;
+        shy = -s->kappa_star * t2;
+    } else if (s->sheet) {
         double I1, I2;
         orc_sheet_I(s->a1, s->a2, s->b1, s->b2, 1, &t1, &t2, &I1, &I2);
         shx = -(s->kappa_star / M_PI) * I1;

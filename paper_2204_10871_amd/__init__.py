@@ -42,7 +42,7 @@ def _check(status, where):
 def make_params(kappa_star, kappa_c, gamma, source_side, npix, rays_per_pixel=0.0, n_rays=0,
                 border=-1.0, method="direct", precision="fp64", level2_spacing=0.0,
                 level2_ray_multiple=0.0, crit_eps=0.0, sheet=True,
-                level2_paper=False) -> Params:
+                level2_paper=False, circle=False) -> Params:
     return Params(float(kappa_star), float(kappa_c), float(gamma), float(source_side),
                   int(npix), float(rays_per_pixel), int(n_rays),
                   float(-1.0 if border is None else border),
@@ -50,7 +50,8 @@ def make_params(kappa_star, kappa_c, gamma, source_side, npix, rays_per_pixel=0.
                   _PRECISIONS[precision] if isinstance(precision, str) else int(precision),
                   float(level2_spacing or 0.0), float(level2_ray_multiple or 0.0),
                   float(crit_eps),
-                  (0 if sheet else IRS_SHEET_OFF) | (_ffi.IRS_LEVEL2_PAPER if level2_paper else 0))
+                  (0 if sheet else IRS_SHEET_OFF) | (_ffi.IRS_LEVEL2_PAPER if level2_paper else 0)
+                  | (_ffi.IRS_CIRCLE if circle else 0))
 
 
 def params_from_workload(w, method="direct", precision="fp64", **over) -> Params:

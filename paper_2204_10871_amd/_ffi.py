@@ -12,6 +12,7 @@ IRS_DIRECT, IRS_INTERP, IRS_LEARNED = 0, 1, 2
 IRS_FP64, IRS_FP32_KAHAN = 0, 1
 IRS_SHEET_OFF = 1 << 0
 IRS_LEVEL2_PAPER = 1 << 1
+IRS_CIRCLE = 1 << 2
 IRS_OUT_ON_DEVICE = 1 << 8
 IRS_TIME_PHASES = 1 << 9
 IRS_LEARN_NFREQ = 64
@@ -43,7 +44,8 @@ class GeometryInfo(C.Structure):
                 ("ray_dy", C.c_double), ("n_lens", C.c_int64), ("dx1", C.c_double),
                 ("n1x", C.c_int64), ("n1y", C.c_int64), ("dx2", C.c_double), ("q", C.c_int64),
                 ("dpix", C.c_double), ("s_img", C.c_double), ("s_src", C.c_double),
-                ("mu_th", C.c_double), ("n_stars_expected", C.c_int64)]
+                ("mu_th", C.c_double), ("n_stars_expected", C.c_int64),
+                ("lens_radius", C.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -91,7 +91,7 @@ DevGeom make_dev_geom(const HostGeometry &hg)
     d.inv_dpix = 1.0 / g.dpix;
     d.sheet_f = -hg.kappa_star / M_PI;
     d.npix = (int32_t)hg.npix;
-    d.sheet = hg.sheet ? 1 : 0;
+    d.sheet = hg.sheet ? (hg.circle ? 2 : 1) : 0;
     d.n1x = (int32_t)g.n1x;
     d.n1y = (int32_t)g.n1y;
     d.q = (int32_t)g.q;

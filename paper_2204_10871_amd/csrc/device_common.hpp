@@ -15,7 +15,7 @@ struct DevGeom {
     double kpg, kmg;            // kappa + gamma, kappa - gamma (macro term, Eq. 6)
     double half_side, dpix;     // S/2 and S/npix: map [-S/2, S/2)^2
     int32_t npix;               // pixels per side
-    int32_t sheet;              // 1: include the negative sheet
+    int32_t sheet;              // 0: no sheet; 1: the rectangle's (Appendix A); 2: circle's
     int32_t n1x, n1y;           // level-1 cells
     int32_t q;                  // level-2 points per level-1 cell side
     int32_t pad_;

@@ -42,6 +42,13 @@ irs_status derive_geometry(const irs_params &p, int64_t n_lens, HostGeometry &ou
         err = "precision must be IRS_FP64 or IRS_FP32_KAHAN";
         return IRS_E_UNSUPPORTED;
     }
+    const bool circle = (p.flags & IRS_CIRCLE) != 0;
+    if (circle && (p.method != IRS_DIRECT || p.precision != IRS_FP64)) {
+        // the level-1 grid (interpolation, FP32 near-lens residuals) tiles the
+        // rectangle, not the circle around it
+        err = "the circular lens plane (IRS_CIRCLE) is supported by the direct method in FP64 only";
+        return IRS_E_UNSUPPORTED;
+    }
     const double kappa = p.kappa_star + p.kappa_c;
     const double lam_x = 1.0 - kappa - p.gamma;   // macro eigenvalue along theta_1
     const double lam_y = 1.0 - kappa + p.gamma;   // macro eigenvalue along theta_2
@@ -122,13 +129,17 @@ irs_status derive_geometry(const irs_params &p, int64_t n_lens, HostGeometry &ou
     g.s_img = g.ray_dx * g.ray_dy;
     g.s_src = g.dpix * g.dpix;
     g.mu_th = 1.0 / (lam_x * lam_y);
-    g.n_stars_expected = round_half_up(p.kappa_star * ix * iy / M_PI);
+    g.lens_radius = circle ? 0.5 * std::sqrt(ix * ix + iy * iy) : 0.0;
+    // lenses at density kappa_*/pi (unit mean mass) over the lens plane
+    g.n_stars_expected = circle ? round_half_up(p.kappa_star * g.lens_radius * g.lens_radius)
+                                : round_half_up(p.kappa_star * ix * iy / M_PI);
     out.kappa_star = p.kappa_star;
     out.kappa_c = p.kappa_c;
     out.gamma = p.gamma;
     out.source_side = p.source_side;
     out.npix = p.npix_side;
     out.sheet = (p.flags & IRS_SHEET_OFF) == 0;
+    out.circle = circle;
     return IRS_OK;
 }
 

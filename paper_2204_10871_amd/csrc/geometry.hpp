@@ -19,6 +19,7 @@ struct HostGeometry {
     double kappa_star, kappa_c, gamma, source_side;
     int64_t npix;
     bool sheet;
+    bool circle;                  // IRS_CIRCLE: circular lens plane, sheet -kappa_* theta
 };
 
 // Fills `out` or returns an error status with a message in `err`.

@@ -38,7 +38,10 @@ __device__ __forceinline__ void assemble(const DevGeom &g, double t1, double t2,
                                          double s2, double &a1, double &a2, int32_t &pix)
 {
     double h1 = 0.0, h2 = 0.0;
-    if (g.sheet) {
+    if (g.sheet == 2) {                      // circular plane: -kappa_* theta (Eq. 9)
+        h1 = -g.kappa_star * t1;
+        h2 = -g.kappa_star * t2;
+    } else if (g.sheet) {
         double I1, I2;
         sheet_unit(g, t1, t2, I1, I2);
         const double f = -g.kappa_star / M_PI;

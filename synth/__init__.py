@@ -7,9 +7,9 @@ geometry rules, no binning): the lens rectangle and the lens count are passed
 in by the caller, who gets them from whichever side it is exercising.
 """
 from .rng import splitmix64, uniform01
-from .lenses import Lenses, uniform_lenses, salpeter_mean_mass
+from .lenses import Lenses, uniform_lenses, disc_lenses, salpeter_mean_mass
 from . import configs
 from . import network
 
-__all__ = ["splitmix64", "uniform01", "Lenses", "uniform_lenses",
+__all__ = ["splitmix64", "uniform01", "Lenses", "uniform_lenses", "disc_lenses",
            "salpeter_mean_mass", "configs", "network"]

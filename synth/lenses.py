@@ -63,3 +63,22 @@ def uniform_lenses(n: int, rect, seed: int, mass: str = "unit",
     else:
         raise ValueError(f"unknown mass function {mass!r}")
     return Lenses(np.ascontiguousarray(x), np.ascontiguousarray(y), m)
+
+
+def disc_lenses(n: int, radius: float, seed: int, mass: str = "unit",
+                m_min: float = 0.1, m_max: float = 1.0,
+                slope: float = SALPETER_SLOPE) -> Lenses:
+    """n lenses uniform in the disc of the given radius about the origin (the
+    circular lens plane): r = radius sqrt(u0), angle 2 pi u1; streams 0/1 as
+    for the rectangle, stream 2 for masses."""
+    r = float(radius) * np.sqrt(uniform01(seed, 0, n))
+    a = 2.0 * np.pi * uniform01(seed, 1, n)
+    x, y = r * np.cos(a), r * np.sin(a)
+    if mass == "unit":
+        m = None
+    elif mass == "salpeter":
+        m = _salpeter_masses(uniform01(seed, 2, n), m_min, m_max, slope)
+        m = m / salpeter_mean_mass(m_min, m_max, slope)
+    else:
+        raise ValueError(f"unknown mass function {mass!r}")
+    return Lenses(np.ascontiguousarray(x), np.ascontiguousarray(y), m)

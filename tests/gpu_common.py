@@ -21,23 +21,28 @@ THREADS = min(16, os.cpu_count() or 1)
 class Case:
     def __init__(self, kappa_star, kappa_c, gamma, source_side, npix, *, n_rays=0,
                  rays_per_pixel=0.0, border=None, n_lens=None, mass="unit", seed=1,
-                 level2_spacing=None, level2_ray_multiple=None, sheet=True, lenses=None):
+                 level2_spacing=None, level2_ray_multiple=None, sheet=True, lenses=None,
+                 circle=False):
         self.kw = dict(kappa_star=kappa_star, kappa_c=kappa_c, gamma=gamma,
                        source_side=source_side, npix=npix)
         g0 = orc.geometry(kappa_star, kappa_c, gamma, source_side, npix,
                           rays_per_pixel=rays_per_pixel, n_rays=n_rays, border=border,
                           level2_spacing=level2_spacing,
-                          level2_ray_multiple=level2_ray_multiple, sheet=sheet)
+                          level2_ray_multiple=level2_ray_multiple, sheet=sheet, circle=circle)
         if lenses is not None:
             self.lenses = lenses
         else:
             n = g0.n_stars_expected if n_lens is None else n_lens
-            self.lenses = synth.uniform_lenses(n, g0.rect, seed, mass=mass)
+            if circle:
+                self.lenses = synth.disc_lenses(n, g0.lens_radius, seed, mass=mass)
+            else:
+                self.lenses = synth.uniform_lenses(n, g0.rect, seed, mass=mass)
         self.geo = g0.with_lens_count(self.lenses.n)
         self.p_extra = dict(n_rays=n_rays, rays_per_pixel=rays_per_pixel,
                             border=-1.0 if border is None else border,
                             level2_spacing=level2_spacing or 0.0,
-                            level2_ray_multiple=level2_ray_multiple or 0.0, sheet=sheet)
+                            level2_ray_multiple=level2_ray_multiple or 0.0, sheet=sheet,
+                            circle=circle)
 
     def plan(self, method="direct", precision="fp64"):
         import paper_2204_10871_amd as irs

@@ -61,6 +61,28 @@ def test_geometry_matches_oracle(irs, orc, case, n_lens):
     assert g["ray_dx"] == o.ray_dx and g["ray_dy"] == o.ray_dy
 
 
+@pytest.mark.parametrize("case", CASES[:2])
+def test_circle_geometry_matches_oracle(irs, orc, case):
+    g = irs.geometry(irs.make_params(circle=True, **case), 0)
+    o = orc.geometry(case["kappa_star"], case["kappa_c"], case["gamma"], case["source_side"],
+                     case["npix"], rays_per_pixel=case.get("rays_per_pixel"),
+                     n_rays=case.get("n_rays"), border=case.get("border"),
+                     level2_ray_multiple=case.get("level2_ray_multiple"), circle=True)
+    assert g["lens_radius"] == pytest.approx(o.lens_radius, rel=1e-14)
+    assert g["n_stars_expected"] == o.n_stars_expected
+    assert irs.geometry(irs.make_params(**case), 0)["lens_radius"] == 0.0
+
+
+def test_circle_needs_the_fp64_direct_sum(irs):
+    kw = dict(kappa_star=0.3, kappa_c=0.0, gamma=0.3, source_side=10.0, npix=64,
+              rays_per_pixel=10.0, circle=True)
+    irs.geometry(irs.make_params(**kw))
+    for over in (dict(method="interp"), dict(method="learned"), dict(precision="fp32")):
+        with pytest.raises(irs.IrsError) as e:
+            irs.geometry(irs.make_params(**{**kw, **over}))
+        assert e.value.status == 5                  # IRS_E_UNSUPPORTED
+
+
 def test_argument_errors(irs):
     with pytest.raises(irs.IrsError) as e:
         irs.geometry(irs.make_params(0.5, 0.0, 0.5, 100.0, 64, rays_per_pixel=10.0))

@@ -48,6 +48,27 @@ def test_direct_fp64_config1_full_map(irs):
     assert st["rays_landed"] == int(counts.sum()) and st["rays_shot"] == pl.n_rays
 
 
+@pytest.mark.parametrize("mass", ["unit", "salpeter"])
+def test_direct_fp64_circular_plane(irs, mass):
+    """The circular lens plane (Sec. 2.1, Eq. 9): lenses in the image
+    rectangle's circumscribed circle, sheet -kappa_* theta; every ray and the
+    map against the FP64 definition."""
+    c = Case(0.3, 0.0, 0.3, 10.0, 256, n_rays=1024 ** 2, seed=synth.configs.CFG1.seed + 3,
+             mass=mass, circle=True)
+    say(f"circle fp64: nx={c.geo.nx} ny={c.geo.ny} N*={c.lenses.n} R={c.geo.lens_radius:.3f}")
+    rect = Case(0.3, 0.0, 0.3, 10.0, 256, n_rays=1024 ** 2).geo.n_stars_expected     # 105
+    assert c.lenses.n == c.geo.n_stars_expected > 2 * rect
+    ref = c.oracle_direct()
+    with c.plan("direct", "fp64") as pl:
+        a1, a2, px = pl.deflect_grid(0, pl.n_rays)
+        counts, st = pl.shoot_map()
+    e = rel_err(a1, a2, ref["alpha1"], ref["alpha2"])
+    assert e.max() < 1e-12, e.max()
+    assert (px != ref["pix"]).sum() <= 2
+    check_map(counts, ref["counts"], px, ref["pix"], min_agree=1 - 1e-5, max_rel_l1=1e-5)
+    assert st["rays_landed"] == int(counts.sum())
+
+
 # ---------------------------------------------------------------------------
 # direct sum, FP32 with compensation
 # ---------------------------------------------------------------------------
