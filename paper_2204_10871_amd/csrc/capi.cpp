@@ -115,6 +115,7 @@ void release(irs_plan_s *p)
     dev_free(p->d_coef);
     dev_free(p->d_part);
     dev_free(p->d_super);
+    dev_free(p->d_mid);
     dev_free(p->d_super_part);
     dev_free(p->d_counts);
     dev_free(p->d_tmp);

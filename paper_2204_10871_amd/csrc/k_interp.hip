@@ -342,7 +342,7 @@ __global__ __launch_bounds__(kThreads) void k_level2_expand(
 // lenses to about (2 R_S + 1)^2 K_S^2 lenses plus N_* / K_S^2, and K_S is
 // chosen per plan to balance the two (super_side).
 // -------------------------------------------------------------------------
-constexpr int kSuperR = 2;                     // R_S
+constexpr int kSuperR = 2;                     // R_S (and the mid cells' block radius)
 constexpr int kSuperKMax = 32;                 // largest super-cell side (cells)
 
 // centre and scale of super cell (X, Y) of side ks cells
@@ -455,18 +455,23 @@ __global__ __launch_bounds__(kThreads) void k_super_reduce(const double *__restr
     out[e] = acc;
 }
 
-// Cell expansions of level-1 rows from c0: the super expansion translated to
-// the cell plus the lenses of the super block outside the cell's 7 x 7 block.
-// One wave per cell, four cells (of one super cell) per workgroup.
-// out[(((cy - c0) n1x + cx) P + n) 2 + c]
-constexpr int kSuperRows = (2 * kSuperR + 1) * kSuperKMax; // cell rows of a super block, at most
+// Child expansions from a parent level: a child (a level-1 cell, kc = 1, or a
+// mid cell of kc x kc cells) takes its parent's expansion (parent cells of ks
+// x ks cells, PS terms about the parent's centre) re-expanded about its own
+// centre, plus the lenses of the parent's 5 x 5 block that lie outside the
+// child's own exclusion block (rc children each way: 7 x 7 cells for a cell,
+// 5 x 5 mid cells for a mid cell), summed into P terms about its centre.
+// One wave per child, four children (of one parent) per workgroup; rows of
+// children from c0:  out[(((cy - c0) nCx + cx) P + n) 2 + c].
+constexpr int kSuperRows = (2 * kSuperR + 1) * kSuperKMax; // cell rows of a parent block, at most
 
 template <bool UNIT, int P, int PS>
 __global__ __launch_bounds__(kThreads) void k_level2_near(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
     const double *__restrict__ lm, const uint32_t *__restrict__ lcxy,
     const int32_t *__restrict__ cell_start, const double *__restrict__ super, int32_t nSx,
-    int32_t c0, int32_t nxb, int32_t ks, double *__restrict__ out)
+    int32_t c0, int32_t nxb, int32_t ks, int32_t kc, int32_t rc, int32_t nCx,
+    double *__restrict__ out)
 {
     __shared__ double s_x[kThreads], s_y[kThreads], s_m[UNIT ? 1 : kThreads];
     __shared__ uint32_t s_c[kThreads];
@@ -477,8 +482,9 @@ __global__ __launch_bounds__(kThreads) void k_level2_near(
     const int32_t cy = c0 + (int32_t)(blockIdx.x / (uint32_t)nxb);
     const int32_t cx0 = (int32_t)(blockIdx.x % (uint32_t)nxb) * kCellsPerBlock;
     const int32_t cx = cx0 + wave;
-    const bool live = cx < g.n1x;
-    const int32_t X = cx0 / ks, Y = cy / ks;             // ks is a multiple of kCellsPerBlock
+    const bool live = cx < nCx;
+    // ks / kc is a multiple of kCellsPerBlock: the workgroup's children share a parent
+    const int32_t X = cx0 * kc / ks, Y = cy * kc / ks;
     // the super expansion and the lens ranges of the super block, row by row
     for (int e = tid; e < PS * 2; e += kThreads) s_E[e / 2][e % 2] = super[((int64_t)Y * nSx + X) * PS * 2 + e];
     const int32_t ya = max(0, (Y - kSuperR) * ks), yb = min(g.n1y, (Y + kSuperR + 1) * ks);
@@ -497,9 +503,9 @@ __global__ __launch_bounds__(kThreads) void k_level2_near(
     __syncthreads();
     const int32_t total = s_off[nrow];
 
-    const double sc = fmax(g.w1, g.h1), isc = 1.0 / sc;
-    const double zcr = g.a1 + ((double)cx + 0.5) * g.w1;
-    const double zci = g.b1 + ((double)cy + 0.5) * g.h1;
+    const double sc = kc * fmax(g.w1, g.h1), isc = 1.0 / sc;
+    const double zcr = g.a1 + ((double)(kc * cx) + 0.5 * kc) * g.w1;
+    const double zci = g.b1 + ((double)(kc * cy) + 0.5 * kc) * g.h1;
 
     double Lr[P], Li[P];
 #pragma unroll
@@ -532,8 +538,8 @@ __global__ __launch_bounds__(kThreads) void k_level2_near(
                 double Xl = zcr + sc, Yl = zci, M = 0.0;   // harmless stand-in
                 if (use) {
                     const uint32_t c = s_c[t];
-                    const int32_t lcx = (int32_t)(c & 0xffffu), lcy = (int32_t)(c >> 16);
-                    use = abs(lcx - cx) > kRing || abs(lcy - cy) > kRing;
+                    const int32_t lcx = (int32_t)(c & 0xffffu) / kc, lcy = (int32_t)(c >> 16) / kc;
+                    use = abs(lcx - cx) > rc || abs(lcy - cy) > rc;
                     if (use) {
                         Xl = s_x[t];
                         Yl = s_y[t];
@@ -588,7 +594,7 @@ __global__ __launch_bounds__(kThreads) void k_level2_near(
     for (int n = 0; n < P; ++n) {
         const double r = wave_sum(Lr[n]) + __shfl(Tr, n), i = wave_sum(Li[n]) + __shfl(Ti, n);
         if (lane == 0 && live) {
-            double *dst = out + ((((int64_t)(cy - c0) * g.n1x + cx)) * P + n) * 2;
+            double *dst = out + ((((int64_t)(cy - c0) * nCx + cx)) * P + n) * 2;
             dst[0] = r;
             dst[1] = i;
         }
@@ -1164,33 +1170,60 @@ int32_t level2_chunks(const irs_plan_s *p)
     return p->n_lens > 0 ? (int32_t)((p->n_lens + kChunkLens - 1) / kChunkLens) : 1;
 }
 
-void level2_reset(irs_plan_s *p) { std::fill(p->super_ok.begin(), p->super_ok.end(), 0); }
-
-// Super-cell side K (cells, a multiple of kCellsPerBlock), once per plan.
-// The super expansions cost about N_* (n1x n1y / K^2) PS terms, the
-// per-cell sums over the super block about n1x n1y min(N_*, nu (2 R_S + 1)^2
-// K^2) P terms (nu = lenses per cell); K in {4, 8, 16, 32} with the smaller
-// total.  The accuracy of either series does not depend on K.
-int32_t super_side(irs_plan_s *p)
+void level2_reset(irs_plan_s *p)
 {
-    if (p->super_k > 0) return p->super_k;
+    std::fill(p->super_ok.begin(), p->super_ok.end(), 0);
+    std::fill(p->mid_ok.begin(), p->mid_ok.end(), 0);
+}
+
+// Super-cell side K_S and mid-cell side K_M (cells; K_M = 0: no mid level),
+// once per plan.  Work in series terms, with nu lenses per cell and B(K) =
+// min(N_*, nu (2 R_S + 1)^2 K^2) the lenses of a 5 x 5 block of K x K cells:
+//   super expansions  N_* (cells / K_S^2) PS
+//   mid expansions    (cells / K_M^2) (B(K_S) PS + PS^2)
+//   cell expansions   cells (B(K_M or K_S) P + PS P)
+// over K_S in {4, .., 32}, K_M in {0, 4, .., K_S / 2}; the accuracy of every
+// series is that of the order rule whatever the sides.
+void choose_sides(irs_plan_s *p)
+{
+    if (p->super_k > 0) return;
     const DevGeom &g = p->dg;
     const double cells = (double)g.n1x * (double)g.n1y, nl = (double)p->n_lens;
     const double nu = cells > 0.0 ? nl / cells : 0.0;
     const double PS = std::max(1, super_order(p)), P = std::max(1, level2_order(p));
-    int32_t best = 8;
-    double best_cost = -1.0;
-    for (int32_t K : {4, 8, 16, 32}) {
-        const double nS = std::ceil(g.n1x / (double)K) * std::ceil(g.n1y / (double)K);
-        const double block = (double)(2 * kSuperR + 1) * K;
-        const double cost = nl * nS * PS + cells * std::min(nl, nu * block * block) * P;
-        if (best_cost < 0.0 || cost < best_cost) {
-            best_cost = cost;
-            best = K;
+    auto block = [&](int32_t K) {
+        const double b = (double)(2 * kSuperR + 1) * K;
+        return std::min(nl, nu * b * b);
+    };
+    auto count = [&](int32_t K) { return std::ceil(g.n1x / (double)K) * std::ceil(g.n1y / (double)K); };
+    int32_t bs = 8, bm = 0;
+    double best = -1.0;
+    for (int32_t KS : {4, 8, 16, 32})
+        for (int32_t KM : {0, 4, 8, 16}) {
+            if (KM != 0 && 2 * KM > KS) continue;
+            double cost = nl * count(KS) * PS + cells * PS * P;
+            if (KM == 0) cost += cells * block(KS) * P;
+            else cost += count(KM) * (block(KS) * PS + PS * PS) + cells * block(KM) * P;
+            if (best < 0.0 || cost < best) {
+                best = cost;
+                bs = KS;
+                bm = KM;
+            }
         }
-    }
-    p->super_k = best;
-    return best;
+    p->super_k = bs;
+    p->mid_k = bm;
+}
+
+int32_t super_side(irs_plan_s *p)
+{
+    choose_sides(p);
+    return p->super_k;
+}
+
+int32_t mid_side(irs_plan_s *p)
+{
+    choose_sides(p);
+    return p->mid_k;
 }
 
 namespace {
@@ -1294,13 +1327,82 @@ irs_status ensure_super_rows(irs_plan_s *p, int64_t Ya, int64_t Yb, double *flop
     return IRS_OK;
 }
 
+int32_t mid_nx(irs_plan_s *p) { const int32_t k = mid_side(p); return (p->dg.n1x + k - 1) / k; }
+int32_t mid_ny(irs_plan_s *p) { const int32_t k = mid_side(p); return (p->dg.n1y + k - 1) / k; }
+
+irs_status ensure_mid_buffers(irs_plan_s *p)
+{
+    if (p->d_mid) return IRS_OK;
+    const int PS = super_order(p);
+    const int32_t nMx = mid_nx(p), nMy = mid_ny(p);
+    if (hipMalloc(&p->d_mid, sizeof(double) * (size_t)nMy * nMx * PS * 2) != hipSuccess) {
+        (void)hipGetLastError();
+        p->d_mid = nullptr;
+        set_error("cannot allocate the mid-cell expansions");
+        return IRS_E_NOMEM;
+    }
+    p->mid_ok.assign((size_t)nMy, 0);
+    return IRS_OK;
+}
+
+// mid rows [Ma, Mb] that are not cached, in runs of consecutive rows: each mid
+// cell takes its super cell's expansion re-expanded about its centre plus the
+// lenses of the super block outside its own 5 x 5 block of mid cells
+irs_status ensure_mid_rows(irs_plan_s *p, int64_t Ma, int64_t Mb, double *flops)
+{
+    const DevGeom &g = p->dg;
+    const int PS = super_order(p);
+    const int32_t ks = super_side(p), km = mid_side(p);
+    irs_status st = ensure_mid_buffers(p);
+    if (st != IRS_OK) return st;
+    if ((st = ensure_super_rows(p, Ma * km / ks, Mb * km / ks, flops)) != IRS_OK) return st;
+    const int32_t nSx = super_nx(p), nMx = mid_nx(p);
+    const int32_t nxb = (nMx + kCellsPerBlock - 1) / kCellsPerBlock;
+    for (int64_t m0 = Ma; m0 <= Mb;) {
+        if (p->mid_ok[m0]) { ++m0; continue; }
+        int64_t m1 = m0;
+        while (m1 + 1 <= Mb && !p->mid_ok[m1 + 1]) ++m1;
+        const unsigned nb = (unsigned)((m1 - m0 + 1) * nxb);
+        double *dst = p->d_mid + m0 * nMx * PS * 2;
+#define IRS_MID(U, PP)                                                                          \
+    hipLaunchKernelGGL((k_level2_near<U, PP, PP>), dim3(nb), dim3(kThreads), 0, p->stream, g,    \
+                       p->d_x, p->d_y, p->d_m, p->d_cxy, p->d_cell_start, p->d_super, nSx,     \
+                       (int32_t)m0, nxb, ks, km, kSuperR, nMx, dst)
+        if (p->unit_mass) {
+            if (PS == 32) IRS_MID(true, 32);
+            else IRS_MID(true, 48);
+        } else {
+            if (PS == 32) IRS_MID(false, 32);
+            else IRS_MID(false, 48);
+        }
+#undef IRS_MID
+        IRS_HIP(hipGetLastError());
+        if (flops)
+            for (int64_t M = m0; M <= m1; ++M)
+                for (int32_t X = 0; X < nMx; ++X) {
+                    const int64_t SX = (int64_t)X * km / ks, SY = M * km / ks;
+                    const int64_t ring =
+                        lenses_in(p, (SX - kSuperR) * ks, (SX + kSuperR + 1) * ks,
+                                  (SY - kSuperR) * ks, (SY + kSuperR + 1) * ks) -
+                        lenses_in(p, ((int64_t)X - kSuperR) * km, ((int64_t)X + kSuperR + 1) * km,
+                                  (M - kSuperR) * km, (M + kSuperR + 1) * km);
+                    *flops += (double)ring * (10.0 + 8.0 * PS) + 8.0 * PS * PS;
+                }
+        for (int64_t M = m0; M <= m1; ++M) p->mid_ok[M] = 1;
+        m0 = m1 + 1;
+    }
+    return IRS_OK;
+}
+
 }  // namespace
 
 irs_status level2_prepare(irs_plan_s *p)
 {
     level2_reset(p);
     if (super_order(p) <= 0) return IRS_OK;
-    return ensure_super_buffers(p, super_ny(p));
+    irs_status st = ensure_super_buffers(p, super_ny(p));
+    if (st != IRS_OK || mid_side(p) == 0) return st;
+    return ensure_mid_buffers(p);
 }
 
 irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *flops)
@@ -1340,14 +1442,19 @@ irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *f
                                                               cy + kRing + 1)) * (10.0 + 8.0 * P);
         return IRS_OK;
     }
-    const int32_t ks = super_side(p);
-    if ((st = ensure_super_rows(p, c0 / ks, c1 / ks, flops)) != IRS_OK) return st;
-    const int32_t nSx = super_nx(p);
+    // the cells' parent level: mid cells if the plan has them, else super cells
+    const int32_t km = mid_side(p);
+    const int32_t ks = km > 0 ? km : super_side(p);
+    if (km > 0) st = ensure_mid_rows(p, c0 / km, c1 / km, flops);
+    else st = ensure_super_rows(p, c0 / ks, c1 / ks, flops);
+    if (st != IRS_OK) return st;
+    const double *parent = km > 0 ? p->d_mid : p->d_super;
+    const int32_t nSx = km > 0 ? mid_nx(p) : super_nx(p);
     const unsigned nb = (unsigned)((c1 - c0 + 1) * nxb);
 #define IRS_LN(U, PP, QS)                                                                         \
     hipLaunchKernelGGL((k_level2_near<U, PP, QS>), dim3(nb), dim3(kThreads), 0, p->stream, g,      \
-                       p->d_x, p->d_y, p->d_m, p->d_cxy, p->d_cell_start, p->d_super, nSx,       \
-                       (int32_t)c0, nxb, ks, p->d_part)
+                       p->d_x, p->d_y, p->d_m, p->d_cxy, p->d_cell_start, parent, nSx,          \
+                       (int32_t)c0, nxb, ks, 1, kRing, g.n1x, p->d_part)
     if (p->unit_mass) {
         if (P == 32) { if (PS == 32) IRS_LN(true, 32, 32); else IRS_LN(true, 32, 48); }
         else { if (PS == 32) IRS_LN(true, 48, 32); else IRS_LN(true, 48, 48); }

@@ -53,6 +53,9 @@ struct irs_plan_s {
     // Level-2 coefficients of one band of level-1 rows: 10 doubles per point
     // (Re/Im of C0..C4), point (gx, gy) at ((gy - band_row0*q) * n1x*q + gx).
     int32_t super_k = 0;                  // super-cell side (cells), chosen once per plan
+    int32_t mid_k = 0;                    // mid-cell side (cells), 0: no mid level
+    double *d_mid = nullptr;              // mid-cell expansions (all rows), like d_super
+    std::vector<char> mid_ok;
     void *d_rows = nullptr;               // level-3 row table (ny entries of 32 B)
     double *d_coef = nullptr;
     int64_t coef_rows_cap = 0;   // level-1 rows the buffer holds
