@@ -638,26 +638,20 @@ __global__ __launch_bounds__(kThreads) void k_level2_points(
         const double x0 = level2_x(g, gx), y0 = level2_y(g, (int64_t)cy * q + gyl);
         const double czr = g.a1 + ((double)ccx + 0.5) * g.w1;
         const double dr = (x0 - czr) * isc, di = (y0 - zci) * isc;
-        // c_k = s^-(k+1) sum_n C(n,k) Lt_n d^(n-k), accumulated forward in n with
-        // C(n,k) by Pascal's rule and E[k] = d^(n-k) shifted along
+        // c_k = s^-(k+1) sum_n C(n,k) Lt_n d^(n-k): the polynomial sum_n Lt_n d^n
+        // and its derivatives over k! by one Horner pass from n = P-1 down
+        // (D_k <- D_k d + D_(k-1), D_0 <- D_0 d + Lt_n)
         double cr[5] = {0, 0, 0, 0, 0}, ci[5] = {0, 0, 0, 0, 0};
-        double b[5] = {1, 0, 0, 0, 0};
-        double er[5] = {1, 0, 0, 0, 0}, ei[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-        for (int n = 0; n < P; ++n) {
-            const double Lr_ = s_L[w][n][0], Li_ = s_L[w][n][1];
+        for (int n = P - 1; n >= 0; --n) {
 #pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                cr[k] += b[k] * (Lr_ * er[k] - Li_ * ei[k]);
-                ci[k] += b[k] * (Lr_ * ei[k] + Li_ * er[k]);
+            for (int k = 4; k >= 0; --k) {
+                const double ar = k > 0 ? cr[k - 1] : s_L[w][n][0];
+                const double ai = k > 0 ? ci[k - 1] : s_L[w][n][1];
+                const double nr = fma(cr[k], dr, fma(-ci[k], di, ar));
+                ci[k] = fma(cr[k], di, fma(ci[k], dr, ai));
+                cr[k] = nr;
             }
-#pragma unroll
-            for (int k = 4; k >= 1; --k) b[k] += b[k - 1];
-#pragma unroll
-            for (int k = 4; k >= 1; --k) { er[k] = er[k - 1]; ei[k] = ei[k - 1]; }
-            const double nr = er[0] * dr - ei[0] * di;
-            ei[0] = er[0] * di + ei[0] * dr;
-            er[0] = nr;
         }
         cplx c[5];
         double sk = isc;                                  // 1/s^(k+1)
@@ -682,7 +676,10 @@ __global__ __launch_bounds__(kThreads) void k_level2_points(
                 const int32_t pe = cell_start[row * g.n1x + xb + 1];
                 for (int32_t pl = pb; pl < pe; ++pl) {
                     const double wr = x0 - lx[pl], wi = y0 - ly[pl];
-                    const double inv = 1.0 / (wr * wr + wi * wi);
+                    // 1/|w|^2: reciprocal estimate and one Newton step (~2^-48)
+                    const double rr = fma(wr, wr, wi * wi);
+                    double inv = __builtin_amdgcn_rcp(rr);
+                    inv = fma(inv, fma(-rr, inv, 1.0), inv);
                     const cplx u = {wr * inv, -wi * inv};
                     cplx t1 = UNIT ? u : cplx{lm[pl] * u.r, lm[pl] * u.i};
                     c[0].r += t1.r; c[0].i += t1.i;
