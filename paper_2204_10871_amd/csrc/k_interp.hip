@@ -602,7 +602,7 @@ __global__ __launch_bounds__(kThreads) void k_level2_near(
 }
 
 template <bool UNIT, int P>
-__global__ __launch_bounds__(kThreads) void k_level2_points(
+__global__ __launch_bounds__(kThreads, 3) void k_level2_points(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
     const double *__restrict__ lm, const int32_t *__restrict__ cell_start, int32_t cy0,
     int32_t nxb, int32_t nchunk, const double *__restrict__ part, double *__restrict__ coef)
