@@ -123,10 +123,11 @@ __device__ __forceinline__ void hidden_layer(const uint4 *__restrict__ wf, const
 {
     const int lane = threadIdx.x % kW, h = lane / 32;
     f32x16 acc[4];
+    // the products accumulate onto the bias (its loads then overlap them)
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[ob][r] = 0.0f;
+        for (int r = 0; r < 16; ++r) acc[ob][r] = bias[drow(ob, r, h)];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
 #pragma unroll
@@ -141,7 +142,7 @@ __device__ __forceinline__ void hidden_layer(const uint4 *__restrict__ wf, const
             float o[8];
 #pragma unroll
             for (int v = 0; v < 8; ++v) {
-                o[v] = fmaxf(acc[mb][8 * j + v] + bias[drow(mb, 8 * j + v, h)], 0.0f);
+                o[v] = fmaxf(acc[mb][8 * j + v], 0.0f);
                 if (SAVE && o[v] > 0.0f) mask |= 1ull << (16 * mb + 8 * j + v);
             }
             B[2 * mb + j] = make_uint4(pack2(o[0], o[1]), pack2(o[2], o[3]), pack2(o[4], o[5]),
