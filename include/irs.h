@@ -156,6 +156,9 @@ typedef struct {
     int32_t pad_;
     double  ray_flops;            /* algorithmic FP64 flops of the level-3 launches   */
                                   /* (interpolation; 46 per ray + 10 per near lens)   */
+    int32_t super_cells;          /* sides, in level-1 cells, of the super and mid     */
+    int32_t mid_cells;            /* cells of the distant-field tree the plan uses     */
+                                  /* (0: level absent or not built yet)                */
 } irs_map_stats;
 
 /*

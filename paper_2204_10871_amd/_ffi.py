@@ -60,7 +60,8 @@ class MapStats(C.Structure):
                 ("n_level2_launches", C.c_int32),
                 ("n_ray_launches", C.c_int32), ("ms_level2", C.c_double),
                 ("ms_level2_expand", C.c_double), ("ms_rays", C.c_double),
-                ("learned", C.c_int32), ("pad_", C.c_int32), ("ray_flops", C.c_double)]
+                ("learned", C.c_int32), ("pad_", C.c_int32), ("ray_flops", C.c_double),
+                ("super_cells", C.c_int32), ("mid_cells", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

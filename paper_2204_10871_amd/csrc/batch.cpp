@@ -512,6 +512,8 @@ irs_status irs_batch_run(irs_batch_t b, uint32_t *const *counts, irs_map_stats *
             s.kappa_star_eff = p->kappa_star_eff;
             s.ms_total = ms;                      // the whole batch's graph launch
             if (p->params.method == IRS_DIRECT) s.direct_pairs = s.rays_shot * p->n_lens;
+            s.super_cells = p->super_k;
+            s.mid_cells = p->super_k > 0 ? p->mid_k : 0;
         }
     }
     set_error("");

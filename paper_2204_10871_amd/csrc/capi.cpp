@@ -387,6 +387,8 @@ static irs_status shoot(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t *
         stats->kappa_star_eff = plan->kappa_star_eff;
         stats->ms_total = ms;
         stats->learned = (plan->params.method == IRS_LEARNED && plan->learn_ok) ? 1 : 0;
+        stats->super_cells = plan->super_k;
+        stats->mid_cells = plan->super_k > 0 ? plan->mid_k : 0;
     }
     set_error("");
     return IRS_OK;

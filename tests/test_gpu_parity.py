@@ -209,6 +209,37 @@ def test_critical_and_invalid_plans(irs):
             pl.shoot_rows(-1, 3, np.zeros(16 * 16, np.uint32))
 
 
+def test_three_level_field_equals_paper_form(irs):
+    """At 3e4 lenses the distant field goes through super cells, mid cells and
+    the cells themselves; the deflections it gives equal those of the
+    per-point sums over every distant lens (the paper's form) to FP64
+    rounding, on a coarse level-2 grid (q = 4) that keeps the latter cheap."""
+    import paper_2204_10871_amd as irs_mod
+    S = irs_mod.source_side_for_n_star(0.45, 0.05, 0.45, 30000)
+    c = Case(0.45, 0.05, 0.45, S, 256, n_rays=2_000_000, level2_ray_multiple=2.0,
+             n_lens=30000, seed=63)
+    g = c.geo
+    assert g.q == 4
+    L = c.lenses
+    out = {}
+    for paper in (False, True):
+        p = irs_mod.make_params(**c.kw, method="interp", precision="fp64",
+                                level2_paper=paper, **c.p_extra)
+        with irs_mod.Plan(p, L.x, L.y, L.m) as pl:
+            a1, a2, px = pl.deflect_grid(0, pl.n_rays)
+            counts, st = pl.shoot_map()
+        out[paper] = (a1, a2, px, counts, st)
+    st = out[False][4]
+    say(f"three levels: cells {g.n1x}x{g.n1y}, super {st['super_cells']}, mid {st['mid_cells']}")
+    assert st["super_cells"] > st["mid_cells"] > 0
+    assert out[True][4]["super_cells"] == 0
+    e = rel_err(out[False][0], out[False][1], out[True][0], out[True][1])
+    say(f"  max e_r three-level vs paper form {e.max():.3e}")
+    assert e.max() < 1e-11
+    assert np.mean(out[False][2] == out[True][2]) >= 1 - 1e-6
+    assert np.abs(out[False][3].astype(np.int64) - out[True][3]).sum() <= 2 * np.sum(out[False][2] != out[True][2])
+
+
 @pytest.mark.parametrize("kind", ["square_cells", "oblong_cells"])
 def test_level2_local_expansion_equals_paper_form(irs, kind):
     """The per-cell local expansion gives the same level-2 coefficients as the
