@@ -1,5 +1,6 @@
 // Direct ray shooting: every ray sums every lens (Eq. 6), then the macro term
-// and the rectangle's negative sheet (Appendix A), the mapping
+// and the negative sheet (the rectangle's closed forms of Appendix A, or
+// -kappa_* theta on a circular lens plane, Eq. 9), the mapping
 // beta = theta - alpha (Eq. 4) and the source-pixel binning.  This is the
 // ordinary IRS the paper compares against (Sec. 3.1), whose cost grows as
 // N_rays * N_* (Eq. 12).

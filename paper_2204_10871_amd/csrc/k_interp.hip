@@ -20,7 +20,10 @@
 // So C_0 = c_0 - kappa_* F(z0), C_k = c_k - kappa_* G^(k)(z0)/k!, and the
 // remaining sheet term -kappa_* conj(h) is exactly linear.  The four corner
 // cells store c_k only (G is singular at the corners); their rays evaluate
-// the sheet in closed form.  Everything in FP64.
+// the sheet in closed form.  Everything in FP64.  k_level2 sums every distant
+// lens at every point, as the paper does (IRS_LEVEL2_PAPER); the default
+// path gets the same c_k, to rounding, from a three-level expansion of the
+// distant field (k_super_expand, k_level2_near, k_level2_points below).
 //
 // Level 3 (k_level3): for every ray, conj(alpha_far + alpha_sheet) =
 // C_0 + C_1 h + ... + C_4 h^4 - kappa_* conj(h) (Horner), plus the nearby
