@@ -105,6 +105,69 @@ __device__ void sheet_coeffs(const DevGeom &g, double x0, double y0, cplx out[5]
     for (int k = 0; k < 5; ++k) out[k] = {-g.kappa_star * gk[k].r, -g.kappa_star * gk[k].i};
 }
 
+// Cells whose level-2 points take the sheet from the cell expansion: G is
+// analytic away from the rectangle's corners, so its Taylor series about the
+// cell centre converges over the cell at the ratio rho = (half diagonal) /
+// (distance to the nearest corner); rho <= 0.2 keeps P = 32 terms within the
+// order rule (the same ratio as the lenses outside the 7 x 7 block).  Both
+// the cell and the point kernels take the decision from this function.
+__device__ __forceinline__ bool sheet_fold_ok(const DevGeom &g, int32_t cx, int32_t cy)
+{
+    if (g.sheet != 1 || corner_cell(g, cx, cy)) return false;
+    const double x = g.a1 + ((double)cx + 0.5) * g.w1, y = g.b1 + ((double)cy + 0.5) * g.h1;
+    const double du = fmin(x - g.a1, g.a2 - x), dv = fmin(y - g.b1, g.b2 - y);
+    const double hd2 = 0.25 * (g.w1 * g.w1 + g.h1 * g.h1);
+    return hd2 <= 0.04 * (du * du + dv * dv);
+}
+
+// Term k of the sheet's part of a cell expansion about (x, y) with scale s,
+// in the cell expansions' convention ((1/s) sum_k L_k u^k, u = (z - zc)/s):
+// -kappa_* s^(k+1) G^(k)(zc)/k!, with G = F - conj(z), G' = 1 - (i/pi) sum_c
+// s_c Log(z - c), G^(k)/k! = -(i/pi) (-1)^k/(k (k-1)) sum_c s_c/(z - c)^(k-1).
+__device__ cplx sheet_cell_term(const DevGeom &g, double x, double y, double s, int k)
+{
+    const double ipi = 1.0 / M_PI;
+    double vr, vi;
+    if (k == 0) {
+        double I1, I2;
+        sheet_unit(g, x, y, I1, I2);
+        vr = (I1 * ipi - x) * s;
+        vi = (-I2 * ipi + y) * s;
+    } else if (k == 1) {
+        double lr = 0.0, li = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double a = (c == 0 || c == 3) ? g.a1 : g.a2;
+            const double b = (c < 2) ? g.b1 : g.b2;
+            const double sgn = (c == 0 || c == 2) ? 1.0 : -1.0;
+            const double u = x - a, v = y - b;
+            lr += sgn * 0.5 * log(u * u + v * v);
+            li += sgn * log_arg(u, v, c >= 2);
+        }
+        vr = (1.0 + li * ipi) * s * s;
+        vi = -lr * ipi * s * s;
+    } else {
+        double ar = 0.0, ai = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double a = (c == 0 || c == 3) ? g.a1 : g.a2;
+            const double b = (c < 2) ? g.b1 : g.b2;
+            const double sgn = (c == 0 || c == 2) ? 1.0 : -1.0;
+            const double u = x - a, v = y - b;
+            const double id = s / (u * u + v * v);
+            const cplx w = {u * id, -v * id};             // s/(z - c)
+            cplx pw = w;
+            for (int e = 2; e < k; ++e) pw = cmul(pw, w);  // (s/(z - c))^(k-1)
+            ar += sgn * pw.r;
+            ai += sgn * pw.i;
+        }
+        const double f = ((k & 1) ? -1.0 : 1.0) / (double)(k * (k - 1)) * s * s;
+        vr = f * ai * ipi;                                 // -(i/pi) f (ar + i ai)
+        vi = -f * ar * ipi;
+    }
+    return {-g.kappa_star * vr, -g.kappa_star * vi};
+}
+
 template <bool UNIT>
 __global__ __launch_bounds__(kThreads) void k_level2(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
@@ -473,7 +536,7 @@ __global__ __launch_bounds__(kThreads) void k_level2_near(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
     const double *__restrict__ lm, const uint32_t *__restrict__ lcxy,
     const int32_t *__restrict__ cell_start, const double *__restrict__ super, int32_t nSx,
-    int32_t c0, int32_t nxb, int32_t ks, int32_t kc, int32_t rc, int32_t nCx,
+    int32_t c0, int32_t nxb, int32_t ks, int32_t kc, int32_t rc, int32_t nCx, int32_t fold,
     double *__restrict__ out)
 {
     __shared__ double s_x[kThreads], s_y[kThreads], s_m[UNIT ? 1 : kThreads];
@@ -591,6 +654,11 @@ __global__ __launch_bounds__(kThreads) void k_level2_near(
             const double f = pow(sc / sS, (double)(k + 1));
             Tr *= f;
             Ti *= f;
+            if (fold && live && sheet_fold_ok(g, cx, cy)) {   // cells only: the sheet's series
+                const cplx t = sheet_cell_term(g, zcr, zci, sc, k);
+                Tr += t.r;
+                Ti += t.i;
+            }
         }
     }
 #pragma unroll
@@ -608,7 +676,8 @@ template <bool UNIT, int P>
 __global__ __launch_bounds__(kThreads, 3) void k_level2_points(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
     const double *__restrict__ lm, const int32_t *__restrict__ cell_start, int32_t cy0,
-    int32_t nxb, int32_t nchunk, const double *__restrict__ part, double *__restrict__ coef)
+    int32_t nxb, int32_t nchunk, int32_t fold, const double *__restrict__ part,
+    double *__restrict__ coef)
 {
     __shared__ double s_L[kCellsPerBlock][P][2];
     const int tid = threadIdx.x;
@@ -698,10 +767,16 @@ __global__ __launch_bounds__(kThreads, 3) void k_level2_points(
             }
         }
         if (g.sheet && !corner_cell(g, ccx, cy)) {
-            cplx sh[5];
-            sheet_coeffs(g, x0, y0, sh);
+            if (fold && sheet_fold_ok(g, ccx, cy)) {
+                // G's series came with the cell expansion; F = conj(z) + G
+                c[0].r -= g.kappa_star * x0;
+                c[0].i += g.kappa_star * y0;
+            } else {
+                cplx sh[5];
+                sheet_coeffs(g, x0, y0, sh);
 #pragma unroll
-            for (int o = 0; o < 5; ++o) { c[o].r += sh[o].r; c[o].i += sh[o].i; }
+                for (int o = 0; o < 5; ++o) { c[o].r += sh[o].r; c[o].i += sh[o].i; }
+            }
         }
         double *dst = coef + (((int64_t)(cy - cy0) * q + gyl) * nxq + gx) * 10;
 #pragma unroll
@@ -1367,7 +1442,7 @@ irs_status ensure_mid_rows(irs_plan_s *p, int64_t Ma, int64_t Mb, double *flops)
 #define IRS_MID(U, PP)                                                                          \
     hipLaunchKernelGGL((k_level2_near<U, PP, PP>), dim3(nb), dim3(kThreads), 0, p->stream, g,    \
                        p->d_x, p->d_y, p->d_m, p->d_cxy, p->d_cell_start, p->d_super, nSx,     \
-                       (int32_t)m0, nxb, ks, km, kSuperR, nMx, dst)
+                       (int32_t)m0, nxb, ks, km, kSuperR, nMx, 0, dst)
         if (p->unit_mass) {
             if (PS == 32) IRS_MID(true, 32);
             else IRS_MID(true, 48);
@@ -1405,7 +1480,8 @@ irs_status level2_prepare(irs_plan_s *p)
     return ensure_mid_buffers(p);
 }
 
-irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *flops)
+irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *flops,
+                                bool fold_sheet)
 {
     const int P = level2_order(p);
     if (P <= 0) {
@@ -1454,7 +1530,7 @@ irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *f
 #define IRS_LN(U, PP, QS)                                                                         \
     hipLaunchKernelGGL((k_level2_near<U, PP, QS>), dim3(nb), dim3(kThreads), 0, p->stream, g,      \
                        p->d_x, p->d_y, p->d_m, p->d_cxy, p->d_cell_start, parent, nSx,          \
-                       (int32_t)c0, nxb, ks, 1, kRing, g.n1x, p->d_part)
+                       (int32_t)c0, nxb, ks, 1, kRing, g.n1x, fold_sheet ? 1 : 0, p->d_part)
     if (p->unit_mass) {
         if (P == 32) { if (PS == 32) IRS_LN(true, 32, 32); else IRS_LN(true, 32, 48); }
         else { if (PS == 32) IRS_LN(true, 48, 32); else IRS_LN(true, 48, 48); }
@@ -1599,9 +1675,12 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
                 // lens chunks (one level) are a property of the plan, so results
                 // do not depend on how a map is cut into calls
                 const int32_t nchunk = level2_chunks(p);
+                // the sheet's series is in the cell expansions when they come
+                // from the super-cell path (launch_level2_expand folds it)
+                const int32_t fold = super_order(p) > 0 ? 1 : 0;
                 const unsigned nbB = (unsigned)((c1 - c0 + 1) * nxb);
                 double fl = 0.0;
-                irs_status st3 = launch_level2_expand(p, c0, c1, cs ? &fl : nullptr);
+                irs_status st3 = launch_level2_expand(p, c0, c1, cs ? &fl : nullptr, true);
                 if (st3 != IRS_OK) return st3;
                 if (cs) {
                     cs->level2_expand_flops += fl;
@@ -1613,7 +1692,7 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
         if (cs && (st2 = cs->begin(s, 2)) != IRS_OK) return st2;                             \
         hipLaunchKernelGGL((k_level2_points<U, PP>), dim3(nbB), dim3(kThreads), 0, s, g,      \
                            p->d_x, p->d_y, p->d_m, p->d_cell_start, (int32_t)c0, nxb, nchunk, \
-                           p->d_part, p->d_coef);                                             \
+                           fold, p->d_part, p->d_coef);                                       \
     } while (0)
                 irs_status st2 = IRS_OK;
                 if (p->unit_mass) {

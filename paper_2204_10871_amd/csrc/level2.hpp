@@ -27,7 +27,10 @@ int32_t level2_chunks(const irs_plan_s *p);
 // order.  Computes the super rows it needs that are not cached.  flops, if
 // not null, receives the algorithmic flops of the launches.  Grows the
 // buffers as needed.  Requires level2_order(p) > 0.
-irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *flops = nullptr);
+// fold_sheet: cells away from the rectangle's corners take the sheet's series
+// into their expansion (the level-2 points then add only -kappa_* conj(z0))
+irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *flops = nullptr,
+                                bool fold_sheet = false);
 
 // Forget the cached super rows (the next expansion recomputes them).
 void level2_reset(irs_plan_s *p);
