@@ -155,9 +155,12 @@ __device__ cplx sheet_cell_term(const DevGeom &g, double x, double y, double s, 
             const double sgn = (c == 0 || c == 2) ? 1.0 : -1.0;
             const double u = x - a, v = y - b;
             const double id = s / (u * u + v * v);
-            const cplx w = {u * id, -v * id};             // s/(z - c)
-            cplx pw = w;
-            for (int e = 2; e < k; ++e) pw = cmul(pw, w);  // (s/(z - c))^(k-1)
+            cplx w = {u * id, -v * id};                   // s/(z - c)
+            cplx pw = {1.0, 0.0};                         // w^(k-1) by squaring
+            for (int e = k - 1; e > 0; e >>= 1) {
+                if (e & 1) pw = cmul(pw, w);
+                w = cmul(w, w);
+            }
             ar += sgn * pw.r;
             ai += sgn * pw.i;
         }
