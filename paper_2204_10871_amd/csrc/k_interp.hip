@@ -1260,8 +1260,10 @@ void level2_reset(irs_plan_s *p)
 //   super expansions  N_* (cells / K_S^2) PS
 //   mid expansions    (cells / K_M^2) (B(K_S) PS + PS^2)
 //   cell expansions   cells (B(K_M or K_S) P + PS P)
-// over K_S in {4, .., 32}, K_M in {0, 4, .., K_S / 2}; the accuracy of every
-// series is that of the order rule whatever the sides.
+// over K_S in {4, .., 32} and K_M in {0, 4, 8} with K_S a multiple of
+// kCellsPerBlock K_M (a workgroup's kCellsPerBlock children must share one
+// parent); the accuracy of every series is that of the order rule whatever
+// the sides.
 void choose_sides(irs_plan_s *p)
 {
     if (p->super_k > 0) return;
@@ -1277,8 +1279,8 @@ void choose_sides(irs_plan_s *p)
     int32_t bs = 8, bm = 0;
     double best = -1.0;
     for (int32_t KS : {4, 8, 16, 32})
-        for (int32_t KM : {0, 4, 8, 16}) {
-            if (KM != 0 && 2 * KM > KS) continue;
+        for (int32_t KM : {0, 4, 8}) {
+            if (KM != 0 && KS % (kCellsPerBlock * KM) != 0) continue;
             double cost = nl * count(KS) * PS + cells * PS * P;
             if (KM == 0) cost += cells * block(KS) * P;
             else cost += count(KM) * (block(KS) * PS + PS * PS) + cells * block(KM) * P;
@@ -1431,6 +1433,10 @@ irs_status ensure_mid_rows(irs_plan_s *p, int64_t Ma, int64_t Mb, double *flops)
     const DevGeom &g = p->dg;
     const int PS = super_order(p);
     const int32_t ks = super_side(p), km = mid_side(p);
+    if (km <= 0 || ks % (kCellsPerBlock * km) != 0) {
+        set_error("internal: mid cells must tile their super cells by workgroups");
+        return IRS_E_INVALID;
+    }
     irs_status st = ensure_mid_buffers(p);
     if (st != IRS_OK) return st;
     if ((st = ensure_super_rows(p, Ma * km / ks, Mb * km / ks, flops)) != IRS_OK) return st;

@@ -209,6 +209,38 @@ def test_critical_and_invalid_plans(irs):
             pl.shoot_rows(-1, 3, np.zeros(16 * 16, np.uint32))
 
 
+@pytest.mark.parametrize("draw", [3, 4, 6])
+def test_tree_sides_on_batch_maps_equal_paper_form(irs, draw):
+    """Maps of the 64-map batch (2477, 25176 and 9115 lenses): the sides the
+    plan picks for its distant-field tree tile their parents by workgroups,
+    and the deflections equal those of the paper's per-point sums, on coarse
+    level-2 grids (q = 4)."""
+    import paper_2204_10871_amd as irs_mod
+    d = synth.configs.batch_draws()[draw]
+    S = irs_mod.source_side_for_n_star(d.kappa_star, d.kappa_c, d.gamma, d.n_star_target)
+    c = Case(d.kappa_star, d.kappa_c, d.gamma, S, 256, n_rays=16 * 16 * d.n_star_target,
+             level2_ray_multiple=4.0, n_lens=d.n_star_target, seed=d.seed)
+    assert c.geo.q == 4
+    L = c.lenses
+    out = {}
+    for paper in (False, True):
+        p = irs_mod.make_params(**c.kw, method="interp", precision="fp64",
+                                level2_paper=paper, **c.p_extra)
+        with irs_mod.Plan(p, L.x, L.y, L.m) as pl:
+            a1, a2, px = pl.deflect_grid(0, pl.n_rays)
+            counts, st = pl.shoot_map()
+        out[paper] = (a1, a2, px, counts, st)
+    st = out[False][4]
+    say(f"batch map {draw}: N*={L.n} cells {c.geo.n1x}x{c.geo.n1y}, super {st['super_cells']}, "
+        f"mid {st['mid_cells']}")
+    if st["mid_cells"] > 0:
+        assert st["super_cells"] % (4 * st["mid_cells"]) == 0
+    e = rel_err(out[False][0], out[False][1], out[True][0], out[True][1])
+    say(f"  max e_r tree vs paper form {e.max():.3e}")
+    assert e.max() < 1e-11
+    assert np.mean(out[False][2] == out[True][2]) >= 1 - 1e-6
+
+
 def test_three_level_field_equals_paper_form(irs):
     """At 3e4 lenses the distant field goes through super cells, mid cells and
     the cells themselves; the deflections it gives equal those of the
