@@ -175,10 +175,15 @@ irs_status irs_geometry(const irs_params *params, int64_t n_lens, irs_geometry_i
  * lenses to the device and pack them into level-1 cells (flow chart, "Lenses
  * packed into level-1 grids").
  *   x, y : n_lens lens positions (host, FP64); m : masses or NULL for all 1.
- *          The arrays are copied; the caller keeps ownership.
+ *          The arrays are copied; the caller keeps ownership.  IRS_INTERP
+ *          and IRS_LEARNED plans need every lens inside the rectangle
+ *          [a1, a2] x [b1, b2] (to 1e-6 of a level-1 cell): the distant
+ *          field's series assume each lens inside its level-1 cell.
  *   hip_stream : hipStream_t to run on, or NULL for the default stream.
  *   out : receives the plan handle (NULL on error).
- * Errors: IRS_E_INVALID, IRS_E_CRITICAL, IRS_E_UNSUPPORTED, IRS_E_NOMEM,
+ * Errors: IRS_E_INVALID (NULL or out-of-range input, a lens position not
+ * finite, a mass not finite or negative, a lens outside the rectangle of an
+ * interpolated plan), IRS_E_CRITICAL, IRS_E_UNSUPPORTED, IRS_E_NOMEM,
  * IRS_E_DEVICE.  The call returns when the plan is ready.
  */
 irs_status irs_plan(const irs_params *params, int64_t n_lens, const double *x,

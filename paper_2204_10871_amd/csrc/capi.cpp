@@ -214,6 +214,19 @@ irs_status irs_plan(const irs_params *params, int64_t n_lens, const double *x, c
         }
         msum += m ? m[i] : 1.0;
     }
+    if (params->method != IRS_DIRECT && n_lens > 0) {
+        // the distant-field series hold for lenses inside their level-1 cells
+        const irs_geometry_info &gi = hg.info;
+        const double tol = 1e-6 * std::min(gi.ix / gi.n1x, gi.iy / gi.n1y);
+        for (int64_t i = 0; i < n_lens; ++i) {
+            if (x[i] < gi.a1 - tol || x[i] > gi.a2 + tol || y[i] < gi.b1 - tol ||
+                y[i] > gi.b2 + tol) {
+                set_error("irs_plan: the interpolated methods need every lens inside the lens "
+                          "rectangle [a1, a2] x [b1, b2]");
+                return IRS_E_INVALID;
+            }
+        }
+    }
     irs_plan_s *p = new (std::nothrow) irs_plan_s();
     if (!p) {
         set_error("irs_plan: host allocation failed");

@@ -815,6 +815,7 @@ struct alignas(32) RowInfo {
     int32_t gy;       // level-2 row
     int32_t cy;       // level-1 row
     int64_t base;     // index of the row's first ray (j nx)
+    double c2;        // t2 - (kappa - gamma) t2 + kappa_* hi (sheet on) + S/2
 };
 
 // floor(num / den) for 0 <= num < 2^53, den > 0, without 64-bit integer division
@@ -847,6 +848,55 @@ __device__ __forceinline__ void near_term(double d1, double d1s, double t2, doub
     n2 = fma(w, d2, n2);
 }
 
+// The same for G rays of one column (rows t2s[0..G-1]): the G quotients
+// m/rr_k come from one reciprocal of their product p = rr_0 ... rr_{G-1},
+// corrected once as above (q = m/p), then back-substitution through the
+// prefix products P_k = rr_0 ... rr_k: m/rr_k = q P_{k-1} for k = G-1 down to
+// 1, q taking q rr_k = m/P_{k-1} after each step, and m/rr_0 = the last q.
+// Each quotient carries at most about 2G + 4 units of rounding.  Where p lies
+// outside [1e-200, 1e200] (a lens exactly on a ray, where rr is kNearTiny,
+// or rr beyond that range) the quotients are taken one by one.
+constexpr double kGroupMin = 1e-200, kGroupMax = 1e200;
+
+template <int G>
+__device__ __forceinline__ void near_group(double d1, double d1s, const double *t2s, double zy,
+                                           double m, double *n1s, double *n2s)
+{
+    double d2[G], rr[G], pre[G], w[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        d2[k] = t2s[k] - zy;
+        rr[k] = fma(d2[k], d2[k], d1s);
+    }
+    pre[0] = rr[0];
+#pragma unroll
+    for (int k = 1; k < G; ++k) pre[k] = pre[k - 1] * rr[k];
+    const double p = pre[G - 1];
+    if (__builtin_expect(p > kGroupMin && p < kGroupMax, 1)) {
+        const double v = __builtin_amdgcn_rcp(p);
+        const double y = m * v;
+        double q = fma(v, fma(-p, y, m), y);          // m / p
+#pragma unroll
+        for (int k = G - 1; k >= 1; --k) {
+            w[k] = q * pre[k - 1];
+            q = q * rr[k];                            // m / P_{k-1}
+        }
+        w[0] = q;
+    } else {
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const double v = __builtin_amdgcn_rcp(rr[k]);
+            const double y = m * v;
+            w[k] = fma(v, fma(-rr[k], y, m), y);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        n1s[k] = fma(w[k], d1, n1s[k]);
+        n2s[k] = fma(w[k], d2[k], n2s[k]);
+    }
+}
+
 // Nearby lenses of RR rays in one column (t1) and RR rows (t2s) that share
 // the level-1 cell row cy: the lenses of cells (xl..xh, cy-1..cy+1).  The
 // loop is the same for the whole wave: it runs over the lenses of cells
@@ -854,7 +904,8 @@ __device__ __forceinline__ void near_term(double d1, double d1s, double t2, doub
 // data come through scalar loads); where the wave's lanes lie in more than
 // one cell column (straddle), a lane gives the lenses outside its own xl..xh
 // mass 0, which adds exact zeros.  Lenses are taken in their sorted order.
-template <bool UNIT, int RR>
+// STRADDLE = false is the same pass for a wave known to lie in one column.
+template <bool UNIT, int RR, bool STRADDLE>
 __device__ __forceinline__ void near_pass(const DevGeom &g, const double2 *__restrict__ lxy,
                                           const double *__restrict__ lm,
                                           const int32_t *__restrict__ cell_start, int32_t cy,
@@ -867,18 +918,22 @@ __device__ __forceinline__ void near_pass(const DevGeom &g, const double2 *__res
         const int32_t pb = cell_start[row * g.n1x + cl];
         const int32_t pe = cell_start[row * g.n1x + ch + 1];
         int32_t lpb = pb, lpe = pe;
-        if (straddle) {
+        if (STRADDLE && straddle) {
             lpb = cell_start[row * g.n1x + xl];
             lpe = cell_start[row * g.n1x + xh + 1];
         }
         for (int32_t q_ = pb; q_ < pe; ++q_) {
             const double2 z = lxy[q_];
             double m = UNIT ? 1.0 : lm[q_];
-            if (straddle) m = (q_ >= lpb && q_ < lpe) ? m : 0.0;
+            if (STRADDLE && straddle) m = (q_ >= lpb && q_ < lpe) ? m : 0.0;
             const double d1 = t1 - z.x;
             const double d1s = fma(d1, d1, kNearTiny);
+            if constexpr (RR > 1) {
+                near_group<RR>(d1, d1s, t2s, z.y, m, n1s, n2s);
+            } else {
 #pragma unroll
-            for (int k = 0; k < RR; ++k) near_term(d1, d1s, t2s[k], z.y, m, n1s[k], n2s[k]);
+                for (int k = 0; k < RR; ++k) near_term(d1, d1s, t2s[k], z.y, m, n1s[k], n2s[k]);
+            }
         }
     }
 }
@@ -907,6 +962,9 @@ __global__ __launch_bounds__(kThreads) void k_row_table(DevGeom g, RowInfo *rows
     r.gy = (int32_t)gy;
     r.cy = (int32_t)(gy / g.q);
     r.base = j * g.nx;
+    const double mac = g.kmg * r.t2;
+    const double sh = g.sheet ? g.kappa_star * r.hi : 0.0;
+    r.c2 = ((r.t2 - mac) + sh) + g.half_side;
     rows[j] = r;
 }
 
@@ -930,9 +988,11 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
     const int64_t tx = (int64_t)blockIdx.x % ntx;
     const int64_t ty = (int64_t)blockIdx.x / ntx;
     constexpr int R = kL3RowsPerWave;
-    const int64_t jb = jr0 + ty * kL3Rows;
+    // tiles start at multiples of kL3Rows whatever [jr0, jr1) is, so a ray
+    // meets the same rows of its wave (and the same rounding) in every launch
+    const int64_t jb = (jr0 / kL3Rows + ty) * kL3Rows;
     const int64_t jw = jb + wave * R;                    // the wave's first row
-    if (tid < kL3Rows) s_t2[tid] = rows[min(jb + tid, jr1 - 1)].t2;
+    if (tid < kL3Rows) s_t2[tid] = rows[min(jb + tid, g.ny - 1)].t2;
     const int64_t i = tx * kWave + lane;
     const bool in_col = i < g.nx;
     const int64_t nxq = (int64_t)g.n1x * g.q;
@@ -940,19 +1000,26 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
     const int32_t cx = (int32_t)gx / g.q;
     const double t1 = ray_x(g, i);
     const double hr = t1 - level2_x(g, gx);
+    // beta_1 + S/2 of the column's rays without the lens terms: the macro
+    // term and the sheet's -kappa_* conj(h) part (the row's c2 holds the
+    // same for beta_2)
+    const double s1 = g.sheet ? g.kappa_star * hr : 0.0;
+    const double mac1 = g.kpg * t1;
+    const double c1 = ((t1 - mac1) + s1) + g.half_side;
     const int32_t xl = cx > 0 ? cx - 1 : 0, xh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
     const uint32_t coff = (uint32_t)gx * 10u * (uint32_t)sizeof(double);   // lane's point in a row
 
-    // the wave's rows (rows past jr1 repeat the last one and bin nothing)
-    const RowInfo *rw = rows + min(jw, jr1 - 1);
-    const int nr = (int)min<int64_t>(R, jr1 - jw);       // rows of the wave inside [jr0, jr1)
-    auto row = [&](int k) -> const RowInfo & { return rw[k < nr ? k : (nr > 0 ? nr - 1 : 0)]; };
+    // the wave's rows jw + k (rows past the grid repeat its last one); rows
+    // k0 <= k < k1 lie inside [jr0, jr1), the others bin nothing
+    const int k0 = (int)max<int64_t>(0, jr0 - jw), k1 = (int)min<int64_t>(R, jr1 - jw);
+    auto row = [&](int k) -> const RowInfo & { return rows[min(jw + k, g.ny - 1)]; };
 
     // nearby lenses, exactly.  A lane's rays are R consecutive rows of one
     // column; they nearly always share their level-1 cell row (a cell spans
-    // hundreds of ray rows), so one pass over the lenses serves them all;
-    // otherwise each ray takes its own pass.  Both add the same terms in the
-    // same order with the same operations.
+    // hundreds of ray rows), so one pass over the lenses serves them all, the
+    // R rows sharing each reciprocal; otherwise each ray takes its own pass.
+    // Which of the two a ray takes, and its partners in the first, depend
+    // only on its row.
     __syncthreads();
     double n1s[R], n2s[R], t2s[R];
 #pragma unroll
@@ -960,7 +1027,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
         n1s[k] = n2s[k] = 0.0;
         t2s[k] = s_t2[wave * R + k];     // row(k).t2, in a vector register
     }
-    if (nr > 0) {                                         // wave-uniform rows
+    if (k1 > k0) {                                        // wave-uniform rows
         // level-1 columns of the wave's first and last ray (lane 0 always
         // holds a ray column)
         const int32_t cxa = __builtin_amdgcn_readfirstlane(cx);
@@ -969,14 +1036,18 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
         const bool straddle = cxa != cxb;
         const int32_t cy0r = row(0).cy;
         if (row(R - 1).cy == cy0r) {                      // rows sorted: all share cy0r
-            near_pass<UNIT, R>(g, lxy, lm, cell_start, cy0r, cl, ch, straddle, xl, xh, t1, t2s,
-                               n1s, n2s);
+            if (straddle)
+                near_pass<UNIT, R, true>(g, lxy, lm, cell_start, cy0r, cl, ch, true, xl, xh, t1,
+                                         t2s, n1s, n2s);
+            else
+                near_pass<UNIT, R, false>(g, lxy, lm, cell_start, cy0r, cl, ch, false, xl, xh, t1,
+                                          t2s, n1s, n2s);
         } else {
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                if (k >= nr) continue;
-                near_pass<UNIT, 1>(g, lxy, lm, cell_start, row(k).cy, cl, ch, straddle, xl, xh,
-                                   t1, &t2s[k], &n1s[k], &n2s[k]);
+                if (k < k0 || k >= k1) continue;
+                near_pass<UNIT, 1, true>(g, lxy, lm, cell_start, row(k).cy, cl, ch, straddle, xl,
+                                         xh, t1, &t2s[k], &n1s[k], &n2s[k]);
             }
         }
     }
@@ -985,9 +1056,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
     auto coef_row = [&](int32_t gy) {
         return (const double2 *)((const char *)(coef + (int64_t)(gy - cy0 * g.q) * nxq * 10) + coff);
     };
-    double2 C[5];
-    int32_t cgy = row(0).gy;
-    {
+    double2 C[5] = {};
+    int32_t cgy = -1;                                     // level-2 row held in C
+    if (k1 > k0) {
+        cgy = row(k0).gy;
         const double2 *cp = coef_row(cgy);
 #pragma unroll
         for (int e = 0; e < 5; ++e) C[e] = cp[e];
@@ -995,19 +1067,19 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
 
     const int32_t i32 = (int32_t)i;
     // rows whose rays all lie in [ray_first, ray_last) need no per-ray test
-    const bool full = nr > 0 && row(0).base >= ray_first && row(nr - 1).base + g.nx <= ray_last;
+    const bool full = k1 > k0 && row(k0).base >= ray_first && row(k1 - 1).base + g.nx <= ray_last;
     int32_t pxs[R], pys[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         bool valid;
         if (full) {
-            valid = k < nr && in_col;
+            valid = k >= k0 && k < k1 && in_col;
         } else {
             // columns of row k inside [ray_first, ray_last), as a lane window
             const int64_t lo = ray_first - row(k).base, hi_ = ray_last - row(k).base;
             const int32_t wlo = (int32_t)(lo < 0 ? 0 : (lo > g.nx ? g.nx : lo));
             const int32_t whi = (int32_t)(hi_ < 0 ? 0 : (hi_ > g.nx ? g.nx : hi_));
-            valid = k < nr && i32 >= wlo && i32 < whi;
+            valid = k >= k0 && k < k1 && i32 >= wlo && i32 < whi;
         }
         pxs[k] = -1;
         pys[k] = -1;
@@ -1018,31 +1090,33 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
             for (int e = 0; e < 5; ++e) C[e] = cp[e];
             cgy = row(k).gy;
         }
-        const double t2 = row(k).t2, hi = row(k).hi;
+        const double hi = row(k).hi;
         const int32_t cy = row(k).cy;
-        // Horner: C0 + h (C1 + h (C2 + h (C3 + h C4)))
-        cplx A = {C[4].x, C[4].y};
+        // Horner: A = C0 + h (C1 + h (C2 + h (C3 + h C4))), two fused
+        // multiply-adds per component and step; conj(A) is the far deflection
+        double Ar = C[4].x, Ai = C[4].y;
 #pragma unroll
         for (int o = 3; o >= 0; --o) {
-            A = cmul(A, cplx{hr, hi});
-            A.r += C[o].x;
-            A.i += C[o].y;
+            const double r = fma(Ar, hr, fma(-Ai, hi, C[o].x));
+            Ai = fma(Ar, hi, fma(Ai, hr, C[o].y));
+            Ar = r;
         }
-        if (g.sheet) {
-            if (corner_cell(g, cx, cy)) {
-                double I1, I2;
-                sheet_unit(g, t1, t2, I1, I2);
-                A.r += g.sheet_f * I1;
-                A.i -= g.sheet_f * I2;
-            } else {
-                A.r -= g.kappa_star * hr;     // -kappa_* conj(h)
-                A.i += g.kappa_star * hi;
-            }
+        // the rectangle's corner cells take the sheet's closed form in place
+        // of the -kappa_* conj(h) that c1 and c2 hold
+        if (g.sheet && corner_cell(g, cx, cy)) {
+            double I1, I2;
+            sheet_unit(g, t1, row(k).t2, I1, I2);
+            Ar += g.sheet_f * I1 + g.kappa_star * hr;
+            Ai -= g.sheet_f * I2 + g.kappa_star * hi;
         }
-        const double a1 = g.kpg * t1 + n1s[k] + A.r;   // conj(A) is the far + sheet deflection
-        const double a2 = g.kmg * t2 + n2s[k] - A.i;
-        pixel_xy(g, t1 - a1, t2 - a2, pxs[k], pys[k]);
+        // beta + S/2 = (c1, c2) - nearby lenses - conj(A)
+        const double xs1 = (c1 - n1s[k]) - Ar;
+        const double xs2 = (row(k).c2 - n2s[k]) + Ai;
+        pixel_xy_shifted(g, xs1, xs2, pxs[k], pys[k]);
         if (!BIN) {
+            const double s2 = g.sheet ? g.kappa_star * hi : 0.0;
+            const double a1 = fma(g.kpg, t1, n1s[k]) + (Ar - s1);
+            const double a2 = fma(g.kmg, row(k).t2, n2s[k]) - (Ai + s2);
             const int64_t o = row(k).base + i - ray_first;
             if (a1o) a1o[o] = a1;
             if (a2o) a2o[o] = a2;
@@ -1725,13 +1799,16 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
         const int64_t jA = std::max(sel.row0, first_row_at(g, c0 * q));
         const int64_t jB = std::min(sel.row1, first_row_at(g, (c1 + 1) * q));
         if (jB <= jA) continue;
-        const int64_t nty = (jB - jA + rows_per_block - 1) / rows_per_block;
+        // tiles of rows_per_block rows at multiples of rows_per_block (the
+        // kernel starts its first tile at the multiple at or below j0)
+        const int64_t ta = jA / rows_per_block;
+        const int64_t nty = (jB + rows_per_block - 1) / rows_per_block - ta;
         const int64_t max_ty = std::max<int64_t>(1, ((int64_t)1 << 24) / ntx);
         for (int64_t t0 = 0; t0 < nty; t0 += max_ty) {
             const int64_t t1 = std::min(nty, t0 + max_ty);
             const unsigned nb3 = (unsigned)((t1 - t0) * ntx);
-            const int64_t j0 = jA + t0 * rows_per_block;
-            const int64_t j1 = std::min(jB, jA + t1 * rows_per_block);
+            const int64_t j0 = std::max(jA, (ta + t0) * rows_per_block);
+            const int64_t j1 = std::min(jB, (ta + t1) * rows_per_block);
             if (cs) {
                 irs_status st = cs->begin(s, 1);
                 if (st != IRS_OK) return st;

@@ -112,6 +112,19 @@ def test_plan_rejects_bad_lenses_before_device(irs):
     assert e.value.status == 1
 
 
+@pytest.mark.parametrize("method", ["interp", "learned"])
+def test_interpolated_plans_reject_lenses_off_the_rectangle(irs, method):
+    """The distant-field series assume every lens inside its level-1 cell: a
+    lens outside the rectangle fails on the host (no device call is made)."""
+    p = irs.make_params(0.3, 0.0, 0.3, 10.0, 64, rays_per_pixel=10.0, method=method)
+    g = irs.geometry(p, 2)
+    for x, y in ((g["a2"] + 0.01 * g["ix"], 0.0), (0.0, g["b1"] - 1e3), (1e60, 0.0)):
+        with pytest.raises(irs.IrsError) as e:
+            irs.Plan(p, np.array([0.0, x]), np.array([0.0, y]))
+        assert e.value.status == 1
+        assert "inside the lens rectangle" in str(e.value)
+
+
 def test_learned_entry_points_reject_bad_arguments(irs):
     """Argument checks of the learned interpolant's entry points (no device work)."""
     import ctypes as C
