@@ -299,11 +299,25 @@ __device__ __forceinline__ double rcp64(double d)
     return fma(v, e, v);
 }
 
-__device__ __forceinline__ double wave_sum(double v)
+}  // namespace
+}  // namespace irs
+// the device library's whole-wave FP64 sum (declared by the HIP headers only
+// on request)
+extern "C" __device__ __attribute__((const)) double __ockl_wfred_add_f64(double);
+namespace irs {
+namespace {
+
+// whole-wave sum (every lane active) through the device library's cross-lane
+// (DPP) sequence; the order of the additions is fixed
+__device__ __forceinline__ double wave_sum(double v) { return __ockl_wfred_add_f64(v); }
+
+// the value lane n (uniform) holds
+__device__ __forceinline__ double lane_value(double v, int n)
 {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, n);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), n);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 template <bool UNIT, int P>
@@ -666,7 +680,8 @@ __global__ __launch_bounds__(kThreads) void k_level2_near(
     }
 #pragma unroll
     for (int n = 0; n < P; ++n) {
-        const double r = wave_sum(Lr[n]) + __shfl(Tr, n), i = wave_sum(Li[n]) + __shfl(Ti, n);
+        const double r = wave_sum(Lr[n]) + lane_value(Tr, n);
+        const double i = wave_sum(Li[n]) + lane_value(Ti, n);
         if (lane == 0 && live) {
             double *dst = out + ((((int64_t)(cy - c0) * nCx + cx)) * P + n) * 2;
             dst[0] = r;
@@ -938,18 +953,11 @@ __device__ __forceinline__ void near_pass(const DevGeom &g, const double2 *__res
     }
 }
 
-__device__ __forceinline__ int wave_min(int v)
-{
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    return v;
-}
-__device__ __forceinline__ int wave_max(int v)
-{
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
-}
+// whole-wave reductions (every lane active) through the device library's
+// cross-lane (DPP) sequences rather than LDS permutes
+__device__ __forceinline__ int wave_min(int v) { return __ockl_wfred_min_i32(v); }
+__device__ __forceinline__ int wave_max(int v) { return __ockl_wfred_max_i32(v); }
+__device__ __forceinline__ int wave_add(int v) { return __ockl_wfred_add_i32(v); }
 
 __global__ __launch_bounds__(kThreads) void k_row_table(DevGeom g, RowInfo *rows)
 {
@@ -1136,13 +1144,11 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
     }
     bx0 = wave_min(bx0); bx1 = wave_max(bx1);
     by0 = wave_min(by0); by1 = wave_max(by1);
-    unsigned long long wl = (unsigned long long)nland;
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) wl += __shfl_xor(wl, o);
+    const int wl = wave_add(nland);
     if (lane == 0) {
         s_box[wave][0] = bx0; s_box[wave][1] = bx1;
         s_box[wave][2] = by0; s_box[wave][3] = by1;
-        s_box[wave][4] = (int)wl;
+        s_box[wave][4] = wl;
     }
     __syncthreads();
     bx0 = INT_MAX; bx1 = -1; by0 = INT_MAX; by1 = -1;
