@@ -62,7 +62,7 @@ def bench_learned(irs, synth, torch, stream, args, result):
     """The learned interpolant on its workload (kappa_* = gamma = 0.5,
     kappa_c = 0.05, N_* = 1e6 unit lenses, 8192^2 px, 100 rays/px): training,
     validation, three level-1 row bands timed against the grid interpolation
-    on the same bands, and a ray sample judged by the oracle's direct sum."""
+    on the same bands, and a ray sample checked against the oracle's direct sum."""
     import numpy as np
     import oracle as orc
     w = synth.configs.CFG5
@@ -102,7 +102,7 @@ def bench_learned(irs, synth, torch, stream, args, result):
             log(f"{name}: whole map {sec:.2f} s (level-2 {st['ms_level2']:.0f} ms, rays "
                 f"{st['ms_rays']:.0f} ms), {st['rays_shot'] / sec:.3e} rays/s")
         out.update(res)
-        # judge: the direct definition on a ray sample of the first band
+        # check: the direct definition on a ray sample of the first band
         og = orc.geometry(w.kappa_star, w.kappa_c, w.gamma, w.source_side, w.npix,
                           rays_per_pixel=w.rays_per_pixel, n_lens=L.n)
         j0, j1 = bands[0]
@@ -122,7 +122,7 @@ def bench_learned(irs, synth, torch, stream, args, result):
             d = np.hypot(g1 - ref["alpha1"], g2 - ref["alpha2"])
             rel = d / np.hypot(ref["alpha1"], ref["alpha2"])
             mis = int(np.sum(gp != ref["pix"]))
-            out[name]["judge"] = {"rays": int(nsamp), "max_abs_alpha_err": float(d.max()),
+            out[name]["direct_check"] = {"rays": int(nsamp), "max_abs_alpha_err": float(d.max()),
                                   "mean_abs_alpha_err": float(d.mean()),
                                   "max_rel_alpha_err": float(rel.max()),
                                   "pixel_mismatches": mis}

@@ -1192,7 +1192,7 @@ double quantile(std::vector<float> v, double q)
 }
 
 // validate the plan's network on n_val samples from rows between the
-// training rows; fills the report's validation fields and the verdict
+// training rows; fills the report's validation fields and the decision
 irs_status validate(irs_plan_s *p, const irs_learn_params &lp, irs_learn_report &rep)
 {
     const int qc = p->learn_qc;
@@ -1516,7 +1516,7 @@ irs_status irs_learn(irs_plan_t p, const irs_learn_params *lpp, const float *fre
     rep.steps = lp.steps;
     rep.ms_train = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 
-    // 3. validation and the verdict
+    // 3. validation and the decision
     if ((st = validate(p, lp, rep)) != IRS_OK) return st;
     if (report) *report = rep;
     set_error("");

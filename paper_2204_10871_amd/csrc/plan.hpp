@@ -69,7 +69,7 @@ struct irs_plan_s {
     double *d_super_part = nullptr;       // per-(super cell, lens chunk) partials
     size_t super_part_bytes = 0;
 
-    // Learned interpolant (IRS_LEARNED): network, validation verdict and the
+    // Learned interpolant (IRS_LEARNED): network, validation decision and the
     // corner table of one band of level-1 rows (4 doubles per corner:
     // Re A, Im A, Re A', Im A'; (qc + 1)^2 corners per cell).
     int learn_qc = 0;                     // squares per cell side; 0: no network

@@ -233,7 +233,7 @@ def test_learned_rays_match_oracle_and_direct(irs, trained):
 
 
 def test_learned_map_vs_direct(irs, trained):
-    """Whole map: the learned map against the direct-sum map (the judge)."""
+    """Whole map: the learned map against the direct-sum map (the reference)."""
     pl, p, L, og, rep = trained
     if rep["fallback"]:
         pytest.skip("the network missed the tolerance; the fallback is tested separately")
