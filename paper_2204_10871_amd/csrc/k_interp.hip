@@ -868,10 +868,9 @@ __device__ __forceinline__ void near_term(double d1, double d1s, double t2, doub
 // corrected once as above (q = m/p), then back-substitution through the
 // prefix products P_k = rr_0 ... rr_k: m/rr_k = q P_{k-1} for k = G-1 down to
 // 1, q taking q rr_k = m/P_{k-1} after each step, and m/rr_0 = the last q.
-// Each quotient carries at most about 2G + 4 units of rounding.  Here d1s is
-// d1^2 alone; where p lies outside [1e-200, 1e200] (a lens exactly on a ray,
-// or rr beyond that range) the quotients are taken one by one from
-// rr + kNearTiny, as in near_term (the same rr wherever rr > 1e-284).
+// Each quotient carries at most about 2G + 4 units of rounding.  Where p lies
+// outside [1e-200, 1e200] (a lens exactly on a ray, where rr is kNearTiny,
+// or rr beyond that range) the quotients are taken one by one.
 constexpr double kGroupMin = 1e-200, kGroupMax = 1e200;
 
 template <int G>
@@ -901,10 +900,9 @@ __device__ __forceinline__ void near_group(double d1, double d1s, const double *
     } else {
 #pragma unroll
         for (int k = 0; k < G; ++k) {
-            const double r = rr[k] + kNearTiny;
-            const double v = __builtin_amdgcn_rcp(r);
+            const double v = __builtin_amdgcn_rcp(rr[k]);
             const double y = m * v;
-            w[k] = fma(v, fma(-r, y, m), y);
+            w[k] = fma(v, fma(-rr[k], y, m), y);
         }
     }
 #pragma unroll
@@ -944,10 +942,10 @@ __device__ __forceinline__ void near_pass(const DevGeom &g, const double2 *__res
             double m = UNIT ? 1.0 : lm[q_];
             if (STRADDLE && straddle) m = (q_ >= lpb && q_ < lpe) ? m : 0.0;
             const double d1 = t1 - z.x;
+            const double d1s = fma(d1, d1, kNearTiny);
             if constexpr (RR > 1) {
-                near_group<RR>(d1, d1 * d1, t2s, z.y, m, n1s, n2s);
+                near_group<RR>(d1, d1s, t2s, z.y, m, n1s, n2s);
             } else {
-                const double d1s = fma(d1, d1, kNearTiny);
 #pragma unroll
                 for (int k = 0; k < RR; ++k) near_term(d1, d1s, t2s[k], z.y, m, n1s[k], n2s[k]);
             }
