@@ -1719,6 +1719,25 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
     const int64_t ntx = (g.nx + kWave - 1) / kWave;
     const int rows_per_block = kL3Rows;
     CallStats *cs = sel.stats;
+    if (level2_order(p) > 0 && super_order(p) > 0 &&
+        !(p->coef_c0 <= cyA && cyB <= p->coef_c1)) {
+        // the super rows of every band of the call in one launch (a band's own
+        // rows, one or two, fill a fraction of the chip); the bands then find
+        // them cached.  Each row's expansion is the same whatever the launch.
+        const int32_t ks = super_side(p);
+        if (cs) {
+            irs_status st = cs->begin(s, 0);
+            if (st != IRS_OK) return st;
+        }
+        double fl = 0.0;
+        irs_status st = ensure_super_rows(p, cyA / ks, cyB / ks, cs ? &fl : nullptr);
+        if (st != IRS_OK) return st;
+        if (cs) {
+            cs->level2_expand_flops += fl;
+            cs->level2_flops += fl;
+            if ((st = cs->end(s)) != IRS_OK) return st;
+        }
+    }
     for (int64_t c0 = cyA; c0 <= cyB; c0 += p->coef_rows_cap) {
         const int64_t c1 = std::min(cyB, c0 + p->coef_rows_cap - 1);
         if (!(p->coef_c0 <= c0 && c1 <= p->coef_c1)) {
