@@ -1721,16 +1721,17 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
     CallStats *cs = sel.stats;
     if (level2_order(p) > 0 && super_order(p) > 0 &&
         !(p->coef_c0 <= cyA && cyB <= p->coef_c1)) {
-        // the super rows of every band of the call in one launch (a band's own
-        // rows, one or two, fill a fraction of the chip); the bands then find
+        // the super (and mid) rows of every band of the call in one launch each
+        // (a band's own rows fill a fraction of the chip); the bands then find
         // them cached.  Each row's expansion is the same whatever the launch.
-        const int32_t ks = super_side(p);
+        const int32_t ks = super_side(p), km = mid_side(p);
         if (cs) {
             irs_status st = cs->begin(s, 0);
             if (st != IRS_OK) return st;
         }
         double fl = 0.0;
-        irs_status st = ensure_super_rows(p, cyA / ks, cyB / ks, cs ? &fl : nullptr);
+        irs_status st = km > 0 ? ensure_mid_rows(p, cyA / km, cyB / km, cs ? &fl : nullptr)
+                               : ensure_super_rows(p, cyA / ks, cyB / ks, cs ? &fl : nullptr);
         if (st != IRS_OK) return st;
         if (cs) {
             cs->level2_expand_flops += fl;
