@@ -98,12 +98,12 @@ __device__ __forceinline__ void sheet_unit(const DevGeom &g, double t1, double t
     I2 = s2;
 }
 
-// floor((b + S/2) / dpix) with the quotient rounded as an IEEE division: the
-// product by 1/dpix is within 1e-9 of that quotient for |quotient| < 1e6, so
-// its floor is the same unless it lies that close to an integer, where the
-// division itself decides.  For |quotient| >= 1e6 the result may differ from
-// that floor by one, which lies off every map (npix <= 46340) either way.
-// The same from xs = b + S/2.
+// floor(xs / dpix) for xs = b + S/2, with the quotient rounded as an IEEE
+// division: the product by 1/dpix is within 1e-9 of that quotient for
+// |quotient| < 1e6, so its floor is the same unless it lies that close to an
+// integer, where the division itself decides.  For |quotient| >= 1e6 the
+// result may differ from that floor by one, which lies off every map
+// (npix <= 46340) either way.
 __device__ __forceinline__ double pixel_floor_shifted(const DevGeom &g, double xs)
 {
     const double q = xs * g.inv_dpix;
@@ -111,25 +111,9 @@ __device__ __forceinline__ double pixel_floor_shifted(const DevGeom &g, double x
     if (fabs((q - f) - 0.5) > 0.5 - 1e-9) return floor(xs / g.dpix);
     return f;
 }
-__device__ __forceinline__ double pixel_floor(const DevGeom &g, double b)
-{
-    return pixel_floor_shifted(g, b + g.half_side);
-}
 
-// Source pixel column and row of beta; false (and -1, -1) off the map.
-__device__ __forceinline__ bool pixel_xy(const DevGeom &g, double b1, double b2, int32_t &ix,
-                                         int32_t &iy)
-{
-    const double fx = pixel_floor(g, b1);
-    const double fy = pixel_floor(g, b2);
-    const double n = (double)g.npix;
-    const bool in = fx >= 0.0 && fx < n && fy >= 0.0 && fy < n;
-    ix = in ? (int32_t)fx : -1;
-    iy = in ? (int32_t)fy : -1;
-    return in;
-}
-
-// The same from (beta_1 + S/2, beta_2 + S/2).
+// Source pixel column and row of beta from (beta_1 + S/2, beta_2 + S/2);
+// false (and -1, -1) off the map.
 __device__ __forceinline__ bool pixel_xy_shifted(const DevGeom &g, double xs1, double xs2,
                                                  int32_t &ix, int32_t &iy)
 {
