@@ -146,15 +146,18 @@ def test_interp_matches_oracle(irs, kind):
 # ---------------------------------------------------------------------------
 
 
-def test_interp_lenses_on_rays(irs):
+@pytest.mark.parametrize("offset", [0.0, 1e-7])
+def test_interp_lenses_on_rays(irs, offset):
     """Lenses placed exactly on rays (rr = 0: their term is exactly zero) make
     the shared reciprocal of those rays' row groups fall back to one
-    reciprocal per ray; every ray still equals the oracle's interpolation to rounding."""
+    reciprocal per ray; lenses 1e-7 ray spacings off a ray (terms ~1e7 times
+    the others in the group) go through the shared reciprocal.  Every ray
+    still equals the oracle's interpolation to rounding."""
     c0 = Case(0.45, 0.05, 0.45, 5.0, 64, n_rays=300_000, seed=71)
     g0 = c0.geo
     rng = np.random.default_rng(72)
     ids = rng.choice(g0.nx * g0.ny, 40, replace=False)
-    xs = g0.a1 + (ids % g0.nx + 0.5) * g0.ray_dx
+    xs = g0.a1 + (ids % g0.nx + 0.5) * g0.ray_dx + offset * g0.ray_dx
     ys = g0.b1 + (ids // g0.nx + 0.5) * g0.ray_dy
     L = synth.Lenses(np.concatenate([c0.lenses.x, xs]), np.concatenate([c0.lenses.y, ys]), None)
     c = Case(0.45, 0.05, 0.45, 5.0, 64, n_rays=300_000, lenses=L)
@@ -163,7 +166,8 @@ def test_interp_lenses_on_rays(irs):
     with c.plan("interp", "fp64") as pl:
         a1, a2, px = pl.deflect_grid(0, pl.n_rays)
     e = rel_err(a1, a2, ref["alpha1"], ref["alpha2"])
-    say(f"lenses on rays: {L.n} lenses, max e_r vs O-2 {e.max():.3e}, on-ray rays {e[ids].max():.3e}")
+    say(f"lenses {offset:g} spacings off rays: {L.n} lenses, max e_r vs O-2 {e.max():.3e}, "
+        f"those rays {e[ids].max():.3e}")
     assert np.all(np.isfinite(a1)) and np.all(np.isfinite(a2))
     assert e.max() < 1e-10
     assert np.mean(px == ref["pix"]) >= 1 - 1e-5
