@@ -7,18 +7,20 @@ source map and 1000 rays per pixel (1e11 rays over a 5117 x 1023 theta_E
 rectangle).  Inputs are seeded and synthetic and resident in HBM before the
 timed region.
 
-One step = one band of ray rows whose level-2 points fall in one level-1
-row of the three-level grid (~2.2e8 rays): the level-2 far-field Taylor
-coefficients of that row (FP64), then every ray of the band (near lenses
-exactly, distant lenses and the sheet by the Taylor series, macro term,
-binning into the device-resident count map).  Steps walk consecutive
-level-1 rows from the middle of the plane; the full map is n1y = 448 steps.
+One step = one whole map through the interpolated path (Sec. 2.4): every
+distant-field expansion and level-2 coefficient band recomputed (FP64), then
+every ray (near lenses exactly, distant lenses and the sheet by the Taylor
+series, macro term, binning into the device-resident count map).
 
-Printed: one JSON line (stdout) with the whole-job throughput in rays/s, the
-roofline of the dominant kernel (level-2, FP64 VALU) from HIP-event timings
-of its launches on the plan's stream, the oracle timed on a bounded ray
-sample of the same band (also the source of the index-agreement figure and
-the map rel-L1 bound), and the FP32 direct sum at N_* = 1e6 for reference.
+Printed: one JSON line (stdout) with the whole-job throughput in rays/s; the
+roofline of the dominant kernel, k_level3 (the level-3 rays, FP64 VALU), from
+HIP-event timings of its launches on the plan's stream; the parity sample
+(1e5 rays drawn over the whole map plus 1e4 rays near lenses, against the
+FP64 oracle's direct definition: per-ray error, index agreement, the map
+rel-L1 bound); the oracle's CPU baseline (median of three timed runs on that
+sample); and the FP32 direct sum at N_* = 1e6 with its own error against the
+oracle.  Optional sections: accuracy against rays (Sec. 3.2), the learned
+interpolant, the 64-map batch, the protective border, the circular plane.
 """
 import argparse
 import json
@@ -40,7 +42,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2204_10871_amd", "csrc", "k_interp.hip")
 
 
 def _traffic(launches):
-    """HBM bytes per launch of the expansion kernel from the committed counter
+    """HBM bytes per launch of k_level3 from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when
     there is none or the kernel source has changed since it was taken."""
     import hashlib
@@ -107,7 +109,7 @@ def bench_learned(irs, synth, torch, stream, args, result):
                           rays_per_pixel=w.rays_per_pixel, n_lens=L.n)
         j0, j1 = bands[0]
         rng = np.random.default_rng(11)
-        nsamp = max(256, args.cpu_sample // 4)
+        nsamp = 4000
         ids = np.sort(rng.choice((j1 - j0) * G["nx"], nsamp, replace=False)) + j0 * G["nx"]
         threads = min(16, os.cpu_count() or 1)
         ref = orc.shoot_direct(og, L, ray_ids=ids, threads=threads, want_counts=False)
@@ -410,19 +412,144 @@ def bench_batch(irs, synth, torch, stream):
             "speedup": ts / tb, "identical_to_sequential": same, "tuned": info}
 
 
+def host_threads():
+    """OpenMP threads for the oracle: the host share of one GPU."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_info():
+    """CPU model, logical CPUs and physical cores of the host (/proc/cpuinfo)."""
+    model, cores = None, set()
+    phys = core = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "model name" and model is None:
+                model = v
+            elif k == "physical id":
+                phys = v
+            elif k == "core id":
+                core = v
+            elif not k and phys is not None and core is not None:
+                cores.add((phys, core))
+                phys = core = None
+    except OSError:
+        pass
+    if phys is not None and core is not None:
+        cores.add((phys, core))
+    return {"model": model, "logical": os.cpu_count(), "physical": len(cores) or None}
+
+
+def wilson_upper(k, n, z=1.96):
+    """95% upper bound (Wilson) on a binomial fraction with k of n observed."""
+    ph = k / n
+    return (ph + z * z / (2 * n) + z * math.sqrt(ph * (1 - ph) / n + z * z / (4 * n * n))) / \
+        (1 + z * z / n)
+
+
+def sample_errors(a1, a2, px, r1, r2, rpx):
+    """Per-ray relative deflection error e_r = |d alpha|/max(|alpha_ref|, 1)
+    and index agreement of a ray sample against the oracle."""
+    import numpy as np
+    d = np.hypot(a1 - r1, a2 - r2)
+    e = d / np.maximum(np.hypot(r1, r2), 1.0)
+    mism = int(np.sum(px != rpx))
+    return {"max_e_r": float(e.max()), "p9999_e_r": float(np.quantile(e, 0.9999)),
+            "max_abs_alpha_err": float(d.max()), "index_mismatches": mism,
+            "agreement": 1.0 - mism / px.size}
+
+
+def near_lens_rays(G, L, n, radius, rng):
+    """n ray ids whose ray lies within `radius` of a lens: a random lens, a
+    random point within radius - (half a ray-cell diagonal) of it, and the
+    ray whose cell holds that point."""
+    import numpy as np
+    if n <= 0:
+        return np.zeros(0, np.int64)
+    half_diag = 0.5 * math.hypot(G["ray_dx"], G["ray_dy"])
+    k = rng.integers(0, L.n, n)
+    rad = (radius - half_diag) * np.sqrt(rng.random(n))
+    ang = 2 * math.pi * rng.random(n)
+    x = L.x[k] + rad * np.cos(ang)
+    y = L.y[k] + rad * np.sin(ang)
+    i = np.clip(np.floor((x - G["a1"]) / G["ray_dx"]).astype(np.int64), 0, G["nx"] - 1)
+    j = np.clip(np.floor((y - G["b1"]) / G["ray_dy"]).astype(np.int64), 0, G["ny"] - 1)
+    return np.unique(j * G["nx"] + i)
+
+
+def gpu_rays(plan, ids):
+    """alpha and pixel of listed rays (sorted ray order), one irs_deflect_grid
+    call per ray."""
+    import numpy as np
+    a1 = np.empty(ids.size)
+    a2 = np.empty(ids.size)
+    px = np.empty(ids.size, np.int64)
+    for k, r in enumerate(ids):
+        x1, x2, p = plan.deflect_grid(int(r), 1)
+        a1[k], a2[k], px[k] = x1[0], x2[0], p[0]
+    return a1, a2, px
+
+
+def direct_check(dplan, G, w, L, n_star, n, rays, landed, torch):
+    """The FP32 direct sum against the oracle's direct definition: n rays
+    drawn from 8 whole ray rows spread over the map (seeded), each row
+    shot by one irs_deflect_grid call."""
+    import numpy as np
+    import oracle as orc
+    rng = np.random.default_rng(8)
+    nx = G["nx"]
+    rows = np.sort(rng.choice(G["ny"], 8, replace=False))
+    per = max(1, n // rows.size)
+    a1 = torch.empty(nx, dtype=torch.float64, device="cuda:0")
+    a2 = torch.empty_like(a1)
+    px = torch.empty(nx, dtype=torch.int64, device="cuda:0")
+    ids, g1, g2, gp = [], [], [], []
+    for j in rows:
+        dplan.deflect_grid_device(int(j) * nx, nx, a1, a2, px)
+        cols = np.sort(rng.choice(nx, per, replace=False))
+        sel = torch.as_tensor(cols, device="cuda:0")
+        ids.append(int(j) * nx + cols)
+        g1.append(a1[sel].cpu().numpy())
+        g2.append(a2[sel].cpu().numpy())
+        gp.append(px[sel].cpu().numpy())
+    ids = np.concatenate(ids)
+    og = orc.geometry(w.kappa_star, w.kappa_c, w.gamma, w.source_side, w.npix,
+                      rays_per_pixel=w.rays_per_pixel, n_lens=n_star)
+    ref = orc.shoot_direct(og, L, ray_ids=ids, threads=host_threads(), want_counts=False)
+    out = sample_errors(np.concatenate(g1), np.concatenate(g2), np.concatenate(gp),
+                        ref["alpha1"], ref["alpha2"], ref["pix"])
+    up = wilson_upper(out["index_mismatches"], ids.size)
+    out.update(rays=int(ids.size), ray_rows=[int(j) for j in rows], f_mis_95=up,
+               map_rel_l1_bound=2 * up * rays / max(1, landed))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=16000,
-                    help="rays of the oracle sample (each sums all 1e6 lenses)")
+    ap.add_argument("--cpu-sample", type=int, default=100_000,
+                    help="uniform rays of the parity sample / oracle baseline (each sums "
+                         "all 1e6 lenses)")
+    ap.add_argument("--near-sample", type=int, default=10_000,
+                    help="extra parity rays within 0.05 theta_E of a lens")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--band-rows", type=int, default=0,
                     help="0: a step is the whole map; R > 0: a step is a band of R level-1 rows "
                          "(for counter runs)")
     ap.add_argument("--direct-rows", type=int, default=64)
+    ap.add_argument("--direct-sample", type=int, default=10_000,
+                    help="rays of the parity sample checked on the FP32 direct sum")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-map batch measurement")
     ap.add_argument("--no-accuracy", action="store_true",
@@ -471,7 +598,6 @@ def main():
     # a step: the whole map (every expansion recomputed: irs_shoot_map keeps
     # nothing from earlier calls), or a band of --band-rows level-1 rows
     c_mid = G["n1y"] // 2
-    sample_band = plan.level1_row_rays(c_mid)
 
     def step(k, timed):
         if args.band_rows > 0:
@@ -541,41 +667,67 @@ def main():
         "phases": phases,
     }
 
-    # ---- the oracle on a bounded sample of the last band (rays it sums one by one)
+    # ---- parity sample and the oracle's CPU baseline (rays it sums one by one)
     if not args.no_cpu_baseline:
         import oracle as orc
-        threads = min(16, os.cpu_count() or 1)
+        threads = host_threads()
         og = orc.geometry(w.kappa_star, w.kappa_c, w.gamma, w.source_side, w.npix,
                           rays_per_pixel=w.rays_per_pixel, n_lens=n_star)
         assert og.nx == G["nx"] and og.ny == G["ny"]
-        j0, j1 = sample_band
         rng = np.random.default_rng(7)
-        nchunk = 16
-        per = max(1, args.cpu_sample // nchunk)
-        firsts = np.sort(rng.integers(j0 * G["nx"], j1 * G["nx"] - per, nchunk))
-        ids = np.concatenate([np.arange(f, f + per) for f in firsts])
-        gpu_pix = np.concatenate([plan.deflect_grid(int(f), per, alpha=False)[2] for f in firsts])
-        log(f"oracle sample: {ids.size} rays x {n_star} lenses on {threads} threads")
-        tc = time.perf_counter()
-        ref = orc.shoot_direct(og, L, ray_ids=ids, threads=threads, want_counts=False)
-        tcpu = time.perf_counter() - tc
-        mism = int(np.sum(gpu_pix != ref["pix"]))
-        n = ids.size
-        # 95% upper bound on the mismatch fraction (Wilson), then the deterministic
-        # bound rel-L1 <= 2 f_mis N_rays / sum(N_ref) (each mismatched ray moves one count)
-        z = 1.96
-        ph = mism / n
-        up = (ph + z * z / (2 * n) + z * math.sqrt(ph * (1 - ph) / n + z * z / (4 * n * n))) / (1 + z * z / n)
-        result["cpu_baseline"] = {"value": n / tcpu, "unit": "rays/s", "cores": threads,
-                                  "kind": "oracle",
-                                  "sample": f"{n} rays (16 contiguous runs) of one band of this "
-                                            f"workload, direct FP64 definition over all {n_star} "
-                                            f"lenses; {tcpu:.1f} s"}
-        result["parity_sample"] = {"rays": n, "index_mismatches": mism,
-                                   "agreement": 1 - ph, "f_mis_95": up,
-                                   "map_rel_l1_bound": 2 * up * rays / max(1, landed)}
+        ids_u = np.sort(rng.choice(G["nx"] * G["ny"], args.cpu_sample, replace=False))
+        ids_n = near_lens_rays(G, L, args.near_sample, 0.05, rng)
+        tg = time.perf_counter()
+        ga1, ga2, gpx = gpu_rays(plan, np.concatenate([ids_u, ids_n]))
+        tg = time.perf_counter() - tg
+        log(f"parity sample: {ids_u.size} uniform + {ids_n.size} near-lens rays from the GPU "
+            f"in {tg:.1f} s; oracle on {threads} threads")
+        # the uniform sample in three parts, each timed: the CPU baseline is the
+        # median rate of the three runs
+        parts, rates, tcpu = [], [], 0.0
+        order = rng.permutation(ids_u.size)
+        for chunk in np.array_split(order, 3):
+            sel = np.sort(chunk)
+            tc = time.perf_counter()
+            parts.append((sel, orc.shoot_direct(og, L, ray_ids=ids_u[sel], threads=threads,
+                                                want_counts=False)))
+            dt = time.perf_counter() - tc
+            tcpu += dt
+            rates.append(sel.size / dt)
+        ref_a1 = np.empty(ids_u.size)
+        ref_a2 = np.empty(ids_u.size)
+        ref_px = np.empty(ids_u.size, np.int64)
+        for sel, r in parts:
+            ref_a1[sel], ref_a2[sel], ref_px[sel] = r["alpha1"], r["alpha2"], r["pix"]
+        refn = orc.shoot_direct(og, L, ray_ids=ids_n, threads=threads, want_counts=False)
+        nu = ids_u.size
+        uni = sample_errors(ga1[:nu], ga2[:nu], gpx[:nu], ref_a1, ref_a2, ref_px)
+        near = sample_errors(ga1[nu:], ga2[nu:], gpx[nu:], refn["alpha1"], refn["alpha2"],
+                             refn["pix"])
+        up = wilson_upper(uni["index_mismatches"], nu)
+        info = cpu_info()
+        result["cpu_baseline"] = {
+            "value": float(np.median(rates)), "unit": "rays/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"direct FP64 definition over all {n_star} lenses for {nu} rays drawn "
+                      f"uniformly (seed 7) over all {G['nx'] * G['ny']} rays of this workload, "
+                      f"timed as three runs of {nu // 3} rays; value = median rate; "
+                      f"{tcpu:.1f} s in total",
+            "runs_rays_per_s": rates, "cpu_model": info["model"],
+            "box_logical_cpus": info["logical"], "box_physical_cores": info["physical"],
+            "threads_note": "OpenMP threads = the host share of one GPU (OMP_NUM_THREADS, "
+                            "else the CPUs this process may run on, at most 16)"}
+        result["parity_sample"] = {
+            "uniform": dict(uni, rays=nu, f_mis_95=up,
+                            map_rel_l1_bound=2 * up * rays / max(1, landed)),
+            "near_lens": dict(near, rays=int(ids_n.size), within_theta_E=0.05),
+            "seconds_gpu": tg}
+        log(f"parity: uniform {nu} rays: {uni['index_mismatches']} index mismatches "
+            f"(95% bound {up:.2e}), max e_r {uni['max_e_r']:.2e}; near-lens {ids_n.size} rays: "
+            f"{near['index_mismatches']} mismatches, max e_r {near['max_e_r']:.2e}")
 
-    # ---- reference: the FP32 direct sum at N_* = 1e6 on a few tile rows
+    # ---- reference: the FP32 direct sum at N_* = 1e6 on a few tile rows, and
+    # its per-ray error against the oracle on part of the parity sample
     if not args.no_direct:
         pd = irs.params_from_workload(w, method="direct", precision="fp32")
         with irs.Plan(pd, L.x, L.y, L.m, stream=stream.cuda_stream) as dplan:
@@ -588,13 +740,21 @@ def main():
             st = dplan.shoot_rows(r0, rows, counts, time_phases=True)
             torch.cuda.synchronize()
             td = time.perf_counter() - td
+            check = None
+            if not args.no_cpu_baseline and args.direct_sample > 0:
+                check = direct_check(dplan, G, w, L, n_star, args.direct_sample, rays, landed,
+                                     torch)
+                log(f"direct fp32 vs oracle on {check['rays']} rays: max e_r "
+                    f"{check['max_e_r']:.2e}, p99.99 {check['p9999_e_r']:.2e}, "
+                    f"{check['index_mismatches']} index mismatches")
         pairs = st["direct_pairs"]
         tf = DIRECT_FLOPS_PER_PAIR * pairs / (st["ms_rays"] * 1e-3) / 1e12
         result["direct_fp32"] = {"rays_per_s": st["rays_shot"] / td,
                                  "interactions_per_s": pairs / td,
                                  "kernel_tflops_alg": tf, "frac_fp32_peak": tf / FP32_PEAK,
                                  "rays": st["rays_shot"], "seconds": td,
-                                 "speedup_interp_over_direct": value / (st["rays_shot"] / td)}
+                                 "speedup_interp_over_direct": value / (st["rays_shot"] / td),
+                                 "oracle_check": check}
         log(f"direct fp32: {pairs / td:.3e} pairs/s, {tf:.1f} TFLOP/s")
 
     plan.close()

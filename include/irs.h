@@ -171,6 +171,28 @@ typedef struct {
 irs_status irs_geometry(const irs_params *params, int64_t n_lens, irs_geometry_info *out);
 
 /*
+ * irs_level1_span -- the rays of level-1 row or column c of a geometry: for
+ * axis 1 the ray rows [*first, *last), for axis 0 the ray columns, whose
+ * level-2 points lie in that level-1 row (column).  Ray row j lies in level-2
+ * row floor((2j+1) n1y q / (2 ny)) (the level-2 points are the centres of a
+ * q x q split of every level-1 cell, Sec. 2.4 flow chart).  Host only.
+ * Errors: IRS_E_INVALID (NULL, axis not 0/1, c outside the level-1 grid).
+ */
+irs_status irs_level1_span(const irs_geometry_info *geo, int32_t axis, int64_t c,
+                           int64_t *first, int64_t *last);
+
+/*
+ * irs_source_side -- the source side S for which the rectangle of params
+ * holds n_star lenses by the lens-count rule round(kappa_* I_x I_y / pi)
+ * (lens density kappa_* / pi at unit mean mass, Appendix A's sheet density;
+ * I_x, I_y from the protective border and S, Sec. 2.3): the smallest S, to
+ * bisection precision, whose n_stars_expected is >= n_star.  params'
+ * source_side, npix_side and ray counts are ignored.  Host only.
+ * Errors: IRS_E_INVALID, IRS_E_CRITICAL.
+ */
+irs_status irs_source_side(const irs_params *params, int64_t n_star, double *source_side);
+
+/*
  * irs_plan -- create a plan: validate inputs, derive the geometry, copy the
  * lenses to the device and pack them into level-1 cells (flow chart, "Lenses
  * packed into level-1 grids").

@@ -18,8 +18,8 @@ Parity status of each function is listed in its docstring ("pinned by ...").
 """
 from .geometry import Geometry, geometry, CriticalLineError, source_side_for_lens_count
 from .core import (build, load, sheet_I, alpha_points, shoot_direct, level1,
-                   level2, level2_grid, shoot_interp, sheet_taylor, setup_of, far_point)
+                   level2, level2_grid, shoot_interp, shoot_interp_rays, sheet_taylor, setup_of, far_point)
 
 __all__ = ["Geometry", "geometry", "CriticalLineError", "source_side_for_lens_count",
            "build", "load", "sheet_I", "alpha_points", "shoot_direct", "level1",
-           "level2", "level2_grid", "shoot_interp", "sheet_taylor", "setup_of", "far_point"]
+           "level2", "level2_grid", "shoot_interp", "shoot_interp_rays", "sheet_taylor", "setup_of", "far_point"]

@@ -56,6 +56,8 @@ def load():
         lib.orc_level2.argtypes = [P(_Setup), i64, vp, vp, vp, vp, vp, i64, vp, vp, vp, C.c_int]
         lib.orc_shoot_interp.argtypes = [P(_Setup), i64, vp, vp, vp, vp, vp, vp, i64, i64, vp,
                                          vp, vp, vp, vp, vp, C.c_int]
+        lib.orc_shoot_interp_rays.argtypes = [P(_Setup), i64, vp, vp, vp, vp, vp, i64, i64, vp,
+                                              vp, vp, vp, vp, vp, C.c_int]
         lib.orc_sheet_taylor_xy.argtypes = [P(_Setup), d, d, vp]
         lib.orc_far_point.argtypes = [P(_Setup), i64, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp,
                                       vp, C.c_int]
@@ -191,6 +193,35 @@ def shoot_interp(g: Geometry, lenses, cell_start, perm, coef, first=0, n=None,
     lib.orc_shoot_interp(C.byref(s), lenses.n, _ptr(lx), _ptr(ly), _ptr(lm), _ptr(cs),
                          _ptr(pm), _ptr(cf), first, n, _ptr(ray_ids), _ptr(ax), _ptr(ay),
                          _ptr(pix), _ptr(counts), _ptr(st), threads)
+    return dict(alpha1=ax, alpha2=ay, pix=pix, counts=counts, landed=int(st[0]),
+                off=int(st[1]), singular=int(st[2]))
+
+
+def shoot_interp_rays(g: Geometry, lenses, cell_start, perm, first=0, n=None, ray_ids=None,
+                      want_alpha=True, want_pix=True, want_counts=False, threads=0):
+    """O-2 for a ray range or list, each ray with the coefficients of its own
+    level-2 point summed on the spot (orc_shoot_interp_rays): the same results
+    as shoot_interp with the whole level-2 grid (pinned bit for bit against it
+    in tests/test_oracle_interp.py) without building that grid, so rays of
+    full-size maps can be checked.  Same outputs as shoot_direct."""
+    lib = load()
+    s = setup_of(g)
+    if ray_ids is not None:
+        ray_ids = np.ascontiguousarray(ray_ids, dtype=np.int64)
+        n = ray_ids.size
+    elif n is None:
+        n = g.n_rays - first
+    ax = np.empty(n) if want_alpha else None
+    ay = np.empty(n) if want_alpha else None
+    pix = np.empty(n, np.int64) if want_pix else None
+    counts = np.zeros(g.npix * g.npix, np.uint32) if want_counts else None
+    st = np.zeros(3, np.int64)
+    lx, ly, lm = _f64(lenses.x), _f64(lenses.y), _f64(lenses.m)
+    cs = np.ascontiguousarray(cell_start, np.int64)
+    pm = np.ascontiguousarray(perm, np.int64)
+    lib.orc_shoot_interp_rays(C.byref(s), lenses.n, _ptr(lx), _ptr(ly), _ptr(lm), _ptr(cs),
+                              _ptr(pm), first, n, _ptr(ray_ids), _ptr(ax), _ptr(ay), _ptr(pix),
+                              _ptr(counts), _ptr(st), threads)
     return dict(alpha1=ax, alpha2=ay, pix=pix, counts=counts, landed=int(st[0]),
                 off=int(st[1]), singular=int(st[2]))
 

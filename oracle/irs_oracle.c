@@ -314,52 +314,60 @@ static int is_near(int64_t cx, int64_t cy, int64_t lcx, int64_t lcy)
 }
 
 /*
- * "Calculate the deflection angle of level2 grid points": for each requested
- * level-2 point (gx[k], gy[k]) the distant lenses (outside the 3 x 3 block of
- * level-1 cells around the point's own cell) give
+ * "Calculate the deflection angle of level2 grid points": at level-2 point
+ * (gx, gy) the distant lenses (outside the 3 x 3 block of level-1 cells around
+ * the point's own cell) give
  *   c_j = sum_far m_i (-1)^j / (z0 - z_i)^(j+1),   j = 0..4,
  * and the sheet adds -kappa_star g_j, so that
  *   conj(alpha_far + alpha_sheet)(z0 + h) ~= C0 + sum_{j=1..4} C_j h^j - kappa_star conj(h).
- * Output C[k*10 + 2j] = Re C_j, C[k*10 + 2j + 1] = Im C_j.
+ * Output C[2j] = Re C_j, C[2j + 1] = Im C_j.
  */
+static void level2_coef(const orc_setup *s, const double *lx, const double *ly,
+                        const double *lm, const int64_t *cell_start, const int64_t *perm,
+                        int64_t gx, int64_t gy, double *C)
+{
+    const double complex z0 = level2_point(s, gx, gy);
+    const int64_t cx = gx / s->q, cy = gy / s->q;
+    double complex c[5] = { 0, 0, 0, 0, 0 };
+    for (int64_t lcy = 0; lcy < s->n1y; ++lcy)
+        for (int64_t lcx = 0; lcx < s->n1x; ++lcx) {
+            if (is_near(cx, cy, lcx, lcy)) continue;
+            const int64_t cell = lcy * s->n1x + lcx;
+            for (int64_t p = cell_start[cell]; p < cell_start[cell + 1]; ++p) {
+                const int64_t i = perm[p];
+                const double m = lm ? lm[i] : 1.0;
+                const double complex w = z0 - (lx[i] + I * ly[i]);
+                double complex wp = w;     /* w^(j+1) */
+                double sign = 1.0;         /* (-1)^j  */
+                for (int j = 0; j < 5; ++j) {
+                    c[j] += sign * m / wp;
+                    wp *= w;
+                    sign = -sign;
+                }
+            }
+        }
+    double complex g[5] = { 0, 0, 0, 0, 0 };
+    if (s->sheet && !is_corner_cell(s, cx, cy)) orc_sheet_taylor(s, z0, g);
+    for (int j = 0; j < 5; ++j) {
+        const double complex Cj = c[j] - s->kappa_star * g[j];
+        C[2 * j] = creal(Cj);
+        C[2 * j + 1] = cimag(Cj);
+    }
+}
+
+/* level2_coef at each requested point (gx[k], gy[k]) into C[k*10 .. k*10 + 9]. */
 void orc_level2(const orc_setup *s, int64_t nl, const double *lx,
                 const double *ly, const double *lm, const int64_t *cell_start,
                 const int64_t *perm, int64_t npts, const int64_t *gx,
                 const int64_t *gy, double *C, int nthreads)
 {
+    (void)nl;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 16)
 #endif
-    for (int64_t k = 0; k < npts; ++k) {
-        const double complex z0 = level2_point(s, gx[k], gy[k]);
-        const int64_t cx = gx[k] / s->q, cy = gy[k] / s->q;
-        double complex c[5] = { 0, 0, 0, 0, 0 };
-        for (int64_t lcy = 0; lcy < s->n1y; ++lcy)
-            for (int64_t lcx = 0; lcx < s->n1x; ++lcx) {
-                if (is_near(cx, cy, lcx, lcy)) continue;
-                const int64_t cell = lcy * s->n1x + lcx;
-                for (int64_t p = cell_start[cell]; p < cell_start[cell + 1]; ++p) {
-                    const int64_t i = perm[p];
-                    const double m = lm ? lm[i] : 1.0;
-                    const double complex w = z0 - (lx[i] + I * ly[i]);
-                    double complex wp = w;     /* w^(j+1) */
-                    double sign = 1.0;         /* (-1)^j  */
-                    for (int j = 0; j < 5; ++j) {
-                        c[j] += sign * m / wp;
-                        wp *= w;
-                        sign = -sign;
-                    }
-                }
-            }
-        double complex g[5] = { 0, 0, 0, 0, 0 };
-        if (s->sheet && !is_corner_cell(s, cx, cy)) orc_sheet_taylor(s, z0, g);
-        for (int j = 0; j < 5; ++j) {
-            const double complex Cj = c[j] - s->kappa_star * g[j];
-            C[k * 10 + 2 * j] = creal(Cj);
-            C[k * 10 + 2 * j + 1] = cimag(Cj);
-        }
-    }
+    for (int64_t k = 0; k < npts; ++k)
+        level2_coef(s, lx, ly, lm, cell_start, perm, gx[k], gy[k], C + k * 10);
 }
 
 /*
@@ -377,11 +385,80 @@ static void ray_subcell(const orc_setup *s, int64_t r, int64_t *gx, int64_t *gy)
 /*
  * "Calculate the deflection angle of all the light rays (level-3 grids)":
  * near lenses summed exactly, distant lenses and the sheet from the local
- * Taylor series of the ray's level-2 point, plus the macro term.  Rays in the
- * four corner cells take the sheet from its closed form (see is_corner_cell).
- *
- * Ccoef holds the coefficients of the whole level-2 grid, point (gx, gy) at
- * index gy*(n1x*q) + gx, 10 doubles each as produced by orc_level2.
+ * Taylor series of the ray's level-2 point (coefficients Cp, 10 doubles as
+ * produced by orc_level2), plus the macro term.  Rays in the four corner
+ * cells take the sheet from its closed form (see is_corner_cell).
+ */
+static void level3_ray(const orc_setup *s, const double *lx, const double *ly,
+                       const double *lm, const int64_t *cell_start, const int64_t *perm,
+                       const double *Cp, int64_t r, double *a1_out, double *a2_out,
+                       int64_t *pix_out, int64_t *nsing)
+{
+    double t1, t2;
+    int64_t gx, gy;
+    ray_theta(s, r, &t1, &t2);
+    ray_subcell(s, r, &gx, &gy);
+    const int64_t cx = gx / s->q, cy = gy / s->q;
+
+    /* near lenses: exact sum over the 3 x 3 block of level-1 cells */
+    double nx_ = 0.0, ny_ = 0.0;
+    for (int64_t lcy = cy - 1; lcy <= cy + 1; ++lcy)
+        for (int64_t lcx = cx - 1; lcx <= cx + 1; ++lcx) {
+            if (lcx < 0 || lcy < 0 || lcx >= s->n1x || lcy >= s->n1y) continue;
+            const int64_t cell = lcy * s->n1x + lcx;
+            for (int64_t p = cell_start[cell]; p < cell_start[cell + 1]; ++p) {
+                const int64_t i = perm[p];
+                const double d1 = t1 - lx[i], d2 = t2 - ly[i];
+                const double r2 = d1 * d1 + d2 * d2;
+                if (r2 == 0.0) { ++*nsing; continue; }
+                const double m = lm ? lm[i] : 1.0;
+                nx_ += m * d1 / r2;
+                ny_ += m * d2 / r2;
+            }
+        }
+
+    /* distant lenses + sheet: local Taylor series about the level-2 point */
+    const double complex z0 = level2_point(s, gx, gy);
+    const double complex h = (t1 + I * t2) - z0;
+    double complex ca = 0.0, hp = 1.0;
+    for (int j = 0; j <= 4; ++j) {
+        ca += (Cp[2 * j] + I * Cp[2 * j + 1]) * hp;
+        hp *= h;
+    }
+    if (s->sheet) {
+        if (is_corner_cell(s, cx, cy)) {
+            double I1, I2;
+            orc_sheet_I(s->a1, s->a2, s->b1, s->b2, 1, &t1, &t2, &I1, &I2);
+            ca += -(s->kappa_star / M_PI) * (I1 - I * I2);
+        } else {
+            ca += -s->kappa_star * conj(h);
+        }
+    }
+    /* conj(ca) is the far + sheet deflection */
+    const double a1 = (s->kappa + s->gamma) * t1 + nx_ + creal(ca);
+    const double a2 = (s->kappa - s->gamma) * t2 + ny_ - cimag(ca);
+    *a1_out = a1;
+    *a2_out = a2;
+    *pix_out = pixel_of(s, t1 - a1, t2 - a2);
+}
+
+/* Counts and landed / off-map totals of the per-ray pixels pix[0..n). */
+static void bin_pixels(int64_t n, const int64_t *pix, uint32_t *counts, int64_t nsing,
+                       int64_t *stats)
+{
+    int64_t landed = 0, off = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        if (pix[k] < 0) { ++off; continue; }
+        ++landed;
+        if (counts) counts[pix[k]] += 1u;
+    }
+    if (stats) { stats[0] = landed; stats[1] = off; stats[2] = nsing; }
+}
+
+/*
+ * Level-3 evaluation of the rays listed in ray_ids (or [first, first+n)) with
+ * the coefficients of the whole level-2 grid, Ccoef: point (gx, gy) at index
+ * gy*(n1x*q) + gx, 10 doubles each as produced by orc_level2.
  */
 void orc_shoot_interp(const orc_setup *s, int64_t nl, const double *lx,
                       const double *ly, const double *lm,
@@ -391,6 +468,7 @@ void orc_shoot_interp(const orc_setup *s, int64_t nl, const double *lx,
                       int64_t *pix_out, uint32_t *counts, int64_t *stats,
                       int nthreads)
 {
+    (void)nl;
     int64_t *pix = pix_out ? pix_out : (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     const int64_t ngx = s->n1x * s->q;
     int64_t nsing_total = 0;
@@ -400,61 +478,52 @@ void orc_shoot_interp(const orc_setup *s, int64_t nl, const double *lx,
 #endif
     for (int64_t k = 0; k < n; ++k) {
         const int64_t r = ray_ids ? ray_ids[k] : first + k;
-        double t1, t2;
-        int64_t gx, gy;
-        ray_theta(s, r, &t1, &t2);
+        int64_t gx, gy, nsing = 0;
+        double a1, a2;
         ray_subcell(s, r, &gx, &gy);
-        const int64_t cx = gx / s->q, cy = gy / s->q;
-
-        /* near lenses: exact sum over the 3 x 3 block of level-1 cells */
-        double nx_ = 0.0, ny_ = 0.0;
-        for (int64_t lcy = cy - 1; lcy <= cy + 1; ++lcy)
-            for (int64_t lcx = cx - 1; lcx <= cx + 1; ++lcx) {
-                if (lcx < 0 || lcy < 0 || lcx >= s->n1x || lcy >= s->n1y) continue;
-                const int64_t cell = lcy * s->n1x + lcx;
-                for (int64_t p = cell_start[cell]; p < cell_start[cell + 1]; ++p) {
-                    const int64_t i = perm[p];
-                    const double d1 = t1 - lx[i], d2 = t2 - ly[i];
-                    const double r2 = d1 * d1 + d2 * d2;
-                    if (r2 == 0.0) { ++nsing_total; continue; }
-                    const double m = lm ? lm[i] : 1.0;
-                    nx_ += m * d1 / r2;
-                    ny_ += m * d2 / r2;
-                }
-            }
-
-        /* distant lenses + sheet: local Taylor series about the level-2 point */
-        const double *Cp = Ccoef + (gy * ngx + gx) * 10;
-        const double complex z0 = level2_point(s, gx, gy);
-        const double complex h = (t1 + I * t2) - z0;
-        double complex ca = 0.0, hp = 1.0;
-        for (int j = 0; j <= 4; ++j) {
-            ca += (Cp[2 * j] + I * Cp[2 * j + 1]) * hp;
-            hp *= h;
-        }
-        if (s->sheet) {
-            if (is_corner_cell(s, cx, cy)) {
-                double I1, I2;
-                orc_sheet_I(s->a1, s->a2, s->b1, s->b2, 1, &t1, &t2, &I1, &I2);
-                ca += -(s->kappa_star / M_PI) * (I1 - I * I2);
-            } else {
-                ca += -s->kappa_star * conj(h);
-            }
-        }
-        /* conj(ca) is the far + sheet deflection */
-        const double a1 = (s->kappa + s->gamma) * t1 + nx_ + creal(ca);
-        const double a2 = (s->kappa - s->gamma) * t2 + ny_ - cimag(ca);
+        level3_ray(s, lx, ly, lm, cell_start, perm, Ccoef + (gy * ngx + gx) * 10, r, &a1, &a2,
+                   &pix[k], &nsing);
+        nsing_total += nsing;
         if (ax_out) ax_out[k] = a1;
         if (ay_out) ay_out[k] = a2;
-        pix[k] = pixel_of(s, t1 - a1, t2 - a2);
     }
-    int64_t landed = 0, off = 0;
+    bin_pixels(n, pix, counts, nsing_total, stats);
+    if (!pix_out) free(pix);
+}
+
+/*
+ * The same level-3 evaluation for rays listed in ray_ids (or [first, first+n)),
+ * each taking the coefficients of its own level-2 point from the distant-lens
+ * sum of orc_level2 computed on the spot.  Results equal orc_shoot_interp's
+ * with the whole level-2 grid; the cost is one distant-lens sum per ray, so
+ * rays of maps whose level-2 grid is too large to build can be checked.
+ */
+void orc_shoot_interp_rays(const orc_setup *s, int64_t nl, const double *lx,
+                           const double *ly, const double *lm,
+                           const int64_t *cell_start, const int64_t *perm, int64_t first,
+                           int64_t n, const int64_t *ray_ids, double *ax_out,
+                           double *ay_out, int64_t *pix_out, uint32_t *counts,
+                           int64_t *stats, int nthreads)
+{
+    (void)nl;
+    int64_t *pix = pix_out ? pix_out : (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t nsing_total = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nsing_total)
+#endif
     for (int64_t k = 0; k < n; ++k) {
-        if (pix[k] < 0) { ++off; continue; }
-        ++landed;
-        if (counts) counts[pix[k]] += 1u;
+        const int64_t r = ray_ids ? ray_ids[k] : first + k;
+        int64_t gx, gy, nsing = 0;
+        double C[10], a1, a2;
+        ray_subcell(s, r, &gx, &gy);
+        level2_coef(s, lx, ly, lm, cell_start, perm, gx, gy, C);
+        level3_ray(s, lx, ly, lm, cell_start, perm, C, r, &a1, &a2, &pix[k], &nsing);
+        nsing_total += nsing;
+        if (ax_out) ax_out[k] = a1;
+        if (ay_out) ay_out[k] = a2;
     }
-    if (stats) { stats[0] = landed; stats[1] = off; stats[2] = nsing_total; }
+    bin_pixels(n, pix, counts, nsing_total, stats);
     if (!pix_out) free(pix);
 }
 

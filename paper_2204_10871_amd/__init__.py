@@ -15,7 +15,8 @@ from ._ffi import (IRS_DIRECT, IRS_INTERP, IRS_LEARNED, IRS_FP64, IRS_FP32_KAHAN
                    IRS_LEARN_FIELDS, EXPORTS, Params, GeometryInfo, MapStats, LearnParams,
                    LearnReport)
 
-__all__ = ["IrsError", "make_params", "params_from_workload", "geometry", "Plan", "Batch", "load",
+__all__ = ["IrsError", "make_params", "params_from_workload", "geometry", "level1_span",
+           "source_side_for_n_star", "Plan", "Batch", "load",
            "learn_params", "mlp_forward", "mlp_loss_grad", "IRS_DIRECT", "IRS_INTERP",
            "IRS_LEARNED", "IRS_FP64", "IRS_FP32_KAHAN", "IRS_LEARN_NPARAMS", "IRS_LEARN_FIELDS",
            "EXPORTS"]
@@ -74,21 +75,24 @@ def geometry(params: Params, n_lens: int = 0) -> dict:
 
 
 def source_side_for_n_star(kappa_star, kappa_c, gamma, n_star, **kw) -> float:
-    """Source side S whose rectangle holds n_star lenses by the lens-count rule
-    (irs_geometry's n_stars_expected), found by bisection on S."""
-    lo, hi = 1e-3, 1.0
-    while geometry(make_params(kappa_star, kappa_c, gamma, hi, 16, n_rays=1, **kw))[
-            "n_stars_expected"] < n_star:
-        hi *= 2.0
-    for _ in range(80):
-        mid = 0.5 * (lo + hi)
-        n = geometry(make_params(kappa_star, kappa_c, gamma, mid, 16, n_rays=1, **kw))[
-            "n_stars_expected"]
-        if n < n_star:
-            lo = mid
-        else:
-            hi = mid
-    return hi
+    """irs_source_side: the source side S whose rectangle holds n_star lenses
+    by the lens-count rule (irs_geometry's n_stars_expected)."""
+    lib = _ffi.load()
+    s = C.c_double()
+    p = make_params(kappa_star, kappa_c, gamma, 1.0, 16, n_rays=1, **kw)
+    _check(lib.irs_source_side(C.byref(p), int(n_star), C.byref(s)), "irs_source_side")
+    return s.value
+
+
+def level1_span(geometry_info: dict, axis: int, c: int):
+    """irs_level1_span: ray rows (axis 1) or columns (axis 0) [first, last)
+    whose level-2 points lie in level-1 row (column) c of a geometry dict."""
+    lib = _ffi.load()
+    gi = GeometryInfo(**{k: geometry_info[k] for k, _ in GeometryInfo._fields_})
+    a, b = C.c_int64(), C.c_int64()
+    _check(lib.irs_level1_span(C.byref(gi), int(axis), int(c), C.byref(a), C.byref(b)),
+           "irs_level1_span")
+    return a.value, b.value
 
 
 def _f64(a):
@@ -292,21 +296,12 @@ class Plan:
                "irs_plan_set_direct_variant")
 
     def level1_row_rays(self, c: int):
-        """Ray rows [j0, j1) whose level-2 points lie in level-1 row c: ray row j
-        sits in level-2 row floor((2j+1) n1y q / (2 ny))."""
-        g = self.geometry
-        M, ny = g["n1y"] * g["q"], g["ny"]
+        """Ray rows [j0, j1) whose level-2 points lie in level-1 row c."""
+        return level1_span(self.geometry, 1, c)
 
-        def first_at(G):
-            lo, hi = 0, ny
-            while lo < hi:
-                mid = (lo + hi) // 2
-                if ((2 * mid + 1) * M) // (2 * ny) >= G:
-                    hi = mid
-                else:
-                    lo = mid + 1
-            return lo
-        return first_at(c * g["q"]), first_at((c + 1) * g["q"])
+    def level1_col_rays(self, c: int):
+        """Ray columns [i0, i1) whose level-2 points lie in level-1 column c."""
+        return level1_span(self.geometry, 0, c)
 
 
 class Batch:

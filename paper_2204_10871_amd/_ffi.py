@@ -20,7 +20,8 @@ IRS_LEARN_NPARAMS = 68112
 IRS_LEARN_FIELDS = 24
 
 # every function include/irs.h declares
-EXPORTS = ("irs_geometry", "irs_plan", "irs_deflect_grid", "irs_shoot_rows", "irs_shoot_map",
+EXPORTS = ("irs_geometry", "irs_level1_span", "irs_source_side", "irs_plan", "irs_deflect_grid",
+           "irs_shoot_rows", "irs_shoot_map",
            "irs_plan_set_direct_variant", "irs_plan_geometry", "irs_free", "irs_last_error",
            "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info",
            "irs_batch_free", "irs_learn_defaults", "irs_learn", "irs_learn_set", "irs_learn_get",
@@ -127,6 +128,8 @@ def load():
     lib = C.CDLL(LIB_PATH)
     P, vp, i64, u64 = C.POINTER, C.c_void_p, C.c_int64, C.c_uint64
     lib.irs_geometry.argtypes = [P(Params), i64, P(GeometryInfo)]
+    lib.irs_level1_span.argtypes = [P(GeometryInfo), C.c_int32, i64, P(i64), P(i64)]
+    lib.irs_source_side.argtypes = [P(Params), i64, P(C.c_double)]
     lib.irs_plan.argtypes = [P(Params), i64, vp, vp, vp, vp, P(vp)]
     lib.irs_deflect_grid.argtypes = [vp, i64, i64, vp, vp, vp, u64]
     lib.irs_shoot_rows.argtypes = [vp, i64, i64, vp, P(MapStats), u64]
@@ -152,8 +155,9 @@ def load():
     lib.irs_free.restype = None
     lib.irs_last_error.argtypes = []
     lib.irs_last_error.restype = C.c_char_p
-    for name in ("irs_geometry", "irs_plan", "irs_deflect_grid", "irs_shoot_rows",
-                 "irs_shoot_map", "irs_plan_geometry", "irs_plan_set_direct_variant",
+    for name in ("irs_geometry", "irs_level1_span", "irs_source_side", "irs_plan",
+                 "irs_deflect_grid", "irs_shoot_rows", "irs_shoot_map",
+                 "irs_plan_geometry", "irs_plan_set_direct_variant",
                  "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info",
                  "irs_learn_defaults", "irs_learn", "irs_learn_set", "irs_learn_get",
                  "irs_learn_corners", "irs_learn_samples", "irs_mlp_forward", "irs_mlp_loss_grad"):

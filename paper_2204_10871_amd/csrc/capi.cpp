@@ -191,6 +191,39 @@ irs_status irs_geometry(const irs_params *params, int64_t n_lens, irs_geometry_i
     return IRS_OK;
 }
 
+irs_status irs_level1_span(const irs_geometry_info *geo, int32_t axis, int64_t c,
+                           int64_t *first, int64_t *last)
+{
+    if (!geo || !first || !last || (axis != 0 && axis != 1)) {
+        set_error("irs_level1_span: NULL argument or axis not 0/1");
+        return IRS_E_INVALID;
+    }
+    const int64_t nc = axis ? geo->n1y : geo->n1x;
+    if (c < 0 || c >= nc || geo->q < 1 || geo->nx < 1 || geo->ny < 1) {
+        set_error("irs_level1_span: level-1 index outside the grid");
+        return IRS_E_INVALID;
+    }
+    level1_span(*geo, axis, c, *first, *last);
+    set_error("");
+    return IRS_OK;
+}
+
+irs_status irs_source_side(const irs_params *params, int64_t n_star, double *source_side)
+{
+    if (!params || !source_side || n_star < 1) {
+        set_error("irs_source_side: NULL argument or n_star < 1");
+        return IRS_E_INVALID;
+    }
+    std::string err;
+    const irs_status st = source_side_for_lens_count(*params, n_star, *source_side, err);
+    if (st != IRS_OK) {
+        set_error("irs_source_side: " + err);
+        return st;
+    }
+    set_error("");
+    return IRS_OK;
+}
+
 irs_status irs_plan(const irs_params *params, int64_t n_lens, const double *x, const double *y,
                     const double *m, void *hip_stream, irs_plan_t *out)
 {

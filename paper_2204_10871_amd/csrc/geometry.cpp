@@ -143,4 +143,57 @@ irs_status derive_geometry(const irs_params &p, int64_t n_lens, HostGeometry &ou
     return IRS_OK;
 }
 
+void level1_span(const irs_geometry_info &g, int axis, int64_t c, int64_t &first, int64_t &last)
+{
+    const int64_t n = axis ? g.ny : g.nx;
+    const int64_t M = (axis ? g.n1y : g.n1x) * g.q;
+    // first ray index whose level-2 index is >= G
+    auto first_at = [&](int64_t G) {
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (((2 * mid + 1) * M) / (2 * n) >= G) hi = mid;
+            else lo = mid + 1;
+        }
+        return lo;
+    };
+    first = first_at(c * g.q);
+    last = first_at((c + 1) * g.q);
+}
+
+irs_status source_side_for_lens_count(const irs_params &p, int64_t n_star, double &side,
+                                      std::string &err)
+{
+    irs_params t = p;
+    t.npix_side = 16;
+    t.n_rays = 1;
+    HostGeometry hg;
+    auto count = [&](double s, int64_t &n) {
+        t.source_side = s;
+        const irs_status st = derive_geometry(t, 0, hg, err);
+        n = hg.info.n_stars_expected;
+        return st;
+    };
+    double lo = 1e-3, hi = 1.0;
+    int64_t n = 0;
+    irs_status st;
+    for (;;) {
+        if ((st = count(hi, n)) != IRS_OK) return st;
+        if (n >= n_star) break;
+        hi *= 2.0;
+        if (hi > 1e12) {
+            err = "no source side holds that many lenses";
+            return IRS_E_INVALID;
+        }
+    }
+    for (int it = 0; it < 80; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if ((st = count(mid, n)) != IRS_OK) return st;
+        if (n < n_star) lo = mid;
+        else hi = mid;
+    }
+    side = hi;
+    return IRS_OK;
+}
+
 }  // namespace irs

@@ -26,4 +26,15 @@ struct HostGeometry {
 irs_status derive_geometry(const irs_params &p, int64_t n_lens, HostGeometry &out,
                            std::string &err);
 
+// Ray rows (axis 1) or ray columns (axis 0) [first, last) whose level-2
+// points lie in level-1 row or column c.  Ray row j lies in level-2 row
+// floor((2j+1) n1y q / (2 ny)), a non-decreasing function of j.
+void level1_span(const irs_geometry_info &g, int axis, int64_t c, int64_t &first, int64_t &last);
+
+// Source side S whose rectangle holds n_star lenses by the lens-count rule
+// (the smallest S, to bisection precision, with n_stars_expected >= n_star;
+// every other field of p is used as given).
+irs_status source_side_for_lens_count(const irs_params &p, int64_t n_star, double &side,
+                                      std::string &err);
+
 }  // namespace irs

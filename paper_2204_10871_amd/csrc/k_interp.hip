@@ -955,9 +955,8 @@ __device__ __forceinline__ void near_pass(const DevGeom &g, const double2 *__res
 
 // whole-wave reductions (every lane active) through the device library's
 // cross-lane (DPP) sequences rather than LDS permutes
-__device__ __forceinline__ int wave_min(int v) { return __ockl_wfred_min_i32(v); }
 __device__ __forceinline__ int wave_max(int v) { return __ockl_wfred_max_i32(v); }
-__device__ __forceinline__ int wave_add(int v) { return __ockl_wfred_add_i32(v); }
+__device__ __forceinline__ uint32_t wave_min_u(uint32_t v) { return __ockl_wfred_min_u32(v); }
 
 __global__ __launch_bounds__(kThreads) void k_row_table(DevGeom g, RowInfo *rows)
 {
@@ -974,6 +973,125 @@ __global__ __launch_bounds__(kThreads) void k_row_table(DevGeom g, RowInfo *rows
     const double sh = g.sheet ? g.kappa_star * r.hi : 0.0;
     r.c2 = ((r.t2 - mac) + sh) + g.half_side;
     rows[j] = r;
+}
+
+// The sheet's deflection in the rectangle's corner cells, in closed form
+// minus the -kappa_* conj(h) part the column and row constants hold: the
+// correction to add to (Re A, Im A).
+struct D2 {
+    double x, y;
+};
+
+__device__ __forceinline__ D2 corner_sheet(const DevGeom &g, double t1, double t2, double hr,
+                                         double hi)
+{
+    double I1, I2;
+    sheet_unit(g, t1, t2, I1, I2);
+    return D2{g.sheet_f * I1 + g.kappa_star * hr, -(g.sheet_f * I2 + g.kappa_star * hi)};
+}
+
+// Pixel column and row of beta from (beta_1 + S/2, beta_2 + S/2): the floor
+// of the products by 1/dpix, or, where either product lies within 1e-9 of an
+// integer, of the IEEE quotients by dpix for both (pixel_floor_shifted's
+// rule, one branch for the pair); (-1, -1) off the map.
+__device__ __forceinline__ void pixel_pair(const DevGeom &g, double xs1, double xs2, int32_t &ix,
+                                           int32_t &iy)
+{
+    const double q1 = xs1 * g.inv_dpix, q2 = xs2 * g.inv_dpix;
+    double f1 = floor(q1), f2 = floor(q2);
+    constexpr double lim = 0.5 - 1e-9;
+    if ((int)(fabs((q1 - f1) - 0.5) > lim) | (int)(fabs((q2 - f2) - 0.5) > lim)) {
+        f1 = floor(xs1 / g.dpix);
+        f2 = floor(xs2 / g.dpix);
+    }
+    const double n = (double)g.npix;
+    const bool in = (int)(f1 >= 0.0) & (int)(f1 < n) & (int)(f2 >= 0.0) & (int)(f2 < n);
+    ix = in ? (int32_t)f1 : -1;
+    iy = in ? (int32_t)f2 : -1;
+}
+
+// What a lane of k_level3 holds for its ray column.
+struct L3Lane {
+    int64_t i;                 // ray column
+    int32_t i32;
+    bool in_col;               // the column lies inside the ray grid
+    bool corner_col;           // ... in the first or last level-1 column
+    bool wave_corner;          // some lane of the wave is (wave-uniform); rays of
+                               // the four corner cells are left to k_level3_corner
+    double t1, hr;             // theta_1, its offset from the level-2 column
+    double c1, s1;             // beta_1 + S/2 without lens terms; kappa_* hr
+    uint32_t coff;             // byte offset of the lane's level-2 point in a row
+};
+
+// Rows k0 <= k < k1 of a wave (k0, k1, jw wave-uniform): Horner of the
+// level-2 series (coefficients reloaded when the level-2 row changes, a
+// wave-uniform test), the corner cells' sheet, beta + S/2 and the pixel.
+// FULL: every ray of these rows lies in [ray_first, ray_last).  BIN: pixels
+// into pxs/pys (-1 for rays not binned); otherwise the per-ray outputs.
+template <bool BIN, bool FULL>
+__device__ __forceinline__ void level3_rows(
+    const DevGeom &g, const RowInfo *__restrict__ rows, const double *__restrict__ coef,
+    int32_t cy0, int64_t nxq, const L3Lane &ln, int32_t jw, int k0, int k1, int64_t ray_first,
+    int64_t ray_last, const double *n1s, const double *n2s, double *a1o, double *a2o,
+    int64_t *pixo, int32_t *pxs, int32_t *pys)
+{
+    constexpr int R = kL3RowsPerWave;
+    const int32_t ny1 = (int32_t)g.ny - 1;
+    double2 C[5] = {};
+    int32_t cgy = -1;                                     // level-2 row held in C
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        pxs[k] = -1;
+        pys[k] = -1;
+        if (k < k0 || k >= k1) continue;                  // wave-uniform
+        const RowInfo &rk = rows[min(jw + k, ny1)];
+        const int32_t gy = rk.gy;
+        if (gy != cgy) {                                  // wave-uniform: next level-2 row
+            const double2 *cp = (const double2 *)((const char *)(coef + (int64_t)(gy - cy0 * g.q) *
+                                                                          nxq * 10) + ln.coff);
+#pragma unroll
+            for (int e = 0; e < 5; ++e) C[e] = cp[e];
+            cgy = gy;
+        }
+        const double hi = rk.hi;
+        // Horner: A = C0 + h (C1 + h (C2 + h (C3 + h C4))), two fused
+        // multiply-adds per component and step; conj(A) is the far deflection
+        double Ar = C[4].x, Ai = C[4].y;
+#pragma unroll
+        for (int o = 3; o >= 0; --o) {
+            const double r = fma(Ar, ln.hr, fma(-Ai, hi, C[o].x));
+            Ai = fma(Ar, hi, fma(Ai, ln.hr, C[o].y));
+            Ar = r;
+        }
+        // beta + S/2 = (c1, c2) - nearby lenses - conj(A)
+        const double xs1 = (ln.c1 - n1s[k]) - Ar;
+        const double xs2 = (rk.c2 - n2s[k]) + Ai;
+        bool valid;
+        if constexpr (FULL) {
+            valid = ln.in_col;
+        } else {
+            // columns of row k inside [ray_first, ray_last), as a lane window
+            const int64_t lo = ray_first - rk.base, hi_ = ray_last - rk.base;
+            const int32_t wlo = (int32_t)(lo < 0 ? 0 : (lo > g.nx ? g.nx : lo));
+            const int32_t whi = (int32_t)(hi_ < 0 ? 0 : (hi_ > g.nx ? g.nx : hi_));
+            valid = (int)(ln.i32 >= wlo) & (int)(ln.i32 < whi);
+        }
+        // rays of the rectangle's four corner cells are k_level3_corner's
+        if (ln.wave_corner && (rk.cy == 0 || rk.cy == g.n1y - 1)) valid = valid && !ln.corner_col;
+        int32_t px, py;
+        pixel_pair(g, xs1, xs2, px, py);
+        pxs[k] = valid ? px : -1;
+        pys[k] = valid ? py : -1;
+        if (!BIN && valid) {
+            const double s2 = g.sheet ? g.kappa_star * hi : 0.0;
+            const double a1 = fma(g.kpg, ln.t1, n1s[k]) + (Ar - ln.s1);
+            const double a2 = fma(g.kmg, rk.t2, n2s[k]) - (Ai + s2);
+            const int64_t o = rk.base + ln.i - ray_first;
+            if (a1o) a1o[o] = a1;
+            if (a2o) a2o[o] = a2;
+            if (pixo) pixo[o] = px < 0 ? -1 : (int64_t)py * g.npix + px;
+        }
+    }
 }
 
 // BIN: count rays into `counts` (a1o, a2o, pixo unused); otherwise write the
@@ -1020,7 +1138,8 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
     // the wave's rows jw + k (rows past the grid repeat its last one); rows
     // k0 <= k < k1 lie inside [jr0, jr1), the others bin nothing
     const int k0 = (int)max<int64_t>(0, jr0 - jw), k1 = (int)min<int64_t>(R, jr1 - jw);
-    auto row = [&](int k) -> const RowInfo & { return rows[min(jw + k, g.ny - 1)]; };
+    const int32_t jw32 = (int32_t)jw, ny1 = (int32_t)g.ny - 1;      // ny < 2^31
+    auto row = [&](int k) -> const RowInfo & { return rows[min(jw32 + k, ny1)]; };
 
     // nearby lenses, exactly.  A lane's rays are R consecutive rows of one
     // column; they nearly always share their level-1 cell row (a cell spans
@@ -1060,91 +1179,36 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
         }
     }
 
-    // coefficients of a lane's level-2 point in band row gy
-    auto coef_row = [&](int32_t gy) {
-        return (const double2 *)((const char *)(coef + (int64_t)(gy - cy0 * g.q) * nxq * 10) + coff);
-    };
-    double2 C[5] = {};
-    int32_t cgy = -1;                                     // level-2 row held in C
-    if (k1 > k0) {
-        cgy = row(k0).gy;
-        const double2 *cp = coef_row(cgy);
-#pragma unroll
-        for (int e = 0; e < 5; ++e) C[e] = cp[e];
-    }
-
-    const int32_t i32 = (int32_t)i;
-    // rows whose rays all lie in [ray_first, ray_last) need no per-ray test
+    // per-row evaluation; rows whose rays all lie in [ray_first, ray_last)
+    // need no per-ray window test
     const bool full = k1 > k0 && row(k0).base >= ray_first && row(k1 - 1).base + g.nx <= ray_last;
+    const bool corner_col = in_col && (cx == 0 || cx == g.n1x - 1);
+    const bool wave_corner = g.sheet && __ballot(corner_col) != 0;     // wave-uniform
+    const L3Lane ln{i, (int32_t)i, in_col, corner_col, wave_corner, t1, hr, c1, s1, coff};
     int32_t pxs[R], pys[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        bool valid;
-        if (full) {
-            valid = k >= k0 && k < k1 && in_col;
-        } else {
-            // columns of row k inside [ray_first, ray_last), as a lane window
-            const int64_t lo = ray_first - row(k).base, hi_ = ray_last - row(k).base;
-            const int32_t wlo = (int32_t)(lo < 0 ? 0 : (lo > g.nx ? g.nx : lo));
-            const int32_t whi = (int32_t)(hi_ < 0 ? 0 : (hi_ > g.nx ? g.nx : hi_));
-            valid = k >= k0 && k < k1 && i32 >= wlo && i32 < whi;
-        }
-        pxs[k] = -1;
-        pys[k] = -1;
-        if (!valid) continue;
-        if (row(k).gy != cgy) {                            // wave-uniform: next level-2 row
-            const double2 *cp = coef_row(row(k).gy);
-#pragma unroll
-            for (int e = 0; e < 5; ++e) C[e] = cp[e];
-            cgy = row(k).gy;
-        }
-        const double hi = row(k).hi;
-        const int32_t cy = row(k).cy;
-        // Horner: A = C0 + h (C1 + h (C2 + h (C3 + h C4))), two fused
-        // multiply-adds per component and step; conj(A) is the far deflection
-        double Ar = C[4].x, Ai = C[4].y;
-#pragma unroll
-        for (int o = 3; o >= 0; --o) {
-            const double r = fma(Ar, hr, fma(-Ai, hi, C[o].x));
-            Ai = fma(Ar, hi, fma(Ai, hr, C[o].y));
-            Ar = r;
-        }
-        // the rectangle's corner cells take the sheet's closed form in place
-        // of the -kappa_* conj(h) that c1 and c2 hold
-        if (g.sheet && corner_cell(g, cx, cy)) {
-            double I1, I2;
-            sheet_unit(g, t1, row(k).t2, I1, I2);
-            Ar += g.sheet_f * I1 + g.kappa_star * hr;
-            Ai -= g.sheet_f * I2 + g.kappa_star * hi;
-        }
-        // beta + S/2 = (c1, c2) - nearby lenses - conj(A)
-        const double xs1 = (c1 - n1s[k]) - Ar;
-        const double xs2 = (row(k).c2 - n2s[k]) + Ai;
-        pixel_xy_shifted(g, xs1, xs2, pxs[k], pys[k]);
-        if (!BIN) {
-            const double s2 = g.sheet ? g.kappa_star * hi : 0.0;
-            const double a1 = fma(g.kpg, t1, n1s[k]) + (Ar - s1);
-            const double a2 = fma(g.kmg, row(k).t2, n2s[k]) - (Ai + s2);
-            const int64_t o = row(k).base + i - ray_first;
-            if (a1o) a1o[o] = a1;
-            if (a2o) a2o[o] = a2;
-            if (pixo) pixo[o] = pxs[k] < 0 ? -1 : (int64_t)pys[k] * g.npix + pxs[k];
-        }
-    }
+    if (full)
+        level3_rows<BIN, true>(g, rows, coef, cy0, nxq, ln, jw32, k0, k1, ray_first,
+                               ray_last, n1s, n2s, a1o, a2o, pixo, pxs, pys);
+    else
+        level3_rows<BIN, false>(g, rows, coef, cy0, nxq, ln, jw32, k0, k1, ray_first,
+                                ray_last, n1s, n2s, a1o, a2o, pixo, pxs, pys);
     if (!BIN) return;
 
-    // bounding box of the tile's landed pixels
-    int bx0 = INT_MAX, bx1 = -1, by0 = INT_MAX, by1 = -1, nland = 0;
+    // bounding box of the tile's landed pixels, branch-free: a ray off the
+    // map has pixel -1, which is the largest unsigned value (never a
+    // minimum) and the smallest signed one (never a maximum)
+    uint32_t ux0 = UINT32_MAX, uy0 = UINT32_MAX;
+    int bx1 = -1, by1 = -1, wl = 0;
 #pragma unroll
     for (int k = 0; k < kL3RowsPerWave; ++k) {
-        if (pxs[k] < 0) continue;
-        bx0 = min(bx0, pxs[k]); bx1 = max(bx1, pxs[k]);
-        by0 = min(by0, pys[k]); by1 = max(by1, pys[k]);
-        ++nland;
+        ux0 = min(ux0, (uint32_t)pxs[k]); bx1 = max(bx1, pxs[k]);
+        uy0 = min(uy0, (uint32_t)pys[k]); by1 = max(by1, pys[k]);
+        wl += __popcll(__ballot(pxs[k] >= 0));              // landed rays of the wave's row
     }
-    bx0 = wave_min(bx0); bx1 = wave_max(bx1);
-    by0 = wave_min(by0); by1 = wave_max(by1);
-    const int wl = wave_add(nland);
+    int bx0 = (int)min(wave_min_u(ux0), (uint32_t)INT_MAX);
+    int by0 = (int)min(wave_min_u(uy0), (uint32_t)INT_MAX);
+    bx1 = wave_max(bx1);
+    by1 = wave_max(by1);
     if (lane == 0) {
         s_box[wave][0] = bx0; s_box[wave][1] = bx1;
         s_box[wave][2] = by0; s_box[wave][3] = by1;
@@ -1213,6 +1277,76 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
         if (row * bw > b) --row;
         else if ((row + 1) * bw <= b) ++row;
         atomicAdd(&counts[(by0 + row) * g.npix + bx0 + (b - row * bw)], v);
+    }
+}
+
+// Rays of one of the rectangle's four corner cells (corner column cxc), which
+// k_level3 leaves out: the sheet's series does not converge over a corner
+// cell, so these rays take its closed form.  One ray per lane over ray
+// columns [i0, i1) and ray rows [j0, j1); nearby lenses one by one
+// (near_term), the level-2 series, the sheet's closed form, beta, the pixel.
+// BIN: global adds into counts and the landed counters; otherwise the
+// per-ray outputs of rays in [ray_first, ray_last).
+template <bool UNIT, bool BIN>
+__global__ __launch_bounds__(kThreads) void k_level3_corner(
+    DevGeom g, const double2 *__restrict__ lxy, const double *__restrict__ lm,
+    const int32_t *__restrict__ cell_start, const RowInfo *__restrict__ rows,
+    const double *__restrict__ coef, int32_t cy0, int64_t i0, int64_t i1, int64_t j0, int64_t j1,
+    int64_t ray_first, int64_t ray_last, double *a1o, double *a2o, int64_t *pixo,
+    uint32_t *counts, unsigned long long *landed)
+{
+    const int64_t ncol = i1 - i0;
+    const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const bool inside = idx < ncol * (j1 - j0);
+    const int64_t i = inside ? i0 + idx % ncol : i0;
+    const RowInfo &rk = rows[inside ? j0 + idx / ncol : j0];
+    const int64_t r = rk.base + i;
+    const bool valid = inside && r >= ray_first && r < ray_last;
+    const int64_t nxq = (int64_t)g.n1x * g.q;
+    const int64_t gx = floor_div((2 * i + 1) * nxq, 2 * g.nx);
+    const int32_t cx = (int32_t)(gx / g.q), cy = rk.cy;
+    const double t1 = ray_x(g, i);
+    const double hr = t1 - level2_x(g, gx);
+    const double s1 = g.kappa_star * hr;
+    const double mac1 = g.kpg * t1;
+    const double c1 = ((t1 - mac1) + s1) + g.half_side;
+    double n1 = 0.0, n2 = 0.0;
+    const int32_t xl = cx > 0 ? cx - 1 : 0, xh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
+    const int32_t yl = cy > 0 ? cy - 1 : 0, yh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
+    for (int32_t row = yl; row <= yh; ++row) {
+        const int32_t pe = cell_start[row * g.n1x + xh + 1];
+        for (int32_t q_ = cell_start[row * g.n1x + xl]; q_ < pe; ++q_) {
+            const double2 z = lxy[q_];
+            const double d1 = t1 - z.x;
+            near_term(d1, fma(d1, d1, kNearTiny), rk.t2, z.y, UNIT ? 1.0 : lm[q_], n1, n2);
+        }
+    }
+    const double2 *cp = (const double2 *)(coef + ((int64_t)(rk.gy - cy0 * g.q) * nxq + gx) * 10);
+    double Ar = cp[4].x, Ai = cp[4].y;
+#pragma unroll
+    for (int o = 3; o >= 0; --o) {
+        const double t = fma(Ar, hr, fma(-Ai, rk.hi, cp[o].x));
+        Ai = fma(Ar, rk.hi, fma(Ai, hr, cp[o].y));
+        Ar = t;
+    }
+    const D2 d = corner_sheet(g, t1, rk.t2, hr, rk.hi);
+    Ar += d.x;
+    Ai += d.y;
+    const double xs1 = (c1 - n1) - Ar;
+    const double xs2 = (rk.c2 - n2) + Ai;
+    int32_t px, py;
+    pixel_pair(g, xs1, xs2, px, py);
+    if (BIN) {
+        const bool bin = valid && px >= 0;
+        if (bin) atomicAdd(&counts[py * g.npix + px], 1u);
+        const uint64_t got = __ballot(bin);
+        if (__lane_id() == 0 && got) landed_add(landed, (unsigned long long)__popcll(got));
+    } else if (valid) {
+        const double s2 = g.kappa_star * rk.hi;
+        const int64_t o = r - ray_first;
+        if (a1o) a1o[o] = fma(g.kpg, t1, n1) + (Ar - s1);
+        if (a2o) a2o[o] = fma(g.kmg, rk.t2, n2) - (Ai + s2);
+        if (pixo) pixo[o] = px < 0 ? -1 : (int64_t)py * g.npix + px;
     }
 }
 
@@ -1397,7 +1531,6 @@ int32_t lens_chunks(const irs_plan_s *p)
 
 irs_status ensure_super_buffers(irs_plan_s *p, int64_t rows)
 {
-    const DevGeom &g = p->dg;
     const int PS = super_order(p);
     const int32_t nSx = super_nx(p), nSy = super_ny(p);
     if (!p->d_super) {
@@ -1701,6 +1834,53 @@ double level3_flops(irs_plan_s *p, int64_t j0, int64_t j1)
     return f;
 }
 
+namespace {
+
+// k_level3_corner over the rays of rows [jA, jB) (level-1 rows c0..c1, whose
+// coefficients are resident from level-1 row band0) in the rectangle's corner
+// cells
+irs_status launch_corners(irs_plan_s *p, const RaySel &sel, int32_t band0, int64_t c0, int64_t c1,
+                          int64_t jA, int64_t jB)
+{
+    const DevGeom &g = p->dg;
+    const irs_geometry_info &gi = p->geo.info;
+    const int64_t cys[2] = {0, g.n1y - 1}, cxs[2] = {0, g.n1x - 1};
+    for (int a = 0; a < (g.n1y > 1 ? 2 : 1); ++a) {
+        if (cys[a] < c0 || cys[a] > c1) continue;
+        int64_t ja, jb;
+        level1_span(gi, 1, cys[a], ja, jb);
+        ja = std::max(ja, jA);
+        jb = std::min(jb, jB);
+        if (jb <= ja) continue;
+        for (int b = 0; b < (g.n1x > 1 ? 2 : 1); ++b) {
+            int64_t ia, ib;
+            level1_span(gi, 0, cxs[b], ia, ib);
+            const int64_t n = (ib - ia) * (jb - ja);
+            if (n <= 0) continue;
+            const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
+#define IRS_L3C(U, B)                                                                         \
+    hipLaunchKernelGGL((k_level3_corner<U, B>), dim3(nb), dim3(kThreads), 0, p->stream, g,    \
+                       (const double2 *)p->d_xy, p->d_m, p->d_cell_start,                     \
+                       (const RowInfo *)p->d_rows, p->d_coef, band0, ia, ib, ja, jb,          \
+                       sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2, sel.pixel,         \
+                       sel.counts, sel.landed)
+            const bool bin = sel.counts != nullptr;
+            if (p->unit_mass) {
+                if (bin) IRS_L3C(true, true);
+                else IRS_L3C(true, false);
+            } else {
+                if (bin) IRS_L3C(false, true);
+                else IRS_L3C(false, false);
+            }
+#undef IRS_L3C
+            IRS_HIP(hipGetLastError());
+        }
+    }
+    return IRS_OK;
+}
+
+}  // namespace
+
 irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
 {
     const DevGeom &g = p->dg;
@@ -1714,7 +1894,10 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
     const int64_t want = cyB - cyA + 1;
     irs_status st0 = ensure_rows(p);
     if (st0 != IRS_OK) return st0;
-    st0 = ensure_bands(p, std::min(band_rows(p), want));
+    // bands of band_rows(p) level-1 rows (the plan's budget, or the batch
+    // tuner's choice), whatever larger buffer the plan holds from earlier
+    const int64_t step = std::min(band_rows(p), want);
+    st0 = ensure_bands(p, step);
     if (st0 != IRS_OK) return st0;
     const int64_t ntx = (g.nx + kWave - 1) / kWave;
     const int rows_per_block = kL3Rows;
@@ -1739,8 +1922,8 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
             if ((st = cs->end(s)) != IRS_OK) return st;
         }
     }
-    for (int64_t c0 = cyA; c0 <= cyB; c0 += p->coef_rows_cap) {
-        const int64_t c1 = std::min(cyB, c0 + p->coef_rows_cap - 1);
+    for (int64_t c0 = cyA; c0 <= cyB; c0 += step) {
+        const int64_t c1 = std::min(cyB, c0 + step - 1);
         if (!(p->coef_c0 <= c0 && c1 <= p->coef_c1)) {
             // the band's level-2 coefficients are not resident: compute them
             const int P = level2_order(p);
@@ -1857,6 +2040,11 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
             }
 #undef IRS_L3
             IRS_HIP(hipGetLastError());
+            if (t1 == nty && g.sheet) {
+                // the band's rays in the rectangle's corner cells
+                irs_status st = launch_corners(p, sel, band0, c0, c1, jA, jB);
+                if (st != IRS_OK) return st;
+            }
             if (cs) {
                 irs_status st = cs->end(s);
                 if (st != IRS_OK) return st;

@@ -1,5 +1,6 @@
-"""Batches of independent maps (one graph launch) against the same maps shot
-one plan at a time, the autotuner's cache, and graph replays."""
+"""Batches of independent maps (one graph launch) against the FP64 oracle's
+direct definition and the same maps shot one plan at a time, the autotuner's
+cache, and graph replays."""
 import os
 
 import numpy as np
@@ -7,6 +8,7 @@ import pytest
 
 import oracle as orc
 import synth
+from gpu_common import THREADS, check_map, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -22,11 +24,12 @@ def irs():
     return irs
 
 
-def _maps(irs, n, method, precision, seed=3, npix=64, n_rays=150_000):
+def _maps(irs, n, method, precision, seed=3, npix=64, n_rays=150_000, with_oracle=False):
     """n uneven maps: kappa_*, gamma, kappa_c and lens counts drawn like the
-    batched workload, shrunk to test size."""
+    batched workload, shrunk to test size.  with_oracle: also return, per map,
+    (oracle geometry, lenses) for the FP64 definition."""
     rng = np.random.default_rng(seed)
-    plans = []
+    plans, refs = [], []
     while len(plans) < n:
         ks, g = rng.uniform(0.1, 0.8, 2)
         kc = float(rng.choice([0.0, 0.2]))
@@ -37,13 +40,57 @@ def _maps(irs, n, method, precision, seed=3, npix=64, n_rays=150_000):
         S = orc.source_side_for_lens_count(ks, kc, g, n_star)
         if S < 2.0:
             continue
-        p = irs.make_params(ks, kc, g, S, npix, n_rays=n_rays + 977 * len(plans),
-                            method=method, precision=precision)
+        nr = n_rays + 977 * len(plans)
+        p = irs.make_params(ks, kc, g, S, npix, n_rays=nr, method=method, precision=precision)
         g0 = irs.geometry(p, 0)
         L = synth.uniform_lenses(g0["n_stars_expected"],
                                  (g0["a1"], g0["a2"], g0["b1"], g0["b2"]), 1000 + len(plans))
         plans.append(irs.Plan(p, L.x, L.y, L.m))
-    return plans
+        if with_oracle:
+            og = orc.geometry(ks, kc, g, S, npix, n_rays=nr).with_lens_count(L.n)
+            refs.append((og, L))
+    return (plans, refs) if with_oracle else plans
+
+
+# tolerances against the direct definition: (max e_r, or None for the
+# 99.99 % rule at 1e-5 / 1e-4; pixel agreement)
+_TOL = {("direct", "fp64"): 1e-12, ("direct", "fp32"): 1e-5, ("interp", "fp64"): 1e-4}
+
+
+@pytest.mark.parametrize("method,precision", [("direct", "fp64"), ("direct", "fp32"),
+                                              ("interp", "fp64")])
+def test_batch_matches_oracle(irs, method, precision):
+    """Every map of a batch run in one graph launch against the FP64 direct
+    definition (O-1): every ray's alpha and pixel (the plan's per-ray call,
+    whose pixels the batch map must histogram to exactly), and the batch's
+    counts: bit-exact on every pixel no mismatched ray touches, rel-L1."""
+    import torch
+    plans, refs = _maps(irs, 7, method, precision, with_oracle=True)
+    counts = [torch.empty(p.params.npix_side ** 2, dtype=torch.int32, device="cuda:0")
+              for p in plans]
+    with irs.Batch(plans) as b:
+        b.tune()
+        st = b.run(counts)
+        torch.cuda.synchronize()
+    tol = _TOL[(method, precision)]
+    for k, (p, (og, L)) in enumerate(zip(plans, refs)):
+        got = counts[k].cpu().numpy().astype(np.int64)
+        a1, a2, px = p.deflect_grid(0, p.n_rays)
+        hist = np.bincount(px[px >= 0], minlength=got.size)
+        assert np.array_equal(hist, got), f"map {k}: batch counts != histogram of its rays"
+        assert st[k]["rays_landed"] == int(got.sum())
+        ref = orc.shoot_direct(og, L, threads=THREADS)
+        e = rel_err(a1, a2, ref["alpha1"], ref["alpha2"])
+        say(f"  map {k}: N*={L.n}, {p.n_rays} rays, max e_r {e.max():.2e}, "
+            f"pixel mismatches {int(np.sum(px != ref['pix']))}")
+        if precision == "fp64" and method == "direct":
+            assert e.max() < tol
+            check_map(got, ref["counts"], px, ref["pix"], min_agree=1 - 1e-5, max_rel_l1=1e-5)
+        else:
+            assert np.mean(e <= tol) >= 0.9999
+            check_map(got, ref["counts"], px, ref["pix"])
+    for p in plans:
+        p.close()
 
 
 @pytest.mark.parametrize("method,precision", [("direct", "fp64"), ("direct", "fp32"),

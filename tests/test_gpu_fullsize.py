@@ -123,3 +123,77 @@ def test_1e6_lens_learned_band(irs):
         assert rep["fallback"] == 0
         j0, j1 = pl.level1_row_rays(pl.geometry["n1y"] // 2 + 1)
         _band_check(irs, pl, j0, j1, og, L, 1500, 1e-4)
+
+
+def _spread_ray_ids(pl, rng, n_random, per_edge):
+    """Ray ids over the whole map: n_random uniform draws over every ray index,
+    plus per_edge draws in each of the first and last level-1 rows and columns
+    (the edge bands) and per_edge // 4 in each of the four corner level-1
+    cells.  Sorted and unique."""
+    g = pl.geometry
+    nx, ny = g["nx"], g["ny"]
+    rows = [pl.level1_row_rays(c) for c in (0, g["n1y"] - 1)]
+    cols = [pl.level1_col_rays(c) for c in (0, g["n1x"] - 1)]
+    ids = [rng.choice(nx * ny, n_random, replace=False)]
+    for j0, j1 in rows:
+        ids.append(rng.integers(j0, j1, per_edge) * nx + rng.integers(0, nx, per_edge))
+    for i0, i1 in cols:
+        ids.append(rng.integers(0, ny, per_edge) * nx + rng.integers(i0, i1, per_edge))
+    for j0, j1 in rows:
+        for i0, i1 in cols:
+            k = max(1, per_edge // 4)
+            ids.append(rng.integers(j0, j1, k) * nx + rng.integers(i0, i1, k))
+    return np.unique(np.concatenate(ids))
+
+
+def _gpu_rays(pl, ids):
+    """alpha and pixel of listed rays, one irs_deflect_grid call per ray (in
+    ray order, so each level-2 band is computed once)."""
+    a1 = np.empty(ids.size)
+    a2 = np.empty(ids.size)
+    px = np.empty(ids.size, np.int64)
+    for k, r in enumerate(ids):
+        x1, x2, p = pl.deflect_grid(int(r), 1)
+        a1[k], a2[k], px[k] = x1[0], x2[0], p[0]
+    return a1, a2, px
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("which", ["n1e6_salpeter", "n1e5_4096"])
+def test_three_level_field_vs_per_ray_oracle(irs, which):
+    """The distant field at full size (super, mid and cell expansions active)
+    against the oracle's interpolation with each ray's own level-2 point summed
+    over every distant lens (O-2 per ray, Sec. 2.4 level-2 coefficients): both
+    evaluate the same fourth-order series, so they agree to FP64 rounding.
+    Rays spread over the whole map, the edge bands and the corner cells
+    included; also against the direct definition at the interpolation budget."""
+    w = synth.configs.CFG3 if which == "n1e6_salpeter" else synth.configs.CFG2T
+    p, L, og = _workload(irs, w, "interp", "fp64")
+    with irs.Plan(p, L.x, L.y, L.m) as pl:
+        rng = np.random.default_rng(17)
+        n_rand, per_edge = (1200, 200) if which == "n1e6_salpeter" else (1600, 200)
+        ids = _spread_ray_ids(pl, rng, n_rand, per_edge)
+        say(f"{which}: {pl.geometry['nx']}x{pl.geometry['ny']} rays, N*={L.n}, "
+            f"level-1 {pl.geometry['n1x']}x{pl.geometry['n1y']}, q={pl.geometry['q']}, "
+            f"{ids.size} rays")
+        a1, a2, px = _gpu_rays(pl, ids)
+        import torch
+        counts = torch.zeros(w.npix * w.npix, dtype=torch.int32, device="cuda:0")
+        sides = pl.shoot_rows(0, 1, counts)       # reports the tree's cell sides
+        del counts
+    assert sides["super_cells"] > 0, "the distant-field tree is not active"
+    cs, perm = orc.level1(og, L)
+    ref = orc.shoot_interp_rays(og, L, cs, perm, ray_ids=ids, threads=THREADS)
+    d = np.hypot(a1 - ref["alpha1"], a2 - ref["alpha2"])
+    e = d / np.maximum(np.hypot(ref["alpha1"], ref["alpha2"]), 1.0)
+    mism = int(np.sum(px != ref["pix"]))
+    say(f"  tree (K_S={sides['super_cells']}, K_M={sides['mid_cells']}) vs per-ray O-2: "
+        f"max |d alpha| {d.max():.2e}, max e_r {e.max():.2e}, pixel mismatches {mism}")
+    assert d.max() < 1e-10, d.max()
+    assert mism == 0
+    ref1 = orc.shoot_direct(og, L, ray_ids=ids, threads=THREADS, want_counts=False)
+    e1 = rel_err(a1, a2, ref1["alpha1"], ref1["alpha2"])
+    mis1 = int(np.sum(px != ref1["pix"]))
+    say(f"  vs O-1: max e_r {e1.max():.2e}, pixel mismatches {mis1}")
+    assert np.sum(e1 > 1e-4) <= ids.size // 10000
+    assert mis1 <= max(1, ids.size // 10000)

@@ -177,3 +177,34 @@ def test_level2_brute_force_50_digits(orc):
         for j in range(5):
             ref = complex(acc[j])
             assert abs(C[k, j] - ref) <= 1e-12 * max(abs(ref), 1e-3)
+
+
+@pytest.mark.parametrize("sheet,mass", [(True, "salpeter"), (False, "unit")])
+def test_per_ray_level2_equals_grid(orc, sheet, mass):
+    """O-2 with each ray's own level-2 point summed on the spot equals O-2 with
+    the whole level-2 grid, bit for bit, on rays spread over the map with the
+    four corner cells and the edge rows and columns included; and the per-ray
+    form obeys the exact far-remainder identity by itself (no sheet)."""
+    g, L = _small(orc, sheet=sheet, mass=mass, seed=31)
+    cs, perm = orc.level1(g, L)
+    coef = orc.level2_grid(g, L, cs, perm, threads=8)
+    rng = np.random.default_rng(12)
+    nx, ny = g.nx, g.ny
+    corners = [0, nx - 1, (ny - 1) * nx, ny * nx - 1]
+    edges = list(rng.integers(0, nx, 20)) + list((ny - 1) * nx + rng.integers(0, nx, 20)) \
+        + list(rng.integers(0, ny, 20) * nx) + list(rng.integers(0, ny, 20) * nx + nx - 1)
+    ids = np.unique(np.concatenate([rng.choice(g.n_rays, 300, replace=False), corners, edges]))
+    grid = orc.shoot_interp(g, L, cs, perm, coef, ray_ids=ids, want_counts=True)
+    own = orc.shoot_interp_rays(g, L, cs, perm, ray_ids=ids, want_counts=True, threads=8)
+    for k in ("alpha1", "alpha2", "pix", "counts"):
+        assert np.array_equal(grid[k], own[k]), k
+    assert (grid["landed"], grid["off"]) == (own["landed"], own["off"])
+    rng_r = orc.shoot_interp_rays(g, L, cs, perm, first=5 * nx + 3, n=700, threads=2)
+    rng_g = orc.shoot_interp(g, L, cs, perm, coef, first=5 * nx + 3, n=700)
+    assert np.array_equal(rng_r["alpha1"], rng_g["alpha1"])
+    if not sheet:
+        dr = orc.shoot_direct(g, L, ray_ids=ids)
+        diff = (own["alpha1"] - dr["alpha1"]) + 1j * (own["alpha2"] - dr["alpha2"])
+        want = -np.conj(_far_remainder(g, L, ids))
+        scale = np.maximum(1.0, np.hypot(dr["alpha1"], dr["alpha2"]))
+        assert np.all(np.abs(diff - want) < 1e-11 * scale)
