@@ -232,6 +232,33 @@ irs_status irs_shoot_rows(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t
                           irs_map_stats *stats, uint64_t flags);
 
 /*
+ * irs_shoot_rows_noalloc -- irs_shoot_rows for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): rays of rows [row0, row0 + nrows) are shot and their
+ * pixel counts ADDED to `counts`, a DEVICE pointer to npix_side^2 uint32 on
+ * the plan's device, with the same kernels and results, bit for bit, as
+ * irs_shoot_rows.  The call allocates nothing: its scratch -- the landed-ray
+ * counters and, for IRS_INTERP plans, the level-2 coefficient band and cell
+ * expansions -- lives in a static 64 MiB device array that each GPU holds
+ * until the process ends; the counters are cleared by a fill kernel, not a
+ * memset.  Every call on one GPU shares that array, so calls that overlap on
+ * one GPU (other plans or threads included) race; serialise them.
+ *   rays_landed : host int64 receiving the rays binned by the call, or NULL
+ *                 (then the call only enqueues work on the plan's stream and
+ *                 does not synchronise).
+ * Requirements: the plan's device is the current device; IRS_DIRECT plans
+ * need nothing else; IRS_INTERP plans need one level-1 row of level-2 scratch
+ * (n1x q^2 80 bytes plus the cell expansions) to fit in the array, and the
+ * plan's own tables (row table, super- and mid-cell expansions) allocated at
+ * whole-map size, which one irs_shoot_map on the plan does.
+ * Errors: IRS_E_INVALID (NULL, range, another device current, a level-1 row
+ * needing more scratch than the array holds, tables not allocated; nothing
+ * is launched then), IRS_E_UNSUPPORTED (IRS_LEARNED plans), IRS_E_DEVICE.
+ */
+irs_status irs_shoot_rows_noalloc(irs_plan_t plan, int64_t row0, int64_t nrows,
+                                  uint32_t *counts, int64_t *rays_landed);
+
+/*
  * irs_shoot_map -- shoot every ray and WRITE the pixel counts N_ij to
  * `counts` (npix_side^2 uint32).  Mag_ij = N_ij * s_img / s_src.
  * Errors: as irs_shoot_rows.

@@ -244,6 +244,16 @@ class Plan:
                    "irs_shoot_rows")
         return st.as_dict()
 
+    def shoot_rows_noalloc(self, row0: int, nrows: int, counts, want_landed=True):
+        """irs_shoot_rows_noalloc: add rows [row0, row0+nrows) into a device
+        tensor of npix^2 32-bit integers without allocating device memory.
+        Returns the rays binned (None when want_landed is False: no sync)."""
+        n = C.c_int64()
+        _check(self._lib.irs_shoot_rows_noalloc(self._h, int(row0), int(nrows), _dev_ptr(counts),
+                                                C.byref(n) if want_landed else None),
+               "irs_shoot_rows_noalloc")
+        return n.value if want_landed else None
+
     # ---- learned interpolant (method "learned")
     def learn(self, freqs, lp: LearnParams = None, theta0=None) -> dict:
         """Train and validate the network (irs_learn); returns the report."""

@@ -21,7 +21,7 @@ IRS_LEARN_FIELDS = 24
 
 # every function include/irs.h declares
 EXPORTS = ("irs_geometry", "irs_level1_span", "irs_source_side", "irs_plan", "irs_deflect_grid",
-           "irs_shoot_rows", "irs_shoot_map",
+           "irs_shoot_rows", "irs_shoot_rows_noalloc", "irs_shoot_map",
            "irs_plan_set_direct_variant", "irs_plan_geometry", "irs_free", "irs_last_error",
            "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info",
            "irs_batch_free", "irs_learn_defaults", "irs_learn", "irs_learn_set", "irs_learn_get",
@@ -133,6 +133,7 @@ def load():
     lib.irs_plan.argtypes = [P(Params), i64, vp, vp, vp, vp, P(vp)]
     lib.irs_deflect_grid.argtypes = [vp, i64, i64, vp, vp, vp, u64]
     lib.irs_shoot_rows.argtypes = [vp, i64, i64, vp, P(MapStats), u64]
+    lib.irs_shoot_rows_noalloc.argtypes = [vp, i64, i64, vp, P(i64)]
     lib.irs_shoot_map.argtypes = [vp, vp, P(MapStats), u64]
     lib.irs_plan_geometry.argtypes = [vp, P(GeometryInfo)]
     lib.irs_plan_set_direct_variant.argtypes = [vp, C.c_int32]
@@ -156,7 +157,7 @@ def load():
     lib.irs_last_error.argtypes = []
     lib.irs_last_error.restype = C.c_char_p
     for name in ("irs_geometry", "irs_level1_span", "irs_source_side", "irs_plan",
-                 "irs_deflect_grid", "irs_shoot_rows", "irs_shoot_map",
+                 "irs_deflect_grid", "irs_shoot_rows", "irs_shoot_rows_noalloc", "irs_shoot_map",
                  "irs_plan_geometry", "irs_plan_set_direct_variant",
                  "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info",
                  "irs_learn_defaults", "irs_learn", "irs_learn_set", "irs_learn_get",

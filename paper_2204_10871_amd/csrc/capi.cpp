@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -19,6 +20,13 @@ thread_local std::string g_last_error;
 }
 
 void set_error(const std::string &msg) { g_last_error = msg; }
+
+irs_status alloc_allowed(const irs_plan_s *p, const char *what)
+{
+    if (!p->no_alloc) return IRS_OK;
+    set_error(std::string("irs_shoot_rows_noalloc: ") + what + " would have to be allocated");
+    return IRS_E_INVALID;
+}
 
 irs_status hip_fail(hipError_t e, const char *what)
 {
@@ -141,6 +149,75 @@ irs_status run(irs_plan_s *p, const RaySel &sel)
     if (p->params.method == IRS_LEARNED) return launch_learned(p, sel);
     return launch_interp(p, sel);
 }
+
+// Scratch of irs_shoot_rows_noalloc: device memory the library never
+// allocates at run time.  Each GPU the library runs on holds its own copy
+// until the process ends.  Layout: the landed-ray counters (kLandedSlots
+// 64-bit words) at offset 0; from kScratchBandOffset, the level-2 coefficient
+// band followed by the cell expansions of an interpolated plan.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr size_t kScratchBandOffset = 4096;
+static_assert(kLandedSlots * sizeof(unsigned long long) <= kScratchBandOffset, "scratch layout");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<char *> g_scratch_dev;    // device address of `scratch`, per device
+
+// Device address of `scratch` on `device` (the current device), looked up
+// once per device.  Host code uses only this address, never the array's name.
+irs_status scratch_address(int device, char **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize((size_t)device + 1, nullptr);
+    if (!g_scratch_dev[device]) {
+        void *ptr = nullptr;
+        IRS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_dev[device] = (char *)ptr;
+    }
+    *out = g_scratch_dev[device];
+    return IRS_OK;
+}
+
+// While alive: the plan allocates nothing, and an interpolated plan's
+// coefficient band and cell expansions live in the scratch (bands of
+// band_rows level-1 rows); afterwards the plan's own buffers are back,
+// unchanged.
+struct NoAllocScope {
+    irs_plan_s *p;
+    double *coef;
+    int64_t cap, c0, c1, budget;
+    double *part;
+    size_t part_bytes;
+    NoAllocScope(irs_plan_s *plan, char *band, int64_t band_rows, int64_t coef_row,
+                 int64_t part_row)
+        : p(plan), coef(plan->d_coef), cap(plan->coef_rows_cap), c0(plan->coef_c0),
+          c1(plan->coef_c1), budget(plan->coef_budget), part(plan->d_part),
+          part_bytes(plan->part_bytes)
+    {
+        p->no_alloc = true;
+        if (band) {
+            p->d_coef = (double *)band;
+            p->coef_rows_cap = band_rows;
+            p->coef_c0 = -1;
+            p->coef_c1 = -2;
+            p->coef_budget = band_rows * coef_row;
+            p->d_part = part_row > 0 ? (double *)(band + band_rows * coef_row) : nullptr;
+            p->part_bytes = (size_t)(band_rows * part_row);
+        }
+    }
+    ~NoAllocScope()
+    {
+        p->no_alloc = false;
+        p->d_coef = coef;
+        p->coef_rows_cap = cap;
+        p->coef_c0 = c0;
+        p->coef_c1 = c1;
+        p->coef_budget = budget;
+        p->d_part = part;
+        p->part_bytes = part_bytes;
+    }
+};
 
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
@@ -455,6 +532,74 @@ irs_status irs_shoot_map(irs_plan_t plan, uint32_t *counts, irs_map_stats *stats
     }
     level2_reset(plan);          // a whole map computes every far-field expansion itself
     return shoot(plan, 0, plan->geo.info.ny, counts, stats, flags, true, "irs_shoot_map");
+}
+
+irs_status irs_shoot_rows_noalloc(irs_plan_t plan, int64_t row0, int64_t nrows,
+                                  uint32_t *counts, int64_t *rays_landed)
+{
+    if (!plan || !counts) {
+        set_error("irs_shoot_rows_noalloc: NULL argument");
+        return IRS_E_INVALID;
+    }
+    const irs_geometry_info &g = plan->geo.info;
+    if (row0 < 0 || nrows < 0 || row0 > g.ny || nrows > g.ny - row0) {
+        set_error("irs_shoot_rows_noalloc: row range outside [0, ny)");
+        return IRS_E_INVALID;
+    }
+    if (plan->params.method == IRS_LEARNED) {
+        set_error("irs_shoot_rows_noalloc: the learned method is not provided");
+        return IRS_E_UNSUPPORTED;
+    }
+    int device = -1;
+    IRS_HIP(hipGetDevice(&device));
+    if (device != plan->device) {
+        set_error("irs_shoot_rows_noalloc: the plan's device must be the current device");
+        return IRS_E_INVALID;
+    }
+    int64_t band = 0, coef_row = 0, part_row = 0;
+    if (plan->params.method == IRS_INTERP) {
+        interp_band_row_bytes(plan, coef_row, part_row);
+        const int64_t room = (int64_t)(kScratchBytes - kScratchBandOffset);
+        band = std::min<int64_t>(g.n1y, room / (coef_row + part_row));
+        if (band < 1) {
+            set_error("irs_shoot_rows_noalloc: one level-1 row of this plan needs " +
+                      std::to_string(coef_row + part_row) + " bytes of level-2 scratch; at most " +
+                      std::to_string(room) + " are available (use irs_shoot_rows)");
+            return IRS_E_INVALID;
+        }
+        irs_status st = interp_tables_ready(plan);
+        if (st != IRS_OK) return st;
+    }
+    char *base = nullptr;
+    irs_status st = scratch_address(device, &base);
+    if (st != IRS_OK) return st;
+    unsigned long long *landed = (unsigned long long *)base;
+    st = launch_zero(plan->stream, landed, kLandedSlots * 2);
+    if (st != IRS_OK) return st;
+    if (nrows > 0) {
+        NoAllocScope scope(plan, band > 0 ? base + kScratchBandOffset : nullptr, band, coef_row,
+                           part_row);
+        RaySel sel{};
+        sel.stats = nullptr;              // no timing events, no work accounting
+        sel.row0 = row0;
+        sel.row1 = row0 + nrows;
+        sel.ray_first = 0;
+        sel.ray_last = g.nx * g.ny;
+        sel.counts = counts;
+        sel.landed = landed;
+        st = run(plan, sel);
+        if (st != IRS_OK) return st;
+    }
+    if (rays_landed) {
+        unsigned long long slots[kLandedSlots];
+        IRS_HIP(hipMemcpyAsync(slots, landed, sizeof slots, hipMemcpyDeviceToHost, plan->stream));
+        IRS_HIP(hipStreamSynchronize(plan->stream));
+        unsigned long long sum = 0;
+        for (unsigned long long v : slots) sum += v;
+        *rays_landed = (int64_t)sum;
+    }
+    set_error("");
+    return IRS_OK;
 }
 
 void irs_free(irs_plan_t plan)

@@ -1407,6 +1407,8 @@ irs_status ensure_part(irs_plan_s *p, int64_t rows)
     if (P <= 0) return IRS_OK;
     const size_t need = (size_t)rows * p->dg.n1x * level2_chunks(p) * P * 2 * sizeof(double);
     if (p->part_bytes < need) {
+        irs_status st = alloc_allowed(p, "the level-2 cell expansions");
+        if (st != IRS_OK) return st;
         dev_free(p->d_part);
         p->d_part = nullptr;
         p->part_bytes = 0;
@@ -1424,6 +1426,8 @@ irs_status ensure_part(irs_plan_s *p, int64_t rows)
 irs_status ensure_bands(irs_plan_s *p, int64_t rows)
 {
     if (p->coef_rows_cap < rows) {
+        irs_status st = alloc_allowed(p, "the level-2 coefficient band");
+        if (st != IRS_OK) return st;
         dev_free(p->d_coef);
         p->d_coef = nullptr;
         p->coef_rows_cap = 0;
@@ -1534,6 +1538,8 @@ irs_status ensure_super_buffers(irs_plan_s *p, int64_t rows)
     const int PS = super_order(p);
     const int32_t nSx = super_nx(p), nSy = super_ny(p);
     if (!p->d_super) {
+        irs_status st = alloc_allowed(p, "the super-cell expansions");
+        if (st != IRS_OK) return st;
         if (hipMalloc(&p->d_super, sizeof(double) * (size_t)nSy * nSx * PS * 2) != hipSuccess) {
             (void)hipGetLastError();
             p->d_super = nullptr;
@@ -1544,6 +1550,8 @@ irs_status ensure_super_buffers(irs_plan_s *p, int64_t rows)
     }
     const size_t need = sizeof(double) * (size_t)rows * nSx * lens_chunks(p) * PS * 2;
     if (p->super_part_bytes < need) {
+        irs_status st = alloc_allowed(p, "the super-cell partial expansions");
+        if (st != IRS_OK) return st;
         dev_free(p->d_super_part);
         p->d_super_part = nullptr;
         p->super_part_bytes = 0;
@@ -1626,6 +1634,8 @@ int32_t mid_ny(irs_plan_s *p) { const int32_t k = mid_side(p); return (p->dg.n1y
 irs_status ensure_mid_buffers(irs_plan_s *p)
 {
     if (p->d_mid) return IRS_OK;
+    irs_status st = alloc_allowed(p, "the mid-cell expansions");
+    if (st != IRS_OK) return st;
     const int PS = super_order(p);
     const int32_t nMx = mid_nx(p), nMy = mid_ny(p);
     if (hipMalloc(&p->d_mid, sizeof(double) * (size_t)nMy * nMx * PS * 2) != hipSuccess) {
@@ -1781,6 +1791,8 @@ irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *f
 irs_status ensure_rows(irs_plan_s *p)
 {
     if (p->d_rows) return IRS_OK;
+    irs_status st = alloc_allowed(p, "the level-3 row table");
+    if (st != IRS_OK) return st;
     const DevGeom &g = p->dg;
     IRS_HIP(hipMalloc(&p->d_rows, (size_t)g.ny * sizeof(RowInfo)));
     const unsigned nb = (unsigned)((g.ny + kThreads - 1) / kThreads);
@@ -1788,6 +1800,31 @@ irs_status ensure_rows(irs_plan_s *p)
                        (RowInfo *)p->d_rows);
     IRS_HIP(hipGetLastError());
     IRS_HIP(hipStreamSynchronize(p->stream));
+    return IRS_OK;
+}
+
+void interp_band_row_bytes(const irs_plan_s *p, int64_t &coef_row, int64_t &part_row)
+{
+    coef_row = level2_row_bytes(p);
+    const int P = level2_order(p);
+    part_row = P > 0 ? (int64_t)p->dg.n1x * level2_chunks(p) * P * 2 * (int64_t)sizeof(double) : 0;
+}
+
+irs_status interp_tables_ready(irs_plan_s *p)
+{
+    const char *missing = nullptr;
+    if (!p->d_rows) missing = "the level-3 row table";
+    else if (super_order(p) > 0) {
+        const size_t whole = sizeof(double) * (size_t)super_ny(p) * super_nx(p) * lens_chunks(p) *
+                             super_order(p) * 2;
+        if (!p->d_super || p->super_part_bytes < whole) missing = "the super-cell expansions";
+        else if (mid_side(p) > 0 && !p->d_mid) missing = "the mid-cell expansions";
+    }
+    if (missing) {
+        set_error(std::string(missing) + " of this plan are not allocated yet (shoot one whole "
+                  "map with irs_shoot_map first; it sizes the plan's tables)");
+        return IRS_E_INVALID;
+    }
     return IRS_OK;
 }
 

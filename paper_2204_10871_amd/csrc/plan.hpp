@@ -39,6 +39,8 @@ struct irs_plan_s {
     bool unit_mass = true;
     double kappa_star_eff = 0.0;
     int direct_variant = 1;              // FP32 direct tile shape (see k_direct.hip)
+    bool no_alloc = false;               // set during irs_shoot_rows_noalloc: every
+                                         // allocation site fails instead of allocating
     int64_t coef_budget = (int64_t)2 << 30;   // bytes for one band of level-2 coefficients
 
     // Lenses packed into level-1 cells (row-major cell order; inside a cell in
@@ -98,6 +100,10 @@ inline void dev_free(void *ptr)
 // Status plumbing shared by the launch wrappers and the C ABI.
 void set_error(const std::string &msg);
 irs_status hip_fail(hipError_t e, const char *what);
+
+// Called where a plan buffer would be (re)allocated: the error of a call that
+// must not allocate (p->no_alloc), else IRS_OK.
+irs_status alloc_allowed(const irs_plan_s *p, const char *what);
 
 #define IRS_HIP(call)                                                  \
     do {                                                               \
@@ -161,6 +167,14 @@ DirectArgs direct_args_full(const irs_plan_s *p, int variant, uint32_t *counts,
                             unsigned long long *landed);
 // Level-2 buffers sized for whole-map bands, allocated now (before a capture).
 irs_status interp_prepare(irs_plan_s *p);
+// Bytes per level-1 row of the level-2 coefficient band and of the cell
+// expansions (0 when the plan has none).
+void interp_band_row_bytes(const irs_plan_s *p, int64_t &coef_row, int64_t &part_row);
+// IRS_OK if a call of the interpolated method on rows of this plan would
+// allocate nothing but its coefficient band and cell expansions: the row
+// table, the super- and mid-cell expansions and their partials exist at
+// whole-map size.  Otherwise an error with a message.
+irs_status interp_tables_ready(irs_plan_s *p);
 // Fill kernel (graph-safe zeroing): n 32-bit words.
 irs_status launch_zero(hipStream_t s, void *ptr, size_t n_words);
 
