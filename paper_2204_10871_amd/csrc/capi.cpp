@@ -120,6 +120,8 @@ void release(irs_plan_s *p)
     dev_free(p->d_cxy);
     dev_free(p->d_xy);
     dev_free(p->d_rows);
+    dev_free(p->d_tcol);
+    dev_free(p->d_trow);
     dev_free(p->d_coef);
     dev_free(p->d_part);
     dev_free(p->d_super);

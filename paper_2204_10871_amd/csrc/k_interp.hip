@@ -820,6 +820,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_level2_points(
 // a lens) falls back to one global add per run of equal pixels in a lane.
 // -------------------------------------------------------------------------
 constexpr int kL3Rows = 32;
+constexpr int kXcds = 8;               // MI355X: workgroups go to the 8 XCDs in turn
 constexpr int kL3RowsPerWave = kL3Rows / (kThreads / kWave);
 constexpr int kHistCap = 8192;
 
@@ -1074,7 +1075,8 @@ __device__ __forceinline__ void level3_rows(
             const int64_t lo = ray_first - rk.base, hi_ = ray_last - rk.base;
             const int32_t wlo = (int32_t)(lo < 0 ? 0 : (lo > g.nx ? g.nx : lo));
             const int32_t whi = (int32_t)(hi_ < 0 ? 0 : (hi_ > g.nx ? g.nx : hi_));
-            valid = (int)(ln.i32 >= wlo) & (int)(ln.i32 < whi);
+            // (lanes past a narrow tile's end hold columns of the next tile)
+            valid = (int)ln.in_col & (int)(ln.i32 >= wlo) & (int)(ln.i32 < whi);
         }
         // rays of the rectangle's four corner cells are k_level3_corner's
         if (ln.wave_corner && (rk.cy == 0 || rk.cy == g.n1y - 1)) valid = valid && !ln.corner_col;
@@ -1094,33 +1096,50 @@ __device__ __forceinline__ void level3_rows(
     }
 }
 
-// BIN: count rays into `counts` (a1o, a2o, pixo unused); otherwise write the
-// per-ray outputs (counts, landed unused).
-template <bool UNIT, bool BIN>
-__global__ __launch_bounds__(kThreads, 4) void k_level3(
-    DevGeom g, const double2 *__restrict__ lxy, const double *__restrict__ lm,
-    const int32_t *__restrict__ cell_start, const RowInfo *__restrict__ rows,
-    const double *__restrict__ coef, int32_t cy0, int64_t ntx, int64_t jr0, int64_t jr1,
-    int64_t ray_first, int64_t ray_last, double *a1o, double *a2o, int64_t *pixo,
-    uint32_t *counts, unsigned long long *landed)
-{
-    __shared__ uint32_t s_hist[kHistCap];
-    __shared__ int s_box[kThreads / kWave][5];
-    __shared__ double s_t2[kL3Rows];
+// What a level-3 launch needs of one map (a kernel argument for a single
+// map; a device table entry for a batch).
+struct L3Map {
+    DevGeom g;
+    const double2 *lxy;             // sorted lenses (x, y)
+    const double *lm;               // masses (null: unit)
+    const int32_t *cell_start;
+    const RowInfo *rows;            // row table
+    const double *coef;             // level-2 coefficients from level-1 row cy0
+    const TileSpan *tcol, *trow;    // the plan's column and row tiles
+    int32_t cy0;
+    int32_t ntx;                    // column tiles
+    int64_t jr0, jr1;               // ray rows of the launch
+    int64_t ray_first, ray_last;    // ray indices (per-ray outputs)
+    double *a1o, *a2o;              // per-ray outputs, indexed r - ray_first, or
+    int64_t *pixo;                  //   ... null
+    uint32_t *counts;               // BIN: the map
+    unsigned long long *landed;     // BIN: landed-ray counters
+};
 
+// One tile of rays: columns tcol[tx] (one per lane) by rows trow[ty]
+// (kL3RowsPerWave per wave), restricted to rows [jr0, jr1).  Every ray: the
+// near lenses exactly, Horner of its level-2 point's C_0..C_4, the macro
+// term, beta and the pixel; BIN: binned through an LDS histogram over the
+// tile's landed-pixel box (flushed with one global atomic per non-empty bin),
+// or, for a box larger than the histogram, global adds by runs of equal
+// pixels down a lane's rows.  Called by every thread of the workgroup.
+template <bool UNIT, bool BIN>
+__device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t ty,
+                                            uint32_t *s_hist, int (*s_box)[5], double *s_t2)
+{
+    const DevGeom &g = m.g;
     const int tid = threadIdx.x;
     const int lane = tid % kWave;
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
-    const int64_t tx = (int64_t)blockIdx.x % ntx;
-    const int64_t ty = (int64_t)blockIdx.x / ntx;
     constexpr int R = kL3RowsPerWave;
-    // tiles start at multiples of kL3Rows whatever [jr0, jr1) is, so a ray
-    // meets the same rows of its wave (and the same rounding) in every launch
-    const int64_t jb = (jr0 / kL3Rows + ty) * kL3Rows;
-    const int64_t jw = jb + wave * R;                    // the wave's first row
-    if (tid < kL3Rows) s_t2[tid] = rows[min(jb + tid, g.ny - 1)].t2;
-    const int64_t i = tx * kWave + lane;
-    const bool in_col = i < g.nx;
+    const TileSpan tc = m.tcol[tx], tr = m.trow[ty];
+    const int32_t ny1 = (int32_t)g.ny - 1;                          // ny < 2^31
+    const int32_t jw = tr.a + wave * R;                             // the wave's first row
+    __syncthreads();                                                // s_t2 of an earlier tile
+    if (tid < kL3Rows) s_t2[tid] = m.rows[min(tr.a + tid, ny1)].t2;
+    const int32_t i32 = tc.a + lane;
+    const int64_t i = i32;
+    const bool in_col = i32 < tc.b;
     const int64_t nxq = (int64_t)g.n1x * g.q;
     const int64_t gx = in_col ? floor_div((2 * i + 1) * nxq, 2 * g.nx) : 0;
     const int32_t cx = (int32_t)gx / g.q;
@@ -1135,18 +1154,19 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
     const int32_t xl = cx > 0 ? cx - 1 : 0, xh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
     const uint32_t coff = (uint32_t)gx * 10u * (uint32_t)sizeof(double);   // lane's point in a row
 
-    // the wave's rows jw + k (rows past the grid repeat its last one); rows
-    // k0 <= k < k1 lie inside [jr0, jr1), the others bin nothing
-    const int k0 = (int)max<int64_t>(0, jr0 - jw), k1 = (int)min<int64_t>(R, jr1 - jw);
-    const int32_t jw32 = (int32_t)jw, ny1 = (int32_t)g.ny - 1;      // ny < 2^31
-    auto row = [&](int k) -> const RowInfo & { return rows[min(jw32 + k, ny1)]; };
+    // the wave's rows jw + k, k < kt, lie in the tile; rows k0 <= k < k1 also
+    // lie in [jr0, jr1), the others bin nothing
+    const int kt = max(0, min(R, tr.b - jw));
+    const int k0 = (int)max<int64_t>(0, m.jr0 - jw);
+    const int k1 = (int)min<int64_t>(kt, m.jr1 - jw);
+    auto row = [&](int k) -> const RowInfo & { return m.rows[min(jw + k, ny1)]; };
 
     // nearby lenses, exactly.  A lane's rays are R consecutive rows of one
-    // column; they nearly always share their level-1 cell row (a cell spans
-    // hundreds of ray rows), so one pass over the lenses serves them all, the
-    // R rows sharing each reciprocal; otherwise each ray takes its own pass.
-    // Which of the two a ray takes, and its partners in the first, depend
-    // only on its row.
+    // column; they nearly always share their level-1 cell row (always where
+    // row tiles follow the cell rows), so one pass over the lenses serves them
+    // all, the R rows sharing each reciprocal; otherwise each ray takes its
+    // own pass.  Which of the two a ray takes, and its partners in the first,
+    // depend only on the plan's tiles, not on the call.
     __syncthreads();
     double n1s[R], n2s[R], t2s[R];
 #pragma unroll
@@ -1162,36 +1182,37 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
         const int32_t cl = cxa > 0 ? cxa - 1 : 0, ch = cxb < g.n1x - 1 ? cxb + 1 : g.n1x - 1;
         const bool straddle = cxa != cxb;
         const int32_t cy0r = row(0).cy;
-        if (row(R - 1).cy == cy0r) {                      // rows sorted: all share cy0r
+        if (row(kt - 1).cy == cy0r) {                     // rows sorted: all share cy0r
             if (straddle)
-                near_pass<UNIT, R, true>(g, lxy, lm, cell_start, cy0r, cl, ch, true, xl, xh, t1,
-                                         t2s, n1s, n2s);
+                near_pass<UNIT, R, true>(g, m.lxy, m.lm, m.cell_start, cy0r, cl, ch, true, xl, xh,
+                                         t1, t2s, n1s, n2s);
             else
-                near_pass<UNIT, R, false>(g, lxy, lm, cell_start, cy0r, cl, ch, false, xl, xh, t1,
-                                          t2s, n1s, n2s);
+                near_pass<UNIT, R, false>(g, m.lxy, m.lm, m.cell_start, cy0r, cl, ch, false, xl,
+                                          xh, t1, t2s, n1s, n2s);
         } else {
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 if (k < k0 || k >= k1) continue;
-                near_pass<UNIT, 1, true>(g, lxy, lm, cell_start, row(k).cy, cl, ch, straddle, xl,
-                                         xh, t1, &t2s[k], &n1s[k], &n2s[k]);
+                near_pass<UNIT, 1, true>(g, m.lxy, m.lm, m.cell_start, row(k).cy, cl, ch,
+                                         straddle, xl, xh, t1, &t2s[k], &n1s[k], &n2s[k]);
             }
         }
     }
 
     // per-row evaluation; rows whose rays all lie in [ray_first, ray_last)
     // need no per-ray window test
-    const bool full = k1 > k0 && row(k0).base >= ray_first && row(k1 - 1).base + g.nx <= ray_last;
+    const bool full = k1 > k0 && row(k0).base >= m.ray_first &&
+                      row(k1 - 1).base + g.nx <= m.ray_last;
     const bool corner_col = in_col && (cx == 0 || cx == g.n1x - 1);
     const bool wave_corner = g.sheet && __ballot(corner_col) != 0;     // wave-uniform
-    const L3Lane ln{i, (int32_t)i, in_col, corner_col, wave_corner, t1, hr, c1, s1, coff};
+    const L3Lane ln{i, i32, in_col, corner_col, wave_corner, t1, hr, c1, s1, coff};
     int32_t pxs[R], pys[R];
     if (full)
-        level3_rows<BIN, true>(g, rows, coef, cy0, nxq, ln, jw32, k0, k1, ray_first,
-                               ray_last, n1s, n2s, a1o, a2o, pixo, pxs, pys);
+        level3_rows<BIN, true>(g, m.rows, m.coef, m.cy0, nxq, ln, jw, k0, k1, m.ray_first,
+                               m.ray_last, n1s, n2s, m.a1o, m.a2o, m.pixo, pxs, pys);
     else
-        level3_rows<BIN, false>(g, rows, coef, cy0, nxq, ln, jw32, k0, k1, ray_first,
-                                ray_last, n1s, n2s, a1o, a2o, pixo, pxs, pys);
+        level3_rows<BIN, false>(g, m.rows, m.coef, m.cy0, nxq, ln, jw, k0, k1, m.ray_first,
+                                m.ray_last, n1s, n2s, m.a1o, m.a2o, m.pixo, pxs, pys);
     if (!BIN) return;
 
     // bounding box of the tile's landed pixels, branch-free: a ray off the
@@ -1200,7 +1221,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
     uint32_t ux0 = UINT32_MAX, uy0 = UINT32_MAX;
     int bx1 = -1, by1 = -1, wl = 0;
 #pragma unroll
-    for (int k = 0; k < kL3RowsPerWave; ++k) {
+    for (int k = 0; k < R; ++k) {
         ux0 = min(ux0, (uint32_t)pxs[k]); bx1 = max(bx1, pxs[k]);
         uy0 = min(uy0, (uint32_t)pys[k]); by1 = max(by1, pys[k]);
         wl += __popcll(__ballot(pxs[k] >= 0));              // landed rays of the wave's row
@@ -1223,17 +1244,18 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
         by0 = min(by0, s_box[w][2]); by1 = max(by1, s_box[w][3]);
         nblock += s_box[w][4];
     }
-    if (tid == 0 && nblock) landed_add(landed, (unsigned long long)nblock);
+    if (tid == 0 && nblock) landed_add(m.landed, (unsigned long long)nblock);
     if (bx1 < 0) return;                                   // nothing landed (block-uniform)
     const int bw = bx1 - bx0 + 1;
     const int64_t area = (int64_t)bw * (by1 - by0 + 1);
+    uint32_t *counts = m.counts;
     if (area > kHistCap) {
         // block-uniform fallback (rays scattered, as near a lens): global
         // adds by runs of equal pixels down a lane's rows
         int32_t cur = -1;
         uint32_t run = 0;
 #pragma unroll
-        for (int k = 0; k < kL3RowsPerWave; ++k) {
+        for (int k = 0; k < R; ++k) {
             const int32_t pix = pxs[k] < 0 ? -1 : pys[k] * g.npix + pxs[k];
             if (pix == cur) {
                 ++run;
@@ -1254,7 +1276,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
         int32_t cur = -1;
         uint32_t run = 0;
 #pragma unroll
-        for (int k = 0; k < kL3RowsPerWave; ++k) {
+        for (int k = 0; k < R; ++k) {
             const int32_t lp = pxs[k] < 0 ? -1 : (pys[k] - by0) * bw + (pxs[k] - bx0);
             if (lp == cur) {
                 ++run;
@@ -1273,11 +1295,27 @@ __global__ __launch_bounds__(kThreads, 4) void k_level3(
     for (int b = tid; b < area; b += kThreads) {
         const uint32_t v = s_hist[b];
         if (!v) continue;
-        int row = (int)((float)b * inv_bw);
-        if (row * bw > b) --row;
-        else if ((row + 1) * bw <= b) ++row;
-        atomicAdd(&counts[(by0 + row) * g.npix + bx0 + (b - row * bw)], v);
+        int row_b = (int)((float)b * inv_bw);
+        if (row_b * bw > b) --row_b;
+        else if ((row_b + 1) * bw <= b) ++row_b;
+        atomicAdd(&counts[(by0 + row_b) * g.npix + bx0 + (b - row_b * bw)], v);
     }
+}
+
+// One map: tile (tx, ty0 + blockIdx.x / ntx_pad) with tx = blockIdx.x mod
+// ntx_pad.  ntx_pad is a multiple of the 8 XCDs, which take consecutive
+// workgroups in turn, so a column tile runs on the same XCD in every tile row
+// and finds its level-2 coefficients and lenses in that XCD's L2.
+template <bool UNIT, bool BIN>
+__global__ __launch_bounds__(kThreads, 4) void k_level3(L3Map m, int32_t ty0, int32_t ntx_pad)
+{
+    __shared__ uint32_t s_hist[kHistCap];
+    __shared__ int s_box[kThreads / kWave][5];
+    __shared__ double s_t2[kL3Rows];
+    const int32_t tx = (int32_t)(blockIdx.x % (uint32_t)ntx_pad);
+    if (tx >= m.ntx) return;                               // padding (block-uniform)
+    level3_tile<UNIT, BIN>(m, tx, ty0 + (int32_t)(blockIdx.x / (uint32_t)ntx_pad), s_hist, s_box,
+                           s_t2);
 }
 
 // Rays of one of the rectangle's four corner cells (corner column cxc), which
@@ -1786,14 +1824,54 @@ irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *f
     return IRS_OK;
 }
 
-// The level-3 row table (geometry only, built once per plan; the build waits
-// for its kernel, so work on other streams may read the table at once).
+// Tiles of one axis: where every level-1 cell spans at least `min_span` rays
+// along it, tiles follow the cells (each cell's rays cut into tiles of at most
+// `tile` rays from its first ray), so no wave straddles two cells;
+// otherwise tiles of `tile` rays from ray 0.
+std::vector<TileSpan> make_tiles(const irs_geometry_info &gi, int axis, int32_t tile,
+                                 int32_t min_span)
+{
+    const int64_t n = axis ? gi.ny : gi.nx, ncell = axis ? gi.n1y : gi.n1x;
+    std::vector<TileSpan> out;
+    bool follow = true;
+    for (int64_t c = 0; c < ncell && follow; ++c) {
+        int64_t a, b;
+        level1_span(gi, axis, c, a, b);
+        follow = b - a >= min_span;
+    }
+    if (follow) {
+        for (int64_t c = 0; c < ncell; ++c) {
+            int64_t a, b;
+            level1_span(gi, axis, c, a, b);
+            for (int64_t s = a; s < b; s += tile)
+                out.push_back(TileSpan{(int32_t)s, (int32_t)std::min<int64_t>(b, s + tile)});
+        }
+    } else {
+        for (int64_t s = 0; s < n; s += tile)
+            out.push_back(TileSpan{(int32_t)s, (int32_t)std::min<int64_t>(n, s + tile)});
+    }
+    return out;
+}
+
+// The level-3 row table and tiles (geometry only, built once per plan; the
+// build waits for its kernel, so work on other streams may read them at once).
 irs_status ensure_rows(irs_plan_s *p)
 {
     if (p->d_rows) return IRS_OK;
     irs_status st = alloc_allowed(p, "the level-3 row table");
     if (st != IRS_OK) return st;
     const DevGeom &g = p->dg;
+    // column tiles follow the cells when a cell holds >= 1.5 waves of
+    // columns (narrower cells would leave too many lanes idle); row tiles
+    // when a cell holds a whole tile of rows
+    p->h_tcol = make_tiles(p->geo.info, 0, kWave, kWave + kWave / 2);
+    p->h_trow = make_tiles(p->geo.info, 1, kL3Rows, kL3Rows);
+    IRS_HIP(hipMalloc(&p->d_tcol, p->h_tcol.size() * sizeof(TileSpan)));
+    IRS_HIP(hipMalloc(&p->d_trow, p->h_trow.size() * sizeof(TileSpan)));
+    IRS_HIP(hipMemcpyAsync(p->d_tcol, p->h_tcol.data(), p->h_tcol.size() * sizeof(TileSpan),
+                           hipMemcpyHostToDevice, p->stream));
+    IRS_HIP(hipMemcpyAsync(p->d_trow, p->h_trow.data(), p->h_trow.size() * sizeof(TileSpan),
+                           hipMemcpyHostToDevice, p->stream));
     IRS_HIP(hipMalloc(&p->d_rows, (size_t)g.ny * sizeof(RowInfo)));
     const unsigned nb = (unsigned)((g.ny + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_row_table, dim3(nb), dim3(kThreads), 0, p->stream, g,
@@ -1936,8 +2014,8 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
     const int64_t step = std::min(band_rows(p), want);
     st0 = ensure_bands(p, step);
     if (st0 != IRS_OK) return st0;
-    const int64_t ntx = (g.nx + kWave - 1) / kWave;
-    const int rows_per_block = kL3Rows;
+    const int64_t ntx = (int64_t)p->h_tcol.size();
+    const int64_t ntx_pad = (ntx + kXcds - 1) / kXcds * kXcds;
     CallStats *cs = sel.stats;
     if (level2_order(p) > 0 && super_order(p) > 0 &&
         !(p->coef_c0 <= cyA && cyB <= p->coef_c1)) {
@@ -2045,28 +2123,50 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
         const int64_t jA = std::max(sel.row0, first_row_at(g, c0 * q));
         const int64_t jB = std::min(sel.row1, first_row_at(g, (c1 + 1) * q));
         if (jB <= jA) continue;
-        // tiles of rows_per_block rows at multiples of rows_per_block (the
-        // kernel starts its first tile at the multiple at or below j0)
-        const int64_t ta = jA / rows_per_block;
-        const int64_t nty = (jB + rows_per_block - 1) / rows_per_block - ta;
-        const int64_t max_ty = std::max<int64_t>(1, ((int64_t)1 << 24) / ntx);
+        // the row tiles that meet rows [jA, jB)
+        const std::vector<TileSpan> &tr = p->h_trow;
+        const int64_t ta = std::upper_bound(tr.begin(), tr.end(), jA,
+                                            [](int64_t v, const TileSpan &t) { return v < t.b; }) -
+                           tr.begin();
+        const int64_t tb = std::lower_bound(tr.begin(), tr.end(), jB,
+                                            [](const TileSpan &t, int64_t v) { return t.a < v; }) -
+                           tr.begin();
+        const int64_t nty = tb - ta;
+        L3Map m{};
+        m.g = g;
+        m.lxy = (const double2 *)p->d_xy;
+        m.lm = p->d_m;
+        m.cell_start = p->d_cell_start;
+        m.rows = (const RowInfo *)p->d_rows;
+        m.coef = p->d_coef;
+        m.tcol = p->d_tcol;
+        m.trow = p->d_trow;
+        m.cy0 = band0;
+        m.ntx = (int32_t)ntx;
+        m.ray_first = sel.ray_first;
+        m.ray_last = sel.ray_last;
+        m.a1o = sel.alpha1;
+        m.a2o = sel.alpha2;
+        m.pixo = sel.pixel;
+        m.counts = sel.counts;
+        m.landed = sel.landed;
+        const int64_t max_ty = std::max<int64_t>(1, ((int64_t)1 << 24) / ntx_pad);
         for (int64_t t0 = 0; t0 < nty; t0 += max_ty) {
             const int64_t t1 = std::min(nty, t0 + max_ty);
-            const unsigned nb3 = (unsigned)((t1 - t0) * ntx);
-            const int64_t j0 = std::max(jA, (ta + t0) * rows_per_block);
-            const int64_t j1 = std::min(jB, (ta + t1) * rows_per_block);
+            const unsigned nb3 = (unsigned)((t1 - t0) * ntx_pad);
+            const int64_t j0 = std::max(jA, (int64_t)tr[ta + t0].a);
+            const int64_t j1 = std::min(jB, (int64_t)tr[ta + t1 - 1].b);
+            m.jr0 = j0;
+            m.jr1 = j1;
             if (cs) {
                 irs_status st = cs->begin(s, 1);
                 if (st != IRS_OK) return st;
                 cs->n_rays++;
-                cs->ray_flops += level3_flops(p, std::max(j0, sel.row0), std::min(j1, sel.row1));
+                cs->ray_flops += level3_flops(p, j0, j1);
             }
 #define IRS_L3(U, B)                                                                          \
-    hipLaunchKernelGGL((k_level3<U, B>), dim3(nb3), dim3(kThreads), 0, s, g,                  \
-                       (const double2 *)p->d_xy, p->d_m, p->d_cell_start,                     \
-                       (const RowInfo *)p->d_rows, p->d_coef, band0, ntx, j0, j1,             \
-                       sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2, sel.pixel,         \
-                       sel.counts, sel.landed)
+    hipLaunchKernelGGL((k_level3<U, B>), dim3(nb3), dim3(kThreads), 0, s, m,                  \
+                       (int32_t)(ta + t0), (int32_t)ntx_pad)
             const bool bin = sel.counts != nullptr;
             if (p->unit_mass) {
                 if (bin) IRS_L3(true, true);

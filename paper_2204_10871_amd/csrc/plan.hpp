@@ -13,6 +13,12 @@
 
 // Arguments of the direct-sum tile routines (one map).
 namespace irs {
+// A half-open range [a, b) of ray columns or rows: one tile of the level-3
+// launch along that axis.
+struct TileSpan {
+    int32_t a, b;
+};
+
 struct DirectArgs {
     DevGeom g;
     const double *lx, *ly, *lm;          // sorted lenses (lm null: unit masses)
@@ -59,6 +65,10 @@ struct irs_plan_s {
     double *d_mid = nullptr;              // mid-cell expansions (all rows), like d_super
     std::vector<char> mid_ok;
     void *d_rows = nullptr;               // level-3 row table (ny entries of 32 B)
+    // level-3 tiles: column tiles of <= 64 ray columns, row tiles of <= 32 ray
+    // rows, following the level-1 cells where cells are wide (tall) enough
+    irs::TileSpan *d_tcol = nullptr, *d_trow = nullptr;
+    std::vector<irs::TileSpan> h_tcol, h_trow;
     double *d_coef = nullptr;
     int64_t coef_rows_cap = 0;   // level-1 rows the buffer holds
     int64_t coef_c0 = -1, coef_c1 = -2;   // level-1 rows whose coefficients it holds now

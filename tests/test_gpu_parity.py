@@ -325,3 +325,25 @@ def test_level2_local_expansion_equals_paper_form(irs, kind):
     assert e.max() < 1e-11
     assert np.mean(out[False][2] == out[True][2]) >= 1 - 1e-6
     assert np.abs(out[False][3].astype(np.int64) - out[True][3]).sum() <= 2 * np.sum(out[False][2] != out[True][2])
+
+
+def test_single_ray_calls_equal_row_calls(irs):
+    """Tiles follow the level-1 cells where cells are wide, so a cell's last
+    column tile is narrower than a wave and its spare lanes hold the next
+    cell's first columns; a call for one ray must still take that ray from
+    its own tile.  Rays at both edges of every level-1 column, shot one at a
+    time, equal the same rays of whole-row calls bit for bit."""
+    c = Case(0.35, 0.1, 0.25, 20.0, 96, n_rays=8_000_000, seed=46)
+    with c.plan("interp", "fp64") as pl:
+        g = pl.geometry
+        assert g["nx"] // g["n1x"] >= 96            # columns per cell: tiles follow cells
+        rows = [0, g["ny"] // 3, g["ny"] - 1]
+        for j in rows:
+            ra1, ra2, rpx = pl.deflect_grid(j * g["nx"], g["nx"])
+            cols = []
+            for cx in range(g["n1x"]):
+                i0, i1 = pl.level1_col_rays(cx)
+                cols += [i0, i0 + 1, i0 + 3, i1 - 4, i1 - 1]
+            for i in cols:
+                a1, a2, px = pl.deflect_grid(j * g["nx"] + i, 1)
+                assert (a1[0], a2[0], px[0]) == (ra1[i], ra2[i], rpx[i]), (j, i)
