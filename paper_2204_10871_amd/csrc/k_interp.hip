@@ -822,7 +822,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_level2_points(
 constexpr int kL3Rows = 32;
 constexpr int kXcds = 8;               // MI355X: workgroups go to the 8 XCDs in turn
 constexpr int kL3RowsPerWave = kL3Rows / (kThreads / kWave);
-constexpr int kHistCap = 8192;
+constexpr int kHistCap = 6144;
 
 // One ray row of the plan's ray grid, as the level-3 kernel reads it.
 struct alignas(32) RowInfo {
@@ -873,6 +873,9 @@ __device__ __forceinline__ void near_term(double d1, double d1s, double t2, doub
 // outside [1e-200, 1e200] (a lens exactly on a ray, where rr is kNearTiny,
 // or rr beyond that range) the quotients are taken one by one.
 constexpr double kGroupMin = 1e-200, kGroupMax = 1e200;
+// rows of a lane that share one reciprocal per lens: four keeps the group's
+// products in few enough registers for five waves per SIMD
+constexpr int kNearGroup = 4;
 
 template <int G>
 __device__ __forceinline__ void near_group(double d1, double d1s, const double *t2s, double zy,
@@ -945,7 +948,10 @@ __device__ __forceinline__ void near_pass(const DevGeom &g, const double2 *__res
             const double d1 = t1 - z.x;
             const double d1s = fma(d1, d1, kNearTiny);
             if constexpr (RR > 1) {
-                near_group<RR>(d1, d1s, t2s, z.y, m, n1s, n2s);
+                static_assert(RR % kNearGroup == 0, "rows in whole groups");
+#pragma unroll
+                for (int h = 0; h < RR; h += kNearGroup)
+                    near_group<kNearGroup>(d1, d1s, t2s + h, z.y, m, n1s + h, n2s + h);
             } else {
 #pragma unroll
                 for (int k = 0; k < RR; ++k) near_term(d1, d1s, t2s[k], z.y, m, n1s[k], n2s[k]);
@@ -1125,7 +1131,7 @@ struct L3Map {
 // pixels down a lane's rows.  Called by every thread of the workgroup.
 template <bool UNIT, bool BIN>
 __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t ty,
-                                            uint32_t *s_hist, int (*s_box)[5], double *s_t2)
+                                            uint32_t *s_hist, int (*s_box)[5])
 {
     const DevGeom &g = m.g;
     const int tid = threadIdx.x;
@@ -1135,8 +1141,7 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
     const TileSpan tc = m.tcol[tx], tr = m.trow[ty];
     const int32_t ny1 = (int32_t)g.ny - 1;                          // ny < 2^31
     const int32_t jw = tr.a + wave * R;                             // the wave's first row
-    __syncthreads();                                                // s_t2 of an earlier tile
-    if (tid < kL3Rows) s_t2[tid] = m.rows[min(tr.a + tid, ny1)].t2;
+    __syncthreads();                          // the LDS of an earlier tile is free again
     const int32_t i32 = tc.a + lane;
     const int64_t i = i32;
     const bool in_col = i32 < tc.b;
@@ -1167,12 +1172,11 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
     // all, the R rows sharing each reciprocal; otherwise each ray takes its
     // own pass.  Which of the two a ray takes, and its partners in the first,
     // depend only on the plan's tiles, not on the call.
-    __syncthreads();
     double n1s[R], n2s[R], t2s[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         n1s[k] = n2s[k] = 0.0;
-        t2s[k] = s_t2[wave * R + k];     // row(k).t2, in a vector register
+        t2s[k] = row(k).t2;              // wave-uniform: kept in scalar registers
     }
     if (k1 > k0) {                                        // wave-uniform rows
         // level-1 columns of the wave's first and last ray (lane 0 always
@@ -1307,15 +1311,13 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
 // workgroups in turn, so a column tile runs on the same XCD in every tile row
 // and finds its level-2 coefficients and lenses in that XCD's L2.
 template <bool UNIT, bool BIN>
-__global__ __launch_bounds__(kThreads, 4) void k_level3(L3Map m, int32_t ty0, int32_t ntx_pad)
+__global__ __launch_bounds__(kThreads, 5) void k_level3(L3Map m, int32_t ty0, int32_t ntx_pad)
 {
     __shared__ uint32_t s_hist[kHistCap];
     __shared__ int s_box[kThreads / kWave][5];
-    __shared__ double s_t2[kL3Rows];
     const int32_t tx = (int32_t)(blockIdx.x % (uint32_t)ntx_pad);
     if (tx >= m.ntx) return;                               // padding (block-uniform)
-    level3_tile<UNIT, BIN>(m, tx, ty0 + (int32_t)(blockIdx.x / (uint32_t)ntx_pad), s_hist, s_box,
-                           s_t2);
+    level3_tile<UNIT, BIN>(m, tx, ty0 + (int32_t)(blockIdx.x / (uint32_t)ntx_pad), s_hist, s_box);
 }
 
 // Rays of one of the rectangle's four corner cells (corner column cxc), which
