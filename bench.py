@@ -370,24 +370,24 @@ def bench_circle(irs, synth, torch, stream):
     return out
 
 
-def bench_batch(irs, synth, torch, stream):
-    """The 64-map batch (kappa_*, gamma ~ U[0.1, 0.8], kappa_c in {0, 0.2},
-    N_* = 10^U[3, 5], 1024^2..4096^2 px, 100 rays/px), interpolated: one tuned
-    graph launch vs the same maps launched one after another."""
+def _batch_plans(irs, synth, torch, stream, method, precision, rays_per_pixel=None):
     draws = synth.configs.batch_draws()
     plans, counts = [], []
-    t0 = time.perf_counter()
     for d in draws:
         S = irs.source_side_for_n_star(d.kappa_star, d.kappa_c, d.gamma, d.n_star_target)
-        p = irs.make_params(d.kappa_star, d.kappa_c, d.gamma, S, d.npix,
-                            rays_per_pixel=d.rays_per_pixel, method="interp", precision="fp64")
+        rpp = d.rays_per_pixel if rays_per_pixel is None else rays_per_pixel
+        p = irs.make_params(d.kappa_star, d.kappa_c, d.gamma, S, d.npix, rays_per_pixel=rpp,
+                            method=method, precision=precision)
         g = irs.geometry(p, 0)
         L = synth.uniform_lenses(g["n_stars_expected"], (g["a1"], g["a2"], g["b1"], g["b2"]),
                                  d.seed)
         plans.append(irs.Plan(p, L.x, L.y, L.m, stream=stream.cuda_stream))
         counts.append(torch.empty(d.npix * d.npix, dtype=torch.int32, device="cuda:0"))
-    rays = sum(p.n_rays for p in plans)
-    log(f"batch: {len(plans)} maps, {rays:.3e} rays, set up in {time.perf_counter() - t0:.1f} s")
+    return plans, counts
+
+
+def _batch_vs_sequential(irs, torch, plans, counts):
+    """(tuned settings, graph seconds, one-by-one seconds, identical maps)."""
     with irs.Batch(plans) as b:
         info = b.tune()
         b.run(counts)                                      # capture + first replay
@@ -404,12 +404,43 @@ def bench_batch(irs, synth, torch, stream):
     torch.cuda.synchronize()
     ts = time.perf_counter() - ts
     same = all(torch.equal(a, c) for a, c in zip(batched, counts))
+    return info, tb, ts, same
+
+
+def bench_batch(irs, synth, torch, stream):
+    """The 64-map batch (kappa_*, gamma ~ U[0.1, 0.8], kappa_c in {0, 0.2},
+    N_* = 10^U[3, 5], 1024^2..4096^2 px): one tuned graph launch against the
+    same maps launched one after another.  Interpolated at 100 rays/px (every
+    map's level 2, then one persistent level-3 queue); and the FP32 direct sum
+    with the tuner's tile shape, at 1 ray/px (the stated 100 rays/px would
+    take ~190 s of direct sums)."""
+    out = {}
+    t0 = time.perf_counter()
+    plans, counts = _batch_plans(irs, synth, torch, stream, "interp", "fp64")
+    rays = sum(p.n_rays for p in plans)
+    log(f"batch: {len(plans)} maps, {rays:.3e} rays, set up in {time.perf_counter() - t0:.1f} s")
+    info, tb, ts, same = _batch_vs_sequential(irs, torch, plans, counts)
     for p in plans:
         p.close()
-    log(f"batch: graph {tb:.2f} s, one by one {ts:.2f} s, identical {same}")
-    return {"maps": len(plans), "rays": rays, "method": "interp", "precision": "fp64",
-            "batched_rays_per_s": rays / tb, "sequential_rays_per_s": rays / ts,
-            "speedup": ts / tb, "identical_to_sequential": same, "tuned": info}
+    log(f"batch interp: graph {tb:.3f} s, one by one {ts:.3f} s, identical {same}, {info}")
+    out.update({"maps": len(plans), "rays": rays, "method": "interp", "precision": "fp64",
+                "batched_rays_per_s": rays / tb, "sequential_rays_per_s": rays / ts,
+                "seconds_batched": tb, "seconds_sequential": ts,
+                "speedup": ts / tb, "identical_to_sequential": same, "tuned": info})
+    plans, counts = _batch_plans(irs, synth, torch, stream, "direct", "fp32", rays_per_pixel=1.0)
+    rays_d = sum(p.n_rays for p in plans)
+    pairs = sum(p.n_rays * p.geometry["n_lens"] for p in plans)
+    info, tb, ts, same = _batch_vs_sequential(irs, torch, plans, counts)
+    for p in plans:
+        p.close()
+    log(f"batch direct fp32 (1 ray/px): graph {tb:.3f} s, one by one {ts:.3f} s, "
+        f"identical {same}, {pairs / tb:.3e} pairs/s, {info}")
+    out["direct_fp32"] = {"rays_per_pixel": 1.0, "rays": rays_d, "pairs": pairs,
+                          "seconds_batched": tb, "seconds_sequential": ts,
+                          "batched_pairs_per_s": pairs / tb, "speedup": ts / tb,
+                          "identical_to_sequential": same, "tuned": info,
+                          "note": "N_av reduced from 100 to 1 so that the direct sums fit the run"}
+    return out
 
 
 def host_threads():

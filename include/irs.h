@@ -294,14 +294,23 @@ typedef struct {
     int32_t direct_variant;       /* FP32 direct tile shape: 0 = 4 rays/lane x 512 lenses
                                      per LDS stage, 1 = 8 x 256, 2 = 16 x 128          */
     int32_t blocks_per_cu;        /* persistent workgroups per compute unit (direct)  */
-    int32_t band_rows;            /* level-1 rows per level-2 band (interpolation)    */
+    int32_t band_rows;            /* level-1 rows per level-2 band (interpolation,     */
+                                  /* 0: every map's whole level-2 field at once)        */
     int32_t tuned;                /* 1 if the settings came from the autotuner         */
     int32_t from_cache;           /* 1 if they were read from the tuning cache         */
     int64_t work_items;           /* queue items of the persistent launch (direct)     */
     double  tune_ms;              /* time the autotuner spent measuring                */
+    int32_t whole_maps;           /* interpolation: 1 if every map's level-2 field is  */
+                                  /* resident at once and level 3 runs in launches of  */
+                                  /* several maps each                                 */
+    int32_t maps_per_launch;      /* ... maps per level-3 launch (1..6)                */
 } irs_batch_info;
 
 /*
+ * Environment: IRS_BATCH_BANDS set (to anything but "0") when a batch is
+ * created keeps an interpolated batch band by band per map (no whole-map
+ * level 2); IRS_TUNE_CACHE names the tuning cache (irs_batch_tune).
+ *
  * irs_batch_create -- group n plans (the motivation: the many maps needed to
  * sample lens-model parameters, Sec. 4) into one batch.  All plans must share
  * method, precision and device, and for the direct method the mass kind
@@ -315,8 +324,10 @@ irs_status irs_batch_create(const irs_plan_t *plans, int32_t n, void *hip_stream
 /*
  * irs_batch_tune -- choose the batch's launch settings by measurement on this
  * device: for the direct method the tile shape and the persistent grid size,
- * timed on the heaviest map's first tiles; for the interpolation the band
- * height, timed on one band of the heaviest map.  cache_path (or, if NULL,
+ * timed on the heaviest map's first tiles; for the interpolation the maps per
+ * level-3 launch (1, 2 or 6), timed on the six heaviest maps (or, when the
+ * maps' level-2 fields do not fit at once, the band height, timed on one
+ * band of the heaviest map).  cache_path (or, if NULL,
  * the IRS_TUNE_CACHE environment variable; neither: no cache) is a text file
  * of "key = settings" lines keyed by method, precision, mass kind, lens-count
  * and aspect buckets; a cached key is reused without measuring.  The chosen
@@ -327,8 +338,12 @@ irs_status irs_batch_tune(irs_batch_t batch, const char *cache_path);
 /*
  * irs_batch_run -- every map of the batch in one graph launch: for the direct
  * method one persistent kernel drains a device queue of (map, ray tile)
- * items ordered longest map first; for the interpolation the maps' band
- * launches in sequence.  counts[k] is a DEVICE pointer to map k's
+ * items ordered longest map first; for the interpolation every map's level-2
+ * field (on parallel branches of the graph), then level 3 in launches of up
+ * to six maps each (every tile and corner-cell ray of those maps), longest
+ * maps first -- when all maps' level-2 fields fit in device memory at once
+ * (60% of the free memory at irs_batch_create, one mass kind); else the maps'
+ * band launches on parallel branches.  counts[k] is a DEVICE pointer to map k's
  * npix_side^2 uint32 counts, overwritten.  The graph is captured on the first
  * call and replayed while the counts pointers stay the same.  stats: n entries
  * or NULL.  Results equal per-plan irs_shoot_map bit for bit.

@@ -72,7 +72,8 @@ class BatchInfo(C.Structure):
     _fields_ = [("n_maps", C.c_int32), ("method", C.c_int32), ("precision", C.c_int32),
                 ("direct_variant", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("band_rows", C.c_int32), ("tuned", C.c_int32), ("from_cache", C.c_int32),
-                ("work_items", C.c_int64), ("tune_ms", C.c_double)]
+                ("work_items", C.c_int64), ("tune_ms", C.c_double), ("whole_maps", C.c_int32),
+                ("maps_per_launch", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -35,6 +35,11 @@ struct irs_batch_s {
     unsigned long long *d_cursor = nullptr;   // [0] cursor, then kLandedSlots landed
                                               // counters per map
     int64_t items = 0;
+    // interpolated batches: every map's level 2 resident at once and level 3
+    // in launches of several maps each (whole), else band by band per map
+    bool whole = false;
+    int maps_per_launch = 6;                 // maps per level-3 launch (whole)
+    std::vector<char> h_args;                // level-3 launch arguments, LPT order
     // interpolated batches: parallel branches of the graph (default priority)
     std::vector<hipStream_t> lanes;
     std::vector<hipEvent_t> lane_done;
@@ -42,12 +47,13 @@ struct irs_batch_s {
     // captured graph
     hipGraphExec_t exec = nullptr;
     std::vector<uint32_t *> graph_counts;
-    int graph_variant = -1, graph_bpc = -1, graph_band_rows = -1;
+    int graph_variant = -1, graph_bpc = -1, graph_band_rows = -1, graph_maps_per_launch = -1;
 };
 
 namespace {
 
 constexpr int kLanes = 4;                  // parallel branches of an interpolated batch
+constexpr double kWholeMemFraction = 0.6;  // of free device memory, for whole-map level 2
 
 void drop_graph(irs_batch_s *b)
 {
@@ -62,6 +68,12 @@ double map_cost(const irs_plan_s *p)
     if (p->params.method == IRS_DIRECT) return rays * (double)std::max<int64_t>(1, p->n_lens);
     const double l2 = (double)p->dg.n1x * p->dg.n1y * (double)std::max<int64_t>(1, p->n_lens);
     return rays * 40.0 + l2 * 300.0;
+}
+
+// level-2 work of a whole map (expansions of its cells against its lenses)
+double map_level2_cost(const irs_plan_s *p)
+{
+    return (double)p->dg.n1x * p->dg.n1y * (double)std::max<int64_t>(1, p->n_lens);
 }
 
 // Tables of the direct queue for the current variant: maps in LPT order.
@@ -86,6 +98,22 @@ irs_status build_direct_tables(irs_batch_s *b, uint32_t *const *counts)
     return IRS_OK;
 }
 
+// Level-3 launch arguments of every map (whole batches), LPT order.
+irs_status build_map_args(irs_batch_s *b, uint32_t *const *counts)
+{
+    const int n = (int)b->plans.size();
+    const size_t sz = interp_map_args_bytes();
+    b->h_args.assign(sz * n, 0);
+    for (int k = 0; k < n; ++k) {
+        const int m = b->order[k];
+        irs_status st = interp_map_args(b->plans[m], counts ? counts[m] : nullptr,
+                                        b->d_cursor + 1 + (size_t)m * kLandedSlots,
+                                        b->h_args.data() + sz * k);
+        if (st != IRS_OK) return st;
+    }
+    return IRS_OK;
+}
+
 // Enqueue the whole batch on b->stream (capturable: kernels only).
 irs_status enqueue_all(irs_batch_s *b, uint32_t *const *counts)
 {
@@ -101,7 +129,9 @@ irs_status enqueue_all(irs_batch_s *b, uint32_t *const *counts)
         return launch_direct_queue(b->stream, b->precision, b->unit, b->variant, b->d_maps,
                                    b->d_item_start, n, b->d_cursor, b->bpc * b->n_cu);
     // the maps run on parallel branches (fork from the batch stream, join back);
-    // longest first, each onto the branch with the least work so far
+    // longest first, each onto the branch with the least work so far.  Queue
+    // batches: the branches compute the maps' level-2 fields, then one
+    // launches of several maps each shoot every map's rays.
     const int nl = (int)b->lanes.size();
     IRS_HIP(hipEventRecord(b->fork, b->stream));
     for (int l = 0; l < nl; ++l) IRS_HIP(hipStreamWaitEvent(b->lanes[l], b->fork, 0));
@@ -110,7 +140,15 @@ irs_status enqueue_all(irs_batch_s *b, uint32_t *const *counts)
         const int m = b->order[k];
         irs_plan_s *p = b->plans[m];
         const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[l] += map_cost(p);
+        load[l] += b->whole ? map_level2_cost(p) : map_cost(p);
+        if (b->whole) {
+            hipStream_t saved = p->stream;
+            p->stream = b->lanes[l];
+            st = interp_level2_whole(p);
+            p->stream = saved;
+            if (st != IRS_OK) return st;
+            continue;
+        }
         RaySel sel{};
         sel.stats = nullptr;
         sel.row0 = 0;
@@ -129,11 +167,20 @@ irs_status enqueue_all(irs_batch_s *b, uint32_t *const *counts)
         IRS_HIP(hipEventRecord(b->lane_done[l], b->lanes[l]));
         IRS_HIP(hipStreamWaitEvent(b->stream, b->lane_done[l], 0));
     }
+    if (b->whole)
+        return launch_interp_maps(b->stream, b->unit, b->h_args.data(), n, b->maps_per_launch);
     return IRS_OK;
 }
 
 irs_status prepare_interp(irs_batch_s *b)
 {
+    if (b->whole) {
+        for (irs_plan_s *p : b->plans) {
+            irs_status st = interp_prepare_whole(p);
+            if (st != IRS_OK) return st;
+        }
+        return IRS_OK;
+    }
     for (irs_plan_s *p : b->plans) {
         if (b->band_rows > 0) {
             const int64_t row_bytes = (int64_t)p->dg.n1x * p->dg.q * p->dg.q * 10 * 8;
@@ -265,6 +312,49 @@ irs_status time_interp(irs_batch_s *b, int rows, uint32_t *scratch, double &ms)
     return st;
 }
 
+// level 3 of the heaviest min(n, 6) maps in launches of per_launch maps each
+// (their level 2 computed first, outside the timing)
+irs_status time_whole(irs_batch_s *b, int per_launch, uint32_t *scratch, double &ms)
+{
+    const int n = std::min<int>((int)b->plans.size(), 6);
+    const size_t sz = interp_map_args_bytes();
+    std::vector<char> args(sz * n);
+    irs_status st = IRS_OK;
+    for (int k = 0; k < n && st == IRS_OK; ++k) {
+        irs_plan_s *p = b->plans[b->order[k]];
+        hipStream_t saved = p->stream;
+        p->stream = b->stream;
+        st = interp_prepare_whole(p);
+        if (st == IRS_OK) st = interp_level2_whole(p);
+        p->stream = saved;
+        // every map counts into the scratch map: only the time matters here
+        if (st == IRS_OK) st = interp_map_args(p, scratch, b->d_cursor + 1, args.data() + sz * k);
+    }
+    if (st != IRS_OK) return st;
+    hipEvent_t e0, e1;
+    IRS_HIP(hipEventCreate(&e0));
+    IRS_HIP(hipEventCreate(&e1));
+    ms = 0.0;
+    for (int rep = 0; rep < 2 && st == IRS_OK; ++rep) {     // first run warms up
+        st = (hipEventRecord(e0, b->stream) == hipSuccess) ? IRS_OK : IRS_E_DEVICE;
+        if (st == IRS_OK) st = launch_interp_maps(b->stream, b->unit, args.data(), n, per_launch);
+        if (st == IRS_OK && hipEventRecord(e1, b->stream) != hipSuccess) st = IRS_E_DEVICE;
+        if (st == IRS_OK && hipEventSynchronize(e1) != hipSuccess) st = IRS_E_DEVICE;
+        float f = 0.0f;
+        if (st == IRS_OK) (void)hipEventElapsedTime(&f, e0, e1);
+        ms = f;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int k = 0; k < n; ++k) {
+        irs_plan_s *p = b->plans[b->order[k]];
+        p->coef_c0 = -1;
+        p->coef_c1 = -2;
+    }
+    if (st != IRS_OK) set_error("autotuner: timing launch failed");
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -332,6 +422,22 @@ irs_status irs_batch_create(const irs_plan_t *plans, int32_t n, void *hip_stream
             if (e == hipSuccess) b->lane_done.push_back(le);
         }
     }
+    if (e == hipSuccess && b->method == IRS_INTERP) {
+        // every map's level 2 at once if it fits comfortably and the maps
+        // share a mass kind (one kernel instance for their level 3)
+        size_t free_b = 0, total_b = 0;
+        int64_t need = 0;
+        bool same_mass = true;
+        for (int k = 0; k < n; ++k) {
+            need += interp_whole_map_bytes(plans[k]);
+            same_mass = same_mass && plans[k]->unit_mass == p0->unit_mass;
+        }
+        e = hipMemGetInfo(&free_b, &total_b);
+        const char *off = std::getenv("IRS_BATCH_BANDS");
+        b->whole = e == hipSuccess && same_mass && !(off && *off && std::strcmp(off, "0") != 0) &&
+                   (double)need <= kWholeMemFraction * (double)free_b;
+        if (b->whole) b->band_rows = 0;
+    }
     if (e == hipSuccess) e = hipMalloc(&b->d_maps, sizeof(DirectArgs) * n);
     if (e == hipSuccess) e = hipMalloc(&b->d_item_start, sizeof(int64_t) * (n + 1));
     if (e == hipSuccess)
@@ -360,12 +466,15 @@ irs_status irs_batch_tune(irs_batch_t b, const char *cache_path)
     const std::string key = tune_key(b);
     std::string val;
     if (!path.empty() && cache_lookup(path, key, val)) {
-        int v = -1, bpc = -1, rows = -1;
-        if (std::sscanf(val.c_str(), "variant=%d bpc=%d band_rows=%d", &v, &bpc, &rows) == 3 &&
-            v >= 0 && v < kDirectVariants && bpc > 0 && rows >= 0) {
+        int v = -1, bpc = -1, rows = -1, mpl = 6;
+        const int got = std::sscanf(val.c_str(), "variant=%d bpc=%d band_rows=%d maps_per_launch=%d",
+                                    &v, &bpc, &rows, &mpl);
+        if (got >= 3 && v >= 0 && v < kDirectVariants && bpc > 0 && rows >= 0 && mpl > 0 &&
+            (rows == 0) == b->whole) {
             b->variant = v;
             b->bpc = bpc;
             b->band_rows = rows;
+            b->maps_per_launch = mpl;
             b->tuned = b->from_cache = true;
             for (irs_plan_s *p : b->plans) p->direct_variant = v;
             drop_graph(b);
@@ -401,6 +510,16 @@ irs_status irs_batch_tune(irs_batch_t b, const char *cache_path)
                 b->bpc = bpc;
             }
         }
+    } else if (b->whole) {
+        for (int per : {1, 2, 6}) {
+            double ms = 0.0;
+            st = time_whole(b, per, scratch, ms);
+            if (st != IRS_OK) break;
+            if (ms < best) {
+                best = ms;
+                b->maps_per_launch = per;
+            }
+        }
     } else {
         const int64_t n1y = heavy->dg.n1y;
         for (int rows : {1, 4, 16}) {
@@ -422,9 +541,9 @@ irs_status irs_batch_tune(irs_batch_t b, const char *cache_path)
     for (irs_plan_s *p : b->plans) p->direct_variant = b->variant;
     drop_graph(b);
     if (!path.empty()) {
-        char buf[96];
-        std::snprintf(buf, sizeof buf, "variant=%d bpc=%d band_rows=%d", b->variant, b->bpc,
-                      b->band_rows);
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "variant=%d bpc=%d band_rows=%d maps_per_launch=%d",
+                      b->variant, b->bpc, b->band_rows, b->maps_per_launch);
         cache_store(path, key, buf);
     }
     set_error("");
@@ -447,12 +566,14 @@ irs_status irs_batch_run(irs_batch_t b, uint32_t *const *counts, irs_map_stats *
         }
     const bool same = b->exec && b->graph_variant == b->variant && b->graph_bpc == b->bpc &&
                       b->graph_band_rows == b->band_rows &&
+                      b->graph_maps_per_launch == b->maps_per_launch &&
                       std::equal(b->graph_counts.begin(), b->graph_counts.end(), counts);
     irs_status st = IRS_OK;
     if (!same) {
         drop_graph(b);
         if (b->method == IRS_DIRECT) st = build_direct_tables(b, counts);
         else st = prepare_interp(b);
+        if (st == IRS_OK && b->whole) st = build_map_args(b, counts);
         if (st != IRS_OK) return st;
         hipGraph_t graph = nullptr;
         IRS_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
@@ -473,6 +594,7 @@ irs_status irs_batch_run(irs_batch_t b, uint32_t *const *counts, irs_map_stats *
         b->graph_variant = b->variant;
         b->graph_bpc = b->bpc;
         b->graph_band_rows = b->band_rows;
+        b->graph_maps_per_launch = b->maps_per_launch;
     }
     hipEvent_t e0, e1;
     IRS_HIP(hipEventCreate(&e0));
@@ -538,6 +660,8 @@ irs_status irs_batch_get_info(irs_batch_t b, irs_batch_info *out)
     for (const irs_plan_s *p : b->plans) items += direct_items(p, b->variant);
     out->work_items = b->method == IRS_DIRECT ? items : 0;
     out->tune_ms = b->tune_ms;
+    out->whole_maps = b->whole ? 1 : 0;
+    out->maps_per_launch = b->whole ? b->maps_per_launch : 0;
     return IRS_OK;
 }
 

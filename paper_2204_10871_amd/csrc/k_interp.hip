@@ -1120,6 +1120,12 @@ struct L3Map {
     int64_t *pixo;                  //   ... null
     uint32_t *counts;               // BIN: the map
     unsigned long long *landed;     // BIN: landed-ray counters
+    // batches (whole maps): tiles and the corner cells' blocks of rays
+    int32_t nty;                    // row tiles
+    int32_t ncorner;                // corner cells with rays (<= 4)
+    int64_t tiles;                  // nty * (ntx padded to a multiple of the XCDs)
+    int64_t corner[4][4];           // their ray columns [0], [1) and rows [2], [3)
+    int64_t corner_items[5];        // prefix of the corners' blocks of kThreads rays
 };
 
 // One tile of rays: columns tcol[tx] (one per lane) by rows trow[ty]
@@ -1320,28 +1326,24 @@ __global__ __launch_bounds__(kThreads, 5) void k_level3(L3Map m, int32_t ty0, in
     level3_tile<UNIT, BIN>(m, tx, ty0 + (int32_t)(blockIdx.x / (uint32_t)ntx_pad), s_hist, s_box);
 }
 
-// Rays of one of the rectangle's four corner cells (corner column cxc), which
-// k_level3 leaves out: the sheet's series does not converge over a corner
-// cell, so these rays take its closed form.  One ray per lane over ray
-// columns [i0, i1) and ray rows [j0, j1); nearby lenses one by one
-// (near_term), the level-2 series, the sheet's closed form, beta, the pixel.
-// BIN: global adds into counts and the landed counters; otherwise the
-// per-ray outputs of rays in [ray_first, ray_last).
+// Ray idx of one of the rectangle's four corner cells (ray columns [i0, i1),
+// rows [j0, j1)), which k_level3 leaves out: the sheet's series does not
+// converge over a corner cell, so these rays take its closed form.  Nearby
+// lenses one by one (near_term), the level-2 series, the sheet's closed
+// form, beta, the pixel.  BIN: a global add into counts and the landed
+// counters; otherwise the per-ray outputs of rays in [ray_first, ray_last).
+// Called by every lane of a wave.
 template <bool UNIT, bool BIN>
-__global__ __launch_bounds__(kThreads) void k_level3_corner(
-    DevGeom g, const double2 *__restrict__ lxy, const double *__restrict__ lm,
-    const int32_t *__restrict__ cell_start, const RowInfo *__restrict__ rows,
-    const double *__restrict__ coef, int32_t cy0, int64_t i0, int64_t i1, int64_t j0, int64_t j1,
-    int64_t ray_first, int64_t ray_last, double *a1o, double *a2o, int64_t *pixo,
-    uint32_t *counts, unsigned long long *landed)
+__device__ __forceinline__ void level3_corner_ray(const L3Map &m, int64_t i0, int64_t i1,
+                                                  int64_t j0, int64_t j1, int64_t idx)
 {
+    const DevGeom &g = m.g;
     const int64_t ncol = i1 - i0;
-    const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const bool inside = idx < ncol * (j1 - j0);
     const int64_t i = inside ? i0 + idx % ncol : i0;
-    const RowInfo &rk = rows[inside ? j0 + idx / ncol : j0];
+    const RowInfo &rk = m.rows[inside ? j0 + idx / ncol : j0];
     const int64_t r = rk.base + i;
-    const bool valid = inside && r >= ray_first && r < ray_last;
+    const bool valid = inside && r >= m.ray_first && r < m.ray_last;
     const int64_t nxq = (int64_t)g.n1x * g.q;
     const int64_t gx = floor_div((2 * i + 1) * nxq, 2 * g.nx);
     const int32_t cx = (int32_t)(gx / g.q), cy = rk.cy;
@@ -1354,14 +1356,15 @@ __global__ __launch_bounds__(kThreads) void k_level3_corner(
     const int32_t xl = cx > 0 ? cx - 1 : 0, xh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
     const int32_t yl = cy > 0 ? cy - 1 : 0, yh = cy < g.n1y - 1 ? cy + 1 : g.n1y - 1;
     for (int32_t row = yl; row <= yh; ++row) {
-        const int32_t pe = cell_start[row * g.n1x + xh + 1];
-        for (int32_t q_ = cell_start[row * g.n1x + xl]; q_ < pe; ++q_) {
-            const double2 z = lxy[q_];
+        const int32_t pe = m.cell_start[row * g.n1x + xh + 1];
+        for (int32_t q_ = m.cell_start[row * g.n1x + xl]; q_ < pe; ++q_) {
+            const double2 z = m.lxy[q_];
             const double d1 = t1 - z.x;
-            near_term(d1, fma(d1, d1, kNearTiny), rk.t2, z.y, UNIT ? 1.0 : lm[q_], n1, n2);
+            near_term(d1, fma(d1, d1, kNearTiny), rk.t2, z.y, UNIT ? 1.0 : m.lm[q_], n1, n2);
         }
     }
-    const double2 *cp = (const double2 *)(coef + ((int64_t)(rk.gy - cy0 * g.q) * nxq + gx) * 10);
+    const double2 *cp =
+        (const double2 *)(m.coef + ((int64_t)(rk.gy - m.cy0 * g.q) * nxq + gx) * 10);
     double Ar = cp[4].x, Ai = cp[4].y;
 #pragma unroll
     for (int o = 3; o >= 0; --o) {
@@ -1378,16 +1381,73 @@ __global__ __launch_bounds__(kThreads) void k_level3_corner(
     pixel_pair(g, xs1, xs2, px, py);
     if (BIN) {
         const bool bin = valid && px >= 0;
-        if (bin) atomicAdd(&counts[py * g.npix + px], 1u);
+        if (bin) atomicAdd(&m.counts[py * g.npix + px], 1u);
         const uint64_t got = __ballot(bin);
-        if (__lane_id() == 0 && got) landed_add(landed, (unsigned long long)__popcll(got));
+        if (__lane_id() == 0 && got) landed_add(m.landed, (unsigned long long)__popcll(got));
     } else if (valid) {
         const double s2 = g.kappa_star * rk.hi;
-        const int64_t o = r - ray_first;
-        if (a1o) a1o[o] = fma(g.kpg, t1, n1) + (Ar - s1);
-        if (a2o) a2o[o] = fma(g.kmg, rk.t2, n2) - (Ai + s2);
-        if (pixo) pixo[o] = px < 0 ? -1 : (int64_t)py * g.npix + px;
+        const int64_t o = r - m.ray_first;
+        if (m.a1o) m.a1o[o] = fma(g.kpg, t1, n1) + (Ar - s1);
+        if (m.a2o) m.a2o[o] = fma(g.kmg, rk.t2, n2) - (Ai + s2);
+        if (m.pixo) m.pixo[o] = px < 0 ? -1 : (int64_t)py * g.npix + px;
     }
+}
+
+// One corner cell's rays of a map, one per lane.
+template <bool UNIT, bool BIN>
+__global__ __launch_bounds__(kThreads) void k_level3_corner(L3Map m, int64_t i0, int64_t i1,
+                                                            int64_t j0, int64_t j1)
+{
+    level3_corner_ray<UNIT, BIN>(m, i0, i1, j0, j1,
+                                 (int64_t)blockIdx.x * kThreads + threadIdx.x);
+}
+
+// A batch's level 3: up to kGroupMaps maps per launch, their arguments in the
+// launch's own argument block (kernel arguments are read through the
+// constant address space and may be reloaded at will, which keeps the tile
+// routine within five waves' registers; a table in ordinary device memory
+// does not).  Workgroup b takes tile b of the maps' tiles laid end to end,
+// each map's column tiles padded to a multiple of the XCDs as for one map.
+constexpr int kGroupMaps = 6;
+
+struct L3Group {
+    L3Map m[kGroupMaps];
+    int64_t start[kGroupMaps + 1];       // prefix of the maps' (padded) tiles
+    int64_t cstart[kGroupMaps + 1];      // prefix of the maps' corner blocks
+    int32_t n;
+};
+
+template <bool UNIT>
+__global__ __launch_bounds__(kThreads, 5) void k_level3_group(L3Group grp)
+{
+    __shared__ uint32_t s_hist[kHistCap];
+    __shared__ int s_box[kThreads / kWave][5];
+    const int64_t bt = blockIdx.x;
+    int32_t k = 0;
+    while (k + 1 < grp.n && grp.start[k + 1] <= bt) ++k;
+    const L3Map &m = grp.m[k];
+    const int64_t local = bt - grp.start[k];
+    const int32_t ntx_pad = (m.ntx + kXcds - 1) / kXcds * kXcds;
+    const int32_t tx = (int32_t)(local % ntx_pad);
+    if (tx >= m.ntx) return;                               // padding (block-uniform)
+    level3_tile<UNIT, true>(m, tx, (int32_t)(local / ntx_pad), s_hist, s_box);
+}
+
+// The same maps' corner-cell rays: block b takes kThreads rays of one
+// corner cell (the maps' corner blocks laid end to end).
+template <bool UNIT>
+__global__ __launch_bounds__(kThreads) void k_level3_group_corners(L3Group grp)
+{
+    const int64_t bt = blockIdx.x;
+    int32_t k = 0;
+    while (k + 1 < grp.n && grp.cstart[k + 1] <= bt) ++k;
+    const L3Map &m = grp.m[k];
+    const int64_t ci = bt - grp.cstart[k];
+    int c = 0;
+    while (c + 1 < m.ncorner && m.corner_items[c + 1] <= ci) ++c;
+    level3_corner_ray<UNIT, true>(m, m.corner[c][0], m.corner[c][1], m.corner[c][2],
+                                  m.corner[c][3],
+                                  (ci - m.corner_items[c]) * kThreads + threadIdx.x);
 }
 
 // first ray row j with level2_row(j) >= G (level2_row is non-decreasing)
@@ -1953,17 +2013,43 @@ double level3_flops(irs_plan_s *p, int64_t j0, int64_t j1)
 
 namespace {
 
-// k_level3_corner over the rays of rows [jA, jB) (level-1 rows c0..c1, whose
-// coefficients are resident from level-1 row band0) in the rectangle's corner
-// cells
-irs_status launch_corners(irs_plan_s *p, const RaySel &sel, int32_t band0, int64_t c0, int64_t c1,
-                          int64_t jA, int64_t jB)
+// The launch arguments of a plan's level 3 over rows [jr0, jr1) with the
+// coefficients resident from level-1 row cy0 (queue fields left empty).
+L3Map map_args(const irs_plan_s *p, const RaySel &sel, int32_t cy0, int64_t jr0, int64_t jr1)
+{
+    L3Map m{};
+    m.g = p->dg;
+    m.lxy = (const double2 *)p->d_xy;
+    m.lm = p->d_m;
+    m.cell_start = p->d_cell_start;
+    m.rows = (const RowInfo *)p->d_rows;
+    m.coef = p->d_coef;
+    m.tcol = p->d_tcol;
+    m.trow = p->d_trow;
+    m.cy0 = cy0;
+    m.ntx = (int32_t)p->h_tcol.size();
+    m.jr0 = jr0;
+    m.jr1 = jr1;
+    m.ray_first = sel.ray_first;
+    m.ray_last = sel.ray_last;
+    m.a1o = sel.alpha1;
+    m.a2o = sel.alpha2;
+    m.pixo = sel.pixel;
+    m.counts = sel.counts;
+    m.landed = sel.landed;
+    return m;
+}
+
+// The rectangle's corner cells that hold rays of rows [jA, jB): ray columns
+// [c[0], c[1]) and rows [c[2], c[3]) each; returns their number.
+int corner_blocks(const irs_plan_s *p, int64_t jA, int64_t jB, int64_t c[4][4])
 {
     const DevGeom &g = p->dg;
     const irs_geometry_info &gi = p->geo.info;
+    int n = 0;
+    if (!g.sheet) return 0;
     const int64_t cys[2] = {0, g.n1y - 1}, cxs[2] = {0, g.n1x - 1};
     for (int a = 0; a < (g.n1y > 1 ? 2 : 1); ++a) {
-        if (cys[a] < c0 || cys[a] > c1) continue;
         int64_t ja, jb;
         level1_span(gi, 1, cys[a], ja, jb);
         ja = std::max(ja, jA);
@@ -1972,27 +2058,154 @@ irs_status launch_corners(irs_plan_s *p, const RaySel &sel, int32_t band0, int64
         for (int b = 0; b < (g.n1x > 1 ? 2 : 1); ++b) {
             int64_t ia, ib;
             level1_span(gi, 0, cxs[b], ia, ib);
-            const int64_t n = (ib - ia) * (jb - ja);
-            if (n <= 0) continue;
-            const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
-#define IRS_L3C(U, B)                                                                         \
-    hipLaunchKernelGGL((k_level3_corner<U, B>), dim3(nb), dim3(kThreads), 0, p->stream, g,    \
-                       (const double2 *)p->d_xy, p->d_m, p->d_cell_start,                     \
-                       (const RowInfo *)p->d_rows, p->d_coef, band0, ia, ib, ja, jb,          \
-                       sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2, sel.pixel,         \
-                       sel.counts, sel.landed)
-            const bool bin = sel.counts != nullptr;
-            if (p->unit_mass) {
-                if (bin) IRS_L3C(true, true);
-                else IRS_L3C(true, false);
-            } else {
-                if (bin) IRS_L3C(false, true);
-                else IRS_L3C(false, false);
-            }
-#undef IRS_L3C
-            IRS_HIP(hipGetLastError());
+            if (ib <= ia) continue;
+            c[n][0] = ia;
+            c[n][1] = ib;
+            c[n][2] = ja;
+            c[n][3] = jb;
+            ++n;
         }
     }
+    return n;
+}
+
+// k_level3_corner over the rays of rows [jA, jB) in the rectangle's corner
+// cells (m: the band's launch arguments)
+irs_status launch_corners(irs_plan_s *p, const L3Map &m, int64_t jA, int64_t jB)
+{
+    int64_t c[4][4];
+    const int nc = corner_blocks(p, jA, jB, c);
+    const bool bin = m.counts != nullptr;
+    for (int k = 0; k < nc; ++k) {
+        const int64_t n = (c[k][1] - c[k][0]) * (c[k][3] - c[k][2]);
+        const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
+#define IRS_L3C(U, B)                                                                        \
+    hipLaunchKernelGGL((k_level3_corner<U, B>), dim3(nb), dim3(kThreads), 0, p->stream, m,   \
+                       c[k][0], c[k][1], c[k][2], c[k][3])
+        if (p->unit_mass) {
+            if (bin) IRS_L3C(true, true);
+            else IRS_L3C(true, false);
+        } else {
+            if (bin) IRS_L3C(false, true);
+            else IRS_L3C(false, false);
+        }
+#undef IRS_L3C
+        IRS_HIP(hipGetLastError());
+    }
+    return IRS_OK;
+}
+
+// The super (and mid) rows that level-1 rows [cyA, cyB] need, in one launch
+// each (a band's own rows fill a fraction of the chip); bands then find them
+// cached.  Each row's expansion is the same whatever the launch.
+irs_status level2_tree_rows(irs_plan_s *p, int64_t cyA, int64_t cyB, CallStats *cs)
+{
+    if (level2_order(p) <= 0 || super_order(p) <= 0) return IRS_OK;
+    hipStream_t s = p->stream;
+    const int32_t ks = super_side(p), km = mid_side(p);
+    if (cs) {
+        irs_status st = cs->begin(s, 0);
+        if (st != IRS_OK) return st;
+    }
+    double fl = 0.0;
+    irs_status st = km > 0 ? ensure_mid_rows(p, cyA / km, cyB / km, cs ? &fl : nullptr)
+                           : ensure_super_rows(p, cyA / ks, cyB / ks, cs ? &fl : nullptr);
+    if (st != IRS_OK) return st;
+    if (cs) {
+        cs->level2_expand_flops += fl;
+        cs->level2_flops += fl;
+        if ((st = cs->end(s)) != IRS_OK) return st;
+    }
+    return IRS_OK;
+}
+
+// The level-2 coefficients of level-1 rows [c0, c1] into p->d_coef (from row
+// c0): the cell expansions and the points' series.  The tree rows they need
+// must be cached (level2_tree_rows).
+irs_status level2_band(irs_plan_s *p, int64_t c0, int64_t c1, CallStats *cs)
+{
+    const DevGeom &g = p->dg;
+    hipStream_t s = p->stream;
+    const int32_t nl = (int32_t)p->n_lens;
+    const int64_t q = g.q;
+    const int64_t row_pts = (int64_t)g.n1x * q * q;            // level-2 points per level-1 row
+    const int P = level2_order(p);
+    if (cs) {
+        irs_status st = cs->begin(s, 0);
+        if (st != IRS_OK) return st;
+        cs->n_level2++;
+        cs->level2_points += (c1 - c0 + 1) * row_pts;
+        const std::vector<int32_t> &hc = p->h_cell_start;
+        auto block = [&](int64_t cx, int64_t cy, int64_t r) {   // lenses in a (2r+1)^2 block
+            const int64_t xl = std::max<int64_t>(0, cx - r), xh = std::min<int64_t>(g.n1x - 1, cx + r);
+            int64_t n = 0;
+            for (int64_t row = std::max<int64_t>(0, cy - r); row <= std::min<int64_t>(g.n1y - 1, cy + r); ++row)
+                n += hc[row * g.n1x + xh + 1] - hc[row * g.n1x + xl];
+            return n;
+        };
+        for (int64_t cy = c0; cy <= c1; ++cy)
+            for (int64_t cx = 0; cx < g.n1x; ++cx) {
+                const int64_t b3 = block(cx, cy, 1);
+                cs->level2_pairs += q * q * (p->n_lens - b3);
+                if (P == 0) {
+                    const double f = 44.0 * (double)(q * q * (p->n_lens - b3));
+                    cs->level2_flops += f;
+                    cs->level2_expand_flops += f;
+                } else {
+                    const int64_t b7 = block(cx, cy, kRing);
+                    cs->level2_flops += (double)(q * q) * (44.0 * (double)(b7 - b3) + 60.0 * P);
+                }
+            }
+    }
+    if (P == 0) {
+        const unsigned nb2 = (unsigned)((c1 - c0 + 1) * g.n1x);
+        if (p->unit_mass)
+            hipLaunchKernelGGL(k_level2<true>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,
+                               p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
+        else
+            hipLaunchKernelGGL(k_level2<false>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,
+                               p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
+    } else {
+        const int32_t nxb = (g.n1x + kCellsPerBlock - 1) / kCellsPerBlock;
+        // lens chunks (one level) are a property of the plan, so results
+        // do not depend on how a map is cut into calls
+        const int32_t nchunk = level2_chunks(p);
+        // the sheet's series is in the cell expansions when they come
+        // from the super-cell path (launch_level2_expand folds it)
+        const int32_t fold = super_order(p) > 0 ? 1 : 0;
+        const unsigned nbB = (unsigned)((c1 - c0 + 1) * nxb);
+        double fl = 0.0;
+        irs_status st3 = launch_level2_expand(p, c0, c1, cs ? &fl : nullptr, true);
+        if (st3 != IRS_OK) return st3;
+        if (cs) {
+            cs->level2_expand_flops += fl;
+            cs->level2_flops += fl;
+        }
+#define IRS_L2L(U, PP)                                                                        \
+    do {                                                                                      \
+        if (cs && (st2 = cs->end(s)) != IRS_OK) return st2;                                  \
+        if (cs && (st2 = cs->begin(s, 2)) != IRS_OK) return st2;                             \
+        hipLaunchKernelGGL((k_level2_points<U, PP>), dim3(nbB), dim3(kThreads), 0, s, g,      \
+                           p->d_x, p->d_y, p->d_m, p->d_cell_start, (int32_t)c0, nxb, nchunk, \
+                           fold, p->d_part, p->d_coef);                                       \
+    } while (0)
+        irs_status st2 = IRS_OK;
+        if (p->unit_mass) {
+            if (P == 32) IRS_L2L(true, 32);
+            else IRS_L2L(true, 48);
+        } else {
+            if (P == 32) IRS_L2L(false, 32);
+            else IRS_L2L(false, 48);
+        }
+#undef IRS_L2L
+    }
+    IRS_HIP(hipGetLastError());
+    if (cs) {
+        irs_status st = cs->end(s);
+        if (st != IRS_OK) return st;
+    }
+    p->coef_c0 = c0;
+    p->coef_c1 = c1;
     return IRS_OK;
 }
 
@@ -2002,10 +2215,8 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
 {
     const DevGeom &g = p->dg;
     hipStream_t s = p->stream;
-    const int32_t nl = (int32_t)p->n_lens;
     if (sel.row1 <= sel.row0) return IRS_OK;
     const int64_t q = g.q;
-    const int64_t row_pts = (int64_t)g.n1x * q * q;            // level-2 points per level-1 row
     const int64_t cyA = level2_row_host(g, sel.row0) / q;
     const int64_t cyB = level2_row_host(g, sel.row1 - 1) / q;  // inclusive
     const int64_t want = cyB - cyA + 1;
@@ -2019,109 +2230,17 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
     const int64_t ntx = (int64_t)p->h_tcol.size();
     const int64_t ntx_pad = (ntx + kXcds - 1) / kXcds * kXcds;
     CallStats *cs = sel.stats;
-    if (level2_order(p) > 0 && super_order(p) > 0 &&
-        !(p->coef_c0 <= cyA && cyB <= p->coef_c1)) {
-        // the super (and mid) rows of every band of the call in one launch each
-        // (a band's own rows fill a fraction of the chip); the bands then find
-        // them cached.  Each row's expansion is the same whatever the launch.
-        const int32_t ks = super_side(p), km = mid_side(p);
-        if (cs) {
-            irs_status st = cs->begin(s, 0);
-            if (st != IRS_OK) return st;
-        }
-        double fl = 0.0;
-        irs_status st = km > 0 ? ensure_mid_rows(p, cyA / km, cyB / km, cs ? &fl : nullptr)
-                               : ensure_super_rows(p, cyA / ks, cyB / ks, cs ? &fl : nullptr);
-        if (st != IRS_OK) return st;
-        if (cs) {
-            cs->level2_expand_flops += fl;
-            cs->level2_flops += fl;
-            if ((st = cs->end(s)) != IRS_OK) return st;
-        }
+    if (!(p->coef_c0 <= cyA && cyB <= p->coef_c1)) {
+        st0 = level2_tree_rows(p, cyA, cyB, cs);
+        if (st0 != IRS_OK) return st0;
     }
     for (int64_t c0 = cyA; c0 <= cyB; c0 += step) {
         const int64_t c1 = std::min(cyB, c0 + step - 1);
         if (!(p->coef_c0 <= c0 && c1 <= p->coef_c1)) {
             // the band's level-2 coefficients are not resident: compute them
-            const int P = level2_order(p);
-            if (cs) {
-                irs_status st = cs->begin(s, 0);
-                if (st != IRS_OK) return st;
-                cs->n_level2++;
-                cs->level2_points += (c1 - c0 + 1) * row_pts;
-                const std::vector<int32_t> &hc = p->h_cell_start;
-                auto block = [&](int64_t cx, int64_t cy, int64_t r) {   // lenses in a (2r+1)^2 block
-                    const int64_t xl = std::max<int64_t>(0, cx - r), xh = std::min<int64_t>(g.n1x - 1, cx + r);
-                    int64_t n = 0;
-                    for (int64_t row = std::max<int64_t>(0, cy - r); row <= std::min<int64_t>(g.n1y - 1, cy + r); ++row)
-                        n += hc[row * g.n1x + xh + 1] - hc[row * g.n1x + xl];
-                    return n;
-                };
-                for (int64_t cy = c0; cy <= c1; ++cy)
-                    for (int64_t cx = 0; cx < g.n1x; ++cx) {
-                        const int64_t b3 = block(cx, cy, 1);
-                        cs->level2_pairs += q * q * (p->n_lens - b3);
-                        if (P == 0) {
-                            const double f = 44.0 * (double)(q * q * (p->n_lens - b3));
-                            cs->level2_flops += f;
-                            cs->level2_expand_flops += f;
-                        } else {
-                            const int64_t b7 = block(cx, cy, kRing);
-                            cs->level2_flops += (double)(q * q) * (44.0 * (double)(b7 - b3) + 60.0 * P);
-                        }
-                    }
-            }
-            if (P == 0) {
-                const unsigned nb2 = (unsigned)((c1 - c0 + 1) * g.n1x);
-                if (p->unit_mass)
-                    hipLaunchKernelGGL(k_level2<true>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,
-                                       p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
-                else
-                    hipLaunchKernelGGL(k_level2<false>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,
-                                       p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
-            } else {
-                const int32_t nxb = (g.n1x + kCellsPerBlock - 1) / kCellsPerBlock;
-                // lens chunks (one level) are a property of the plan, so results
-                // do not depend on how a map is cut into calls
-                const int32_t nchunk = level2_chunks(p);
-                // the sheet's series is in the cell expansions when they come
-                // from the super-cell path (launch_level2_expand folds it)
-                const int32_t fold = super_order(p) > 0 ? 1 : 0;
-                const unsigned nbB = (unsigned)((c1 - c0 + 1) * nxb);
-                double fl = 0.0;
-                irs_status st3 = launch_level2_expand(p, c0, c1, cs ? &fl : nullptr, true);
-                if (st3 != IRS_OK) return st3;
-                if (cs) {
-                    cs->level2_expand_flops += fl;
-                    cs->level2_flops += fl;
-                }
-#define IRS_L2L(U, PP)                                                                        \
-    do {                                                                                      \
-        if (cs && (st2 = cs->end(s)) != IRS_OK) return st2;                                  \
-        if (cs && (st2 = cs->begin(s, 2)) != IRS_OK) return st2;                             \
-        hipLaunchKernelGGL((k_level2_points<U, PP>), dim3(nbB), dim3(kThreads), 0, s, g,      \
-                           p->d_x, p->d_y, p->d_m, p->d_cell_start, (int32_t)c0, nxb, nchunk, \
-                           fold, p->d_part, p->d_coef);                                       \
-    } while (0)
-                irs_status st2 = IRS_OK;
-                if (p->unit_mass) {
-                    if (P == 32) IRS_L2L(true, 32);
-                    else IRS_L2L(true, 48);
-                } else {
-                    if (P == 32) IRS_L2L(false, 32);
-                    else IRS_L2L(false, 48);
-                }
-#undef IRS_L2L
-            }
-            IRS_HIP(hipGetLastError());
-            if (cs) {
-                irs_status st = cs->end(s);
-                if (st != IRS_OK) return st;
-            }
-            p->coef_c0 = c0;
-            p->coef_c1 = c1;
+            st0 = level2_band(p, c0, c1, cs);
+            if (st0 != IRS_OK) return st0;
         }
-        const int32_t band0 = (int32_t)p->coef_c0;
         const int64_t jA = std::max(sel.row0, first_row_at(g, c0 * q));
         const int64_t jB = std::min(sel.row1, first_row_at(g, (c1 + 1) * q));
         if (jB <= jA) continue;
@@ -2134,24 +2253,7 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
                                             [](const TileSpan &t, int64_t v) { return t.a < v; }) -
                            tr.begin();
         const int64_t nty = tb - ta;
-        L3Map m{};
-        m.g = g;
-        m.lxy = (const double2 *)p->d_xy;
-        m.lm = p->d_m;
-        m.cell_start = p->d_cell_start;
-        m.rows = (const RowInfo *)p->d_rows;
-        m.coef = p->d_coef;
-        m.tcol = p->d_tcol;
-        m.trow = p->d_trow;
-        m.cy0 = band0;
-        m.ntx = (int32_t)ntx;
-        m.ray_first = sel.ray_first;
-        m.ray_last = sel.ray_last;
-        m.a1o = sel.alpha1;
-        m.a2o = sel.alpha2;
-        m.pixo = sel.pixel;
-        m.counts = sel.counts;
-        m.landed = sel.landed;
+        L3Map m = map_args(p, sel, (int32_t)p->coef_c0, 0, 0);
         const int64_t max_ty = std::max<int64_t>(1, ((int64_t)1 << 24) / ntx_pad);
         for (int64_t t0 = 0; t0 < nty; t0 += max_ty) {
             const int64_t t1 = std::min(nty, t0 + max_ty);
@@ -2179,15 +2281,101 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
             }
 #undef IRS_L3
             IRS_HIP(hipGetLastError());
-            if (t1 == nty && g.sheet) {
+            if (t1 == nty) {
                 // the band's rays in the rectangle's corner cells
-                irs_status st = launch_corners(p, sel, band0, c0, c1, jA, jB);
+                irs_status st = launch_corners(p, m, jA, jB);
                 if (st != IRS_OK) return st;
             }
             if (cs) {
                 irs_status st = cs->end(s);
                 if (st != IRS_OK) return st;
             }
+        }
+    }
+    return IRS_OK;
+}
+
+// ---- a batch's level 3 as one persistent launch -----------------------------
+
+size_t interp_map_args_bytes() { return sizeof(L3Map); }
+
+int64_t interp_whole_map_bytes(const irs_plan_s *p)
+{
+    int64_t coef_row = 0, part_row = 0;
+    interp_band_row_bytes(p, coef_row, part_row);
+    return (int64_t)p->dg.n1y * (coef_row + part_row);
+}
+
+irs_status interp_prepare_whole(irs_plan_s *p)
+{
+    p->coef_budget = (int64_t)p->dg.n1y * level2_row_bytes(p);
+    return interp_prepare(p);
+}
+
+irs_status interp_level2_whole(irs_plan_s *p)
+{
+    irs_status st = level2_tree_rows(p, 0, p->dg.n1y - 1, nullptr);
+    if (st != IRS_OK) return st;
+    return level2_band(p, 0, p->dg.n1y - 1, nullptr);
+}
+
+irs_status interp_map_args(irs_plan_s *p, uint32_t *counts, unsigned long long *landed,
+                           void *out)
+{
+    if (!p->d_rows || p->coef_rows_cap < p->dg.n1y) {
+        set_error("internal: a batch map's whole-map level-2 buffers are missing");
+        return IRS_E_INVALID;
+    }
+    RaySel sel{};
+    sel.ray_first = 0;
+    sel.ray_last = p->dg.nx * p->dg.ny;
+    sel.counts = counts;
+    sel.landed = landed;
+    L3Map m = map_args(p, sel, 0, 0, p->dg.ny);
+    m.nty = (int32_t)p->h_trow.size();
+    m.tiles = (int64_t)m.nty * ((m.ntx + kXcds - 1) / kXcds * kXcds);
+    m.ncorner = corner_blocks(p, 0, p->dg.ny, m.corner);
+    m.corner_items[0] = 0;
+    for (int c = 0; c < 4; ++c) {
+        const int64_t rays =
+            c < m.ncorner ? (m.corner[c][1] - m.corner[c][0]) * (m.corner[c][3] - m.corner[c][2])
+                          : 0;
+        m.corner_items[c + 1] = m.corner_items[c] + (rays + kThreads - 1) / kThreads;
+    }
+    *(L3Map *)out = m;
+    return IRS_OK;
+}
+
+irs_status launch_interp_maps(hipStream_t s, bool unit, const void *args, int32_t n,
+                              int32_t per_launch)
+{
+    const L3Map *maps = (const L3Map *)args;
+    per_launch = std::max(1, std::min(per_launch, kGroupMaps));
+    for (int32_t k0 = 0; k0 < n; k0 += per_launch) {
+        L3Group grp{};
+        grp.n = std::min(per_launch, n - k0);
+        for (int32_t k = 0; k < grp.n; ++k) {
+            grp.m[k] = maps[k0 + k];
+            grp.start[k + 1] = grp.start[k] + maps[k0 + k].tiles;
+            grp.cstart[k + 1] = grp.cstart[k] + maps[k0 + k].corner_items[4];
+        }
+        if (grp.start[grp.n] > 0) {
+            if (unit)
+                hipLaunchKernelGGL(k_level3_group<true>, dim3((unsigned)grp.start[grp.n]),
+                                   dim3(kThreads), 0, s, grp);
+            else
+                hipLaunchKernelGGL(k_level3_group<false>, dim3((unsigned)grp.start[grp.n]),
+                                   dim3(kThreads), 0, s, grp);
+            IRS_HIP(hipGetLastError());
+        }
+        if (grp.cstart[grp.n] > 0) {
+            if (unit)
+                hipLaunchKernelGGL(k_level3_group_corners<true>, dim3((unsigned)grp.cstart[grp.n]),
+                                   dim3(kThreads), 0, s, grp);
+            else
+                hipLaunchKernelGGL(k_level3_group_corners<false>, dim3((unsigned)grp.cstart[grp.n]),
+                                   dim3(kThreads), 0, s, grp);
+            IRS_HIP(hipGetLastError());
         }
     }
     return IRS_OK;

@@ -185,6 +185,20 @@ void interp_band_row_bytes(const irs_plan_s *p, int64_t &coef_row, int64_t &part
 // table, the super- and mid-cell expansions and their partials exist at
 // whole-map size.  Otherwise an error with a message.
 irs_status interp_tables_ready(irs_plan_s *p);
+// Interpolated batches with every map's level 2 resident at once: the bytes
+// a map's whole-map level-2 buffers take; allocate them (before a capture);
+// compute a map's whole level-2 field on its stream; a map's level-3 launch
+// arguments (interp_map_args_bytes() bytes into out); and the level 3 of n
+// maps (args: their arguments, in launch order) in launches of up to
+// per_launch maps each (at most 6), every map's tiles and corner-cell rays.
+int64_t interp_whole_map_bytes(const irs_plan_s *p);
+irs_status interp_prepare_whole(irs_plan_s *p);
+irs_status interp_level2_whole(irs_plan_s *p);
+size_t interp_map_args_bytes();
+irs_status interp_map_args(irs_plan_s *p, uint32_t *counts, unsigned long long *landed,
+                           void *out);
+irs_status launch_interp_maps(hipStream_t s, bool unit, const void *args, int32_t n,
+                              int32_t per_launch);
 // Fill kernel (graph-safe zeroing): n 32-bit words.
 irs_status launch_zero(hipStream_t s, void *ptr, size_t n_words);
 

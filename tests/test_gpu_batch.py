@@ -57,19 +57,26 @@ def _maps(irs, n, method, precision, seed=3, npix=64, n_rays=150_000, with_oracl
 _TOL = {("direct", "fp64"): 1e-12, ("direct", "fp32"): 1e-5, ("interp", "fp64"): 1e-4}
 
 
-@pytest.mark.parametrize("method,precision", [("direct", "fp64"), ("direct", "fp32"),
-                                              ("interp", "fp64")])
-def test_batch_matches_oracle(irs, method, precision):
+@pytest.mark.parametrize("method,precision,whole", [("direct", "fp64", None),
+                                                    ("direct", "fp32", None),
+                                                    ("interp", "fp64", 1), ("interp", "fp64", 0)])
+def test_batch_matches_oracle(irs, method, precision, whole, monkeypatch):
     """Every map of a batch run in one graph launch against the FP64 direct
     definition (O-1): every ray's alpha and pixel (the plan's per-ray call,
     whose pixels the batch map must histogram to exactly), and the batch's
-    counts: bit-exact on every pixel no mismatched ray touches, rel-L1."""
+    counts: bit-exact on every pixel no mismatched ray touches, rel-L1.
+    Interpolated batches both with every map's level 2 at once (level 3 in
+    multi-map launches) and band by band."""
     import torch
+    if whole == 0:
+        monkeypatch.setenv("IRS_BATCH_BANDS", "1")
     plans, refs = _maps(irs, 7, method, precision, with_oracle=True)
     counts = [torch.empty(p.params.npix_side ** 2, dtype=torch.int32, device="cuda:0")
               for p in plans]
     with irs.Batch(plans) as b:
-        b.tune()
+        info = b.tune()
+        if whole is not None:
+            assert info["whole_maps"] == whole, info
         st = b.run(counts)
         torch.cuda.synchronize()
     tol = _TOL[(method, precision)]
