@@ -276,6 +276,17 @@ irs_status irs_plan_set_direct_variant(irs_plan_t plan, int32_t variant);
 /* irs_plan_geometry -- the geometry the plan uses (n_lens = the plan's lens count). */
 irs_status irs_plan_geometry(irs_plan_t plan, irs_geometry_info *out);
 
+/*
+ * irs_plan_level1 -- the plan's packing of the lenses into level-1 cells (Sec.
+ * 2.4 flow chart, "Lenses packed into level-1 grids").  Host buffers owned by
+ * the caller: cell_start[n1x n1y + 1], cell c = cy n1x + cx holding packed
+ * lenses [cell_start[c], cell_start[c+1]); order[n_lens], order[k] = input
+ * index of packed lens k.  Inside a cell the packed order is the input order
+ * (the packing is a stable sort by cell).  order may be NULL when the plan has
+ * no lenses.  IRS_E_INVALID on a NULL argument, IRS_E_HIP if the copy fails.
+ */
+irs_status irs_plan_level1(irs_plan_t plan, int32_t *cell_start, int32_t *order);
+
 /* irs_free -- release a plan and all its device memory.  NULL is ignored. */
 void irs_free(irs_plan_t plan);
 

@@ -37,7 +37,7 @@ import numpy as np
 from scipy import integrate, special
 
 KATZ_C = 3.05        # Katz, Balbus & Paczynski (1986), Eq. 13
-MODIFIED_C = 1.454   # the paper's Eq. 14
+MODIFIED_C = 1.454   # the paper's Eq. 11
 
 
 def x_max(n, c):

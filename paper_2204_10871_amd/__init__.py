@@ -194,6 +194,15 @@ class Plan:
     def n_rays(self) -> int:
         return self.geometry["nx"] * self.geometry["ny"]
 
+    def level1(self):
+        """The level-1 packing: (cell_start[n1x*n1y + 1], order[n_lens]) as int32
+        host arrays; packed lens k is input lens order[k]."""
+        g = self.geometry
+        cs = np.empty(g["n1x"] * g["n1y"] + 1, np.int32)
+        order = np.empty(max(g["n_lens"], 1), np.int32)
+        _check(self._lib.irs_plan_level1(self._h, _vp(cs), _vp(order)), "irs_plan_level1")
+        return cs, order[:g["n_lens"]]
+
     def deflect_grid(self, first_ray: int, n: int, alpha=True, pixel=True):
         """Per-ray alpha1, alpha2 (FP64) and pixel index (-1 off map), host arrays."""
         a1 = np.empty(n) if alpha else None

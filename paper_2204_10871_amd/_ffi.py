@@ -22,7 +22,8 @@ IRS_LEARN_FIELDS = 24
 # every function include/irs.h declares
 EXPORTS = ("irs_geometry", "irs_level1_span", "irs_source_side", "irs_plan", "irs_deflect_grid",
            "irs_shoot_rows", "irs_shoot_rows_noalloc", "irs_shoot_map",
-           "irs_plan_set_direct_variant", "irs_plan_geometry", "irs_free", "irs_last_error",
+           "irs_plan_set_direct_variant", "irs_plan_geometry", "irs_plan_level1", "irs_free",
+           "irs_last_error",
            "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info",
            "irs_batch_free", "irs_learn_defaults", "irs_learn", "irs_learn_set", "irs_learn_get",
            "irs_learn_corners", "irs_learn_samples", "irs_mlp_forward", "irs_mlp_loss_grad")
@@ -137,6 +138,7 @@ def load():
     lib.irs_shoot_rows_noalloc.argtypes = [vp, i64, i64, vp, P(i64)]
     lib.irs_shoot_map.argtypes = [vp, vp, P(MapStats), u64]
     lib.irs_plan_geometry.argtypes = [vp, P(GeometryInfo)]
+    lib.irs_plan_level1.argtypes = [vp, vp, vp]
     lib.irs_plan_set_direct_variant.argtypes = [vp, C.c_int32]
     lib.irs_batch_create.argtypes = [P(vp), C.c_int32, vp, P(vp)]
     lib.irs_batch_tune.argtypes = [vp, C.c_char_p]
@@ -159,7 +161,7 @@ def load():
     lib.irs_last_error.restype = C.c_char_p
     for name in ("irs_geometry", "irs_level1_span", "irs_source_side", "irs_plan",
                  "irs_deflect_grid", "irs_shoot_rows", "irs_shoot_rows_noalloc", "irs_shoot_map",
-                 "irs_plan_geometry", "irs_plan_set_direct_variant",
+                 "irs_plan_geometry", "irs_plan_level1", "irs_plan_set_direct_variant",
                  "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info",
                  "irs_learn_defaults", "irs_learn", "irs_learn_set", "irs_learn_get",
                  "irs_learn_corners", "irs_learn_samples", "irs_mlp_forward", "irs_mlp_loss_grad"):

@@ -118,6 +118,7 @@ void release(irs_plan_s *p)
     dev_free(p->d_m);
     dev_free(p->d_cell_start);
     dev_free(p->d_cxy);
+    dev_free(p->d_order);
     dev_free(p->d_xy);
     dev_free(p->d_rows);
     dev_free(p->d_tcol);
@@ -390,6 +391,22 @@ irs_status irs_plan_geometry(irs_plan_t plan, irs_geometry_info *out)
         return IRS_E_INVALID;
     }
     *out = plan->geo.info;
+    return IRS_OK;
+}
+
+irs_status irs_plan_level1(irs_plan_t plan, int32_t *cell_start, int32_t *order)
+{
+    if (!plan || !cell_start || (plan->n_lens > 0 && !order)) {
+        set_error("irs_plan_level1: NULL argument");
+        return IRS_E_INVALID;
+    }
+    std::copy(plan->h_cell_start.begin(), plan->h_cell_start.end(), cell_start);
+    if (plan->n_lens > 0) {
+        IRS_HIP(hipMemcpyAsync(order, plan->d_order, sizeof(int32_t) * (size_t)plan->n_lens,
+                               hipMemcpyDeviceToHost, plan->stream));
+        IRS_HIP(hipStreamSynchronize(plan->stream));
+    }
+    set_error("");
     return IRS_OK;
 }
 

@@ -996,15 +996,18 @@ irs_status set_smem_limits()
 template <typename T>
 struct DevBuf {
     T *p = nullptr;
+    size_t n = 0;                         // elements
     ~DevBuf() { dev_free(p); }
-    irs_status alloc(size_t n)
+    irs_status alloc(size_t count)
     {
-        if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
+        if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
             (void)hipGetLastError();
             p = nullptr;
+            n = 0;
             set_error("cannot allocate device memory for the learned interpolant");
             return IRS_E_NOMEM;
         }
+        n = count;
         return IRS_OK;
     }
 };
@@ -1278,10 +1281,31 @@ struct TrainBufs {
     }
 };
 
+// The furthest element each training kernel indexes, against the buffers:
+// k_mlp_train writes act[(5 kHd) bn], dz[(4 kHd + kNO) bn] and loss_part[nbt]
+// for slots up to nbt kThreads (so bn must be a multiple of kThreads);
+// k_mlp_wgrad reads slots [kc chunk16, min(bn, kc chunk16 + chunk16)) in
+// steps of 16 and writes part[nchunk kNP]; k_mlp_reduce reads what they wrote.
+bool train_extents_ok(const TrainBufs &tb, int32_t n_valid)
+{
+    const int64_t nbt = (tb.bn + kThreads - 1) / kThreads;
+    const int32_t chunk = (tb.bn + tb.nchunk - 1) / tb.nchunk;
+    const int64_t chunk16 = (chunk + 15) / 16 * 16;
+    return tb.bn > 0 && tb.bn % kThreads == 0 && n_valid >= 0 && n_valid <= tb.bn &&
+           nbt * kThreads == tb.bn && tb.act.n >= (size_t)5 * kHd * tb.bn &&
+           tb.dz.n >= (size_t)(4 * kHd + kNO) * tb.bn && tb.loss_part.n >= (size_t)nbt &&
+           tb.part.n >= (size_t)tb.nchunk * kNP && chunk16 % 16 == 0 &&
+           (int64_t)tb.nchunk * chunk16 >= tb.bn && tb.bn % 16 == 0;
+}
+
 irs_status grad_step(hipStream_t s, TrainBufs &tb, const void *wf, const void *wb, const float *theta,
                      const float *freq, const float *samples, int64_t n_samples, uint64_t base,
                      uint64_t mult, int32_t n_valid, float *grad, double *loss)
 {
+    if (!train_extents_ok(tb, n_valid)) {
+        set_error("internal: training buffers smaller than the kernels index");
+        return IRS_E_INVALID;
+    }
     const unsigned nbt = (unsigned)((tb.bn + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_mlp_train, dim3(nbt), dim3(kThreads), 0, s, (const uint4 *)wf,
                        (const uint4 *)wb, theta, freq, samples, n_samples, base, mult, n_valid, tb.bn,

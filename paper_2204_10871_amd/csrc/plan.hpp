@@ -54,6 +54,7 @@ struct irs_plan_s {
     double *d_x = nullptr, *d_y = nullptr, *d_m = nullptr;   // d_m null when unit masses
     int32_t *d_cell_start = nullptr;                         // n1x*n1y + 1
     uint32_t *d_cxy = nullptr;                               // per sorted lens: cy << 16 | cx
+    int32_t *d_order = nullptr;                              // per sorted lens: input index
     double *d_xy = nullptr;                                  // (x, y) pairs, sorted order
     std::vector<int32_t> h_cell_start;                       // host copy (work counts)
     std::vector<int64_t> h_cell_cols;                        // ray columns per cell column

@@ -6,6 +6,7 @@ edges in both directions, several level-1 cells and level-2 bands."""
 import numpy as np
 import pytest
 
+import oracle as orc
 import synth
 from gpu_common import Case, check_map, rel_err
 
@@ -347,3 +348,62 @@ def test_single_ray_calls_equal_row_calls(irs):
             for i in cols:
                 a1, a2, px = pl.deflect_grid(j * g["nx"] + i, 1)
                 assert (a1[0], a2[0], px[0]) == (ra1[i], ra2[i], rpx[i]), (j, i)
+
+
+def _clustered_lenses(rect, n, n_pile, seed):
+    """n lenses uniform over rect, of which n_pile (spread through the input
+    order) sit inside a square of side 2e-4 well inside one level-1 cell."""
+    L = synth.uniform_lenses(n, rect, seed)
+    x, y = L.x.copy(), L.y.copy()
+    cx = rect[0] + 0.3137 * (rect[1] - rect[0])
+    cy = rect[2] + 0.6071 * (rect[3] - rect[2])
+    idx = np.arange(0, n, n // n_pile)[:n_pile]
+    u = synth.uniform_lenses(n_pile, (-1e-4, 1e-4, -1e-4, 1e-4), seed + 1)
+    x[idx] = cx + u.x
+    y[idx] = cy + u.y
+    return synth.Lenses(x, y, None)
+
+
+def _edge_lenses(geo, n, seed):
+    """Lenses on level-1 cell edges (and the rect's own edges) and uniform ones."""
+    L = synth.uniform_lenses(n, geo.rect, seed)
+    x, y = L.x.copy(), L.y.copy()
+    w1 = (geo.rect[1] - geo.rect[0]) / geo.n1x
+    h1 = (geo.rect[3] - geo.rect[2]) / geo.n1y
+    k = np.arange(n // 2)
+    x[: n // 2] = geo.rect[0] + (k % (geo.n1x + 1)) * w1
+    y[: n // 2] = geo.rect[2] + (k % (geo.n1y + 1)) * h1
+    return synth.Lenses(np.minimum(x, geo.rect[1]), np.minimum(y, geo.rect[3]), None)
+
+
+@pytest.mark.parametrize("kind", ["uniform_ragged", "clustered", "cell_edges", "one_lens"])
+def test_level1_packing_equals_oracle(irs, kind):
+    """The packing (Sec. 2.4 flow chart, lenses into level-1 cells) equals the
+    oracle's stable counting sort index for index: same cell_start, and inside
+    every cell the lenses in input order.  "clustered" puts a third of the
+    lenses into one cell, "uniform_ragged" needs three 8-bit digit passes
+    (about 1e5 cells) with a lens count that is no multiple of the 1024-lens
+    sort block."""
+    kw = (0.45, 0.05, 0.45, 25.0, 64)
+    g0 = Case(*kw, n_rays=10_000, n_lens=8).geo
+    if kind == "uniform_ragged":
+        c = Case(*kw, n_rays=10_000, n_lens=100_003, seed=51)
+    elif kind == "clustered":
+        c = Case(*kw, n_rays=10_000, lenses=_clustered_lenses(g0.rect, 90_000, 30_000, 52))
+    elif kind == "cell_edges":
+        g1 = Case(*kw, n_rays=10_000, n_lens=20_000).geo
+        c = Case(*kw, n_rays=10_000, lenses=_edge_lenses(g1, 20_000, 53))
+        assert (c.geo.n1x, c.geo.n1y) == (g1.n1x, g1.n1y)
+    else:
+        c = Case(*kw, n_rays=10_000, lenses=synth.Lenses(np.array([1.5]), np.array([-2.0]), None))
+    ncell = c.geo.n1x * c.geo.n1y
+    say(f"level1 {kind}: N*={c.lenses.n} cells={ncell}")
+    cs_ref, perm_ref = orc.level1(c.geo, c.lenses)
+    with c.plan("interp", "fp64") as pl:
+        cs, order = pl.level1()
+    assert np.array_equal(cs.astype(np.int64), cs_ref)
+    assert np.array_equal(order.astype(np.int64), perm_ref)
+    if kind == "clustered":
+        assert np.diff(cs_ref).max() >= 30_000
+    if kind == "uniform_ragged":
+        assert ncell > 1 << 16
