@@ -99,6 +99,7 @@ DevGeom make_dev_geom(const HostGeometry &hg)
     d.inv_dpix = 1.0 / g.dpix;
     d.sheet_f = -hg.kappa_star / M_PI;
     d.npix = (int32_t)hg.npix;
+    d.npix_f = (double)hg.npix;
     d.sheet = hg.sheet ? (hg.circle ? 2 : 1) : 0;
     d.n1x = (int32_t)g.n1x;
     d.n1y = (int32_t)g.n1y;
@@ -121,6 +122,7 @@ void release(irs_plan_s *p)
     dev_free(p->d_order);
     dev_free(p->d_xy);
     dev_free(p->d_rows);
+    dev_free(p->d_cols);
     dev_free(p->d_tcol);
     dev_free(p->d_trow);
     dev_free(p->d_coef);

@@ -23,6 +23,7 @@ struct DevGeom {
     double w2, h2;              // level-2 subcell sides (w1/q, h1/q)
     double inv_dpix;            // npix/S
     double sheet_f;             // -kappa_*/pi: the sheet's deflection over (I1, I2)
+    double npix_f;              // npix as a double
 };
 
 constexpr int kWave = 64;

@@ -103,6 +103,12 @@ irs_status derive_geometry(const irs_params &p, int64_t n_lens, HostGeometry &ou
         err = "level-2 grid finer than 256 points per level-1 cell side";
         return IRS_E_INVALID;
     }
+    if (p.method != IRS_DIRECT && dx1 > 1e24) {
+        // the level-3 kernel takes products of four squared lens-ray distances
+        // (at most 18 dx1^2 each) and needs them far from overflow
+        err = "level-1 cells wider than 1e24: the interpolation needs narrower cells";
+        return IRS_E_INVALID;
+    }
 
     irs_geometry_info &g = out.info;
     g.kappa = kappa;

@@ -824,6 +824,16 @@ constexpr int kXcds = 8;               // MI355X: workgroups go to the 8 XCDs in
 constexpr int kL3RowsPerWave = kL3Rows / (kThreads / kWave);
 constexpr int kHistCap = 6144;
 
+// A level-3 workgroup's LDS: the histogram over the tile's landed-pixel box
+// (row pitch a power of two) with one more bin that takes the rays it does
+// not bin, the box (through LDS atomics) and the landed-ray count.
+struct L3Lds {
+    uint32_t hist[kHistCap + 1];
+    uint32_t bmin[2];         // min x, min y of landed pixels (unsigned: -1 never wins)
+    int32_t bmax[2];          // max x, max y (signed: -1 never wins)
+    uint32_t landed;
+};
+
 // One ray row of the plan's ray grid, as the level-3 kernel reads it.
 struct alignas(32) RowInfo {
     double t2;        // theta_2 of the row
@@ -851,6 +861,10 @@ __device__ __forceinline__ int64_t floor_div(int64_t num, int64_t den)
 // lens-ray distance that occurs) keeps rr > 0 where a lens sits exactly on
 // a ray, whose term is then exactly 0 because d = 0; it changes no other rr.
 constexpr double kNearTiny = 1e-300;
+// Largest level-1 cell side a plan may have: every nearby lens then lies
+// within 3 sqrt(2) kMaxCell of a ray, so rr < 1e49 and a product of four
+// rr stays below kGroupMax.
+constexpr double kMaxCell = 1e24;
 
 __device__ __forceinline__ void near_term(double d1, double d1s, double t2, double zy, double m,
                                           double &n1, double &n2)
@@ -870,9 +884,10 @@ __device__ __forceinline__ void near_term(double d1, double d1s, double t2, doub
 // prefix products P_k = rr_0 ... rr_k: m/rr_k = q P_{k-1} for k = G-1 down to
 // 1, q taking q rr_k = m/P_{k-1} after each step, and m/rr_0 = the last q.
 // Each quotient carries at most about 2G + 4 units of rounding.  Where p lies
-// outside [1e-200, 1e200] (a lens exactly on a ray, where rr is kNearTiny,
-// or rr beyond that range) the quotients are taken one by one.
-constexpr double kGroupMin = 1e-200, kGroupMax = 1e200;
+// at or below 1e-200 (a lens on or extremely close to a ray) the quotients are
+// taken one by one, with kNearTiny added to each rr.  Cells no wider than
+// kMaxCell keep p below 1e200, far from overflow, so p needs no upper test.
+constexpr double kGroupMin = 1e-200;
 // rows of a lane that share one reciprocal per lens: four keeps the group's
 // products in few enough registers for five waves per SIMD
 constexpr int kNearGroup = 4;
@@ -881,6 +896,7 @@ template <int G>
 __device__ __forceinline__ void near_group(double d1, double d1s, const double *t2s, double zy,
                                            double m, double *n1s, double *n2s)
 {
+    // d1s = d1^2 here (no kNearTiny: that is added on the one-by-one path)
     double d2[G], rr[G], pre[G], w[G];
 #pragma unroll
     for (int k = 0; k < G; ++k) {
@@ -891,7 +907,7 @@ __device__ __forceinline__ void near_group(double d1, double d1s, const double *
 #pragma unroll
     for (int k = 1; k < G; ++k) pre[k] = pre[k - 1] * rr[k];
     const double p = pre[G - 1];
-    if (__builtin_expect(p > kGroupMin && p < kGroupMax, 1)) {
+    if (__builtin_expect(p > kGroupMin, 1)) {
         const double v = __builtin_amdgcn_rcp(p);
         const double y = m * v;
         double q = fma(v, fma(-p, y, m), y);          // m / p
@@ -904,9 +920,10 @@ __device__ __forceinline__ void near_group(double d1, double d1s, const double *
     } else {
 #pragma unroll
         for (int k = 0; k < G; ++k) {
-            const double v = __builtin_amdgcn_rcp(rr[k]);
+            const double r = fma(d2[k], d2[k], d1s + kNearTiny);
+            const double v = __builtin_amdgcn_rcp(r);
             const double y = m * v;
-            w[k] = fma(v, fma(-rr[k], y, m), y);
+            w[k] = fma(v, fma(-r, y, m), y);
         }
     }
 #pragma unroll
@@ -946,13 +963,14 @@ __device__ __forceinline__ void near_pass(const DevGeom &g, const double2 *__res
             double m = UNIT ? 1.0 : lm[q_];
             if (STRADDLE && straddle) m = (q_ >= lpb && q_ < lpe) ? m : 0.0;
             const double d1 = t1 - z.x;
-            const double d1s = fma(d1, d1, kNearTiny);
             if constexpr (RR > 1) {
+                const double d1s = d1 * d1;
                 static_assert(RR % kNearGroup == 0, "rows in whole groups");
 #pragma unroll
                 for (int h = 0; h < RR; h += kNearGroup)
                     near_group<kNearGroup>(d1, d1s, t2s + h, z.y, m, n1s + h, n2s + h);
             } else {
+                const double d1s = fma(d1, d1, kNearTiny);
 #pragma unroll
                 for (int k = 0; k < RR; ++k) near_term(d1, d1s, t2s[k], z.y, m, n1s[k], n2s[k]);
             }
@@ -964,6 +982,38 @@ __device__ __forceinline__ void near_pass(const DevGeom &g, const double2 *__res
 // cross-lane (DPP) sequences rather than LDS permutes
 __device__ __forceinline__ int wave_max(int v) { return __ockl_wfred_max_i32(v); }
 __device__ __forceinline__ uint32_t wave_min_u(uint32_t v) { return __ockl_wfred_min_u32(v); }
+
+// One ray column of the plan's ray grid, as the level-3 kernel reads it.
+struct alignas(16) ColInfo {
+    double t1;        // theta_1 of the column
+    double hr;        // t1 minus the x of its level-2 column
+    double c1;        // t1 - (kappa + gamma) t1 + kappa_* hr (sheet on) + S/2
+    double s1;        // kappa_* hr (sheet on), else 0
+    uint32_t coff;    // byte offset of the column's level-2 point in a level-2 row
+    int32_t cx;       // level-1 column
+    int64_t pad_;
+};
+
+__global__ __launch_bounds__(kThreads) void k_col_table(DevGeom g, ColInfo *cols)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= g.nx) return;
+    const int64_t nxq = (int64_t)g.n1x * g.q;
+    const int64_t gx = floor_div((2 * i + 1) * nxq, 2 * g.nx);
+    ColInfo c;
+    c.t1 = ray_x(g, i);
+    c.hr = c.t1 - level2_x(g, gx);
+    // beta_1 + S/2 of the column's rays without the lens terms: the macro
+    // term and the sheet's -kappa_* conj(h) part (the row's c2 holds the
+    // same for beta_2)
+    c.s1 = g.sheet ? g.kappa_star * c.hr : 0.0;
+    const double mac1 = g.kpg * c.t1;
+    c.c1 = ((c.t1 - mac1) + c.s1) + g.half_side;
+    c.coff = (uint32_t)gx * 10u * (uint32_t)sizeof(double);
+    c.cx = (int32_t)(gx / g.q);
+    c.pad_ = 0;
+    cols[i] = c;
+}
 
 __global__ __launch_bounds__(kThreads) void k_row_table(DevGeom g, RowInfo *rows)
 {
@@ -1011,8 +1061,8 @@ __device__ __forceinline__ void pixel_pair(const DevGeom &g, double xs1, double 
         f1 = floor(xs1 / g.dpix);
         f2 = floor(xs2 / g.dpix);
     }
-    const double n = (double)g.npix;
-    const bool in = (int)(f1 >= 0.0) & (int)(f1 < n) & (int)(f2 >= 0.0) & (int)(f2 < n);
+    // on the map: 0 <= min(f1, f2) and max(f1, f2) < npix
+    const bool in = (int)(fmin(f1, f2) >= 0.0) & (int)(fmax(f1, f2) < g.npix_f);
     ix = in ? (int32_t)f1 : -1;
     iy = in ? (int32_t)f2 : -1;
 }
@@ -1110,6 +1160,7 @@ struct L3Map {
     const double *lm;               // masses (null: unit)
     const int32_t *cell_start;
     const RowInfo *rows;            // row table
+    const ColInfo *cols;            // column table
     const double *coef;             // level-2 coefficients from level-1 row cy0
     const TileSpan *tcol, *trow;    // the plan's column and row tiles
     int32_t cy0;
@@ -1136,8 +1187,7 @@ struct L3Map {
 // or, for a box larger than the histogram, global adds by runs of equal
 // pixels down a lane's rows.  Called by every thread of the workgroup.
 template <bool UNIT, bool BIN>
-__device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t ty,
-                                            uint32_t *s_hist, int (*s_box)[5])
+__device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t ty, L3Lds *lds)
 {
     const DevGeom &g = m.g;
     const int tid = threadIdx.x;
@@ -1147,23 +1197,22 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
     const TileSpan tc = m.tcol[tx], tr = m.trow[ty];
     const int32_t ny1 = (int32_t)g.ny - 1;                          // ny < 2^31
     const int32_t jw = tr.a + wave * R;                             // the wave's first row
-    __syncthreads();                          // the LDS of an earlier tile is free again
+    if (BIN && tid == 0) {                    // one tile per workgroup: set up its LDS
+        lds->bmin[0] = lds->bmin[1] = UINT32_MAX;
+        lds->bmax[0] = lds->bmax[1] = -1;
+        lds->landed = 0u;
+    }
+    __syncthreads();
     const int32_t i32 = tc.a + lane;
     const int64_t i = i32;
     const bool in_col = i32 < tc.b;
     const int64_t nxq = (int64_t)g.n1x * g.q;
-    const int64_t gx = in_col ? floor_div((2 * i + 1) * nxq, 2 * g.nx) : 0;
-    const int32_t cx = (int32_t)gx / g.q;
-    const double t1 = ray_x(g, i);
-    const double hr = t1 - level2_x(g, gx);
-    // beta_1 + S/2 of the column's rays without the lens terms: the macro
-    // term and the sheet's -kappa_* conj(h) part (the row's c2 holds the
-    // same for beta_2)
-    const double s1 = g.sheet ? g.kappa_star * hr : 0.0;
-    const double mac1 = g.kpg * t1;
-    const double c1 = ((t1 - mac1) + s1) + g.half_side;
+    // the lane's column (lanes past the tile's end take its first column and
+    // bin nothing); what the rows need of it is read after the lens pass
+    const ColInfo *col = &m.cols[in_col ? i32 : tc.a];
+    const int32_t cx = col->cx;
+    const double t1 = col->t1;
     const int32_t xl = cx > 0 ? cx - 1 : 0, xh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
-    const uint32_t coff = (uint32_t)gx * 10u * (uint32_t)sizeof(double);   // lane's point in a row
 
     // the wave's rows jw + k, k < kt, lie in the tile; rows k0 <= k < k1 also
     // lie in [jr0, jr1), the others bin nothing
@@ -1215,7 +1264,8 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
                       row(k1 - 1).base + g.nx <= m.ray_last;
     const bool corner_col = in_col && (cx == 0 || cx == g.n1x - 1);
     const bool wave_corner = g.sheet && __ballot(corner_col) != 0;     // wave-uniform
-    const L3Lane ln{i, i32, in_col, corner_col, wave_corner, t1, hr, c1, s1, coff};
+    const L3Lane ln{i, i32, in_col, corner_col, wave_corner, t1, col->hr, col->c1, col->s1,
+                    col->coff};
     int32_t pxs[R], pys[R];
     if (full)
         level3_rows<BIN, true>(g, m.rows, m.coef, m.cy0, nxq, ln, jw, k0, k1, m.ray_first,
@@ -1225,9 +1275,10 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
                                 m.ray_last, n1s, n2s, m.a1o, m.a2o, m.pixo, pxs, pys);
     if (!BIN) return;
 
-    // bounding box of the tile's landed pixels, branch-free: a ray off the
-    // map has pixel -1, which is the largest unsigned value (never a
-    // minimum) and the smallest signed one (never a maximum)
+    // the block's box of landed pixels and its landed rays: per wave by
+    // cross-lane reductions, then across the waves by LDS atomics.  A ray not
+    // binned has pixel -1, the largest unsigned value (never a minimum) and
+    // the smallest signed one (never a maximum)
     uint32_t ux0 = UINT32_MAX, uy0 = UINT32_MAX;
     int bx1 = -1, by1 = -1, wl = 0;
 #pragma unroll
@@ -1236,28 +1287,29 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
         uy0 = min(uy0, (uint32_t)pys[k]); by1 = max(by1, pys[k]);
         wl += __popcll(__ballot(pxs[k] >= 0));              // landed rays of the wave's row
     }
-    int bx0 = (int)min(wave_min_u(ux0), (uint32_t)INT_MAX);
-    int by0 = (int)min(wave_min_u(uy0), (uint32_t)INT_MAX);
+    ux0 = wave_min_u(ux0);
+    uy0 = wave_min_u(uy0);
     bx1 = wave_max(bx1);
     by1 = wave_max(by1);
     if (lane == 0) {
-        s_box[wave][0] = bx0; s_box[wave][1] = bx1;
-        s_box[wave][2] = by0; s_box[wave][3] = by1;
-        s_box[wave][4] = wl;
+        atomicMin(&lds->bmin[0], ux0);
+        atomicMin(&lds->bmin[1], uy0);
+        atomicMax(&lds->bmax[0], bx1);
+        atomicMax(&lds->bmax[1], by1);
+        if (wl) atomicAdd(&lds->landed, (uint32_t)wl);
     }
     __syncthreads();
-    bx0 = INT_MAX; bx1 = -1; by0 = INT_MAX; by1 = -1;
-    int nblock = 0;
-#pragma unroll
-    for (int w = 0; w < kThreads / kWave; ++w) {
-        bx0 = min(bx0, s_box[w][0]); bx1 = max(bx1, s_box[w][1]);
-        by0 = min(by0, s_box[w][2]); by1 = max(by1, s_box[w][3]);
-        nblock += s_box[w][4];
-    }
+    // every lane reads the same words: uniform values, in scalar registers
+    const int bx0 = __builtin_amdgcn_readfirstlane((int)min(lds->bmin[0], (uint32_t)INT_MAX));
+    const int by0 = __builtin_amdgcn_readfirstlane((int)min(lds->bmin[1], (uint32_t)INT_MAX));
+    bx1 = __builtin_amdgcn_readfirstlane(lds->bmax[0]);
+    by1 = __builtin_amdgcn_readfirstlane(lds->bmax[1]);
+    const int nblock = __builtin_amdgcn_readfirstlane((int)lds->landed);
     if (tid == 0 && nblock) landed_add(m.landed, (unsigned long long)nblock);
     if (bx1 < 0) return;                                   // nothing landed (block-uniform)
-    const int bw = bx1 - bx0 + 1;
-    const int64_t area = (int64_t)bw * (by1 - by0 + 1);
+    // histogram rows of pitch 2^sh >= the box's width
+    const int sh = 32 - __clz(bx1 - bx0);
+    const int64_t area = (int64_t)(by1 - by0 + 1) << sh;
     uint32_t *counts = m.counts;
     if (area > kHistCap) {
         // block-uniform fallback (rays scattered, as near a lens): global
@@ -1278,37 +1330,33 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
         if (cur >= 0) atomicAdd(&counts[cur], run);
         return;
     }
-    for (int b = tid; b < area; b += kThreads) s_hist[b] = 0u;
+    const int nbin = (int)area;
+    for (int b = tid; b < nbin; b += kThreads) lds->hist[b] = 0u;
+    // bins of a lane's rays (kHistCap: not binned)
+    int lp[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+        lp[k] = pxs[k] < 0 ? kHistCap : ((pys[k] - by0) << sh) + (pxs[k] - bx0);
     __syncthreads();
     // LDS adds by runs: a lane's rays are consecutive rows of one column and
-    // mostly land in one pixel, so each run of equal bins is added once
+    // mostly land in one pixel, so each run of equal bins is added once, at
+    // its last row
     {
-        int32_t cur = -1;
-        uint32_t run = 0;
+        int first = 0;                                     // the current run's first row
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const int32_t lp = pxs[k] < 0 ? -1 : (pys[k] - by0) * bw + (pxs[k] - bx0);
-            if (lp == cur) {
-                ++run;
-                continue;
+            if (k == R - 1 || lp[k] != lp[k + 1]) {
+                atomicAdd(&lds->hist[lp[k]], (uint32_t)(k + 1 - first));
+                first = k + 1;
             }
-            if (cur >= 0) atomicAdd(&s_hist[cur], run);
-            cur = lp;
-            run = 1;
         }
-        if (cur >= 0) atomicAdd(&s_hist[cur], run);
     }
     __syncthreads();
-    // flush: bin b is (row b / bw, column b % bw) of the box; the quotient
-    // from a float estimate, corrected to the exact integer
-    const float inv_bw = 1.0f / (float)bw;
-    for (int b = tid; b < area; b += kThreads) {
-        const uint32_t v = s_hist[b];
-        if (!v) continue;
-        int row_b = (int)((float)b * inv_bw);
-        if (row_b * bw > b) --row_b;
-        else if ((row_b + 1) * bw <= b) ++row_b;
-        atomicAdd(&counts[(by0 + row_b) * g.npix + bx0 + (b - row_b * bw)], v);
+    // flush: bin b is (row b >> sh, column b & (2^sh - 1)) of the box
+    const int colmask = (1 << sh) - 1;
+    for (int b = tid; b < nbin; b += kThreads) {
+        const uint32_t v = lds->hist[b];
+        if (v) atomicAdd(&counts[(by0 + (b >> sh)) * g.npix + bx0 + (b & colmask)], v);
     }
 }
 
@@ -1319,11 +1367,10 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
 template <bool UNIT, bool BIN>
 __global__ __launch_bounds__(kThreads, 5) void k_level3(L3Map m, int32_t ty0, int32_t ntx_pad)
 {
-    __shared__ uint32_t s_hist[kHistCap];
-    __shared__ int s_box[kThreads / kWave][5];
+    __shared__ L3Lds lds;
     const int32_t tx = (int32_t)(blockIdx.x % (uint32_t)ntx_pad);
     if (tx >= m.ntx) return;                               // padding (block-uniform)
-    level3_tile<UNIT, BIN>(m, tx, ty0 + (int32_t)(blockIdx.x / (uint32_t)ntx_pad), s_hist, s_box);
+    level3_tile<UNIT, BIN>(m, tx, ty0 + (int32_t)(blockIdx.x / (uint32_t)ntx_pad), &lds);
 }
 
 // Ray idx of one of the rectangle's four corner cells (ray columns [i0, i1),
@@ -1420,8 +1467,7 @@ struct L3Group {
 template <bool UNIT>
 __global__ __launch_bounds__(kThreads, 5) void k_level3_group(L3Group grp)
 {
-    __shared__ uint32_t s_hist[kHistCap];
-    __shared__ int s_box[kThreads / kWave][5];
+    __shared__ L3Lds lds;
     const int64_t bt = blockIdx.x;
     int32_t k = 0;
     while (k + 1 < grp.n && grp.start[k + 1] <= bt) ++k;
@@ -1430,7 +1476,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_level3_group(L3Group grp)
     const int32_t ntx_pad = (m.ntx + kXcds - 1) / kXcds * kXcds;
     const int32_t tx = (int32_t)(local % ntx_pad);
     if (tx >= m.ntx) return;                               // padding (block-uniform)
-    level3_tile<UNIT, true>(m, tx, (int32_t)(local / ntx_pad), s_hist, s_box);
+    level3_tile<UNIT, true>(m, tx, (int32_t)(local / ntx_pad), &lds);
 }
 
 // The same maps' corner-cell rays: block b takes kThreads rays of one
@@ -1919,7 +1965,7 @@ std::vector<TileSpan> make_tiles(const irs_geometry_info &gi, int axis, int32_t 
 // build waits for its kernel, so work on other streams may read them at once).
 irs_status ensure_rows(irs_plan_s *p)
 {
-    if (p->d_rows) return IRS_OK;
+    if (p->d_rows) return IRS_OK;                 // set last: the tables are all there
     irs_status st = alloc_allowed(p, "the level-3 row table");
     if (st != IRS_OK) return st;
     const DevGeom &g = p->dg;
@@ -1928,18 +1974,32 @@ irs_status ensure_rows(irs_plan_s *p)
     // when a cell holds a whole tile of rows
     p->h_tcol = make_tiles(p->geo.info, 0, kWave, kWave + kWave / 2);
     p->h_trow = make_tiles(p->geo.info, 1, kL3Rows, kL3Rows);
+    dev_free(p->d_tcol);
+    dev_free(p->d_trow);
+    dev_free(p->d_cols);
+    p->d_tcol = p->d_trow = nullptr;
+    p->d_cols = nullptr;
     IRS_HIP(hipMalloc(&p->d_tcol, p->h_tcol.size() * sizeof(TileSpan)));
     IRS_HIP(hipMalloc(&p->d_trow, p->h_trow.size() * sizeof(TileSpan)));
     IRS_HIP(hipMemcpyAsync(p->d_tcol, p->h_tcol.data(), p->h_tcol.size() * sizeof(TileSpan),
                            hipMemcpyHostToDevice, p->stream));
     IRS_HIP(hipMemcpyAsync(p->d_trow, p->h_trow.data(), p->h_trow.size() * sizeof(TileSpan),
                            hipMemcpyHostToDevice, p->stream));
-    IRS_HIP(hipMalloc(&p->d_rows, (size_t)g.ny * sizeof(RowInfo)));
-    const unsigned nb = (unsigned)((g.ny + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_row_table, dim3(nb), dim3(kThreads), 0, p->stream, g,
-                       (RowInfo *)p->d_rows);
+    IRS_HIP(hipMalloc(&p->d_cols, (size_t)g.nx * sizeof(ColInfo)));
+    hipLaunchKernelGGL(k_col_table, dim3((unsigned)((g.nx + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, p->stream, g, (ColInfo *)p->d_cols);
     IRS_HIP(hipGetLastError());
-    IRS_HIP(hipStreamSynchronize(p->stream));
+    void *rows = nullptr;
+    IRS_HIP(hipMalloc(&rows, (size_t)g.ny * sizeof(RowInfo)));
+    const unsigned nb = (unsigned)((g.ny + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_row_table, dim3(nb), dim3(kThreads), 0, p->stream, g, (RowInfo *)rows);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) {
+        dev_free(rows);
+        return hip_fail(e, "the level-3 row and column tables");
+    }
+    p->d_rows = rows;
     return IRS_OK;
 }
 
@@ -1970,6 +2030,10 @@ irs_status interp_tables_ready(irs_plan_s *p)
 
 irs_status interp_prepare(irs_plan_s *p)
 {
+    if (std::max(p->dg.w1, p->dg.h1) > kMaxCell) {
+        set_error("level-1 cells wider than 1e24: the interpolation needs narrower cells");
+        return IRS_E_INVALID;
+    }
     p->coef_c0 = -1;                 // nothing resident that a replay could rely on
     p->coef_c1 = -2;
     irs_status st = ensure_rows(p);
@@ -2023,6 +2087,7 @@ L3Map map_args(const irs_plan_s *p, const RaySel &sel, int32_t cy0, int64_t jr0,
     m.lm = p->d_m;
     m.cell_start = p->d_cell_start;
     m.rows = (const RowInfo *)p->d_rows;
+    m.cols = (const ColInfo *)p->d_cols;
     m.coef = p->d_coef;
     m.tcol = p->d_tcol;
     m.trow = p->d_trow;
@@ -2254,7 +2319,9 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
                            tr.begin();
         const int64_t nty = tb - ta;
         L3Map m = map_args(p, sel, (int32_t)p->coef_c0, 0, 0);
-        const int64_t max_ty = std::max<int64_t>(1, ((int64_t)1 << 24) / ntx_pad);
+        // at most 2^23 workgroups (2^31 work-items) per launch: the dispatch's
+        // grid size in work-items is a 32-bit number
+        const int64_t max_ty = std::max<int64_t>(1, ((int64_t)1 << 23) / ntx_pad);
         for (int64_t t0 = 0; t0 < nty; t0 += max_ty) {
             const int64_t t1 = std::min(nty, t0 + max_ty);
             const unsigned nb3 = (unsigned)((t1 - t0) * ntx_pad);

@@ -66,6 +66,7 @@ struct irs_plan_s {
     double *d_mid = nullptr;              // mid-cell expansions (all rows), like d_super
     std::vector<char> mid_ok;
     void *d_rows = nullptr;               // level-3 row table (ny entries of 32 B)
+    void *d_cols = nullptr;               // level-3 column table (nx entries of 48 B)
     // level-3 tiles: column tiles of <= 64 ray columns, row tiles of <= 32 ray
     // rows, following the level-1 cells where cells are wide (tall) enough
     irs::TileSpan *d_tcol = nullptr, *d_trow = nullptr;
