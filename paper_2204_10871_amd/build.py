@@ -31,6 +31,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-ffp-contract=on",
           f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # every atomic here is issued by one lane or to lane-varying
+          # addresses; the compiler's wave-level combining of atomics only
+          # adds instructions around them
+          "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
           "-I", os.path.join(HERE, "..", "include")]
 
 

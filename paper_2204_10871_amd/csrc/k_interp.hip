@@ -1061,8 +1061,8 @@ __device__ __forceinline__ void pixel_pair(const DevGeom &g, double xs1, double 
         f1 = floor(xs1 / g.dpix);
         f2 = floor(xs2 / g.dpix);
     }
-    // on the map: 0 <= min(f1, f2) and max(f1, f2) < npix
-    const bool in = (int)(fmin(f1, f2) >= 0.0) & (int)(fmax(f1, f2) < g.npix_f);
+    const bool in = (int)(f1 >= 0.0) & (int)(f1 < g.npix_f) & (int)(f2 >= 0.0) &
+                    (int)(f2 < g.npix_f);
     ix = in ? (int32_t)f1 : -1;
     iy = in ? (int32_t)f2 : -1;
 }
@@ -1080,9 +1080,13 @@ struct L3Lane {
     uint32_t coff;             // byte offset of the lane's level-2 point in a row
 };
 
-// Rows k0 <= k < k1 of a wave (k0, k1, jw wave-uniform): Horner of the
-// level-2 series (coefficients reloaded when the level-2 row changes, a
-// wave-uniform test), the corner cells' sheet, beta + S/2 and the pixel.
+// Rows k0 <= k < k1 of a wave (k0, k1, jw wave-uniform): the level-2 series
+// (coefficients reloaded when the level-2 row changes, a wave-uniform test),
+// the corner cells' sheet, beta + S/2 and the pixel.  The series
+// A(h) = sum_k C_k h^k, h = hr + i hi, is re-expanded at each reload about the
+// lane's own column offset hr (a Taylor shift by synthetic division:
+// A = sum_j D_j (i hi)^j), so that each row evaluates a polynomial in its
+// real hi.
 // FULL: every ray of these rows lies in [ray_first, ray_last).  BIN: pixels
 // into pxs/pys (-1 for rays not binned); otherwise the per-ray outputs.
 template <bool BIN, bool FULL>
@@ -1108,18 +1112,24 @@ __device__ __forceinline__ void level3_rows(
                                                                           nxq * 10) + ln.coff);
 #pragma unroll
             for (int e = 0; e < 5; ++e) C[e] = cp[e];
+            // D_j = sum_{k >= j} binom(k, j) C_k hr^(k-j), in place
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int o = 3; o >= j; --o) {
+                    C[o].x = fma(ln.hr, C[o + 1].x, C[o].x);
+                    C[o].y = fma(ln.hr, C[o + 1].y, C[o].y);
+                }
             cgy = gy;
         }
         const double hi = rk.hi;
-        // Horner: A = C0 + h (C1 + h (C2 + h (C3 + h C4))), two fused
-        // multiply-adds per component and step; conj(A) is the far deflection
-        double Ar = C[4].x, Ai = C[4].y;
-#pragma unroll
-        for (int o = 3; o >= 0; --o) {
-            const double r = fma(Ar, ln.hr, fma(-Ai, hi, C[o].x));
-            Ai = fma(Ar, hi, fma(Ai, ln.hr, C[o].y));
-            Ar = r;
-        }
+        // A = sum_j D_j (i hi)^j with i^j = 1, i, -1, -i, 1: Horner in hi,
+        // one fused multiply-add per component and step; conj(A) is the far
+        // deflection
+        const double Ar =
+            fma(fma(fma(fma(C[4].x, hi, C[3].y), hi, -C[2].x), hi, -C[1].y), hi, C[0].x);
+        const double Ai =
+            fma(fma(fma(fma(C[4].y, hi, -C[3].x), hi, -C[2].y), hi, C[1].x), hi, C[0].y);
         // beta + S/2 = (c1, c2) - nearby lenses - conj(A)
         const double xs1 = (ln.c1 - n1s[k]) - Ar;
         const double xs2 = (rk.c2 - n2s[k]) + Ai;
@@ -1332,21 +1342,27 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
     }
     const int nbin = (int)area;
     for (int b = tid; b < nbin; b += kThreads) lds->hist[b] = 0u;
-    // bins of a lane's rays (kHistCap: not binned)
-    int lp[R];
+    // byte offsets of a lane's bins; a ray not binned (pixel -1 in both
+    // coordinates) gives a negative offset, which the unsigned minimum turns
+    // into the spare bin's
+    uint32_t lb[R];
+    const uint32_t spare = (uint32_t)kHistCap * 4u;
 #pragma unroll
-    for (int k = 0; k < R; ++k)
-        lp[k] = pxs[k] < 0 ? kHistCap : ((pys[k] - by0) << sh) + (pxs[k] - bx0);
+    for (int k = 0; k < R; ++k) {
+        const uint32_t xb = (uint32_t)(pxs[k] - bx0) * 4u;
+        lb[k] = min(((uint32_t)(pys[k] - by0) << (sh + 2)) + xb, spare);
+    }
     __syncthreads();
     // LDS adds by runs: a lane's rays are consecutive rows of one column and
     // mostly land in one pixel, so each run of equal bins is added once, at
     // its last row
     {
+        char *h = (char *)lds->hist;
         int first = 0;                                     // the current run's first row
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            if (k == R - 1 || lp[k] != lp[k + 1]) {
-                atomicAdd(&lds->hist[lp[k]], (uint32_t)(k + 1 - first));
+            if (k == R - 1 || lb[k] != lb[k + 1]) {
+                atomicAdd((uint32_t *)(h + lb[k]), (uint32_t)(k + 1 - first));
                 first = k + 1;
             }
         }
