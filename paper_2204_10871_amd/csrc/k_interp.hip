@@ -834,6 +834,7 @@ struct L3Lds {
     uint32_t landed;
 };
 
+
 // One ray row of the plan's ray grid, as the level-3 kernel reads it.
 struct alignas(32) RowInfo {
     double t2;        // theta_2 of the row
@@ -893,16 +894,13 @@ constexpr double kGroupMin = 1e-200;
 constexpr int kNearGroup = 4;
 
 template <int G>
-__device__ __forceinline__ void near_group(double d1, double d1s, const double *t2s, double zy,
-                                           double m, double *n1s, double *n2s)
+__device__ __forceinline__ void near_group_d2(double d1, double d1s, const double *d2, double m,
+                                              double *n1s, double *n2s)
 {
     // d1s = d1^2 here (no kNearTiny: that is added on the one-by-one path)
-    double d2[G], rr[G], pre[G], w[G];
+    double rr[G], pre[G], w[G];
 #pragma unroll
-    for (int k = 0; k < G; ++k) {
-        d2[k] = t2s[k] - zy;
-        rr[k] = fma(d2[k], d2[k], d1s);
-    }
+    for (int k = 0; k < G; ++k) rr[k] = fma(d2[k], d2[k], d1s);
     pre[0] = rr[0];
 #pragma unroll
     for (int k = 1; k < G; ++k) pre[k] = pre[k - 1] * rr[k];
@@ -920,7 +918,7 @@ __device__ __forceinline__ void near_group(double d1, double d1s, const double *
     } else {
 #pragma unroll
         for (int k = 0; k < G; ++k) {
-            const double r = fma(d2[k], d2[k], d1s + kNearTiny);
+            const double r = rr[k] + kNearTiny;
             const double v = __builtin_amdgcn_rcp(r);
             const double y = m * v;
             w[k] = fma(v, fma(-r, y, m), y);
@@ -931,6 +929,16 @@ __device__ __forceinline__ void near_group(double d1, double d1s, const double *
         n1s[k] = fma(w[k], d1, n1s[k]);
         n2s[k] = fma(w[k], d2[k], n2s[k]);
     }
+}
+
+template <int G>
+__device__ __forceinline__ void near_group(double d1, double d1s, const double *t2s, double zy,
+                                           double m, double *n1s, double *n2s)
+{
+    double d2[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) d2[k] = t2s[k] - zy;
+    near_group_d2<G>(d1, d1s, d2, m, n1s, n2s);
 }
 
 // Nearby lenses of RR rays in one column (t1) and RR rows (t2s) that share
@@ -978,10 +986,29 @@ __device__ __forceinline__ void near_pass(const DevGeom &g, const double2 *__res
     }
 }
 
-// whole-wave reductions (every lane active) through the device library's
-// cross-lane (DPP) sequences rather than LDS permutes
-__device__ __forceinline__ int wave_max(int v) { return __ockl_wfred_max_i32(v); }
-__device__ __forceinline__ uint32_t wave_min_u(uint32_t v) { return __ockl_wfred_min_u32(v); }
+// Reductions over each row of 16 lanes (every lane active): four DPP row
+// shifts, after which lane 15 of a row holds the row's result.  Lanes that
+// a shift leaves without a source keep the identity.
+constexpr int kDppRowShr = 0x110;   // row_shr:n is kDppRowShr + n
+template <int N>
+__device__ __forceinline__ uint32_t shr_min_u(uint32_t v)
+{
+    return min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)UINT32_MAX, (int)v, kDppRowShr + N,
+                                                        0xf, 0xf, false));
+}
+template <int N>
+__device__ __forceinline__ int shr_max(int v)
+{
+    return max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, kDppRowShr + N, 0xf, 0xf, false));
+}
+__device__ __forceinline__ uint32_t row_min_u(uint32_t v)
+{
+    return shr_min_u<8>(shr_min_u<4>(shr_min_u<2>(shr_min_u<1>(v))));
+}
+__device__ __forceinline__ int row_max(int v)
+{
+    return shr_max<8>(shr_max<4>(shr_max<2>(shr_max<1>(v))));
+}
 
 // One ray column of the plan's ray grid, as the level-3 kernel reads it.
 struct alignas(16) ColInfo {
@@ -1240,14 +1267,15 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
     double n1s[R], n2s[R], t2s[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        n1s[k] = n2s[k] = 0.0;
+        n1s[k] = 0.0;
+        n2s[k] = 0.0;
         t2s[k] = row(k).t2;              // wave-uniform: kept in scalar registers
     }
     if (k1 > k0) {                                        // wave-uniform rows
-        // level-1 columns of the wave's first and last ray (lane 0 always
-        // holds a ray column)
-        const int32_t cxa = __builtin_amdgcn_readfirstlane(cx);
-        const int32_t cxb = __builtin_amdgcn_readfirstlane(wave_max(in_col ? cx : cxa));
+        // level-1 columns of the wave's first and last ray (the tile's first
+        // and last columns: the level-1 column grows with the ray column)
+        const int32_t cxa = m.cols[tc.a].cx;
+        const int32_t cxb = m.cols[tc.b - 1].cx;
         const int32_t cl = cxa > 0 ? cxa - 1 : 0, ch = cxb < g.n1x - 1 ? cxb + 1 : g.n1x - 1;
         const bool straddle = cxa != cxb;
         const int32_t cy0r = row(0).cy;
@@ -1285,10 +1313,10 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
                                 m.ray_last, n1s, n2s, m.a1o, m.a2o, m.pixo, pxs, pys);
     if (!BIN) return;
 
-    // the block's box of landed pixels and its landed rays: per wave by
-    // cross-lane reductions, then across the waves by LDS atomics.  A ray not
-    // binned has pixel -1, the largest unsigned value (never a minimum) and
-    // the smallest signed one (never a maximum)
+    // the block's box of landed pixels and its landed rays: per row of 16
+    // lanes by cross-lane reductions, then across the rows and waves by LDS
+    // atomics.  A ray not binned has pixel -1, the largest unsigned value
+    // (never a minimum) and the smallest signed one (never a maximum)
     uint32_t ux0 = UINT32_MAX, uy0 = UINT32_MAX;
     int bx1 = -1, by1 = -1, wl = 0;
 #pragma unroll
@@ -1297,17 +1325,17 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
         uy0 = min(uy0, (uint32_t)pys[k]); by1 = max(by1, pys[k]);
         wl += __popcll(__ballot(pxs[k] >= 0));              // landed rays of the wave's row
     }
-    ux0 = wave_min_u(ux0);
-    uy0 = wave_min_u(uy0);
-    bx1 = wave_max(bx1);
-    by1 = wave_max(by1);
-    if (lane == 0) {
+    ux0 = row_min_u(ux0);
+    uy0 = row_min_u(uy0);
+    bx1 = row_max(bx1);
+    by1 = row_max(by1);
+    if (lane % 16 == 15) {
         atomicMin(&lds->bmin[0], ux0);
         atomicMin(&lds->bmin[1], uy0);
         atomicMax(&lds->bmax[0], bx1);
         atomicMax(&lds->bmax[1], by1);
-        if (wl) atomicAdd(&lds->landed, (uint32_t)wl);
     }
+    if (lane == 0 && wl) atomicAdd(&lds->landed, (uint32_t)wl);
     __syncthreads();
     // every lane reads the same words: uniform values, in scalar registers
     const int bx0 = __builtin_amdgcn_readfirstlane((int)min(lds->bmin[0], (uint32_t)INT_MAX));
