@@ -1077,14 +1077,16 @@ __device__ __forceinline__ D2 corner_sheet(const DevGeom &g, double t1, double t
 // Pixel column and row of beta from (beta_1 + S/2, beta_2 + S/2): the floor
 // of the products by 1/dpix, or, where either product lies within 1e-9 of an
 // integer, of the IEEE quotients by dpix for both (pixel_floor_shifted's
-// rule, one branch for the pair); (-1, -1) off the map.
+// rule, one branch for the pair); (-1, -1) off the map.  The floor is taken
+// as the nearest integer to the product minus 1/2 (one fused multiply-add),
+// whose distance from that integer is the edge test.
 __device__ __forceinline__ void pixel_pair(const DevGeom &g, double xs1, double xs2, int32_t &ix,
                                            int32_t &iy)
 {
-    const double q1 = xs1 * g.inv_dpix, q2 = xs2 * g.inv_dpix;
-    double f1 = floor(q1), f2 = floor(q2);
+    const double m1 = fma(xs1, g.inv_dpix, -0.5), m2 = fma(xs2, g.inv_dpix, -0.5);
+    double f1 = rint(m1), f2 = rint(m2);
     constexpr double lim = 0.5 - 1e-9;
-    if ((int)(fabs((q1 - f1) - 0.5) > lim) | (int)(fabs((q2 - f2) - 0.5) > lim)) {
+    if ((int)(fabs(m1 - f1) > lim) | (int)(fabs(m2 - f2) > lim)) {
         f1 = floor(xs1 / g.dpix);
         f2 = floor(xs2 / g.dpix);
     }
