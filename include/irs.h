@@ -293,6 +293,15 @@ void irs_free(irs_plan_t plan);
 /* irs_last_error -- message for the last failed call on this thread ("" if none). */
 const char *irs_last_error(void);
 
+/*
+ * irs_debug_fail_alloc -- fault injection for tests of the out-of-memory
+ * paths: the next `after` device allocations of the library (any thread, any
+ * plan or batch) succeed and the one after them fails as an exhausted
+ * hipMalloc would (the call returns IRS_E_NOMEM).  The failure uses the
+ * setting up; after < 0 switches it off.  Process-wide.  Returns IRS_OK.
+ */
+irs_status irs_debug_fail_alloc(int64_t after);
+
 /* ------------------------------------------------------------------------ */
 /* Batches of independent maps.                                              */
 /* ------------------------------------------------------------------------ */

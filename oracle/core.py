@@ -15,7 +15,9 @@ from .geometry import Geometry
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "irs_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# IRS_ORACLE_LIB: load a prebuilt copy instead (the sanitizer build of the tests)
+_LIB_ENV = os.environ.get("IRS_ORACLE_LIB", "")
+_LIB = _LIB_ENV or os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
@@ -30,12 +32,24 @@ class _Setup(C.Structure):
 
 def build(force: bool = True) -> str:
     """Compile irs_oracle.c into liboracle.so (gcc, OpenMP)."""
-    tmp = _LIB + ".tmp%d" % os.getpid()
+    lib = os.path.join(_HERE, "liboracle.so")
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
            "-Wall", "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB)
-    return _LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build_sanitized(path: str) -> str:
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (every report fatal) into path, for IRS_ORACLE_LIB.  A process that loads
+    it must preload gcc's libasan and libubsan."""
+    cmd = ["gcc", "-O1", "-g", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-fno-omit-frame-pointer", "-o", path, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return path
 
 
 def load():
@@ -43,7 +57,8 @@ def load():
     with _lock:
         if _lib is not None:
             return _lib
-        if (not os.path.exists(_LIB)) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not _LIB_ENV and ((not os.path.exists(_LIB)) or
+                             os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build()
         lib = C.CDLL(_LIB)
         P = C.POINTER

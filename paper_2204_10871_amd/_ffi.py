@@ -23,7 +23,7 @@ IRS_LEARN_FIELDS = 24
 EXPORTS = ("irs_geometry", "irs_level1_span", "irs_source_side", "irs_plan", "irs_deflect_grid",
            "irs_shoot_rows", "irs_shoot_rows_noalloc", "irs_shoot_map",
            "irs_plan_set_direct_variant", "irs_plan_geometry", "irs_plan_level1", "irs_free",
-           "irs_last_error",
+           "irs_last_error", "irs_debug_fail_alloc",
            "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info",
            "irs_batch_free", "irs_learn_defaults", "irs_learn", "irs_learn_set", "irs_learn_get",
            "irs_learn_corners", "irs_learn_samples", "irs_mlp_forward", "irs_mlp_loss_grad")
@@ -127,7 +127,13 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library {LIB_PATH} is missing: build it first "
                            "(python -m paper_2204_10871_amd.build or __graft_entry__.build())")
-    lib = C.CDLL(LIB_PATH)
+    _lib = declare(C.CDLL(LIB_PATH))
+    return _lib
+
+
+def declare(lib):
+    """Argument and result types of every entry point on a loaded copy of
+    the library; returns lib."""
     P, vp, i64, u64 = C.POINTER, C.c_void_p, C.c_int64, C.c_uint64
     lib.irs_geometry.argtypes = [P(Params), i64, P(GeometryInfo)]
     lib.irs_level1_span.argtypes = [P(GeometryInfo), C.c_int32, i64, P(i64), P(i64)]
@@ -157,6 +163,8 @@ def load():
     lib.irs_mlp_loss_grad.argtypes = [i64, vp, vp, vp, P(C.c_double), vp, vp]
     lib.irs_free.argtypes = [vp]
     lib.irs_free.restype = None
+    lib.irs_debug_fail_alloc.argtypes = [i64]
+    lib.irs_debug_fail_alloc.restype = C.c_int
     lib.irs_last_error.argtypes = []
     lib.irs_last_error.restype = C.c_char_p
     for name in ("irs_geometry", "irs_level1_span", "irs_source_side", "irs_plan",
@@ -166,5 +174,4 @@ def load():
                  "irs_learn_defaults", "irs_learn", "irs_learn_set", "irs_learn_get",
                  "irs_learn_corners", "irs_learn_samples", "irs_mlp_forward", "irs_mlp_loss_grad"):
         getattr(lib, name).restype = C.c_int
-    _lib = lib
     return lib

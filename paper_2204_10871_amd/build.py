@@ -72,5 +72,54 @@ def build(verbose=False):
     return LIB
 
 
+# AddressSanitizer and UndefinedBehaviorSanitizer for the host pass only (the
+# sanitizers are not for device code here), every report fatal
+SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_host_sanitized(out_dir: str) -> str:
+    """A copy of the library, out_dir/libirs_san.so, whose host sources (the
+    geometry, the C ABI's argument checks and plan management, the batch
+    front end) are compiled with SAN_HOST; the HIP sources' objects are the
+    regular ones from build().  A process that loads it must preload
+    asan_runtime().  Returns the library's path."""
+    if not all(os.path.exists(os.path.join(BUILD, s + ".o")) for s in sources()):
+        build()
+    os.makedirs(out_dir, exist_ok=True)
+    objs = []
+    for s in sources():
+        if s.endswith(".cpp"):
+            obj = os.path.join(out_dir, s + ".san.o")
+            cmd = [_hipcc()] + [f for f in COMMON if f != "-O3"] + ["-O1", "-g"] + SAN_HOST + \
+                  ["-c", os.path.join(CSRC, s), "-o", obj]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+            objs.append(obj)
+        else:
+            objs.append(os.path.join(BUILD, s + ".o"))
+    lib = os.path.join(out_dir, "libirs_san.so")
+    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", lib] + SAN_HOST + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return lib
+
+
+def asan_runtime() -> str:
+    """The compiler's shared AddressSanitizer runtime (it carries the
+    UndefinedBehaviorSanitizer handlers too)."""
+    r = subprocess.run([_hipcc(), "-print-resource-dir"], capture_output=True, text=True,
+                       check=True)
+    base = r.stdout.strip().splitlines()[-1]
+    for rel in ("lib/linux/libclang_rt.asan-x86_64.so",
+                "lib/x86_64-unknown-linux-gnu/libclang_rt.asan.so"):
+        path = os.path.join(base, rel)
+        if os.path.exists(path):
+            return path
+    raise RuntimeError(f"no AddressSanitizer runtime under {base}")
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

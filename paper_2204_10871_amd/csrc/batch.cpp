@@ -438,10 +438,10 @@ irs_status irs_batch_create(const irs_plan_t *plans, int32_t n, void *hip_stream
                    (double)need <= kWholeMemFraction * (double)free_b;
         if (b->whole) b->band_rows = 0;
     }
-    if (e == hipSuccess) e = hipMalloc(&b->d_maps, sizeof(DirectArgs) * n);
-    if (e == hipSuccess) e = hipMalloc(&b->d_item_start, sizeof(int64_t) * (n + 1));
+    if (e == hipSuccess) e = dev_alloc(&b->d_maps, sizeof(DirectArgs) * n);
+    if (e == hipSuccess) e = dev_alloc(&b->d_item_start, sizeof(int64_t) * (n + 1));
     if (e == hipSuccess)
-        e = hipMalloc(&b->d_cursor, sizeof(unsigned long long) * (1 + (size_t)n * kLandedSlots));
+        e = dev_alloc(&b->d_cursor, sizeof(unsigned long long) * (1 + (size_t)n * kLandedSlots));
     if (e != hipSuccess) st = hip_fail(e, "irs_batch_create");
     if (st != IRS_OK) {
         irs_batch_free(b);
@@ -484,7 +484,7 @@ irs_status irs_batch_tune(irs_batch_t b, const char *cache_path)
     irs_plan_s *heavy = b->plans[b->order[0]];
     const size_t map_bytes = sizeof(uint32_t) * (size_t)heavy->geo.npix * (size_t)heavy->geo.npix;
     uint32_t *scratch = nullptr;
-    IRS_HIP(hipMalloc(&scratch, map_bytes));
+    IRS_HIP(dev_alloc(&scratch, map_bytes));
     auto t0 = std::chrono::steady_clock::now();
     irs_status st = IRS_OK;
     double best = 1e300;

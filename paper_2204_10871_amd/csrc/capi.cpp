@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -26,6 +27,21 @@ irs_status alloc_allowed(const irs_plan_s *p, const char *what)
     if (!p->no_alloc) return IRS_OK;
     set_error(std::string("irs_shoot_rows_noalloc: ") + what + " would have to be allocated");
     return IRS_E_INVALID;
+}
+
+// Allocations left before the one that fails (-1: none fails).
+static std::atomic<int64_t> g_fail_alloc_after{-1};
+
+hipError_t dev_alloc_bytes(void **ptr, size_t bytes)
+{
+    int64_t left = g_fail_alloc_after.load();
+    while (left >= 0 && !g_fail_alloc_after.compare_exchange_weak(left, left - 1)) {
+    }
+    if (left == 0) {                 // this one fails; the countdown is now -1
+        *ptr = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(ptr, bytes);
 }
 
 irs_status hip_fail(hipError_t e, const char *what)
@@ -143,7 +159,7 @@ irs_status ensure_tmp(irs_plan_s *p, size_t bytes)
     dev_free(p->d_tmp);
     p->d_tmp = nullptr;
     p->tmp_bytes = 0;
-    IRS_HIP(hipMalloc(&p->d_tmp, bytes));
+    IRS_HIP(dev_alloc(&p->d_tmp, bytes));
     p->tmp_bytes = bytes;
     return IRS_OK;
 }
@@ -255,6 +271,12 @@ extern "C" {
 
 const char *irs_last_error(void) { return g_last_error.c_str(); }
 
+irs_status irs_debug_fail_alloc(int64_t after)
+{
+    g_fail_alloc_after.store(after < 0 ? -1 : after);
+    return IRS_OK;
+}
+
 irs_status irs_geometry(const irs_params *params, int64_t n_lens, irs_geometry_info *out)
 {
     if (!params || !out) {
@@ -360,7 +382,7 @@ irs_status irs_plan(const irs_params *params, int64_t n_lens, const double *x, c
         release(p);
         return st;
     }
-    e = hipMalloc(&p->d_landed, sizeof(unsigned long long) * kLandedSlots);
+    e = dev_alloc(&p->d_landed, sizeof(unsigned long long) * kLandedSlots);
     if (e != hipSuccess) {
         st = hip_fail(e, "hipMalloc");
         release(p);
@@ -479,7 +501,7 @@ static irs_status shoot(irs_plan_t plan, int64_t row0, int64_t nrows, uint32_t *
     Timer timer(s);
     uint32_t *dst = counts;
     if (!on_dev) {
-        if (!plan->d_counts) IRS_HIP(hipMalloc(&plan->d_counts, map_bytes));
+        if (!plan->d_counts) IRS_HIP(dev_alloc(&plan->d_counts, map_bytes));
         dst = plan->d_counts;
     }
     if (!on_dev || overwrite) IRS_HIP(hipMemsetAsync(dst, 0, map_bytes, s));

@@ -1604,7 +1604,7 @@ irs_status ensure_part(irs_plan_s *p, int64_t rows)
         dev_free(p->d_part);
         p->d_part = nullptr;
         p->part_bytes = 0;
-        if (hipMalloc(&p->d_part, need) != hipSuccess) {
+        if (dev_alloc(&p->d_part, need) != hipSuccess) {
             (void)hipGetLastError();
             set_error("cannot allocate the level-2 partial expansions");
             return IRS_E_NOMEM;
@@ -1625,7 +1625,7 @@ irs_status ensure_bands(irs_plan_s *p, int64_t rows)
         p->coef_rows_cap = 0;
         p->coef_c0 = -1;
         p->coef_c1 = -2;
-        if (hipMalloc(&p->d_coef, (size_t)(rows * level2_row_bytes(p))) != hipSuccess) {
+        if (dev_alloc(&p->d_coef, (size_t)(rows * level2_row_bytes(p))) != hipSuccess) {
             (void)hipGetLastError();
             set_error("cannot allocate the level-2 coefficient band");
             return IRS_E_NOMEM;
@@ -1662,6 +1662,8 @@ void level2_reset(irs_plan_s *p)
 {
     std::fill(p->super_ok.begin(), p->super_ok.end(), 0);
     std::fill(p->mid_ok.begin(), p->mid_ok.end(), 0);
+    p->coef_c0 = -1;                 // no band of coefficients resident either
+    p->coef_c1 = -2;
 }
 
 // Super-cell side K_S and mid-cell side K_M (cells; K_M = 0: no mid level),
@@ -1732,7 +1734,7 @@ irs_status ensure_super_buffers(irs_plan_s *p, int64_t rows)
     if (!p->d_super) {
         irs_status st = alloc_allowed(p, "the super-cell expansions");
         if (st != IRS_OK) return st;
-        if (hipMalloc(&p->d_super, sizeof(double) * (size_t)nSy * nSx * PS * 2) != hipSuccess) {
+        if (dev_alloc(&p->d_super, sizeof(double) * (size_t)nSy * nSx * PS * 2) != hipSuccess) {
             (void)hipGetLastError();
             p->d_super = nullptr;
             set_error("cannot allocate the super-cell expansions");
@@ -1747,7 +1749,7 @@ irs_status ensure_super_buffers(irs_plan_s *p, int64_t rows)
         dev_free(p->d_super_part);
         p->d_super_part = nullptr;
         p->super_part_bytes = 0;
-        if (hipMalloc(&p->d_super_part, need) != hipSuccess) {
+        if (dev_alloc(&p->d_super_part, need) != hipSuccess) {
             (void)hipGetLastError();
             set_error("cannot allocate the super-cell partial expansions");
             return IRS_E_NOMEM;
@@ -1830,7 +1832,7 @@ irs_status ensure_mid_buffers(irs_plan_s *p)
     if (st != IRS_OK) return st;
     const int PS = super_order(p);
     const int32_t nMx = mid_nx(p), nMy = mid_ny(p);
-    if (hipMalloc(&p->d_mid, sizeof(double) * (size_t)nMy * nMx * PS * 2) != hipSuccess) {
+    if (dev_alloc(&p->d_mid, sizeof(double) * (size_t)nMy * nMx * PS * 2) != hipSuccess) {
         (void)hipGetLastError();
         p->d_mid = nullptr;
         set_error("cannot allocate the mid-cell expansions");
@@ -2025,18 +2027,18 @@ irs_status ensure_rows(irs_plan_s *p)
     dev_free(p->d_cols);
     p->d_tcol = p->d_trow = nullptr;
     p->d_cols = nullptr;
-    IRS_HIP(hipMalloc(&p->d_tcol, p->h_tcol.size() * sizeof(TileSpan)));
-    IRS_HIP(hipMalloc(&p->d_trow, p->h_trow.size() * sizeof(TileSpan)));
+    IRS_HIP(dev_alloc(&p->d_tcol, p->h_tcol.size() * sizeof(TileSpan)));
+    IRS_HIP(dev_alloc(&p->d_trow, p->h_trow.size() * sizeof(TileSpan)));
     IRS_HIP(hipMemcpyAsync(p->d_tcol, p->h_tcol.data(), p->h_tcol.size() * sizeof(TileSpan),
                            hipMemcpyHostToDevice, p->stream));
     IRS_HIP(hipMemcpyAsync(p->d_trow, p->h_trow.data(), p->h_trow.size() * sizeof(TileSpan),
                            hipMemcpyHostToDevice, p->stream));
-    IRS_HIP(hipMalloc(&p->d_cols, (size_t)g.nx * sizeof(ColInfo)));
+    IRS_HIP(dev_alloc(&p->d_cols, (size_t)g.nx * sizeof(ColInfo)));
     hipLaunchKernelGGL(k_col_table, dim3((unsigned)((g.nx + kThreads - 1) / kThreads)),
                        dim3(kThreads), 0, p->stream, g, (ColInfo *)p->d_cols);
     IRS_HIP(hipGetLastError());
     void *rows = nullptr;
-    IRS_HIP(hipMalloc(&rows, (size_t)g.ny * sizeof(RowInfo)));
+    IRS_HIP(dev_alloc(&rows, (size_t)g.ny * sizeof(RowInfo)));
     const unsigned nb = (unsigned)((g.ny + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_row_table, dim3(nb), dim3(kThreads), 0, p->stream, g, (RowInfo *)rows);
     hipError_t e = hipGetLastError();

@@ -1000,7 +1000,7 @@ struct DevBuf {
     ~DevBuf() { dev_free(p); }
     irs_status alloc(size_t count)
     {
-        if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+        if (dev_alloc(&p, count * sizeof(T)) != hipSuccess) {
             (void)hipGetLastError();
             p = nullptr;
             n = 0;
@@ -1160,9 +1160,9 @@ void init_params(uint64_t seed, std::vector<float> &th)
 
 irs_status upload_network(irs_plan_s *p, const float *freqs, const float *theta)
 {
-    if (!p->d_theta) IRS_HIP(hipMalloc(&p->d_theta, sizeof(float) * kNP));
-    if (!p->d_freqs) IRS_HIP(hipMalloc(&p->d_freqs, sizeof(float) * 2 * kNF));
-    if (!p->d_wfwd) IRS_HIP(hipMalloc(&p->d_wfwd, sizeof(uint4) * kFragFwd));
+    if (!p->d_theta) IRS_HIP(dev_alloc(&p->d_theta, sizeof(float) * kNP));
+    if (!p->d_freqs) IRS_HIP(dev_alloc(&p->d_freqs, sizeof(float) * 2 * kNF));
+    if (!p->d_wfwd) IRS_HIP(dev_alloc(&p->d_wfwd, sizeof(uint4) * kFragFwd));
     IRS_HIP(hipMemcpyAsync(p->d_theta, theta, sizeof(float) * kNP, hipMemcpyHostToDevice, p->stream));
     IRS_HIP(hipMemcpyAsync(p->d_freqs, freqs, sizeof(float) * 2 * kNF, hipMemcpyHostToDevice, p->stream));
     const int64_t ne = (int64_t)kFragFwd * 8;
@@ -1362,7 +1362,7 @@ irs_status launch_learned(irs_plan_s *p, const RaySel &sel)
         p->corner_rows_cap = 0;
         p->corner_c0 = -1;
         p->corner_c1 = -2;
-        IRS_HIP(hipMalloc(&p->d_corner, (size_t)(band * corner_row_bytes(p, qc))));
+        IRS_HIP(dev_alloc(&p->d_corner, (size_t)(band * corner_row_bytes(p, qc))));
         p->corner_rows_cap = band;
     }
     CallStats *cs = sel.stats;

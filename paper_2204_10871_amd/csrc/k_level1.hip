@@ -219,7 +219,7 @@ irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const 
     const int32_t ncell = (int32_t)ncell64;
     hipStream_t s = p->stream;
 
-    IRS_HIP(hipMalloc(&p->d_cell_start, sizeof(int32_t) * (size_t)(ncell + 1)));
+    IRS_HIP(dev_alloc(&p->d_cell_start, sizeof(int32_t) * (size_t)(ncell + 1)));
     p->h_cell_start.assign((size_t)ncell + 1, 0);
     if (n == 0) {
         IRS_HIP(hipMemsetAsync(p->d_cell_start, 0, sizeof(int32_t) * (size_t)(ncell + 1), s));
@@ -227,11 +227,11 @@ irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const 
         return IRS_OK;
     }
     const size_t nb = sizeof(double) * (size_t)n;
-    IRS_HIP(hipMalloc(&p->d_x, nb));
-    IRS_HIP(hipMalloc(&p->d_y, nb));
-    if (hm) IRS_HIP(hipMalloc(&p->d_m, nb));
-    IRS_HIP(hipMalloc(&p->d_cxy, sizeof(uint32_t) * (size_t)n));
-    IRS_HIP(hipMalloc(&p->d_xy, 2 * nb));
+    IRS_HIP(dev_alloc(&p->d_x, nb));
+    IRS_HIP(dev_alloc(&p->d_y, nb));
+    if (hm) IRS_HIP(dev_alloc(&p->d_m, nb));
+    IRS_HIP(dev_alloc(&p->d_cxy, sizeof(uint32_t) * (size_t)n));
+    IRS_HIP(dev_alloc(&p->d_xy, 2 * nb));
 
     double *ux = nullptr, *uy = nullptr, *um = nullptr;
     int32_t *key = nullptr, *val = nullptr, *key2 = nullptr, *val2 = nullptr;
@@ -265,16 +265,16 @@ irs_status pack_level1(irs_plan_s *p, const double *hx, const double *hy, const 
         return hipGetLastError();
     };
 
-    IRS_TRY(hipMalloc(&ux, nb));
-    IRS_TRY(hipMalloc(&uy, nb));
-    if (hm) IRS_TRY(hipMalloc(&um, nb));
-    IRS_TRY(hipMalloc(&key, sizeof(int32_t) * (size_t)n));
-    IRS_TRY(hipMalloc(&val, sizeof(int32_t) * (size_t)n));
-    IRS_TRY(hipMalloc(&key2, sizeof(int32_t) * (size_t)n));
-    IRS_TRY(hipMalloc(&val2, sizeof(int32_t) * (size_t)n));
-    IRS_TRY(hipMalloc(&cnt, sizeof(int32_t) * (size_t)nscan));
-    IRS_TRY(hipMalloc(&hist, sizeof(int32_t) * (size_t)nhist));
-    IRS_TRY(hipMalloc(&sums, sizeof(int32_t) * (size_t)nsums));
+    IRS_TRY(dev_alloc(&ux, nb));
+    IRS_TRY(dev_alloc(&uy, nb));
+    if (hm) IRS_TRY(dev_alloc(&um, nb));
+    IRS_TRY(dev_alloc(&key, sizeof(int32_t) * (size_t)n));
+    IRS_TRY(dev_alloc(&val, sizeof(int32_t) * (size_t)n));
+    IRS_TRY(dev_alloc(&key2, sizeof(int32_t) * (size_t)n));
+    IRS_TRY(dev_alloc(&val2, sizeof(int32_t) * (size_t)n));
+    IRS_TRY(dev_alloc(&cnt, sizeof(int32_t) * (size_t)nscan));
+    IRS_TRY(dev_alloc(&hist, sizeof(int32_t) * (size_t)nhist));
+    IRS_TRY(dev_alloc(&sums, sizeof(int32_t) * (size_t)nsums));
     IRS_TRY(hipMemcpyAsync(ux, hx, nb, hipMemcpyHostToDevice, s));
     IRS_TRY(hipMemcpyAsync(uy, hy, nb, hipMemcpyHostToDevice, s));
     if (hm) IRS_TRY(hipMemcpyAsync(um, hm, nb, hipMemcpyHostToDevice, s));

@@ -109,6 +109,16 @@ inline void dev_free(void *ptr)
     if (ptr) (void)hipFree(ptr);
 }
 
+// Every device allocation of the library: hipMalloc, or hipErrorOutOfMemory
+// (nothing allocated, *ptr null) for the allocation that the countdown of
+// irs_debug_fail_alloc selects.
+hipError_t dev_alloc_bytes(void **ptr, size_t bytes);
+template <class T>
+inline hipError_t dev_alloc(T **ptr, size_t bytes)
+{
+    return dev_alloc_bytes((void **)ptr, bytes);
+}
+
 // Status plumbing shared by the launch wrappers and the C ABI.
 void set_error(const std::string &msg);
 irs_status hip_fail(hipError_t e, const char *what);

@@ -1,0 +1,159 @@
+"""Out-of-memory paths through the C ABI.  irs_debug_fail_alloc makes one
+chosen device allocation of the library fail, as an exhausted hipMalloc
+would: the call must return IRS_E_NOMEM, a failed irs_plan or
+irs_batch_create must leave a NULL handle, nothing the failed call allocated
+may stay allocated, and a plan that exists must keep working (the next call
+without the failure gives the same map as a fresh plan)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from gpu_common import Case
+
+pytestmark = pytest.mark.gpu
+
+IRS_E_NOMEM = 3
+SLACK = 4 << 20          # bytes of device memory the runtime may keep in its pools
+
+
+@pytest.fixture(scope="module")
+def irs():
+    import paper_2204_10871_amd as irs
+    irs.load()
+    return irs
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def _used():
+    import torch
+    torch.cuda.synchronize()
+    free, total = torch.cuda.mem_get_info()
+    return total - free
+
+
+def _case():
+    # about 2e5 lenses: every plan buffer is a few MB, so a leaked one shows
+    return Case(0.45, 0.05, 0.45, 40.0, 96, n_rays=300_000, n_lens=200_003, seed=61)
+
+
+def _plan_args(irs, c, method):
+    p = irs.make_params(**c.kw, method=method, precision="fp64", **c.p_extra)
+    x = np.ascontiguousarray(c.lenses.x, np.float64)
+    y = np.ascontiguousarray(c.lenses.y, np.float64)
+    return p, x, y
+
+
+def _plan_cycle(lib, c, p, x, y):
+    """irs_plan with each of its allocations failing in turn, then once
+    without a failure (freed at once).  Returns the number of failures."""
+    k = 0
+    while True:
+        lib.irs_debug_fail_alloc(k)
+        h = C.c_void_p(1)                   # not NULL: the call must clear it
+        st = lib.irs_plan(C.byref(p), c.lenses.n, x.ctypes.data, y.ctypes.data, None, None,
+                          C.byref(h))
+        lib.irs_debug_fail_alloc(-1)
+        if st == 0:
+            lib.irs_free(h)
+            return k
+        assert st == IRS_E_NOMEM, (k, st)
+        assert h.value is None, k
+        assert lib.irs_last_error()                 # a message says what failed
+        k += 1
+        assert k < 100
+
+
+# A leak on a failure path repeats with every cycle of failures, while what
+# the runtime keeps in its own pools after the first cycle does not: each
+# test runs its cycle once, then measures a second, identical cycle.
+
+@pytest.mark.parametrize("method", ["direct", "interp"])
+def test_plan_fails_cleanly_at_every_allocation(irs, method):
+    lib = irs._ffi.load()
+    c = _case()
+    p, x, y = _plan_args(irs, c, method)
+    k = _plan_cycle(lib, c, p, x, y)
+    base = _used()
+    assert _plan_cycle(lib, c, p, x, y) == k
+    leaked = _used() - base
+    say(f"irs_plan ({method}): {k} allocations failed in turn, {leaked} bytes kept")
+    assert k >= 5
+    assert leaked <= SLACK
+
+
+def _map_cycle(irs, lib, c, want):
+    """A fresh plan whose first map has each allocation fail in turn, then
+    succeed; the map must equal want, also on a second call."""
+    k = 0
+    with c.plan("interp", "fp64") as pl:
+        npix = c.geo.npix
+        while True:
+            counts = np.zeros(npix * npix, np.uint32)
+            st_ = irs.MapStats()
+            lib.irs_debug_fail_alloc(k)
+            st = lib.irs_shoot_map(pl.handle, counts.ctypes.data, C.byref(st_), 0)
+            lib.irs_debug_fail_alloc(-1)
+            if st == 0:
+                break
+            assert st == IRS_E_NOMEM, (k, st)
+            k += 1
+            assert k < 100
+        assert np.array_equal(counts.reshape(npix, npix), want)
+        got, _ = pl.shoot_map()
+        assert np.array_equal(got, want)
+    return k
+
+
+def test_map_fails_cleanly_and_the_plan_recovers(irs):
+    """Each allocation of the first interpolated map (tables, coefficient
+    band, expansions, count buffer) fails in turn; the plan then shoots the
+    same map as a fresh plan."""
+    lib = irs._ffi.load()
+    c = _case()
+    with c.plan("interp", "fp64") as ref:
+        want, _ = ref.shoot_map()
+    k = _map_cycle(irs, lib, c, want)
+    base = _used()
+    assert _map_cycle(irs, lib, c, want) == k
+    leaked = _used() - base
+    say(f"irs_shoot_map: {k} allocations failed in turn, {leaked} bytes kept")
+    assert k >= 3
+    assert leaked <= SLACK
+
+
+def _batch_cycle(lib, arr, n):
+    k = 0
+    while True:
+        lib.irs_debug_fail_alloc(k)
+        h = C.c_void_p(1)
+        st = lib.irs_batch_create(arr, n, None, C.byref(h))
+        lib.irs_debug_fail_alloc(-1)
+        if st == 0:
+            lib.irs_batch_free(h)
+            return k
+        assert st == IRS_E_NOMEM, (k, st)
+        assert h.value is None, k
+        k += 1
+        assert k < 100
+
+
+def test_batch_create_fails_cleanly(irs):
+    lib = irs._ffi.load()
+    cases = [Case(0.3, 0.0, 0.3, 8.0, 64, n_rays=100_000, seed=70 + i) for i in range(3)]
+    plans = [cc.plan("direct", "fp32") for cc in cases]
+    try:
+        arr = (C.c_void_p * len(plans))(*[pl.handle.value for pl in plans])
+        k = _batch_cycle(lib, arr, len(plans))
+        base = _used()
+        assert _batch_cycle(lib, arr, len(plans)) == k
+        leaked = _used() - base
+        say(f"irs_batch_create: {k} allocations failed in turn, {leaked} bytes kept")
+        assert k >= 1
+        assert leaked <= SLACK
+    finally:
+        for pl in plans:
+            pl.close()

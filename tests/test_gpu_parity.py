@@ -202,6 +202,20 @@ def test_single_ray_and_single_lens(irs, method, precision):
     assert px[0] == ref["pix"][0]
 
 
+def test_each_map_computes_its_level2(irs):
+    """irs_shoot_map computes every far-field expansion and coefficient band
+    itself, also where the previous map left its whole band resident (this
+    map fits one band), and gives the same map again."""
+    c = Case(0.35, 0.1, 0.25, 4.0, 64, n_rays=400_000, seed=41)
+    with c.plan("interp", "fp64") as pl:
+        c1, s1 = pl.shoot_map(time_phases=True)
+        c2, s2 = pl.shoot_map(time_phases=True)
+    assert s1["level2_points"] > 0
+    assert s2["level2_points"] == s1["level2_points"]
+    assert s2["n_level2_launches"] == s1["n_level2_launches"] > 0
+    assert np.array_equal(c1, c2)
+
+
 @pytest.mark.parametrize("method,precision", [("direct", "fp32"), ("interp", "fp64")])
 def test_row_bands_add_up_and_are_deterministic(irs, method, precision):
     """Disjoint row bands sum exactly to the full map (resume by bands), two
