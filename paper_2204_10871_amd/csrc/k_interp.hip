@@ -1010,16 +1010,33 @@ __device__ __forceinline__ int row_max(int v)
     return shr_max<8>(shr_max<4>(shr_max<2>(shr_max<1>(v))));
 }
 
-// One ray column of the plan's ray grid, as the level-3 kernel reads it.
+// One ray column of the plan's ray grid, as the level-3 kernel reads it: what
+// takes 64-bit integer division to find (16 bytes, so that one XCD's share of
+// the table stays in its L2 from one tile row to the next).
 struct alignas(16) ColInfo {
-    double t1;        // theta_1 of the column
-    double hr;        // t1 minus the x of its level-2 column
-    double c1;        // t1 - (kappa + gamma) t1 + kappa_* hr (sheet on) + S/2
-    double s1;        // kappa_* hr (sheet on), else 0
+    double hr;        // theta_1 minus the x of the column's level-2 column
     uint32_t coff;    // byte offset of the column's level-2 point in a level-2 row
     int32_t cx;       // level-1 column
-    int64_t pad_;
 };
+static_assert(sizeof(ColInfo) == 16, "one 16-byte load a lane");
+
+// theta_1 of ray column i < 2^31, rounded as ray_x rounds it
+__device__ __forceinline__ double ray_x32(const DevGeom &g, int32_t i)
+{
+#pragma clang fp contract(off)
+    return g.a1 + ((double)i + 0.5) * g.ray_dx;
+}
+
+// beta_1 + S/2 of a column's rays without the lens terms: the macro term and
+// the sheet's -kappa_* conj(h) part (s1 = kappa_* hr; the row's c2 holds the
+// same for beta_2)
+__device__ __forceinline__ void column_terms(const DevGeom &g, double t1, double hr, double &c1,
+                                             double &s1)
+{
+    s1 = g.sheet ? g.kappa_star * hr : 0.0;
+    const double mac1 = g.kpg * t1;
+    c1 = ((t1 - mac1) + s1) + g.half_side;
+}
 
 __global__ __launch_bounds__(kThreads) void k_col_table(DevGeom g, ColInfo *cols)
 {
@@ -1028,17 +1045,9 @@ __global__ __launch_bounds__(kThreads) void k_col_table(DevGeom g, ColInfo *cols
     const int64_t nxq = (int64_t)g.n1x * g.q;
     const int64_t gx = floor_div((2 * i + 1) * nxq, 2 * g.nx);
     ColInfo c;
-    c.t1 = ray_x(g, i);
-    c.hr = c.t1 - level2_x(g, gx);
-    // beta_1 + S/2 of the column's rays without the lens terms: the macro
-    // term and the sheet's -kappa_* conj(h) part (the row's c2 holds the
-    // same for beta_2)
-    c.s1 = g.sheet ? g.kappa_star * c.hr : 0.0;
-    const double mac1 = g.kpg * c.t1;
-    c.c1 = ((c.t1 - mac1) + c.s1) + g.half_side;
+    c.hr = ray_x(g, i) - level2_x(g, gx);
     c.coff = (uint32_t)gx * 10u * (uint32_t)sizeof(double);
     c.cx = (int32_t)(gx / g.q);
-    c.pad_ = 0;
     cols[i] = c;
 }
 
@@ -1248,9 +1257,10 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
     const int64_t nxq = (int64_t)g.n1x * g.q;
     // the lane's column (lanes past the tile's end take its first column and
     // bin nothing); what the rows need of it is read after the lens pass
-    const ColInfo *col = &m.cols[in_col ? i32 : tc.a];
+    const int32_t ic = in_col ? i32 : tc.a;
+    const ColInfo *col = &m.cols[ic];
     const int32_t cx = col->cx;
-    const double t1 = col->t1;
+    const double t1 = ray_x32(g, ic);
     const int32_t xl = cx > 0 ? cx - 1 : 0, xh = cx < g.n1x - 1 ? cx + 1 : g.n1x - 1;
 
     // the wave's rows jw + k, k < kt, lie in the tile; rows k0 <= k < k1 also
@@ -1304,8 +1314,10 @@ __device__ __forceinline__ void level3_tile(const L3Map &m, int32_t tx, int32_t 
                       row(k1 - 1).base + g.nx <= m.ray_last;
     const bool corner_col = in_col && (cx == 0 || cx == g.n1x - 1);
     const bool wave_corner = g.sheet && __ballot(corner_col) != 0;     // wave-uniform
-    const L3Lane ln{i, i32, in_col, corner_col, wave_corner, t1, col->hr, col->c1, col->s1,
-                    col->coff};
+    const double hr = col->hr;
+    double c1, s1;
+    column_terms(g, t1, hr, c1, s1);
+    const L3Lane ln{i, i32, in_col, corner_col, wave_corner, t1, hr, c1, s1, col->coff};
     int32_t pxs[R], pys[R];
     if (full)
         level3_rows<BIN, true>(g, m.rows, m.coef, m.cy0, nxq, ln, jw, k0, k1, m.ray_first,
@@ -2232,10 +2244,10 @@ irs_status level2_tree_rows(irs_plan_s *p, int64_t cyA, int64_t cyB, CallStats *
     return IRS_OK;
 }
 
-// The level-2 coefficients of level-1 rows [c0, c1] into p->d_coef (from row
-// c0): the cell expansions and the points' series.  The tree rows they need
+// The level-2 coefficients of level-1 rows [c0, c1] into coef (from row c0):
+// the cell expansions and the points' series, on the plan's stream.  The tree rows they need
 // must be cached (level2_tree_rows).
-irs_status level2_band(irs_plan_s *p, int64_t c0, int64_t c1, CallStats *cs)
+irs_status level2_band(irs_plan_s *p, int64_t c0, int64_t c1, double *coef, CallStats *cs)
 {
     const DevGeom &g = p->dg;
     hipStream_t s = p->stream;
@@ -2274,10 +2286,10 @@ irs_status level2_band(irs_plan_s *p, int64_t c0, int64_t c1, CallStats *cs)
         const unsigned nb2 = (unsigned)((c1 - c0 + 1) * g.n1x);
         if (p->unit_mass)
             hipLaunchKernelGGL(k_level2<true>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,
-                               p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
+                               p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, coef);
         else
             hipLaunchKernelGGL(k_level2<false>, dim3(nb2), dim3(kThreads), 0, s, g, p->d_x,
-                               p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, p->d_coef);
+                               p->d_y, p->d_m, p->d_cell_start, nl, (int32_t)c0, coef);
     } else {
         const int32_t nxb = (g.n1x + kCellsPerBlock - 1) / kCellsPerBlock;
         // lens chunks (one level) are a property of the plan, so results
@@ -2300,7 +2312,7 @@ irs_status level2_band(irs_plan_s *p, int64_t c0, int64_t c1, CallStats *cs)
         if (cs && (st2 = cs->begin(s, 2)) != IRS_OK) return st2;                             \
         hipLaunchKernelGGL((k_level2_points<U, PP>), dim3(nbB), dim3(kThreads), 0, s, g,      \
                            p->d_x, p->d_y, p->d_m, p->d_cell_start, (int32_t)c0, nxb, nchunk, \
-                           fold, p->d_part, p->d_coef);                                       \
+                           fold, p->d_part, coef);                                       \
     } while (0)
         irs_status st2 = IRS_OK;
         if (p->unit_mass) {
@@ -2317,8 +2329,78 @@ irs_status level2_band(irs_plan_s *p, int64_t c0, int64_t c1, CallStats *cs)
         irs_status st = cs->end(s);
         if (st != IRS_OK) return st;
     }
-    p->coef_c0 = c0;
-    p->coef_c1 = c1;
+    return IRS_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Level 3 of one band of level-1 rows [c0, c1] whose coefficients are in
+// coef (from level-1 row cy0), on stream s: the band's row tiles, then its
+// rays in the rectangle's corner cells.
+irs_status level3_band(irs_plan_s *p, const RaySel &sel, int64_t c0, int64_t c1,
+                       const double *coef, int64_t cy0, hipStream_t s)
+{
+    const DevGeom &g = p->dg;
+    const int64_t q = g.q;
+    const int64_t jA = std::max(sel.row0, first_row_at(g, c0 * q));
+    const int64_t jB = std::min(sel.row1, first_row_at(g, (c1 + 1) * q));
+    if (jB <= jA) return IRS_OK;
+    CallStats *cs = sel.stats;
+    const int64_t ntx = (int64_t)p->h_tcol.size();
+    const int64_t ntx_pad = (ntx + kXcds - 1) / kXcds * kXcds;
+    // the row tiles that meet rows [jA, jB)
+    const std::vector<TileSpan> &tr = p->h_trow;
+    const int64_t ta = std::upper_bound(tr.begin(), tr.end(), jA,
+                                        [](int64_t v, const TileSpan &t) { return v < t.b; }) -
+                       tr.begin();
+    const int64_t tb = std::lower_bound(tr.begin(), tr.end(), jB,
+                                        [](const TileSpan &t, int64_t v) { return t.a < v; }) -
+                       tr.begin();
+    const int64_t nty = tb - ta;
+    L3Map m = map_args(p, sel, (int32_t)cy0, 0, 0);
+    m.coef = coef;
+    // at most 2^23 workgroups (2^31 work-items) per launch: the dispatch's
+    // grid size in work-items is a 32-bit number
+    const int64_t max_ty = std::max<int64_t>(1, ((int64_t)1 << 23) / ntx_pad);
+    for (int64_t t0 = 0; t0 < nty; t0 += max_ty) {
+        const int64_t t1 = std::min(nty, t0 + max_ty);
+        const unsigned nb3 = (unsigned)((t1 - t0) * ntx_pad);
+        const int64_t j0 = std::max(jA, (int64_t)tr[ta + t0].a);
+        const int64_t j1 = std::min(jB, (int64_t)tr[ta + t1 - 1].b);
+        m.jr0 = j0;
+        m.jr1 = j1;
+        if (cs) {
+            irs_status st = cs->begin(s, 1);
+            if (st != IRS_OK) return st;
+            cs->n_rays++;
+            cs->ray_flops += level3_flops(p, j0, j1);
+        }
+#define IRS_L3(U, B)                                                                          \
+    hipLaunchKernelGGL((k_level3<U, B>), dim3(nb3), dim3(kThreads), 0, s, m,                  \
+                       (int32_t)(ta + t0), (int32_t)ntx_pad)
+        const bool bin = sel.counts != nullptr;
+        if (p->unit_mass) {
+            if (bin) IRS_L3(true, true);
+            else IRS_L3(true, false);
+        } else {
+            if (bin) IRS_L3(false, true);
+            else IRS_L3(false, false);
+        }
+#undef IRS_L3
+        IRS_HIP(hipGetLastError());
+        if (t1 == nty) {
+            // the band's rays in the rectangle's corner cells (launched on
+            // the plan's stream, which is s here)
+            irs_status st = launch_corners(p, m, jA, jB);
+            if (st != IRS_OK) return st;
+        }
+        if (cs) {
+            irs_status st = cs->end(s);
+            if (st != IRS_OK) return st;
+        }
+    }
     return IRS_OK;
 }
 
@@ -2340,10 +2422,9 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
     const int64_t step = std::min(band_rows(p), want);
     st0 = ensure_bands(p, step);
     if (st0 != IRS_OK) return st0;
-    const int64_t ntx = (int64_t)p->h_tcol.size();
-    const int64_t ntx_pad = (ntx + kXcds - 1) / kXcds * kXcds;
     CallStats *cs = sel.stats;
-    if (!(p->coef_c0 <= cyA && cyB <= p->coef_c1)) {
+    const bool resident = p->coef_c0 <= cyA && cyB <= p->coef_c1;
+    if (!resident) {
         st0 = level2_tree_rows(p, cyA, cyB, cs);
         if (st0 != IRS_OK) return st0;
     }
@@ -2351,61 +2432,16 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
         const int64_t c1 = std::min(cyB, c0 + step - 1);
         if (!(p->coef_c0 <= c0 && c1 <= p->coef_c1)) {
             // the band's level-2 coefficients are not resident: compute them
-            st0 = level2_band(p, c0, c1, cs);
+            // (the buffer holds no complete band until they are done)
+            p->coef_c0 = -1;
+            p->coef_c1 = -2;
+            st0 = level2_band(p, c0, c1, p->d_coef, cs);
             if (st0 != IRS_OK) return st0;
+            p->coef_c0 = c0;
+            p->coef_c1 = c1;
         }
-        const int64_t jA = std::max(sel.row0, first_row_at(g, c0 * q));
-        const int64_t jB = std::min(sel.row1, first_row_at(g, (c1 + 1) * q));
-        if (jB <= jA) continue;
-        // the row tiles that meet rows [jA, jB)
-        const std::vector<TileSpan> &tr = p->h_trow;
-        const int64_t ta = std::upper_bound(tr.begin(), tr.end(), jA,
-                                            [](int64_t v, const TileSpan &t) { return v < t.b; }) -
-                           tr.begin();
-        const int64_t tb = std::lower_bound(tr.begin(), tr.end(), jB,
-                                            [](const TileSpan &t, int64_t v) { return t.a < v; }) -
-                           tr.begin();
-        const int64_t nty = tb - ta;
-        L3Map m = map_args(p, sel, (int32_t)p->coef_c0, 0, 0);
-        // at most 2^23 workgroups (2^31 work-items) per launch: the dispatch's
-        // grid size in work-items is a 32-bit number
-        const int64_t max_ty = std::max<int64_t>(1, ((int64_t)1 << 23) / ntx_pad);
-        for (int64_t t0 = 0; t0 < nty; t0 += max_ty) {
-            const int64_t t1 = std::min(nty, t0 + max_ty);
-            const unsigned nb3 = (unsigned)((t1 - t0) * ntx_pad);
-            const int64_t j0 = std::max(jA, (int64_t)tr[ta + t0].a);
-            const int64_t j1 = std::min(jB, (int64_t)tr[ta + t1 - 1].b);
-            m.jr0 = j0;
-            m.jr1 = j1;
-            if (cs) {
-                irs_status st = cs->begin(s, 1);
-                if (st != IRS_OK) return st;
-                cs->n_rays++;
-                cs->ray_flops += level3_flops(p, j0, j1);
-            }
-#define IRS_L3(U, B)                                                                          \
-    hipLaunchKernelGGL((k_level3<U, B>), dim3(nb3), dim3(kThreads), 0, s, m,                  \
-                       (int32_t)(ta + t0), (int32_t)ntx_pad)
-            const bool bin = sel.counts != nullptr;
-            if (p->unit_mass) {
-                if (bin) IRS_L3(true, true);
-                else IRS_L3(true, false);
-            } else {
-                if (bin) IRS_L3(false, true);
-                else IRS_L3(false, false);
-            }
-#undef IRS_L3
-            IRS_HIP(hipGetLastError());
-            if (t1 == nty) {
-                // the band's rays in the rectangle's corner cells
-                irs_status st = launch_corners(p, m, jA, jB);
-                if (st != IRS_OK) return st;
-            }
-            if (cs) {
-                irs_status st = cs->end(s);
-                if (st != IRS_OK) return st;
-            }
-        }
+        st0 = level3_band(p, sel, c0, c1, p->d_coef, p->coef_c0, s);
+        if (st0 != IRS_OK) return st0;
     }
     return IRS_OK;
 }
@@ -2429,9 +2465,15 @@ irs_status interp_prepare_whole(irs_plan_s *p)
 
 irs_status interp_level2_whole(irs_plan_s *p)
 {
+    p->coef_c0 = -1;
+    p->coef_c1 = -2;
     irs_status st = level2_tree_rows(p, 0, p->dg.n1y - 1, nullptr);
     if (st != IRS_OK) return st;
-    return level2_band(p, 0, p->dg.n1y - 1, nullptr);
+    st = level2_band(p, 0, p->dg.n1y - 1, p->d_coef, nullptr);
+    if (st != IRS_OK) return st;
+    p->coef_c0 = 0;
+    p->coef_c1 = p->dg.n1y - 1;
+    return IRS_OK;
 }
 
 irs_status interp_map_args(irs_plan_s *p, uint32_t *counts, unsigned long long *landed,
