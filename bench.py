@@ -583,7 +583,7 @@ def main():
                     help="0: a step is the whole map; R > 0: a step is a band of R level-1 rows "
                          "(for counter runs)")
     ap.add_argument("--direct-rows", type=int, default=64)
-    ap.add_argument("--direct-sample", type=int, default=40_000,
+    ap.add_argument("--direct-sample", type=int, default=100_000,
                     help="rays of the parity sample checked on the FP32 direct sum")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-map batch measurement")

@@ -1099,10 +1099,15 @@ __device__ __forceinline__ void pixel_pair(const DevGeom &g, double xs1, double 
         f1 = floor(xs1 / g.dpix);
         f2 = floor(xs2 / g.dpix);
     }
-    const bool in = (int)(f1 >= 0.0) & (int)(f1 < g.npix_f) & (int)(f2 >= 0.0) &
-                    (int)(f2 < g.npix_f);
-    ix = in ? (int32_t)f1 : -1;
-    iy = in ? (int32_t)f2 : -1;
+    // the hardware conversion saturates (a value beyond the int32 range gives
+    // INT32_MIN or INT32_MAX; no NaN arises here), which a C++ cast does not
+    // promise: a floor off the map stays off it as an unsigned index >= npix
+    int32_t jx, jy;
+    asm("v_cvt_i32_f64 %0, %1" : "=v"(jx) : "v"(f1));
+    asm("v_cvt_i32_f64 %0, %1" : "=v"(jy) : "v"(f2));
+    const bool in = (int)((uint32_t)jx < (uint32_t)g.npix) & (int)((uint32_t)jy < (uint32_t)g.npix);
+    ix = in ? jx : -1;
+    iy = in ? jy : -1;
 }
 
 // What a lane of k_level3 holds for its ray column.
