@@ -296,11 +296,20 @@ const char *irs_last_error(void);
 /*
  * irs_debug_fail_alloc -- fault injection for tests of the out-of-memory
  * paths: the next `after` device allocations of the library (any thread, any
- * plan or batch) succeed and the one after them fails as an exhausted
- * hipMalloc would (the call returns IRS_E_NOMEM).  The failure uses the
- * setting up; after < 0 switches it off.  Process-wide.  Returns IRS_OK.
+ * plan or batch, set-up included) succeed and the one after them fails as an
+ * exhausted hipMalloc would (the call returns IRS_E_NOMEM); after < 0
+ * switches it off.  Process-wide.  Returns IRS_OK.
  */
 irs_status irs_debug_fail_alloc(int64_t after);
+
+/*
+ * irs_debug_live_allocs -- the library's device allocations that are live
+ * now (made and not yet freed, over every plan and batch of the process):
+ * their number into *count and their total size in bytes into *bytes.  For
+ * leak checks that must not depend on what the HIP runtime itself keeps.
+ * IRS_E_INVALID on a NULL argument.
+ */
+irs_status irs_debug_live_allocs(int64_t *count, int64_t *bytes);
 
 /* ------------------------------------------------------------------------ */
 /* Batches of independent maps.                                              */
@@ -321,9 +330,9 @@ typedef struct {
     int64_t work_items;           /* queue items of the persistent launch (direct)     */
     double  tune_ms;              /* time the autotuner spent measuring                */
     int32_t whole_maps;           /* interpolation: 1 if every map's level-2 field is  */
-                                  /* resident at once and level 3 runs in launches of  */
-                                  /* several maps each                                 */
-    int32_t maps_per_launch;      /* ... maps per level-3 launch (1..6)                */
+                                  /* resident at once and level 3 runs as one launch   */
+                                  /* over every map's tiles                            */
+    int32_t maps_per_launch;      /* ... maps in that launch (the batch's n; 0 if not) */
 } irs_batch_info;
 
 /*
@@ -344,10 +353,10 @@ irs_status irs_batch_create(const irs_plan_t *plans, int32_t n, void *hip_stream
 /*
  * irs_batch_tune -- choose the batch's launch settings by measurement on this
  * device: for the direct method the tile shape and the persistent grid size,
- * timed on the heaviest map's first tiles; for the interpolation the maps per
- * level-3 launch (1, 2 or 6), timed on the six heaviest maps (or, when the
- * maps' level-2 fields do not fit at once, the band height, timed on one
- * band of the heaviest map).  cache_path (or, if NULL,
+ * timed on the heaviest map's first tiles; for the interpolation, when the
+ * maps' level-2 fields do not fit at once, the band height, timed on one band
+ * of the heaviest map (when they fit, level 3 is one launch of a workgroup
+ * per tile and nothing is measured).  cache_path (or, if NULL,
  * the IRS_TUNE_CACHE environment variable; neither: no cache) is a text file
  * of "key = settings" lines keyed by method, precision, mass kind, lens-count
  * and aspect buckets; a cached key is reused without measuring.  The chosen
@@ -359,9 +368,9 @@ irs_status irs_batch_tune(irs_batch_t batch, const char *cache_path);
  * irs_batch_run -- every map of the batch in one graph launch: for the direct
  * method one persistent kernel drains a device queue of (map, ray tile)
  * items ordered longest map first; for the interpolation every map's level-2
- * field (on parallel branches of the graph), then level 3 in launches of up
- * to six maps each (every tile and corner-cell ray of those maps), longest
- * maps first -- when all maps' level-2 fields fit in device memory at once
+ * field (on parallel branches of the graph), then level 3 as one launch of a
+ * workgroup per tile over every map's tiles laid end to end, longest map
+ * first, and one launch over every map's corner-cell rays -- when all maps' level-2 fields fit in device memory at once
  * (60% of the free memory at irs_batch_create, one mass kind); else the maps'
  * band launches on parallel branches.  counts[k] is a DEVICE pointer to map k's
  * npix_side^2 uint32 counts, overwritten.  The graph is captured on the first

@@ -23,7 +23,7 @@ IRS_LEARN_FIELDS = 24
 EXPORTS = ("irs_geometry", "irs_level1_span", "irs_source_side", "irs_plan", "irs_deflect_grid",
            "irs_shoot_rows", "irs_shoot_rows_noalloc", "irs_shoot_map",
            "irs_plan_set_direct_variant", "irs_plan_geometry", "irs_plan_level1", "irs_free",
-           "irs_last_error", "irs_debug_fail_alloc",
+           "irs_last_error", "irs_debug_fail_alloc", "irs_debug_live_allocs",
            "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info",
            "irs_batch_free", "irs_learn_defaults", "irs_learn", "irs_learn_set", "irs_learn_get",
            "irs_learn_corners", "irs_learn_samples", "irs_mlp_forward", "irs_mlp_loss_grad")
@@ -165,6 +165,8 @@ def declare(lib):
     lib.irs_free.restype = None
     lib.irs_debug_fail_alloc.argtypes = [i64]
     lib.irs_debug_fail_alloc.restype = C.c_int
+    lib.irs_debug_live_allocs.argtypes = [vp, vp]
+    lib.irs_debug_live_allocs.restype = C.c_int
     lib.irs_last_error.argtypes = []
     lib.irs_last_error.restype = C.c_char_p
     for name in ("irs_geometry", "irs_level1_span", "irs_source_side", "irs_plan",

@@ -36,10 +36,12 @@ struct irs_batch_s {
                                               // counters per map
     int64_t items = 0;
     // interpolated batches: every map's level 2 resident at once and level 3
-    // in launches of several maps each (whole), else band by band per map
+    // as one launch over every map's tiles (whole), else band by band per map
     bool whole = false;
-    int maps_per_launch = 6;                 // maps per level-3 launch (whole)
     std::vector<char> h_args;                // level-3 launch arguments, LPT order
+    void *d_l3 = nullptr;                    // ... their table on the device
+    int64_t *d_l3start = nullptr;            // the maps' first tiles, then all tiles
+    int64_t *d_l3cstart = nullptr;           // the same for their corner-cell blocks
     // interpolated batches: parallel branches of the graph (default priority)
     std::vector<hipStream_t> lanes;
     std::vector<hipEvent_t> lane_done;
@@ -47,7 +49,7 @@ struct irs_batch_s {
     // captured graph
     hipGraphExec_t exec = nullptr;
     std::vector<uint32_t *> graph_counts;
-    int graph_variant = -1, graph_bpc = -1, graph_band_rows = -1, graph_maps_per_launch = -1;
+    int graph_variant = -1, graph_bpc = -1, graph_band_rows = -1;
 };
 
 namespace {
@@ -98,7 +100,8 @@ irs_status build_direct_tables(irs_batch_s *b, uint32_t *const *counts)
     return IRS_OK;
 }
 
-// Level-3 launch arguments of every map (whole batches), LPT order.
+// Level-3 launch arguments of every map (whole batches), LPT order, and
+// their device table (before a capture: the launch reads the table).
 irs_status build_map_args(irs_batch_s *b, uint32_t *const *counts)
 {
     const int n = (int)b->plans.size();
@@ -111,7 +114,8 @@ irs_status build_map_args(irs_batch_s *b, uint32_t *const *counts)
                                         b->h_args.data() + sz * k);
         if (st != IRS_OK) return st;
     }
-    return IRS_OK;
+    return interp_maps_table(b->h_args.data(), n, b->d_l3, b->d_l3start, b->d_l3cstart,
+                             b->stream);
 }
 
 // Enqueue the whole batch on b->stream (capturable: kernels only).
@@ -131,7 +135,7 @@ irs_status enqueue_all(irs_batch_s *b, uint32_t *const *counts)
     // the maps run on parallel branches (fork from the batch stream, join back);
     // longest first, each onto the branch with the least work so far.  Queue
     // batches: the branches compute the maps' level-2 fields, then one
-    // launches of several maps each shoot every map's rays.
+    // launch shoots every map's tiles, longest map first.
     const int nl = (int)b->lanes.size();
     IRS_HIP(hipEventRecord(b->fork, b->stream));
     for (int l = 0; l < nl; ++l) IRS_HIP(hipStreamWaitEvent(b->lanes[l], b->fork, 0));
@@ -168,7 +172,8 @@ irs_status enqueue_all(irs_batch_s *b, uint32_t *const *counts)
         IRS_HIP(hipStreamWaitEvent(b->stream, b->lane_done[l], 0));
     }
     if (b->whole)
-        return launch_interp_maps(b->stream, b->unit, b->h_args.data(), n, b->maps_per_launch);
+        return launch_interp_maps(b->stream, b->unit, b->h_args.data(), b->d_l3, b->d_l3start,
+                                  b->d_l3cstart, n);
     return IRS_OK;
 }
 
@@ -312,49 +317,6 @@ irs_status time_interp(irs_batch_s *b, int rows, uint32_t *scratch, double &ms)
     return st;
 }
 
-// level 3 of the heaviest min(n, 6) maps in launches of per_launch maps each
-// (their level 2 computed first, outside the timing)
-irs_status time_whole(irs_batch_s *b, int per_launch, uint32_t *scratch, double &ms)
-{
-    const int n = std::min<int>((int)b->plans.size(), 6);
-    const size_t sz = interp_map_args_bytes();
-    std::vector<char> args(sz * n);
-    irs_status st = IRS_OK;
-    for (int k = 0; k < n && st == IRS_OK; ++k) {
-        irs_plan_s *p = b->plans[b->order[k]];
-        hipStream_t saved = p->stream;
-        p->stream = b->stream;
-        st = interp_prepare_whole(p);
-        if (st == IRS_OK) st = interp_level2_whole(p);
-        p->stream = saved;
-        // every map counts into the scratch map: only the time matters here
-        if (st == IRS_OK) st = interp_map_args(p, scratch, b->d_cursor + 1, args.data() + sz * k);
-    }
-    if (st != IRS_OK) return st;
-    hipEvent_t e0, e1;
-    IRS_HIP(hipEventCreate(&e0));
-    IRS_HIP(hipEventCreate(&e1));
-    ms = 0.0;
-    for (int rep = 0; rep < 2 && st == IRS_OK; ++rep) {     // first run warms up
-        st = (hipEventRecord(e0, b->stream) == hipSuccess) ? IRS_OK : IRS_E_DEVICE;
-        if (st == IRS_OK) st = launch_interp_maps(b->stream, b->unit, args.data(), n, per_launch);
-        if (st == IRS_OK && hipEventRecord(e1, b->stream) != hipSuccess) st = IRS_E_DEVICE;
-        if (st == IRS_OK && hipEventSynchronize(e1) != hipSuccess) st = IRS_E_DEVICE;
-        float f = 0.0f;
-        if (st == IRS_OK) (void)hipEventElapsedTime(&f, e0, e1);
-        ms = f;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    for (int k = 0; k < n; ++k) {
-        irs_plan_s *p = b->plans[b->order[k]];
-        p->coef_c0 = -1;
-        p->coef_c1 = -2;
-    }
-    if (st != IRS_OK) set_error("autotuner: timing launch failed");
-    return st;
-}
-
 }  // namespace
 
 extern "C" {
@@ -438,6 +400,11 @@ irs_status irs_batch_create(const irs_plan_t *plans, int32_t n, void *hip_stream
                    (double)need <= kWholeMemFraction * (double)free_b;
         if (b->whole) b->band_rows = 0;
     }
+    if (e == hipSuccess && b->method == IRS_INTERP) {
+        e = dev_alloc(&b->d_l3, interp_map_args_bytes() * n);
+        if (e == hipSuccess) e = dev_alloc(&b->d_l3start, sizeof(int64_t) * (n + 1));
+        if (e == hipSuccess) e = dev_alloc(&b->d_l3cstart, sizeof(int64_t) * (n + 1));
+    }
     if (e == hipSuccess) e = dev_alloc(&b->d_maps, sizeof(DirectArgs) * n);
     if (e == hipSuccess) e = dev_alloc(&b->d_item_start, sizeof(int64_t) * (n + 1));
     if (e == hipSuccess)
@@ -466,15 +433,14 @@ irs_status irs_batch_tune(irs_batch_t b, const char *cache_path)
     const std::string key = tune_key(b);
     std::string val;
     if (!path.empty() && cache_lookup(path, key, val)) {
-        int v = -1, bpc = -1, rows = -1, mpl = 6;
-        const int got = std::sscanf(val.c_str(), "variant=%d bpc=%d band_rows=%d maps_per_launch=%d",
-                                    &v, &bpc, &rows, &mpl);
-        if (got >= 3 && v >= 0 && v < kDirectVariants && bpc > 0 && rows >= 0 && mpl > 0 &&
+        int v = -1, bpc = -1, rows = -1;
+        const int got = std::sscanf(val.c_str(), "variant=%d bpc=%d band_rows=%d", &v, &bpc,
+                                    &rows);
+        if (got >= 3 && v >= 0 && v < kDirectVariants && bpc > 0 && rows >= 0 &&
             (rows == 0) == b->whole) {
             b->variant = v;
             b->bpc = bpc;
             b->band_rows = rows;
-            b->maps_per_launch = mpl;
             b->tuned = b->from_cache = true;
             for (irs_plan_s *p : b->plans) p->direct_variant = v;
             drop_graph(b);
@@ -511,15 +477,7 @@ irs_status irs_batch_tune(irs_batch_t b, const char *cache_path)
             }
         }
     } else if (b->whole) {
-        for (int per : {1, 2, 6}) {
-            double ms = 0.0;
-            st = time_whole(b, per, scratch, ms);
-            if (st != IRS_OK) break;
-            if (ms < best) {
-                best = ms;
-                b->maps_per_launch = per;
-            }
-        }
+        // one level-3 launch of a workgroup per tile: nothing to choose
     } else {
         const int64_t n1y = heavy->dg.n1y;
         for (int rows : {1, 4, 16}) {
@@ -542,8 +500,8 @@ irs_status irs_batch_tune(irs_batch_t b, const char *cache_path)
     drop_graph(b);
     if (!path.empty()) {
         char buf[128];
-        std::snprintf(buf, sizeof buf, "variant=%d bpc=%d band_rows=%d maps_per_launch=%d",
-                      b->variant, b->bpc, b->band_rows, b->maps_per_launch);
+        std::snprintf(buf, sizeof buf, "variant=%d bpc=%d band_rows=%d", b->variant, b->bpc,
+                      b->band_rows);
         cache_store(path, key, buf);
     }
     set_error("");
@@ -566,7 +524,6 @@ irs_status irs_batch_run(irs_batch_t b, uint32_t *const *counts, irs_map_stats *
         }
     const bool same = b->exec && b->graph_variant == b->variant && b->graph_bpc == b->bpc &&
                       b->graph_band_rows == b->band_rows &&
-                      b->graph_maps_per_launch == b->maps_per_launch &&
                       std::equal(b->graph_counts.begin(), b->graph_counts.end(), counts);
     irs_status st = IRS_OK;
     if (!same) {
@@ -594,7 +551,6 @@ irs_status irs_batch_run(irs_batch_t b, uint32_t *const *counts, irs_map_stats *
         b->graph_variant = b->variant;
         b->graph_bpc = b->bpc;
         b->graph_band_rows = b->band_rows;
-        b->graph_maps_per_launch = b->maps_per_launch;
     }
     hipEvent_t e0, e1;
     IRS_HIP(hipEventCreate(&e0));
@@ -661,7 +617,7 @@ irs_status irs_batch_get_info(irs_batch_t b, irs_batch_info *out)
     out->work_items = b->method == IRS_DIRECT ? items : 0;
     out->tune_ms = b->tune_ms;
     out->whole_maps = b->whole ? 1 : 0;
-    out->maps_per_launch = b->whole ? b->maps_per_launch : 0;
+    out->maps_per_launch = b->whole ? (int32_t)b->plans.size() : 0;
     return IRS_OK;
 }
 
@@ -673,6 +629,9 @@ void irs_batch_free(irs_batch_t b)
     dev_free(b->d_maps);
     dev_free(b->d_item_start);
     dev_free(b->d_cursor);
+    dev_free(b->d_l3);
+    dev_free(b->d_l3start);
+    dev_free(b->d_l3cstart);
     for (hipStream_t ls : b->lanes) {
         (void)hipStreamSynchronize(ls);
         (void)hipStreamDestroy(ls);

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "level2.hpp"
@@ -32,6 +33,11 @@ irs_status alloc_allowed(const irs_plan_s *p, const char *what)
 // Allocations left before the one that fails (-1: none fails).
 static std::atomic<int64_t> g_fail_alloc_after{-1};
 
+// Live device allocations: address -> bytes, and their sum.
+static std::mutex g_live_mu;
+static std::unordered_map<void *, size_t> g_live;
+static int64_t g_live_bytes = 0;
+
 hipError_t dev_alloc_bytes(void **ptr, size_t bytes)
 {
     int64_t left = g_fail_alloc_after.load();
@@ -41,7 +47,27 @@ hipError_t dev_alloc_bytes(void **ptr, size_t bytes)
         *ptr = nullptr;
         return hipErrorOutOfMemory;
     }
-    return hipMalloc(ptr, bytes);
+    const hipError_t e = hipMalloc(ptr, bytes);
+    if (e == hipSuccess && *ptr) {
+        std::lock_guard<std::mutex> lock(g_live_mu);
+        g_live[*ptr] = bytes;
+        g_live_bytes += (int64_t)bytes;
+    }
+    return e;
+}
+
+void dev_free(void *ptr)
+{
+    if (!ptr) return;
+    {
+        std::lock_guard<std::mutex> lock(g_live_mu);
+        auto it = g_live.find(ptr);
+        if (it != g_live.end()) {
+            g_live_bytes -= (int64_t)it->second;
+            g_live.erase(it);
+        }
+    }
+    (void)hipFree(ptr);
 }
 
 irs_status hip_fail(hipError_t e, const char *what)
@@ -274,6 +300,18 @@ const char *irs_last_error(void) { return g_last_error.c_str(); }
 irs_status irs_debug_fail_alloc(int64_t after)
 {
     g_fail_alloc_after.store(after < 0 ? -1 : after);
+    return IRS_OK;
+}
+
+irs_status irs_debug_live_allocs(int64_t *count, int64_t *bytes)
+{
+    if (!count || !bytes) {
+        set_error("irs_debug_live_allocs: NULL argument");
+        return IRS_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lock(g_live_mu);
+    *count = (int64_t)g_live.size();
+    *bytes = g_live_bytes;
     return IRS_OK;
 }
 

@@ -1512,46 +1512,58 @@ __global__ __launch_bounds__(kThreads) void k_level3_corner(L3Map m, int64_t i0,
                                  (int64_t)blockIdx.x * kThreads + threadIdx.x);
 }
 
-// A batch's level 3: up to kGroupMaps maps per launch, their arguments in the
-// launch's own argument block (kernel arguments are read through the
-// constant address space and may be reloaded at will, which keeps the tile
-// routine within five waves' registers; a table in ordinary device memory
-// does not).  Workgroup b takes tile b of the maps' tiles laid end to end,
-// each map's column tiles padded to a multiple of the XCDs as for one map.
-constexpr int kGroupMaps = 6;
+// A batch's level 3 as one launch over every map's tiles.  The maps'
+// arguments sit in a table in device memory that does not change during the
+// launch.  Read through the constant address space, its fields come in scalar
+// loads that the compiler may repeat where it needs them, as it does for
+// kernel arguments, so the tile routine stays within five waves' registers;
+// read through a plain pointer it spilled.
+typedef const __attribute__((address_space(4))) L3Map ConstL3Map;
+typedef const __attribute__((address_space(4))) int64_t ConstI64;
 
-struct L3Group {
-    L3Map m[kGroupMaps];
-    int64_t start[kGroupMaps + 1];       // prefix of the maps' (padded) tiles
-    int64_t cstart[kGroupMaps + 1];      // prefix of the maps' corner blocks
-    int32_t n;
-};
-
+// The tiles of n maps laid end to end (start[k] = map k's first tile,
+// start[n] = all tiles; a map's column tiles padded to a multiple of the
+// XCDs, so every start[k] is one too).  Workgroup (x, y) takes tile
+// y gridDim.x + x, gridDim.x a multiple of the XCDs: a column tile always runs
+// on the same XCD, and the dispatcher hands the tiles out in order, longest
+// map first.  (A grid-stride loop over the tiles made the compiler spill.)
 template <bool UNIT>
-__global__ __launch_bounds__(kThreads, 5) void k_level3_group(L3Group grp)
+__global__ __launch_bounds__(kThreads, 5) void k_level3_maps(const L3Map *maps_in,
+                                                             const int64_t *start_in, int32_t n)
 {
     __shared__ L3Lds lds;
-    const int64_t bt = blockIdx.x;
-    int32_t k = 0;
-    while (k + 1 < grp.n && grp.start[k + 1] <= bt) ++k;
-    const L3Map &m = grp.m[k];
-    const int64_t local = bt - grp.start[k];
+    ConstL3Map *maps = (ConstL3Map *)maps_in;
+    ConstI64 *start = (ConstI64 *)start_in;
+    const int64_t t = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (t >= start[n]) return;                              // the last grid row's tail
+    int32_t lo = 0, hi = n;                                 // start[lo] <= t < start[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (start[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    const L3Map &m = *(const L3Map *)&maps[lo];
+    const int64_t local = t - start[lo];
     const int32_t ntx_pad = (m.ntx + kXcds - 1) / kXcds * kXcds;
     const int32_t tx = (int32_t)(local % ntx_pad);
-    if (tx >= m.ntx) return;                               // padding (block-uniform)
-    level3_tile<UNIT, true>(m, tx, (int32_t)(local / ntx_pad), &lds);
+    if (tx < m.ntx)                                         // padding (block-uniform)
+        level3_tile<UNIT, true>(m, tx, (int32_t)(local / ntx_pad), &lds);
 }
 
-// The same maps' corner-cell rays: block b takes kThreads rays of one
-// corner cell (the maps' corner blocks laid end to end).
+// The same maps' corner-cell rays: block b takes kThreads rays of one corner
+// cell (the maps' corner blocks laid end to end, cstart like start).
 template <bool UNIT>
-__global__ __launch_bounds__(kThreads) void k_level3_group_corners(L3Group grp)
+__global__ __launch_bounds__(kThreads) void k_level3_maps_corners(const L3Map *maps_in,
+                                                                  const int64_t *cstart_in,
+                                                                  int32_t n)
 {
+    ConstL3Map *maps = (ConstL3Map *)maps_in;
+    ConstI64 *cstart = (ConstI64 *)cstart_in;
     const int64_t bt = blockIdx.x;
     int32_t k = 0;
-    while (k + 1 < grp.n && grp.cstart[k + 1] <= bt) ++k;
-    const L3Map &m = grp.m[k];
-    const int64_t ci = bt - grp.cstart[k];
+    while (k + 1 < n && cstart[k + 1] <= bt) ++k;
+    const L3Map &m = *(const L3Map *)&maps[k];
+    const int64_t ci = bt - cstart[k];
     int c = 0;
     while (c + 1 < m.ncorner && m.corner_items[c + 1] <= ci) ++c;
     level3_corner_ray<UNIT, true>(m, m.corner[c][0], m.corner[c][1], m.corner[c][2],
@@ -2451,7 +2463,7 @@ irs_status launch_interp(irs_plan_s *p, const RaySel &sel)
     return IRS_OK;
 }
 
-// ---- a batch's level 3 as one persistent launch -----------------------------
+// ---- a batch's level 3 as one launch over every map's tiles ------------------
 
 size_t interp_map_args_bytes() { return sizeof(L3Map); }
 
@@ -2508,37 +2520,57 @@ irs_status interp_map_args(irs_plan_s *p, uint32_t *counts, unsigned long long *
     return IRS_OK;
 }
 
-irs_status launch_interp_maps(hipStream_t s, bool unit, const void *args, int32_t n,
-                              int32_t per_launch)
+irs_status interp_maps_table(const void *args, int32_t n, void *d_maps, int64_t *d_start,
+                             int64_t *d_cstart, hipStream_t s)
 {
     const L3Map *maps = (const L3Map *)args;
-    per_launch = std::max(1, std::min(per_launch, kGroupMaps));
-    for (int32_t k0 = 0; k0 < n; k0 += per_launch) {
-        L3Group grp{};
-        grp.n = std::min(per_launch, n - k0);
-        for (int32_t k = 0; k < grp.n; ++k) {
-            grp.m[k] = maps[k0 + k];
-            grp.start[k + 1] = grp.start[k] + maps[k0 + k].tiles;
-            grp.cstart[k + 1] = grp.cstart[k] + maps[k0 + k].corner_items[4];
+    std::vector<int64_t> start(n + 1, 0), cstart(n + 1, 0);
+    for (int32_t k = 0; k < n; ++k) {
+        start[k + 1] = start[k] + maps[k].tiles;
+        cstart[k + 1] = cstart[k] + maps[k].corner_items[4];
+    }
+    IRS_HIP(hipMemcpyAsync(d_maps, args, sizeof(L3Map) * (size_t)n, hipMemcpyHostToDevice, s));
+    IRS_HIP(hipMemcpyAsync(d_start, start.data(), sizeof(int64_t) * (size_t)(n + 1),
+                           hipMemcpyHostToDevice, s));
+    IRS_HIP(hipMemcpyAsync(d_cstart, cstart.data(), sizeof(int64_t) * (size_t)(n + 1),
+                           hipMemcpyHostToDevice, s));
+    IRS_HIP(hipStreamSynchronize(s));
+    return IRS_OK;
+}
+
+irs_status launch_interp_maps(hipStream_t s, bool unit, const void *args, const void *d_maps,
+                              const int64_t *d_start, const int64_t *d_cstart, int32_t n)
+{
+    const L3Map *maps = (const L3Map *)args;
+    int64_t tiles = 0, corners = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        tiles += maps[k].tiles;
+        corners += maps[k].corner_items[4];
+    }
+    if (tiles > 0) {
+        // rows of up to 2^23 workgroups (a multiple of the XCDs; 2^31 threads)
+        const int64_t gx = std::min<int64_t>((tiles + kXcds - 1) / kXcds * kXcds, 1 << 23);
+        const int64_t gy = (tiles + gx - 1) / gx;
+        if (gy > 65535) {
+            set_error("too many level-3 tiles in one batch");
+            return IRS_E_INVALID;
         }
-        if (grp.start[grp.n] > 0) {
-            if (unit)
-                hipLaunchKernelGGL(k_level3_group<true>, dim3((unsigned)grp.start[grp.n]),
-                                   dim3(kThreads), 0, s, grp);
-            else
-                hipLaunchKernelGGL(k_level3_group<false>, dim3((unsigned)grp.start[grp.n]),
-                                   dim3(kThreads), 0, s, grp);
-            IRS_HIP(hipGetLastError());
-        }
-        if (grp.cstart[grp.n] > 0) {
-            if (unit)
-                hipLaunchKernelGGL(k_level3_group_corners<true>, dim3((unsigned)grp.cstart[grp.n]),
-                                   dim3(kThreads), 0, s, grp);
-            else
-                hipLaunchKernelGGL(k_level3_group_corners<false>, dim3((unsigned)grp.cstart[grp.n]),
-                                   dim3(kThreads), 0, s, grp);
-            IRS_HIP(hipGetLastError());
-        }
+        if (unit)
+            hipLaunchKernelGGL(k_level3_maps<true>, dim3((unsigned)gx, (unsigned)gy),
+                               dim3(kThreads), 0, s, (const L3Map *)d_maps, d_start, n);
+        else
+            hipLaunchKernelGGL(k_level3_maps<false>, dim3((unsigned)gx, (unsigned)gy),
+                               dim3(kThreads), 0, s, (const L3Map *)d_maps, d_start, n);
+        IRS_HIP(hipGetLastError());
+    }
+    if (corners > 0) {
+        if (unit)
+            hipLaunchKernelGGL(k_level3_maps_corners<true>, dim3((unsigned)corners),
+                               dim3(kThreads), 0, s, (const L3Map *)d_maps, d_cstart, n);
+        else
+            hipLaunchKernelGGL(k_level3_maps_corners<false>, dim3((unsigned)corners),
+                               dim3(kThreads), 0, s, (const L3Map *)d_maps, d_cstart, n);
+        IRS_HIP(hipGetLastError());
     }
     return IRS_OK;
 }

@@ -104,15 +104,12 @@ struct irs_plan_s {
 
 namespace irs {
 
-inline void dev_free(void *ptr)
-{
-    if (ptr) (void)hipFree(ptr);
-}
-
 // Every device allocation of the library: hipMalloc, or hipErrorOutOfMemory
 // (nothing allocated, *ptr null) for the allocation that the countdown of
-// irs_debug_fail_alloc selects.
+// irs_debug_fail_alloc selects; and its release (NULL ignored).  Both keep
+// the ledger of live allocations that irs_debug_live_allocs reports.
 hipError_t dev_alloc_bytes(void **ptr, size_t bytes);
+void dev_free(void *ptr);
 template <class T>
 inline hipError_t dev_alloc(T **ptr, size_t bytes)
 {
@@ -200,17 +197,21 @@ irs_status interp_tables_ready(irs_plan_s *p);
 // Interpolated batches with every map's level 2 resident at once: the bytes
 // a map's whole-map level-2 buffers take; allocate them (before a capture);
 // compute a map's whole level-2 field on its stream; a map's level-3 launch
-// arguments (interp_map_args_bytes() bytes into out); and the level 3 of n
-// maps (args: their arguments, in launch order) in launches of up to
-// per_launch maps each (at most 6), every map's tiles and corner-cell rays.
+// arguments (interp_map_args_bytes() bytes into out); the device table of n
+// maps' arguments (args, in launch order) and their tile and corner-block
+// prefixes (d_maps: n args, d_start and d_cstart: n + 1 each; copied and
+// synchronised on s); and the level 3 of those maps as one launch over every
+// map's tiles (a workgroup a tile) plus one over their corner-cell rays.
 int64_t interp_whole_map_bytes(const irs_plan_s *p);
 irs_status interp_prepare_whole(irs_plan_s *p);
 irs_status interp_level2_whole(irs_plan_s *p);
 size_t interp_map_args_bytes();
 irs_status interp_map_args(irs_plan_s *p, uint32_t *counts, unsigned long long *landed,
                            void *out);
-irs_status launch_interp_maps(hipStream_t s, bool unit, const void *args, int32_t n,
-                              int32_t per_launch);
+irs_status interp_maps_table(const void *args, int32_t n, void *d_maps, int64_t *d_start,
+                             int64_t *d_cstart, hipStream_t s);
+irs_status launch_interp_maps(hipStream_t s, bool unit, const void *args, const void *d_maps,
+                              const int64_t *d_start, const int64_t *d_cstart, int32_t n);
 // Fill kernel (graph-safe zeroing): n 32-bit words.
 irs_status launch_zero(hipStream_t s, void *ptr, size_t n_words);
 

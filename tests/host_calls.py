@@ -114,6 +114,7 @@ def run(path):
         "mlp_forward": lambda: lib.irs_mlp_forward(-1, None, None, None, None, None),
         "mlp_loss_grad": lambda: lib.irs_mlp_loss_grad(-1, None, None, None, None, None, None),
         "fail_alloc": lambda: lib.irs_debug_fail_alloc(-1),
+        "live_allocs": lambda: lib.irs_debug_live_allocs(None, None),
     }
     for name, f in calls.items():
         out[f"call {name}"] = [f(), _error(lib)]

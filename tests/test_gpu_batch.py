@@ -66,7 +66,7 @@ def test_batch_matches_oracle(irs, method, precision, whole, monkeypatch):
     whose pixels the batch map must histogram to exactly), and the batch's
     counts: bit-exact on every pixel no mismatched ray touches, rel-L1.
     Interpolated batches both with every map's level 2 at once (level 3 in
-    multi-map launches) and band by band."""
+    one launch over every map's tiles) and band by band."""
     import torch
     if whole == 0:
         monkeypatch.setenv("IRS_BATCH_BANDS", "1")

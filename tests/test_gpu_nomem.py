@@ -2,8 +2,12 @@
 chosen device allocation of the library fail, as an exhausted hipMalloc
 would: the call must return IRS_E_NOMEM, a failed irs_plan or
 irs_batch_create must leave a NULL handle, nothing the failed call allocated
-may stay allocated, and a plan that exists must keep working (the next call
-without the failure gives the same map as a fresh plan)."""
+may stay allocated, and a plan or batch that exists must keep working (the
+next call without the failure gives the same map as a fresh plan).
+
+What stays allocated is read from the library's own ledger of live device
+allocations (irs_debug_live_allocs), exactly: the device's free memory is no
+measure of it, since the HIP runtime may keep freed memory for a while."""
 import ctypes as C
 
 import numpy as np
@@ -14,7 +18,6 @@ from gpu_common import Case
 pytestmark = pytest.mark.gpu
 
 IRS_E_NOMEM = 3
-SLACK = 4 << 20          # bytes of device memory the runtime may keep in its pools
 
 
 @pytest.fixture(scope="module")
@@ -28,11 +31,11 @@ def say(msg):
     print(msg, flush=True)
 
 
-def _used():
-    import torch
-    torch.cuda.synchronize()
-    free, total = torch.cuda.mem_get_info()
-    return total - free
+def _live(lib):
+    """(count, bytes) of the library's live device allocations."""
+    n, b = C.c_int64(-1), C.c_int64(-1)
+    assert lib.irs_debug_live_allocs(C.byref(n), C.byref(b)) == 0
+    return n.value, b.value
 
 
 def _case():
@@ -67,22 +70,16 @@ def _plan_cycle(lib, c, p, x, y):
         assert k < 100
 
 
-# A leak on a failure path repeats with every cycle of failures, while what
-# the runtime keeps in its own pools after the first cycle does not: each
-# test runs its cycle once, then measures a second, identical cycle.
-
 @pytest.mark.parametrize("method", ["direct", "interp"])
 def test_plan_fails_cleanly_at_every_allocation(irs, method):
     lib = irs._ffi.load()
     c = _case()
     p, x, y = _plan_args(irs, c, method)
+    before = _live(lib)
     k = _plan_cycle(lib, c, p, x, y)
-    base = _used()
-    assert _plan_cycle(lib, c, p, x, y) == k
-    leaked = _used() - base
-    say(f"irs_plan ({method}): {k} allocations failed in turn, {leaked} bytes kept")
+    say(f"irs_plan ({method}): {k} allocations failed in turn, live after: {_live(lib)}")
     assert k >= 5
-    assert leaked <= SLACK
+    assert _live(lib) == before
 
 
 def _map_cycle(irs, lib, c, want):
@@ -116,13 +113,11 @@ def test_map_fails_cleanly_and_the_plan_recovers(irs):
     c = _case()
     with c.plan("interp", "fp64") as ref:
         want, _ = ref.shoot_map()
+    before = _live(lib)
     k = _map_cycle(irs, lib, c, want)
-    base = _used()
-    assert _map_cycle(irs, lib, c, want) == k
-    leaked = _used() - base
-    say(f"irs_shoot_map: {k} allocations failed in turn, {leaked} bytes kept")
+    say(f"irs_shoot_map: {k} allocations failed in turn, live after: {_live(lib)}")
     assert k >= 3
-    assert leaked <= SLACK
+    assert _live(lib) == before
 
 
 def _batch_cycle(lib, arr, n):
@@ -141,19 +136,72 @@ def _batch_cycle(lib, arr, n):
         assert k < 100
 
 
-def test_batch_create_fails_cleanly(irs):
+def _small_cases(seed):
+    return [Case(0.3, 0.0, 0.3, 8.0, 64, n_rays=100_000 + 977 * i, seed=seed + i)
+            for i in range(3)]
+
+
+@pytest.mark.parametrize("method,precision", [("direct", "fp32"), ("interp", "fp64")])
+def test_batch_create_fails_cleanly(irs, method, precision):
     lib = irs._ffi.load()
-    cases = [Case(0.3, 0.0, 0.3, 8.0, 64, n_rays=100_000, seed=70 + i) for i in range(3)]
-    plans = [cc.plan("direct", "fp32") for cc in cases]
+    before = _live(lib)
+    plans = [cc.plan(method, precision) for cc in _small_cases(70)]
     try:
+        with_plans = _live(lib)
         arr = (C.c_void_p * len(plans))(*[pl.handle.value for pl in plans])
         k = _batch_cycle(lib, arr, len(plans))
-        base = _used()
-        assert _batch_cycle(lib, arr, len(plans)) == k
-        leaked = _used() - base
-        say(f"irs_batch_create: {k} allocations failed in turn, {leaked} bytes kept")
+        say(f"irs_batch_create ({method}): {k} allocations failed in turn")
         assert k >= 1
-        assert leaked <= SLACK
+        assert _live(lib) == with_plans
     finally:
         for pl in plans:
             pl.close()
+    assert _live(lib) == before
+
+
+def test_batch_run_fails_cleanly_and_recovers(irs):
+    """Each allocation of an interpolated batch's first run (every map's
+    whole-map level-2 buffers and tables) fails in turn; the run that
+    follows gives every map as its plan alone does, and freeing the batch
+    and plans leaves nothing allocated."""
+    import torch
+    lib = irs._ffi.load()
+    cases = _small_cases(80)
+    want = []
+    for cc in cases:
+        with cc.plan("interp", "fp64") as pl:
+            want.append(pl.shoot_map()[0])
+    before = _live(lib)
+    plans = [cc.plan("interp", "fp64") for cc in cases]
+    try:
+        with irs.Batch(plans) as b:
+            info = b.info()
+            assert info["whole_maps"] == 1, info
+            counts = [torch.empty(cc.geo.npix ** 2, dtype=torch.int32, device="cuda:0")
+                      for cc in cases]
+            ptrs = (C.c_void_p * len(counts))(*[t.data_ptr() for t in counts])
+            k = 0
+            while True:
+                lib.irs_debug_fail_alloc(k)
+                st = lib.irs_batch_run(b._h, ptrs, None, 0)
+                lib.irs_debug_fail_alloc(-1)
+                if st == 0:
+                    break
+                assert st == IRS_E_NOMEM, (k, st)
+                k += 1
+                assert k < 200
+            torch.cuda.synchronize()
+            say(f"irs_batch_run: {k} allocations failed in turn")
+            assert k >= 3
+            for cc, t, w in zip(cases, counts, want):
+                got = t.cpu().numpy().view(np.uint32).reshape(cc.geo.npix, cc.geo.npix)
+                assert np.array_equal(got, w)
+            assert lib.irs_batch_run(b._h, ptrs, None, 0) == 0          # the graph replays
+            torch.cuda.synchronize()
+            for cc, t, w in zip(cases, counts, want):
+                got = t.cpu().numpy().view(np.uint32).reshape(cc.geo.npix, cc.geo.npix)
+                assert np.array_equal(got, w)
+    finally:
+        for pl in plans:
+            pl.close()
+    assert _live(lib) == before
