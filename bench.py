@@ -26,6 +26,7 @@ import argparse
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -390,23 +391,27 @@ def _batch_plans(irs, synth, torch, stream, method, precision, rays_per_pixel=No
     return plans, counts
 
 
-def _batch_vs_sequential(irs, torch, plans, counts):
-    """(tuned settings, graph seconds, one-by-one seconds, identical maps)."""
+def _batch_vs_sequential(irs, torch, plans, counts, repeats=3):
+    """(tuned settings, graph seconds, one-by-one seconds, identical maps);
+    each time the median of `repeats` runs."""
+    def timed(f):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        f()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
     with irs.Batch(plans) as b:
         info = b.tune()
         b.run(counts)                                      # capture + first replay
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        b.run(counts)
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - tb
+        tb = statistics.median(timed(lambda: b.run(counts)) for _ in range(repeats))
     batched = [c.clone() for c in counts]
-    torch.cuda.synchronize()
-    ts = time.perf_counter()
-    for p, c in zip(plans, counts):
-        p.shoot_map_device(c)            # computes every expansion, as the graph does
-    torch.cuda.synchronize()
-    ts = time.perf_counter() - ts
+
+    def one_by_one():
+        for p, c in zip(plans, counts):
+            p.shoot_map_device(c)        # computes every expansion, as the graph does
+
+    ts = statistics.median(timed(one_by_one) for _ in range(repeats))
     same = all(torch.equal(a, c) for a, c in zip(batched, counts))
     return info, tb, ts, same
 
@@ -415,7 +420,7 @@ def bench_batch(irs, synth, torch, stream):
     """The 64-map batch (kappa_*, gamma ~ U[0.1, 0.8], kappa_c in {0, 0.2},
     N_* = 10^U[3, 5], 1024^2..4096^2 px): one tuned graph launch against the
     same maps launched one after another.  Interpolated at 100 rays/px (every
-    map's level 2, then one persistent level-3 queue); and the FP32 direct sum
+    map's level 2, then one level-3 launch over every map's tiles); and the FP32 direct sum
     with the tuner's tile shape, at 1 ray/px (the stated 100 rays/px would
     take ~190 s of direct sums)."""
     out = {}

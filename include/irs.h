@@ -503,6 +503,17 @@ irs_status irs_learn_samples(irs_plan_t plan, int32_t coarse, int64_t row0, int6
                              int32_t per_cell, uint64_t seed, float *out);
 
 /*
+ * irs_learn_weights -- the plan's learned weights L(h) at n in-square offsets,
+ * exactly as its rays take them: the network's 16 outputs at the 33 x 33
+ * nodes (a/32, b/32) of the unit square, tabulated whenever irs_learn or
+ * irs_learn_set validates a network, blended bilinearly between the four
+ * nodes around h (h clamped to [0, 1]^2).  h: DEVICE, 2 x n (hx row then hy
+ * row); y: DEVICE, 16 x n (y[o n + k]).  Runs on the plan's stream and waits
+ * for it.  IRS_E_INVALID on a NULL argument, n < 0 or a plan with no network.
+ */
+irs_status irs_learn_weights(irs_plan_t plan, int64_t n, const float *h, float *y);
+
+/*
  * irs_mlp_forward -- the network's outputs y (DEVICE, 16 x n: y[o n + k]) at
  * offsets h (DEVICE, 2 x n: hx row then hy row), with the inference kernel.
  * freqs, theta: host arrays as above.  hip_stream: NULL for the default stream.

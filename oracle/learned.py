@@ -26,6 +26,13 @@ The correction is linear in the local data (for an analytic field the error of
 I is a linear functional of A that vanishes on linear functions), so the network
 only has to learn interpolation weights as functions of the position h.
 
+Rays take those weights from a table: L depends on h alone, so the network is
+evaluated at the (T+1)^2 nodes (a/T, b/T), a, b = 0..T, T = 32, of the unit
+square, and a ray's weights are the bilinear blend of the four nodes around
+its h (h clamped to [0, 1]^2; cell (a, b) = (min(floor(T hx), T-1), ...)).
+The training fits the network itself; the validation and the rays use the
+blended table.
+
 Network (all real):
   phi_j(h)   = sin(2 pi f_j . (h - 1/2)),  phi_{64+j} = cos(2 pi f_j . (h - 1/2)),
                j = 0..63, frequencies f (64 x 2) given;
@@ -37,8 +44,9 @@ Training loss over n samples: (1/n) sum |sum_k L_k D_k - T|^2 with
 T = (A(z) - I(z)) / sigma.
 
 Pinned by: central finite differences of the loss (the backward pass), a
-closed-form forward special case, and the base interpolant's closed-form error
-on quadratic fields (tests/test_oracle_learned.py).
+closed-form forward special case, the base interpolant's closed-form error
+on quadratic fields, and the table blend's exactness on bilinear functions and
+its error bound on smooth ones (tests/test_oracle_learned.py).
 """
 import numpy as np
 
@@ -83,6 +91,35 @@ def forward(theta, freqs, h):
         cache.append(a)
     y = a @ P[2 * N_LAYERS].T + P[2 * N_LAYERS + 1]
     return y, cache
+
+
+TABLE_SIDE = 32
+
+
+def table_nodes(T=TABLE_SIDE):
+    """Offsets (n, 2) of the table's nodes, node b (T+1) + a at (a/T, b/T)."""
+    a = np.arange(T + 1, dtype=np.float64) / T
+    hx, hy = np.meshgrid(a, a)               # hx varies along a row (a), hy down (b)
+    return np.stack([hx.ravel(), hy.ravel()], axis=1)
+
+
+def table_blend(Y, h, T=TABLE_SIDE):
+    """Bilinear blend (n, m) of node values Y ((T+1)^2, m) at offsets h (n, 2)."""
+    h = np.clip(np.asarray(h, dtype=np.float64), 0.0, 1.0) * T
+    a = np.minimum(np.floor(h[:, 0]).astype(np.int64), T - 1)
+    b = np.minimum(np.floor(h[:, 1]).astype(np.int64), T - 1)
+    fu = (h[:, 0] - a)[:, None]
+    fv = (h[:, 1] - b)[:, None]
+    k = b * (T + 1) + a
+    return ((1 - fu) * (1 - fv) * Y[k] + fu * (1 - fv) * Y[k + 1]
+            + (1 - fu) * fv * Y[k + T + 1] + fu * fv * Y[k + T + 2])
+
+
+def table_weights(theta, freqs, h):
+    """The weights (n, 16) the rays take at offsets h: the network's outputs
+    at the table's nodes, blended."""
+    Y, _ = forward(theta, freqs, table_nodes())
+    return table_blend(Y, h)
 
 
 def weights_complex(y):
@@ -158,9 +195,10 @@ def local_data(zc, Ac, dAc, sx, sy, tiny=1e-280):
 
 
 def learned_value(theta, freqs, zc, Ac, dAc, sx, sy, h, z):
-    """I(z) + sigma sum_k L_k(h) D_k."""
+    """I(z) + sigma sum_k L_k(h) D_k, L from the blended table."""
     D, sigma = local_data(zc, Ac, dAc, sx, sy)
-    return base_interp(zc, Ac, dAc, h, z) + sigma * predict(theta, freqs, h, D)
+    L = weights_complex(table_weights(theta, freqs, h))
+    return base_interp(zc, Ac, dAc, h, z) + sigma * np.sum(L * D, axis=1)
 
 
 # ---------------------------------------------------------------------------

@@ -309,6 +309,12 @@ class Plan:
                                            int(per_cell), int(seed), _dev_ptr(out)),
                "irs_learn_samples")
 
+    def learn_weights(self, h, y):
+        """The plan's learned weights, as its rays take them, into y (device
+        tensor, 16 x n float32) at offsets h (device tensor, 2 x n float32)."""
+        _check(self._lib.irs_learn_weights(self._h, int(h.shape[-1]), _dev_ptr(h), _dev_ptr(y)),
+               "irs_learn_weights")
+
     def set_direct_variant(self, v: int):
         """FP32 direct tile shape (0, 1, 2); results are identical for all."""
         _check(self._lib.irs_plan_set_direct_variant(self._h, int(v)),

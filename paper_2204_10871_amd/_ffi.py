@@ -26,7 +26,8 @@ EXPORTS = ("irs_geometry", "irs_level1_span", "irs_source_side", "irs_plan", "ir
            "irs_last_error", "irs_debug_fail_alloc", "irs_debug_live_allocs",
            "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info",
            "irs_batch_free", "irs_learn_defaults", "irs_learn", "irs_learn_set", "irs_learn_get",
-           "irs_learn_corners", "irs_learn_samples", "irs_mlp_forward", "irs_mlp_loss_grad")
+           "irs_learn_corners", "irs_learn_samples", "irs_learn_weights", "irs_mlp_forward",
+           "irs_mlp_loss_grad")
 
 
 class Params(C.Structure):
@@ -159,6 +160,7 @@ def declare(lib):
     lib.irs_learn_get.argtypes = [vp, vp, vp, P(i32)]
     lib.irs_learn_corners.argtypes = [vp, i32, i64, i64, vp]
     lib.irs_learn_samples.argtypes = [vp, i32, i64, i64, i32, u64, vp]
+    lib.irs_learn_weights.argtypes = [vp, i64, vp, vp]
     lib.irs_mlp_forward.argtypes = [i64, vp, vp, vp, vp, vp]
     lib.irs_mlp_loss_grad.argtypes = [i64, vp, vp, vp, P(C.c_double), vp, vp]
     lib.irs_free.argtypes = [vp]
@@ -174,6 +176,7 @@ def declare(lib):
                  "irs_plan_geometry", "irs_plan_level1", "irs_plan_set_direct_variant",
                  "irs_batch_create", "irs_batch_tune", "irs_batch_run", "irs_batch_get_info",
                  "irs_learn_defaults", "irs_learn", "irs_learn_set", "irs_learn_get",
-                 "irs_learn_corners", "irs_learn_samples", "irs_mlp_forward", "irs_mlp_loss_grad"):
+                 "irs_learn_corners", "irs_learn_samples", "irs_learn_weights",
+                 "irs_mlp_forward", "irs_mlp_loss_grad"):
         getattr(lib, name).restype = C.c_int
     return lib

@@ -235,22 +235,36 @@ __device__ __forceinline__ void square_eval(const double C[4][4], double X0, dou
     }
     mAr *= 0.25; mAi *= 0.25; mdr *= 0.25; mdi *= 0.25; mzx *= 0.25; mzy *= 0.25;
     const double s = 0.5 * (lg.sx + lg.sy);
-    double dd[16];
-    double sig = 0.0;
+    // the data of corner c (delta_c, eps_c), formed twice (for sigma, then
+    // scaled) so that the 16 values are never held at once; sigma is the
+    // root of the largest squared size (the root is monotonic: the same
+    // value as the largest root)
+    auto data = [&](int c, double dd[4]) {
+        dd[0] = (C[c][2] - mdr) * s;
+        dd[1] = (C[c][3] - mdi) * s;
+        const double vx = zx[c] - mzx, vy = zy[c] - mzy;
+        dd[2] = C[c][0] - mAr - (mdr * vx - mdi * vy);
+        dd[3] = C[c][1] - mAi - (mdr * vy + mdi * vx);
+    };
+    double sig2 = 0.0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        dd[2 * c] = (C[c][2] - mdr) * s;
-        dd[2 * c + 1] = (C[c][3] - mdi) * s;
-        const double vx = zx[c] - mzx, vy = zy[c] - mzy;
-        dd[8 + 2 * c] = C[c][0] - mAr - (mdr * vx - mdi * vy);
-        dd[8 + 2 * c + 1] = C[c][1] - mAi - (mdr * vy + mdi * vx);
-        sig = fmax(sig, sqrt(dd[2 * c] * dd[2 * c] + dd[2 * c + 1] * dd[2 * c + 1]));
-        sig = fmax(sig, sqrt(dd[8 + 2 * c] * dd[8 + 2 * c] + dd[8 + 2 * c + 1] * dd[8 + 2 * c + 1]));
+        double dd[4];
+        data(c, dd);
+        sig2 = fmax(sig2, dd[0] * dd[0] + dd[1] * dd[1]);
+        sig2 = fmax(sig2, dd[2] * dd[2] + dd[3] * dd[3]);
     }
-    sig = fmax(sig, 1e-280);
+    const double sig = fmax(sqrt(sig2), 1e-280);
     const double is = 1.0 / sig;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) o.D[k] = (float)(dd[k] * is);
+    for (int c = 0; c < 4; ++c) {
+        double dd[4];
+        data(c, dd);
+        o.D[2 * c] = (float)(dd[0] * is);
+        o.D[2 * c + 1] = (float)(dd[1] * is);
+        o.D[8 + 2 * c] = (float)(dd[2] * is);
+        o.D[8 + 2 * c + 1] = (float)(dd[3] * is);
+    }
     o.Ir = Ir;
     o.Ii = Ii;
     o.sigma = sig;
@@ -265,6 +279,64 @@ __device__ __forceinline__ void combine(const float y[kNO], const float D[16], f
     for (int k = 0; k < 8; ++k) {
         pr = fmaf(y[2 * k], D[2 * k], fmaf(-y[2 * k + 1], D[2 * k + 1], pr));
         pi = fmaf(y[2 * k], D[2 * k + 1], fmaf(y[2 * k + 1], D[2 * k], pi));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The weights L(h) as the rays take them: the network's 16 outputs at the
+// (kLTab + 1)^2 nodes (a/kLTab, b/kLTab) of the unit square (node b (kLTab+1)
+// + a), blended bilinearly between the four nodes around h.  L depends on h
+// alone, so the network runs once per node instead of once per ray; the
+// blend's own error is far inside the network's (its features turn slowly
+// over the square, and the validation measures the blended weights).
+// ---------------------------------------------------------------------------
+constexpr int kLTab = 32;
+constexpr int kLNodes = (kLTab + 1) * (kLTab + 1);
+
+// value (o, node k) = t[k NS + o OS]; h outside [0, 1] (rounding) is clamped
+template <int NS, int OS>
+__device__ __forceinline__ void ltab_blend(const float *__restrict__ t, float hx, float hy,
+                                           float y[kNO])
+{
+    const float u = fminf(fmaxf(hx, 0.0f), 1.0f) * (float)kLTab;
+    const float v = fminf(fmaxf(hy, 0.0f), 1.0f) * (float)kLTab;
+    const int a = min((int)u, kLTab - 1), b = min((int)v, kLTab - 1);
+    const float fu = u - (float)a, fv = v - (float)b;
+    const float w00 = (1.0f - fu) * (1.0f - fv), w10 = fu * (1.0f - fv);
+    const float w01 = (1.0f - fu) * fv, w11 = fu * fv;
+    const float *t00 = t + (b * (kLTab + 1) + a) * NS;
+    const float *t01 = t00 + (kLTab + 1) * NS;
+#pragma unroll
+    for (int o = 0; o < kNO; ++o)
+        y[o] = w00 * t00[o * OS] + w10 * t00[NS + o * OS] + w01 * t01[o * OS] +
+               w11 * t01[NS + o * OS];
+}
+
+// sum_k L_k D_k with L the table's blend at (hx, hy) (combine's arithmetic on
+// ltab_blend's weights, one weight pair at a time)
+template <int NS, int OS>
+__device__ __forceinline__ void ltab_combine(const float *__restrict__ t, float hx, float hy,
+                                             const float D[16], float &pr, float &pi)
+{
+    const float u = fminf(fmaxf(hx, 0.0f), 1.0f) * (float)kLTab;
+    const float v = fminf(fmaxf(hy, 0.0f), 1.0f) * (float)kLTab;
+    const int a = min((int)u, kLTab - 1), b = min((int)v, kLTab - 1);
+    const float fu = u - (float)a, fv = v - (float)b;
+    const float w00 = (1.0f - fu) * (1.0f - fv), w10 = fu * (1.0f - fv);
+    const float w01 = (1.0f - fu) * fv, w11 = fu * fv;
+    const float *t00 = t + (b * (kLTab + 1) + a) * NS;
+    const float *t01 = t00 + (kLTab + 1) * NS;
+    auto at = [&](int o) {
+        return w00 * t00[o * OS] + w10 * t00[NS + o * OS] + w01 * t01[o * OS] +
+               w11 * t01[NS + o * OS];
+    };
+    pr = 0.0f;
+    pi = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float yr = at(2 * k), yi = at(2 * k + 1);
+        pr = fmaf(yr, D[2 * k], fmaf(-yi, D[2 * k + 1], pr));
+        pi = fmaf(yr, D[2 * k + 1], fmaf(yi, D[2 * k], pi));
     }
 }
 
@@ -817,10 +889,25 @@ __global__ __launch_bounds__(kThreads) void k_learn_err(const float *__restrict_
     err_base[k] = sg * sqrtf(Tr * Tr + Ti * Ti);
 }
 
+// The blended weights at n offsets hin (hx row, hy row) from the table tab
+// (output-major: tab[o kLNodes + node]) into yout (16 x n: yout[o n + k]).
+__global__ __launch_bounds__(kThreads) void k_ltab_eval(const float *__restrict__ tab, int64_t n,
+                                                        const float *__restrict__ hin,
+                                                        float *__restrict__ yout)
+{
+    for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * kThreads) {
+        float y[kNO];
+        ltab_blend<1, kLNodes>(tab, hin[k], hin[n + k], y);
+#pragma unroll
+        for (int o = 0; o < kNO; ++o) yout[(int64_t)o * n + k] = y[o];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Rays with the learned interpolant.  One wave = 64 consecutive rays of a row;
-// a persistent workgroup of 8 waves keeps the network in LDS and walks the
-// band's (row, 64-column) items.
+// a persistent workgroup of 8 waves keeps the weight table in LDS and walks
+// the band's (row, 64-column) items.
 // ---------------------------------------------------------------------------
 constexpr int kL3Threads = 512;
 
@@ -848,29 +935,37 @@ __device__ __forceinline__ void near_lens(double t1, double t2, double zx, doubl
     n2 = fma(w, d2, n2);
 }
 
-template <bool UNIT>
-__global__ __launch_bounds__(kL3Threads) void k_level3_learned(
-    DevGeom g, LearnGeom lg, const double *__restrict__ lx, const double *__restrict__ ly,
-    const double *__restrict__ lm, const int32_t *__restrict__ cell_start,
-    const double *__restrict__ corner, int32_t cy0, const uint4 *__restrict__ wf,
-    const float *__restrict__ theta, const float *__restrict__ freq, int64_t ntx, int64_t j0,
-    int64_t j1, int64_t ray_first, int64_t ray_last, double *a1o, double *a2o, int64_t *pixo,
-    uint32_t *counts, unsigned long long *landed)
+// Rays of columns [i0, i1) and rows [j0, j1) in items of 64 columns of one
+// row.  CORNER = false: the sheet's analytic part outside the four corner
+// cells of the rectangle, whose rays (with a sheet) it leaves out;
+// CORNER = true: rays of one of those cells, with the sheet's closed form
+// (its logarithms would otherwise set every ray's register budget).
+#define IRS_LEARNED_RAY_ARGS                                                                      \
+    DevGeom g, LearnGeom lg, const double *__restrict__ lx, const double *__restrict__ ly,        \
+        const double *__restrict__ lm, const int32_t *__restrict__ cell_start,                    \
+        const double *__restrict__ corner, int32_t cy0, const float *__restrict__ tab, int64_t i0, \
+        int64_t i1, int64_t j0, int64_t j1, int64_t ray_first, int64_t ray_last, double *a1o,     \
+        double *a2o, int64_t *pixo, uint32_t *counts, unsigned long long *landed
+template <bool UNIT, bool CORNER>
+__device__ __forceinline__ void learned_rays(IRS_LEARNED_RAY_ARGS)
 {
     extern __shared__ uint4 s_raw[];
-    MlpSmem &sm = *reinterpret_cast<MlpSmem *>(s_raw);
-    stage_network(sm, wf, theta, freq);
+    float *s_tab = reinterpret_cast<float *>(s_raw);          // node-major: [node][16]
+    for (int e = threadIdx.x; e < kLNodes * kNO; e += blockDim.x)
+        s_tab[e] = tab[(int64_t)(e % kNO) * kLNodes + e / kNO];
+    __syncthreads();
     const int lane = threadIdx.x % kW, wave = threadIdx.x / kW;
     constexpr int kWaves = kL3Threads / kW;
+    const int64_t ntx = (i1 - i0 + kW - 1) / kW;
     const int64_t items = (j1 - j0) * ntx;
     const int q1 = lg.qc + 1;
     const int64_t nxc = (int64_t)g.n1x * lg.qc, nyc = (int64_t)g.n1y * lg.qc;
     unsigned long long nland = 0;
     for (int64_t it = (int64_t)blockIdx.x * kWaves + wave; it < items; it += (int64_t)gridDim.x * kWaves) {
         const int64_t j = j0 + it / ntx;
-        const int64_t i = (it % ntx) * kW + lane;
+        const int64_t i = i0 + (it % ntx) * kW + lane;
         const int64_t r = j * g.nx + i;
-        const bool valid = i < g.nx && r >= ray_first && r < ray_last;
+        bool valid = i < i1 && r >= ray_first && r < ray_last;
         double b1 = 0.0, b2 = 0.0, sig = 0.0;
         float hx = 0.5f, hy = 0.5f;
         float D[16];
@@ -883,7 +978,7 @@ __global__ __launch_bounds__(kL3Threads) void k_level3_learned(
         // outside its own 3 x 3 cells mass 0, adding exact zeros)
         double n1 = 0.0, n2 = 0.0;
         {
-            const int64_t ic = i < g.nx ? i : g.nx - 1;
+            const int64_t ic = i < i1 ? i : i1 - 1;
             const int32_t cxl = (int32_t)(((2 * ic + 1) * (int64_t)g.n1x) / (2 * g.nx));
             const int32_t cya = (int32_t)(((2 * j + 1) * (int64_t)g.n1y) / (2 * g.ny));
             const int32_t cy_ = __builtin_amdgcn_readfirstlane(cya);
@@ -913,6 +1008,7 @@ __global__ __launch_bounds__(kL3Threads) void k_level3_learned(
             const int64_t gyc = ((2 * j + 1) * nyc) / (2 * g.ny);
             const int64_t cx = gxc / lg.qc, cy = gyc / lg.qc;
             const int a = (int)(gxc - cx * lg.qc), b = (int)(gyc - cy * lg.qc);
+            if (!CORNER && g.sheet && corner_cell_l(g, cx, cy)) valid = false;
             const double X0 = corner_x(g, lg, gxc), X1 = corner_x(g, lg, gxc + 1);
             const double Y0 = corner_y(g, lg, gyc), Y1 = corner_y(g, lg, gyc + 1);
             const double dhx = (t1 - X0) / lg.sx, dhy = (t2 - Y0) / lg.sy;
@@ -922,7 +1018,7 @@ __global__ __launch_bounds__(kL3Threads) void k_level3_learned(
             square_eval(C, X0, X1, Y0, Y1, lg, t1, t2, dhx, dhy, sq);
             double Ar = sq.Ir, Ai = sq.Ii;
             if (g.sheet) {
-                if (corner_cell_l(g, cx, cy)) {
+                if constexpr (CORNER) {
                     double I1, I2;
                     sheet_unit(g, t1, t2, I1, I2);
                     const double f = -g.kappa_star / M_PI;
@@ -941,12 +1037,10 @@ __global__ __launch_bounds__(kL3Threads) void k_level3_learned(
 #pragma unroll
             for (int e = 0; e < 16; ++e) D[e] = sq.D[e];
         }
-        float y[kNO];
-        mlp_forward(sm.w, sm.bias, sm.freq, hx, hy, y);
         int32_t pix = -1;
         if (valid) {
             float pr, pi;
-            combine(y, D, pr, pi);
+            ltab_combine<kNO, 1>(s_tab, hx, hy, D, pr, pi);
             const double a1 = b1 + sig * (double)pr;     // conj of the correction
             const double a2 = b2 - sig * (double)pi;
             pix = pixel_of(g, t1 - a1, t2 - a2);
@@ -965,6 +1059,24 @@ __global__ __launch_bounds__(kL3Threads) void k_level3_learned(
     if (counts && lane == 0 && nland) landed_add(landed, nland);
 }
 
+#define IRS_LEARNED_RAY_PASS                                                                      \
+    g, lg, lx, ly, lm, cell_start, corner, cy0, tab, i0, i1, j0, j1, ray_first, ray_last, a1o, a2o, \
+        pixo, counts, landed
+// four waves a SIMD (the table's LDS allows two workgroups a CU)
+template <bool UNIT>
+__global__ __launch_bounds__(kL3Threads, 4) void k_level3_learned(IRS_LEARNED_RAY_ARGS)
+{
+    learned_rays<UNIT, false>(IRS_LEARNED_RAY_PASS);
+}
+// the corner cells: fewer waves, no spills
+template <bool UNIT>
+__global__ __launch_bounds__(kL3Threads) void k_level3_learned_corner(IRS_LEARNED_RAY_ARGS)
+{
+    learned_rays<UNIT, true>(IRS_LEARNED_RAY_PASS);
+}
+#undef IRS_LEARNED_RAY_PASS
+#undef IRS_LEARNED_RAY_ARGS
+
 int device_cus()
 {
     int dev = 0, n = 0;
@@ -975,6 +1087,7 @@ int device_cus()
 }
 
 constexpr size_t kMlpSmem = sizeof(MlpSmem);
+constexpr size_t kLTabSmem = sizeof(float) * kLNodes * kNO;
 
 irs_status set_smem_limits()
 {
@@ -982,10 +1095,12 @@ irs_status set_smem_limits()
     if (done) return IRS_OK;
     IRS_HIP(hipFuncSetAttribute((const void *)k_mlp_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)kMlpSmem));
-    IRS_HIP(hipFuncSetAttribute((const void *)k_level3_learned<true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMlpSmem));
-    IRS_HIP(hipFuncSetAttribute((const void *)k_level3_learned<false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMlpSmem));
+    const void *ray_kernels[4] = {(const void *)k_level3_learned<true>,
+                                  (const void *)k_level3_learned_corner<true>,
+                                  (const void *)k_level3_learned<false>,
+                                  (const void *)k_level3_learned_corner<false>};
+    for (const void *f : ray_kernels)
+        IRS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLTabSmem));
     done = true;
     return IRS_OK;
 }
@@ -1186,6 +1301,36 @@ irs_status launch_mlp_fwd(hipStream_t s, const void *wf, const float *theta, con
     return IRS_OK;
 }
 
+// the plan's weight table from its current network (on its stream, waited for)
+irs_status build_table(irs_plan_s *p)
+{
+    if (!p->d_ltab) IRS_HIP(dev_alloc(&p->d_ltab, sizeof(float) * kNO * kLNodes));
+    std::vector<float> h(2 * kLNodes);
+    for (int b = 0; b <= kLTab; ++b)
+        for (int a = 0; a <= kLTab; ++a) {
+            h[b * (kLTab + 1) + a] = (float)a / (float)kLTab;             // exact: kLTab = 2^5
+            h[kLNodes + b * (kLTab + 1) + a] = (float)b / (float)kLTab;
+        }
+    DevBuf<float> dh;
+    irs_status st = dh.alloc(h.size());
+    if (st != IRS_OK) return st;
+    IRS_HIP(hipMemcpyAsync(dh.p, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, p->stream));
+    if ((st = launch_mlp_fwd(p->stream, p->d_wfwd, p->d_theta, p->d_freqs, kLNodes, dh.p,
+                             p->d_ltab)) != IRS_OK)
+        return st;
+    IRS_HIP(hipStreamSynchronize(p->stream));             // before dh is freed
+    return IRS_OK;
+}
+
+irs_status launch_ltab_eval(hipStream_t s, const float *tab, int64_t n, const float *h, float *y)
+{
+    const int64_t want = (n + kThreads - 1) / kThreads;
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 64 * device_cus()));
+    hipLaunchKernelGGL(k_ltab_eval, dim3(nb), dim3(kThreads), 0, s, tab, n, h, y);
+    IRS_HIP(hipGetLastError());
+    return IRS_OK;
+}
+
 double quantile(std::vector<float> v, double q)
 {
     if (v.empty()) return 0.0;
@@ -1194,11 +1339,14 @@ double quantile(std::vector<float> v, double q)
     return v[k];
 }
 
-// validate the plan's network on n_val samples from rows between the
-// training rows; fills the report's validation fields and the decision
+// tabulate the plan's network and validate the weights the rays will take
+// (the table's) on n_val samples from rows between the training rows; fills
+// the report's validation fields and the decision
 irs_status validate(irs_plan_s *p, const irs_learn_params &lp, irs_learn_report &rep)
 {
     const int qc = p->learn_qc;
+    irs_status st0 = build_table(p);
+    if (st0 != IRS_OK) return st0;
     const std::vector<int64_t> rows = sample_rows(p, std::max(1, lp.train_rows), 0.5 + 0.25);
     const int64_t per_row_cells = p->dg.n1x;
     const int per_cell = (int)std::max<int64_t>(
@@ -1213,7 +1361,7 @@ irs_status validate(irs_plan_s *p, const irs_learn_params &lp, irs_learn_report 
     if (st != IRS_OK) return st;
     st = gather_samples(p, qc, rows, per_cell, lp.seed ^ 0x5a5a5a5aull, smp.p, n);
     if (st != IRS_OK) return st;
-    st = launch_mlp_fwd(p->stream, p->d_wfwd, p->d_theta, p->d_freqs, n, smp.p, y.p);
+    st = launch_ltab_eval(p->stream, p->d_ltab, n, smp.p, y.p);
     if (st != IRS_OK) return st;
     hipLaunchKernelGGL(k_learn_err, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                        p->stream, smp.p, n, y.p, el.p, eb.p);
@@ -1330,9 +1478,11 @@ void learn_release(irs_plan_s *p)
     dev_free(p->d_theta);
     dev_free(p->d_freqs);
     dev_free(p->d_wfwd);
+    dev_free(p->d_ltab);
     dev_free(p->d_corner);
     p->d_theta = p->d_freqs = nullptr;
     p->d_wfwd = nullptr;
+    p->d_ltab = nullptr;
     p->d_corner = nullptr;
 }
 
@@ -1366,8 +1516,15 @@ irs_status launch_learned(irs_plan_s *p, const RaySel &sel)
         p->corner_rows_cap = band;
     }
     CallStats *cs = sel.stats;
-    const int64_t ntx = (g.nx + kW - 1) / kW;
     const int ncu = device_cus();
+    int per_cu = 0;                         // resident workgroups per CU (the table in LDS)
+    if (p->unit_mass)
+        IRS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_level3_learned<true>,
+                                                             kL3Threads, kLTabSmem));
+    else
+        IRS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_level3_learned<false>,
+                                                             kL3Threads, kLTabSmem));
+    per_cu = std::max(1, per_cu);
     for (int64_t c0 = cyA; c0 <= cyB; c0 += p->corner_rows_cap) {
         const int64_t c1 = std::min(cyB, c0 + p->corner_rows_cap - 1);
         if (!(p->corner_c0 <= c0 && c1 <= p->corner_c1)) {
@@ -1400,18 +1557,40 @@ irs_status launch_learned(irs_plan_s *p, const RaySel &sel)
             if (st != IRS_OK) return st;
             cs->n_rays++;
         }
-        const int64_t items = (jB - jA) * ntx;
-        const unsigned nb = (unsigned)std::max<int64_t>(
-            1, std::min<int64_t>(ncu, (items + kL3Threads / kW - 1) / (kL3Threads / kW)));
-#define IRS_L3L(U)                                                                                \
-    hipLaunchKernelGGL(k_level3_learned<U>, dim3(nb), dim3(kL3Threads), kMlpSmem, p->stream, g, lg, \
-                       p->d_x, p->d_y, p->d_m, p->d_cell_start, p->d_corner, (int32_t)p->corner_c0, \
-                       (const uint4 *)p->d_wfwd, p->d_theta, p->d_freqs, ntx, jA, jB,              \
-                       sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2, sel.pixel, sel.counts,  \
-                       sel.landed)
-        if (p->unit_mass) IRS_L3L(true);
-        else IRS_L3L(false);
+        // rays of columns [i0, i1), rows [ja, jb): the main kernel, or one
+        // corner cell's
+        auto launch = [&](bool corner_cell, int64_t i0, int64_t i1, int64_t ja, int64_t jb) {
+            const int64_t items = (jb - ja) * ((i1 - i0 + kW - 1) / kW);
+            const unsigned nb = (unsigned)std::max<int64_t>(
+                1, std::min<int64_t>((int64_t)per_cu * ncu, (items + kL3Threads / kW - 1) / (kL3Threads / kW)));
+#define IRS_L3L(K)                                                                                 \
+    hipLaunchKernelGGL(K, dim3(nb), dim3(kL3Threads), kLTabSmem, p->stream, g, lg, p->d_x, p->d_y,  \
+                       p->d_m, p->d_cell_start, p->d_corner, (int32_t)p->corner_c0, p->d_ltab, i0, \
+                       i1, ja, jb, sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2, sel.pixel, \
+                       sel.counts, sel.landed)
+            if (p->unit_mass) {
+                if (corner_cell) IRS_L3L(k_level3_learned_corner<true>);
+                else IRS_L3L(k_level3_learned<true>);
+            } else {
+                if (corner_cell) IRS_L3L(k_level3_learned_corner<false>);
+                else IRS_L3L(k_level3_learned<false>);
+            }
 #undef IRS_L3L
+        };
+        launch(false, 0, g.nx, jA, jB);
+        if (g.sheet) {
+            // the rectangle's corner cells (distinct ones) that meet these rows
+            const int64_t cxs[2] = {0, g.n1x - 1}, cys[2] = {0, g.n1y - 1};
+            for (int ky = 0; ky < (g.n1y > 1 ? 2 : 1); ++ky)
+                for (int kx = 0; kx < (g.n1x > 1 ? 2 : 1); ++kx) {
+                    int64_t ia, ib, ra, rb;
+                    level1_span(p->geo.info, 0, cxs[kx], ia, ib);
+                    level1_span(p->geo.info, 1, cys[ky], ra, rb);
+                    ra = std::max(ra, jA);
+                    rb = std::min(rb, jB);
+                    if (ia < ib && ra < rb) launch(true, ia, ib, ra, rb);
+                }
+        }
         IRS_HIP(hipGetLastError());
         if (cs && (st = cs->end(p->stream)) != IRS_OK) return st;
     }
@@ -1615,6 +1794,23 @@ irs_status irs_learn_samples(irs_plan_t p, int32_t coarse, int64_t row0, int64_t
     for (int64_t r = row0; r < row0 + nrows; ++r) rows.push_back(r);
     const int64_t n = nrows * p->dg.n1x * per_cell;
     if ((st = gather_samples(p, coarse, rows, per_cell, seed, out, n)) != IRS_OK) return st;
+    IRS_HIP(hipStreamSynchronize(p->stream));
+    return IRS_OK;
+}
+
+irs_status irs_learn_weights(irs_plan_t p, int64_t n, const float *h, float *y)
+{
+    if (!p || n < 0 || (n > 0 && (!h || !y))) {
+        set_error("irs_learn_weights: NULL argument or n < 0");
+        return IRS_E_INVALID;
+    }
+    if (p->learn_qc == 0 || !p->d_ltab) {
+        set_error("irs_learn_weights: the plan has no network");
+        return IRS_E_INVALID;
+    }
+    if (n == 0) return IRS_OK;
+    irs_status st = launch_ltab_eval(p->stream, p->d_ltab, n, h, y);
+    if (st != IRS_OK) return st;
     IRS_HIP(hipStreamSynchronize(p->stream));
     return IRS_OK;
 }

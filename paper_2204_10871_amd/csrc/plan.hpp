@@ -91,6 +91,7 @@ struct irs_plan_s {
     float *d_theta = nullptr;             // FP32 parameters
     float *d_freqs = nullptr;             // 64 x 2
     void *d_wfwd = nullptr;               // BF16 forward fragments
+    float *d_ltab = nullptr;              // the weights at the table's nodes (16 x nodes)
     double *d_corner = nullptr;
     int64_t corner_rows_cap = 0;
     int64_t corner_c0 = -1, corner_c1 = -2;

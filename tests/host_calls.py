@@ -111,6 +111,8 @@ def run(path):
         "learn_get": lambda: lib.irs_learn_get(None, None, None, None),
         "learn_corners": lambda: lib.irs_learn_corners(None, 8, 0, 1, None),
         "learn_samples": lambda: lib.irs_learn_samples(None, 8, 0, 1, 4, 1, None),
+        "learn_weights": lambda: lib.irs_learn_weights(None, 4, None, None),
+        "learn_weights": lambda: lib.irs_learn_weights(None, 4, None, None),
         "mlp_forward": lambda: lib.irs_mlp_forward(-1, None, None, None, None, None),
         "mlp_loss_grad": lambda: lib.irs_mlp_loss_grad(-1, None, None, None, None, None, None),
         "fail_alloc": lambda: lib.irs_debug_fail_alloc(-1),

@@ -64,6 +64,35 @@ def test_mlp_forward_matches_oracle(irs):
     assert err.max() < FWD_TOL
 
 
+def test_learned_weights_match_oracle(irs):
+    """The weights the rays take (irs_learn_weights: the BF16 network
+    tabulated at the 33 x 33 nodes and blended) against the oracle's FP64
+    table blend, at random offsets, the square's edges and offsets a rounding
+    step outside it.  The blend is a convex combination of node values, so
+    its error is at most the blend of the nodes' FWD_TOL bounds."""
+    import torch
+    fr, th = _net()
+    p, L, og = _plan(irs, npix=32, n_rays=20_000)
+    rng = np.random.default_rng(4)
+    h = rng.uniform(0, 1, (2000, 2))
+    h[:6] = [[0, 0], [1, 1], [1, 0], [0, 1], [-1e-7, 0.5], [0.5, 1 + 1e-7]]
+    with irs.Plan(p, L.x, L.y, L.m) as pl:
+        pl.learn_set(fr, th, irs.learn_params(coarse=4, n_val=2000, train_rows=2))
+        hd = torch.tensor(h.T.astype(np.float32).copy(), device="cuda:0")
+        yd = torch.empty((16, h.shape[0]), dtype=torch.float32, device="cuda:0")
+        pl.learn_weights(hd, yd)
+        y = yd.cpu().numpy().T.astype(np.float64)
+    th64, fr64 = th.astype(np.float64), fr.astype(np.float64)
+    h32 = h.astype(np.float32).astype(np.float64)
+    yo = ol.table_weights(th64, fr64, h32)
+    _, cache = ol.forward(th64, fr64, ol.table_nodes())
+    P = ol.unpack(th64)
+    scale = ol.table_blend(np.abs(cache[4]) @ np.abs(P[8]).T + np.abs(P[9]), h32)
+    err = np.abs(y - yo) / scale
+    say(f"table weights: max |dy|/scale {err.max():.3e}, mean {err.mean():.3e}")
+    assert err.max() < FWD_TOL
+
+
 def _records(rng, n):
     """Sample records with random h, unit-size D and targets (fields as the
     sample kernel writes them)."""

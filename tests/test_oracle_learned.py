@@ -110,6 +110,54 @@ def test_base_interpolant_linear_and_quadratic():
         assert np.max(np.abs(Ik - A(zc[:, c], zm))) < 1e-12
 
 
+def test_table_nodes_and_blend():
+    """The rays' weight table: node b (T+1) + a sits at (a/T, b/T); the blend
+    returns a node's values at the node, reproduces any bilinear function
+    c0 + c1 hx + c2 hy + c3 hx hy exactly (different coefficients per output,
+    so a swapped axis or a shifted node fails), clamps offsets outside the
+    square, and on a smooth function stays within the bilinear bound
+    (d^2/8)(max|f_xx| + max|f_yy|), d = 1/T."""
+    T = ol.TABLE_SIDE
+    nodes = ol.table_nodes()
+    assert nodes.shape == ((T + 1) ** 2, 2)
+    a, b = 5, 17
+    assert np.array_equal(nodes[b * (T + 1) + a], [a / T, b / T])
+    rng = np.random.default_rng(11)
+    c = rng.normal(size=(4, 16))
+    f = lambda h: (c[0] + np.outer(h[:, 0], c[1]) + np.outer(h[:, 1], c[2])
+                   + np.outer(h[:, 0] * h[:, 1], c[3]))
+    Y = f(nodes)
+    assert np.array_equal(ol.table_blend(Y, nodes), Y)
+    h = rng.uniform(0, 1, (500, 2))
+    h[:4] = [[0, 0], [1, 1], [1, 0], [0.5, 1]]               # edges of the square
+    assert np.max(np.abs(ol.table_blend(Y, h) - f(h))) < 1e-13
+    out = np.array([[-0.25, 0.3], [1.5, 0.3], [0.7, -1e-9], [0.7, 1 + 1e-9]])
+    assert np.allclose(ol.table_blend(Y, out), f(np.clip(out, 0, 1)), rtol=0, atol=1e-13)
+    k1, k2 = 2 * np.pi * 1.3, 2 * np.pi * 0.7
+    g = lambda h: np.sin(k1 * h[:, 0] + k2 * h[:, 1])[:, None]
+    err = np.abs(ol.table_blend(g(nodes), h) - g(h)).max()
+    bound = (1.0 / T) ** 2 / 8 * (k1 ** 2 + k2 ** 2)
+    assert 0.05 * bound < err <= bound
+
+
+def test_learned_value_uses_the_table():
+    """learned_value's correction is sigma sum_k L_k D_k with L the blended
+    table of the network's outputs: at a node it equals the network's own."""
+    rng = np.random.default_rng(12)
+    th = _random_theta(rng)
+    fr = rng.normal(0, 0.25, (64, 2))
+    zc, sx, sy = _square(rng, 6)
+    Ac = rng.normal(size=(6, 4)) + 1j * rng.normal(size=(6, 4))
+    dAc = rng.normal(size=(6, 4)) + 1j * rng.normal(size=(6, 4))
+    T = ol.TABLE_SIDE
+    h = np.array([[3, 7], [0, 0], [T, T], [12, 31], [31, 1], [16, 16]], float) / T
+    z = zc[:, 0] + h[:, 0] * sx + 1j * h[:, 1] * sy
+    D, sigma = ol.local_data(zc, Ac, dAc, sx, sy)
+    want = ol.base_interp(zc, Ac, dAc, h, z) + sigma * ol.predict(th, fr, h, D)
+    got = ol.learned_value(th, fr, zc, Ac, dAc, sx, sy, h, z)
+    assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(want))
+
+
 def test_local_data_invariants():
     """delta and eps sum to zero over the corners, vanish for linear fields
     (up to rounding), and a quadratic field's delta equals 2 a u_c s."""
