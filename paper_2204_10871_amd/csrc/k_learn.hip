@@ -889,6 +889,16 @@ __global__ __launch_bounds__(kThreads) void k_learn_err(const float *__restrict_
     err_base[k] = sg * sqrtf(Tr * Tr + Ti * Ti);
 }
 
+// The learned path's column table: ray column i's square column
+// gxc = floor((i + 1/2) n1x qc / nx) and level-1 column gxc / qc.
+__global__ __launch_bounds__(kThreads) void k_learn_cols(DevGeom g, int32_t qc, int2 *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= g.nx) return;
+    const int64_t gxc = ((2 * i + 1) * ((int64_t)g.n1x * qc)) / (2 * g.nx);
+    out[i] = make_int2((int32_t)gxc, (int32_t)(gxc / qc));
+}
+
 // The blended weights at n offsets hin (hx row, hy row) from the table tab
 // (output-major: tab[o kLNodes + node]) into yout (16 x n: yout[o n + k]).
 __global__ __launch_bounds__(kThreads) void k_ltab_eval(const float *__restrict__ tab, int64_t n,
@@ -910,13 +920,6 @@ __global__ __launch_bounds__(kThreads) void k_ltab_eval(const float *__restrict_
 // the band's (row, 64-column) items.
 // ---------------------------------------------------------------------------
 constexpr int kL3Threads = 512;
-
-__device__ __forceinline__ int lane_max(int v)
-{
-#pragma unroll
-    for (int o = kW / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
-}
 
 // One nearby lens's term m (d1, d2)/r^2, d = theta - z: m/r^2 is the
 // hardware reciprocal estimate times m corrected once (relative error about
@@ -943,7 +946,8 @@ __device__ __forceinline__ void near_lens(double t1, double t2, double zx, doubl
 #define IRS_LEARNED_RAY_ARGS                                                                      \
     DevGeom g, LearnGeom lg, const double *__restrict__ lx, const double *__restrict__ ly,        \
         const double *__restrict__ lm, const int32_t *__restrict__ cell_start,                    \
-        const double *__restrict__ corner, int32_t cy0, const float *__restrict__ tab, int64_t i0, \
+        const double *__restrict__ corner, int32_t cy0, const float *__restrict__ tab,            \
+        const int2 *__restrict__ lcol, int64_t i0,                                                \
         int64_t i1, int64_t j0, int64_t j1, int64_t ray_first, int64_t ray_last, double *a1o,     \
         double *a2o, int64_t *pixo, uint32_t *counts, unsigned long long *landed
 template <bool UNIT, bool CORNER>
@@ -954,12 +958,13 @@ __device__ __forceinline__ void learned_rays(IRS_LEARNED_RAY_ARGS)
     for (int e = threadIdx.x; e < kLNodes * kNO; e += blockDim.x)
         s_tab[e] = tab[(int64_t)(e % kNO) * kLNodes + e / kNO];
     __syncthreads();
-    const int lane = threadIdx.x % kW, wave = threadIdx.x / kW;
+    const int lane = threadIdx.x % kW;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);   // items are wave-uniform
     constexpr int kWaves = kL3Threads / kW;
     const int64_t ntx = (i1 - i0 + kW - 1) / kW;
     const int64_t items = (j1 - j0) * ntx;
     const int q1 = lg.qc + 1;
-    const int64_t nxc = (int64_t)g.n1x * lg.qc, nyc = (int64_t)g.n1y * lg.qc;
+    const int64_t nyc = (int64_t)g.n1y * lg.qc;
     unsigned long long nland = 0;
     for (int64_t it = (int64_t)blockIdx.x * kWaves + wave; it < items; it += (int64_t)gridDim.x * kWaves) {
         const int64_t j = j0 + it / ntx;
@@ -977,13 +982,16 @@ __device__ __forceinline__ void learned_rays(IRS_LEARNED_RAY_ARGS)
         // columns straddle two level-1 columns a lane gives the lenses
         // outside its own 3 x 3 cells mass 0, adding exact zeros)
         double n1 = 0.0, n2 = 0.0;
+        // the lane's square column and level-1 column (lanes past the
+        // range take its last column); the row's square row (wave-uniform)
+        const int2 sq = lcol[i < i1 ? i : i1 - 1];
+        const int64_t gyc = ((2 * j + 1) * nyc) / (2 * g.ny);
+        const int32_t cy_ = (int32_t)(gyc / lg.qc);
         {
-            const int64_t ic = i < i1 ? i : i1 - 1;
-            const int32_t cxl = (int32_t)(((2 * ic + 1) * (int64_t)g.n1x) / (2 * g.nx));
-            const int32_t cya = (int32_t)(((2 * j + 1) * (int64_t)g.n1y) / (2 * g.ny));
-            const int32_t cy_ = __builtin_amdgcn_readfirstlane(cya);
-            const int32_t cxa = __builtin_amdgcn_readfirstlane(cxl);   // lane 0 holds a column
-            const int32_t cxb = __builtin_amdgcn_readfirstlane(lane_max(cxl));
+            const int32_t cxl = sq.y;
+            // columns grow with the lane: lane 0 has the first, lane 63 the last
+            const int32_t cxa = __builtin_amdgcn_readfirstlane(cxl);
+            const int32_t cxb = __builtin_amdgcn_readlane(cxl, kW - 1);
             const int32_t cl = cxa > 0 ? cxa - 1 : 0, ch = cxb < g.n1x - 1 ? cxb + 1 : g.n1x - 1;
             const int32_t xl = cxl > 0 ? cxl - 1 : 0, xh = cxl < g.n1x - 1 ? cxl + 1 : g.n1x - 1;
             const bool straddle = cxa != cxb;
@@ -1004,9 +1012,8 @@ __device__ __forceinline__ void learned_rays(IRS_LEARNED_RAY_ARGS)
             }
         }
         if (valid) {
-            const int64_t gxc = ((2 * i + 1) * nxc) / (2 * g.nx);
-            const int64_t gyc = ((2 * j + 1) * nyc) / (2 * g.ny);
-            const int64_t cx = gxc / lg.qc, cy = gyc / lg.qc;
+            const int64_t gxc = sq.x;
+            const int64_t cx = sq.y, cy = cy_;
             const int a = (int)(gxc - cx * lg.qc), b = (int)(gyc - cy * lg.qc);
             if (!CORNER && g.sheet && corner_cell_l(g, cx, cy)) valid = false;
             const double X0 = corner_x(g, lg, gxc), X1 = corner_x(g, lg, gxc + 1);
@@ -1060,8 +1067,8 @@ __device__ __forceinline__ void learned_rays(IRS_LEARNED_RAY_ARGS)
 }
 
 #define IRS_LEARNED_RAY_PASS                                                                      \
-    g, lg, lx, ly, lm, cell_start, corner, cy0, tab, i0, i1, j0, j1, ray_first, ray_last, a1o, a2o, \
-        pixo, counts, landed
+    g, lg, lx, ly, lm, cell_start, corner, cy0, tab, lcol, i0, i1, j0, j1, ray_first, ray_last, a1o, \
+        a2o, pixo, counts, landed
 // four waves a SIMD (the table's LDS allows two workgroups a CU)
 template <bool UNIT>
 __global__ __launch_bounds__(kL3Threads, 4) void k_level3_learned(IRS_LEARNED_RAY_ARGS)
@@ -1211,6 +1218,10 @@ irs_status check_learned_plan(const irs_plan_s *p, int qc, const char *who)
     if (qc < 1 || qc > 32) {
         set_error(std::string(who) + ": coarse must be in 1..32");
         return IRS_E_INVALID;
+    }
+    if ((int64_t)p->dg.n1x * qc >= INT32_MAX || (int64_t)p->dg.n1y * qc >= INT32_MAX) {
+        set_error(std::string(who) + ": too many squares across the map for 32-bit indices");
+        return IRS_E_UNSUPPORTED;
     }
     return IRS_OK;
 }
@@ -1479,10 +1490,13 @@ void learn_release(irs_plan_s *p)
     dev_free(p->d_freqs);
     dev_free(p->d_wfwd);
     dev_free(p->d_ltab);
+    dev_free(p->d_lcol);
     dev_free(p->d_corner);
     p->d_theta = p->d_freqs = nullptr;
     p->d_wfwd = nullptr;
     p->d_ltab = nullptr;
+    p->d_lcol = nullptr;
+    p->lcol_qc = 0;
     p->d_corner = nullptr;
 }
 
@@ -1514,6 +1528,16 @@ irs_status launch_learned(irs_plan_s *p, const RaySel &sel)
         p->corner_c1 = -2;
         IRS_HIP(dev_alloc(&p->d_corner, (size_t)(band * corner_row_bytes(p, qc))));
         p->corner_rows_cap = band;
+    }
+    if (!p->d_lcol || p->lcol_qc != qc) {                 // the column table, per coarse grid
+        dev_free(p->d_lcol);
+        p->d_lcol = nullptr;
+        p->lcol_qc = 0;
+        IRS_HIP(dev_alloc(&p->d_lcol, sizeof(int2) * (size_t)g.nx));
+        hipLaunchKernelGGL(k_learn_cols, dim3((unsigned)((g.nx + kThreads - 1) / kThreads)),
+                           dim3(kThreads), 0, p->stream, g, (int32_t)qc, (int2 *)p->d_lcol);
+        IRS_HIP(hipGetLastError());
+        p->lcol_qc = qc;
     }
     CallStats *cs = sel.stats;
     const int ncu = device_cus();
@@ -1565,7 +1589,8 @@ irs_status launch_learned(irs_plan_s *p, const RaySel &sel)
                 1, std::min<int64_t>((int64_t)per_cu * ncu, (items + kL3Threads / kW - 1) / (kL3Threads / kW)));
 #define IRS_L3L(K)                                                                                 \
     hipLaunchKernelGGL(K, dim3(nb), dim3(kL3Threads), kLTabSmem, p->stream, g, lg, p->d_x, p->d_y,  \
-                       p->d_m, p->d_cell_start, p->d_corner, (int32_t)p->corner_c0, p->d_ltab, i0, \
+                       p->d_m, p->d_cell_start, p->d_corner, (int32_t)p->corner_c0, p->d_ltab,      \
+                       (const int2 *)p->d_lcol, i0,                                                \
                        i1, ja, jb, sel.ray_first, sel.ray_last, sel.alpha1, sel.alpha2, sel.pixel, \
                        sel.counts, sel.landed)
             if (p->unit_mass) {

@@ -92,6 +92,8 @@ struct irs_plan_s {
     float *d_freqs = nullptr;             // 64 x 2
     void *d_wfwd = nullptr;               // BF16 forward fragments
     float *d_ltab = nullptr;              // the weights at the table's nodes (16 x nodes)
+    void *d_lcol = nullptr;               // per ray column: square column, level-1 column
+    int32_t lcol_qc = 0;                  // ... for this coarse grid
     double *d_corner = nullptr;
     int64_t corner_rows_cap = 0;
     int64_t corner_c0 = -1, corner_c1 = -2;
