@@ -164,4 +164,22 @@ __device__ __forceinline__ void bin_wave(uint32_t *__restrict__ counts, int32_t 
     }
 }
 
+// Histogram update by runs: the wave's lanes hold consecutive rays of one
+// row, which mostly share a pixel with their neighbours; each run of equal
+// pixels in lane order adds its length once, from its last lane.  A pixel the
+// wave meets in several runs gets several adds.  Must be called by every lane
+// of the wave (pix = -1 for lanes with nothing to add).
+__device__ __forceinline__ void bin_runs(uint32_t *__restrict__ counts, int32_t pix)
+{
+    const int lane = (int)__lane_id();
+    const int32_t prev = __shfl_up(pix, 1);                 // lane 0 gets its own
+    const uint64_t starts = __ballot(lane == 0 || pix != prev);
+    const bool last = lane == 63 || ((starts >> (lane + 1)) & 1ull);
+    if (last && pix >= 0) {
+        const uint64_t upto = starts & (~0ull >> (63 - lane));  // run starts at or below
+        const int first = 63 - __clzll((long long)upto);
+        atomicAdd(&counts[pix], (uint32_t)(lane - first + 1));
+    }
+}
+
 }  // namespace irs

@@ -1059,7 +1059,7 @@ __device__ __forceinline__ void learned_rays(IRS_LEARNED_RAY_ARGS)
             }
         }
         if (counts) {
-            bin_wave(counts, pix);
+            bin_runs(counts, pix);
             nland += __popcll(__ballot(pix >= 0));
         }
     }
