@@ -460,8 +460,10 @@ irs_status irs_learn_defaults(irs_learn_params *out);
  * irs_learn -- generate exact samples, train the network and validate it on an
  * IRS_LEARNED plan.  freqs: IRS_LEARN_NFREQ x 2 host floats; theta0: initial
  * parameters (host, IRS_LEARN_NPARAMS) or NULL for a seeded He initialisation.
- * report may be NULL.  Afterwards the plan's shooting calls use the network,
- * or the grid interpolation if report->fallback is 1.
+ * report may be NULL.  The trained network is tabulated over the in-square
+ * offset (irs_learn_weights) and the validation measures the tabulated
+ * weights, which the rays use.  Afterwards the plan's shooting calls use
+ * them, or the grid interpolation if report->fallback is 1.
  * Errors: IRS_E_INVALID (not an IRS_LEARNED plan, settings out of range),
  * IRS_E_UNSUPPORTED (IRS_LEVEL2_PAPER plans), IRS_E_NOMEM, IRS_E_DEVICE.
  */
