@@ -2010,19 +2010,35 @@ irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *f
 }
 
 // Tiles of one axis: where every level-1 cell spans at least `min_span` rays
-// along it, tiles follow the cells (each cell's rays cut into tiles of at most
-// `tile` rays from its first ray), so no wave straddles two cells;
-// otherwise tiles of `tile` rays from ray 0.
+// along it (and, with `weigh`, the lanes this leaves idle cost less than the
+// extra lenses of tiles that straddle cells), tiles follow the cells (each
+// cell's rays cut into tiles of at most `tile` rays from its first ray), so
+// no wave straddles two cells; otherwise tiles of `tile` rays from ray 0.
+// Either way every ray takes the same near lenses with the same arithmetic
+// (a straddling wave's lanes give the lenses outside their own cells mass 0).
 std::vector<TileSpan> make_tiles(const irs_geometry_info &gi, int axis, int32_t tile,
-                                 int32_t min_span)
+                                 int32_t min_span, bool weigh)
 {
     const int64_t n = axis ? gi.ny : gi.nx, ncell = axis ? gi.n1y : gi.n1x;
     std::vector<TileSpan> out;
     bool follow = true;
+    int64_t slots = 0;                            // tile positions when following
     for (int64_t c = 0; c < ncell && follow; ++c) {
         int64_t a, b;
         level1_span(gi, axis, c, a, b);
         follow = b - a >= min_span;
+        slots += (b - a + tile - 1) / tile * tile;
+    }
+    if (follow && weigh && slots > 0) {
+        // following the cells leaves the lanes past a cell's last column idle;
+        // fixed tiles keep every lane busy, but a tile that crosses a cell
+        // boundary takes the lenses of one more cell column (4 instead of 3)
+        // in its near-lens pass, which is about 0.55 of the level-3 work.  A
+        // tile of `tile` columns crosses (tile - 1)/C boundaries on average.
+        const double idle = 1.0 - (double)n / (double)slots;
+        const double cols = (double)n / (double)ncell;
+        const double extra = 0.55 * ((double)(tile - 1) / cols) / 3.0;
+        follow = idle <= extra;
     }
     if (follow) {
         for (int64_t c = 0; c < ncell; ++c) {
@@ -2047,10 +2063,10 @@ irs_status ensure_rows(irs_plan_s *p)
     if (st != IRS_OK) return st;
     const DevGeom &g = p->dg;
     // column tiles follow the cells when a cell holds >= 1.5 waves of
-    // columns (narrower cells would leave too many lanes idle); row tiles
-    // when a cell holds a whole tile of rows
-    p->h_tcol = make_tiles(p->geo.info, 0, kWave, kWave + kWave / 2);
-    p->h_trow = make_tiles(p->geo.info, 1, kL3Rows, kL3Rows);
+    // columns and the idle lanes cost less than straddling; row tiles when a
+    // cell holds a whole tile of rows
+    p->h_tcol = make_tiles(p->geo.info, 0, kWave, kWave + kWave / 2, true);
+    p->h_trow = make_tiles(p->geo.info, 1, kL3Rows, kL3Rows, false);
     dev_free(p->d_tcol);
     dev_free(p->d_trow);
     dev_free(p->d_cols);
