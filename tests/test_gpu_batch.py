@@ -8,7 +8,7 @@ import pytest
 
 import oracle as orc
 import synth
-from gpu_common import THREADS, check_map, rel_err
+from gpu_common import THREADS, Case, check_map, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -118,6 +118,46 @@ def test_batch_equals_single_plans(irs, method, precision):
             assert st[k]["rays_landed"] == int(singles[k].sum())
     for p in plans:
         p.close()
+
+
+@pytest.mark.parametrize("which", ["mixed", "one"])
+def test_interp_batch_mixed_maps(irs, which):
+    """The one-launch level 3 over maps of different kinds: column tiles that
+    follow the level-1 cells (124 columns a cell) and tiles that straddle them
+    (25), a map without the sheet (no corner-cell rays), a map of 2,000 rays;
+    and a batch of one map.  Every map equals its own plan bit for bit and
+    meets the oracle's direct definition."""
+    import torch
+    specs = [((0.25, 0.0, 0.05, 4.0, 64), dict(n_rays=1_960_000)),
+             ((0.3, 0.0, 0.3, 8.0, 64), dict(n_rays=150_000)),
+             ((0.45, 0.05, 0.45, 6.0, 32), dict(n_rays=20_000, sheet=False)),
+             ((0.2, 0.2, 0.1, 10.0, 48), dict(n_rays=2_000))]
+    if which == "one":
+        specs = specs[2:3]
+    cases = [Case(*a, seed=90 + k, **kw) for k, (a, kw) in enumerate(specs)]
+    plans = [c.plan("interp", "fp64") for c in cases]
+    try:
+        singles = [p.shoot_map()[0].ravel().astype(np.int64) for p in plans]
+        counts = [torch.empty(c.geo.npix ** 2, dtype=torch.int32, device="cuda:0") for c in cases]
+        with irs.Batch(plans) as b:
+            info = b.info()
+            assert info["whole_maps"] == 1 and info["maps_per_launch"] == len(plans), info
+            st = b.run(counts)
+            torch.cuda.synchronize()
+        for k, (c, p) in enumerate(zip(cases, plans)):
+            got = counts[k].cpu().numpy().astype(np.int64)
+            assert np.array_equal(got, singles[k]), f"map {k} differs from its plan"
+            assert st[k]["rays_landed"] == int(got.sum())
+            a1, a2, px = p.deflect_grid(0, p.n_rays)
+            ref = c.oracle_direct()
+            e = rel_err(a1, a2, ref["alpha1"], ref["alpha2"])
+            say(f"  map {k}: N*={c.lenses.n}, {p.n_rays} rays, max e_r {e.max():.2e}, "
+                f"pixel mismatches {int(np.sum(px != ref['pix']))}")
+            assert np.mean(e <= 1e-4) >= 0.9999
+            check_map(got, ref["counts"], px, ref["pix"])
+    finally:
+        for p in plans:
+            p.close()
 
 
 def test_direct_fp32_tile_shapes_identical(irs):
