@@ -690,8 +690,20 @@ __global__ __launch_bounds__(kThreads) void k_level2_near(
     }
 }
 
-template <bool UNIT, int P>
-__global__ __launch_bounds__(kThreads, 3) void k_level2_points(
+// Cells whose level-2 points take the sheet's closed-form coefficients: with
+// the sheet, outside the corner cells, where its series is not folded into
+// the cell expansion (near the rectangle's edges, or no folding at all).
+__device__ __forceinline__ bool sheet_closed_form(const DevGeom &g, int32_t fold, int32_t cx,
+                                                  int32_t cy)
+{
+    return g.sheet && !corner_cell(g, cx, cy) && !(fold && sheet_fold_ok(g, cx, cy));
+}
+
+// CLOSED = false: the cells that do not take the closed form; CLOSED = true:
+// the cells that do (a workgroup with none returns at once).  The closed
+// form's logarithms would otherwise set every point's register budget.
+template <bool UNIT, int P, bool CLOSED>
+__global__ __launch_bounds__(kThreads) void k_level2_points(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
     const double *__restrict__ lm, const int32_t *__restrict__ cell_start, int32_t cy0,
     int32_t nxb, int32_t nchunk, int32_t fold, const double *__restrict__ part,
@@ -701,6 +713,12 @@ __global__ __launch_bounds__(kThreads, 3) void k_level2_points(
     const int tid = threadIdx.x;
     const int32_t cy = cy0 + (int32_t)(blockIdx.x / (uint32_t)nxb);
     const int32_t cx0 = (int32_t)(blockIdx.x % (uint32_t)nxb) * kCellsPerBlock;
+    if constexpr (CLOSED) {                                  // block-uniform
+        bool any = false;
+        for (int w = 0; w < kCellsPerBlock; ++w)
+            any = any || (cx0 + w < g.n1x && sheet_closed_form(g, fold, cx0 + w, cy));
+        if (!any) return;
+    }
     const double sc = fmax(g.w1, g.h1), isc = 1.0 / sc;
     const double zci = g.b1 + ((double)cy + 0.5) * g.h1;
     // sum the chunks' partial expansions, in chunk order
@@ -722,7 +740,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_level2_points(
     for (int pp = tid; pp < kCellsPerBlock * npts; pp += kThreads) {
         const int w = pp / npts, pt = pp % npts;
         const int32_t ccx = cx0 + w;
-        if (ccx >= g.n1x) continue;
+        if (ccx >= g.n1x || sheet_closed_form(g, fold, ccx, cy) != CLOSED) continue;
         const int64_t gx = (int64_t)ccx * q + pt % q;
         const int64_t gyl = pt / q;
         const double x0 = level2_x(g, gx), y0 = level2_y(g, (int64_t)cy * q + gyl);
@@ -785,7 +803,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_level2_points(
             }
         }
         if (g.sheet && !corner_cell(g, ccx, cy)) {
-            if (fold && sheet_fold_ok(g, ccx, cy)) {
+            if constexpr (!CLOSED) {
                 // G's series came with the cell expansion; F = conj(z) + G
                 c[0].r -= g.kappa_star * x0;
                 c[0].i += g.kappa_star * y0;
@@ -2343,9 +2361,13 @@ irs_status level2_band(irs_plan_s *p, int64_t c0, int64_t c1, double *coef, Call
     do {                                                                                      \
         if (cs && (st2 = cs->end(s)) != IRS_OK) return st2;                                  \
         if (cs && (st2 = cs->begin(s, 2)) != IRS_OK) return st2;                             \
-        hipLaunchKernelGGL((k_level2_points<U, PP>), dim3(nbB), dim3(kThreads), 0, s, g,      \
-                           p->d_x, p->d_y, p->d_m, p->d_cell_start, (int32_t)c0, nxb, nchunk, \
-                           fold, p->d_part, coef);                                       \
+        hipLaunchKernelGGL((k_level2_points<U, PP, false>), dim3(nbB), dim3(kThreads), 0, s, \
+                           g, p->d_x, p->d_y, p->d_m, p->d_cell_start, (int32_t)c0, nxb,      \
+                           nchunk, fold, p->d_part, coef);                                   \
+        if (g.sheet)                                                                          \
+            hipLaunchKernelGGL((k_level2_points<U, PP, true>), dim3(nbB), dim3(kThreads), 0,  \
+                               s, g, p->d_x, p->d_y, p->d_m, p->d_cell_start, (int32_t)c0,    \
+                               nxb, nchunk, fold, p->d_part, coef);                          \
     } while (0)
         irs_status st2 = IRS_OK;
         if (p->unit_mass) {
