@@ -3,20 +3,26 @@
 // irs.h).  The nearby lenses stay exact; the distant lenses and the analytic
 // part of the sheet, an analytic function A(z) inside each level-1 cell, are
 // known exactly at the corners of a coarse grid of squares and interpolated in
-// between by I(z) + sigma * sum_k L_k(h) D_k, L from a small network.
+// between by I(z) + sigma * sum_k L_k(h) D_k, L from a small network.  The
+// rays take L from the network's outputs tabulated at 33 x 33 nodes of the
+// unit square, blended bilinearly.
 //
 // Kernels
 //   k_learn_corners   A, A' at every corner of the squares of a band of cells
 //   k_learn_samples   exact samples (h, D, T = (A - I)/sigma, sigma)
 //   k_mlp_pack        FP32 parameters -> BF16 MFMA operand fragments
-//   k_mlp_fwd         network outputs at given offsets (inference kernel)
+//   k_mlp_fwd         network outputs at given offsets (inference kernel; also
+//                     the rays' table of weights)
 //   k_mlp_train       forward, loss gradient and backward of a batch
 //   k_mlp_wgrad       weight and bias gradients, per chunk of the batch
 //   k_mlp_reduce      chunk sums in fixed order, batch loss
 //   k_adam            Adam step on the FP32 parameters
 //   k_learn_err       per-sample validation errors
+//   k_ltab_eval       the tabulated weights at given offsets
+//   k_learn_cols      per ray column: square column and level-1 column
 //   k_level3_learned  rays: near lenses exact, learned distant field, macro
-//                     term, beta, pixel, binning
+//                     term, beta, pixel, binning by runs (the rectangle's
+//                     corner cells in k_level3_learned_corner)
 //
 // Matrix-core layout (v_mfma_f32_32x32x16_bf16, one wave): A is 32 x 16, lane
 // l holds A[l%32][8(l/32) + v]; B is 16 x 32, lane l holds B[8(l/32) + v][l%32];
