@@ -222,20 +222,33 @@ struct Sq {
 };
 
 // C: the four corners' (Re A, Im A, Re A', Im A'), order lower-left,
-// lower-right, upper-left, upper-right; X0/X1, Y0/Y1 their coordinates
-__device__ __forceinline__ void square_eval(const double C[4][4], double X0, double X1, double Y0,
-                                            double Y1, const LearnGeom &lg, double x, double y,
-                                            double hx, double hy, Sq &o)
+// lower-right, upper-left, upper-right; X0/X1, Y0/Y1 their coordinates.
+// The base interpolant at (x, y), in-square offset (hx, hy).
+__device__ __forceinline__ void square_base(const double C[4][4], double X0, double X1, double Y0,
+                                            double Y1, double x, double y, double hx, double hy,
+                                            double &Ir, double &Ii)
 {
     const double zx[4] = {X0, X1, X0, X1}, zy[4] = {Y0, Y0, Y1, Y1};
     const double w[4] = {(1 - hx) * (1 - hy), hx * (1 - hy), (1 - hx) * hy, hx * hy};
-    double Ir = 0.0, Ii = 0.0;
-    double mAr = 0, mAi = 0, mdr = 0, mdi = 0, mzx = 0, mzy = 0;
+    Ir = 0.0;
+    Ii = 0.0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const double ux = x - zx[c], uy = y - zy[c];
         Ir += w[c] * (C[c][0] + (C[c][2] * ux - C[c][3] * uy));
         Ii += w[c] * (C[c][1] + (C[c][2] * uy + C[c][3] * ux));
+    }
+}
+
+// The square's local data D (normalised) and its size sigma.
+__device__ __forceinline__ void square_local(const double C[4][4], double X0, double X1, double Y0,
+                                             double Y1, const LearnGeom &lg, float D[16],
+                                             double &sigma)
+{
+    const double zx[4] = {X0, X1, X0, X1}, zy[4] = {Y0, Y0, Y1, Y1};
+    double mAr = 0, mAi = 0, mdr = 0, mdi = 0, mzx = 0, mzy = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
         mAr += C[c][0]; mAi += C[c][1]; mdr += C[c][2]; mdi += C[c][3];
         mzx += zx[c]; mzy += zy[c];
     }
@@ -260,20 +273,25 @@ __device__ __forceinline__ void square_eval(const double C[4][4], double X0, dou
         sig2 = fmax(sig2, dd[0] * dd[0] + dd[1] * dd[1]);
         sig2 = fmax(sig2, dd[2] * dd[2] + dd[3] * dd[3]);
     }
-    const double sig = fmax(sqrt(sig2), 1e-280);
-    const double is = 1.0 / sig;
+    sigma = fmax(sqrt(sig2), 1e-280);
+    const double is = 1.0 / sigma;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         double dd[4];
         data(c, dd);
-        o.D[2 * c] = (float)(dd[0] * is);
-        o.D[2 * c + 1] = (float)(dd[1] * is);
-        o.D[8 + 2 * c] = (float)(dd[2] * is);
-        o.D[8 + 2 * c + 1] = (float)(dd[3] * is);
+        D[2 * c] = (float)(dd[0] * is);
+        D[2 * c + 1] = (float)(dd[1] * is);
+        D[8 + 2 * c] = (float)(dd[2] * is);
+        D[8 + 2 * c + 1] = (float)(dd[3] * is);
     }
-    o.Ir = Ir;
-    o.Ii = Ii;
-    o.sigma = sig;
+}
+
+__device__ __forceinline__ void square_eval(const double C[4][4], double X0, double X1, double Y0,
+                                            double Y1, const LearnGeom &lg, double x, double y,
+                                            double hx, double hy, Sq &o)
+{
+    square_base(C, X0, X1, Y0, Y1, x, y, hx, hy, o.Ir, o.Ii);
+    square_local(C, X0, X1, Y0, Y1, lg, o.D, o.sigma);
 }
 
 // sum_k L_k D_k with L_k = y_2k + i y_2k+1
@@ -921,11 +939,11 @@ __global__ __launch_bounds__(kThreads) void k_ltab_eval(const float *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Rays with the learned interpolant.  One wave = 64 consecutive rays of a row;
-// a persistent workgroup of 8 waves keeps the weight table in LDS and walks
-// the band's (row, 64-column) items.
+// Rays with the learned interpolant.  One wave item = 64 consecutive columns
+// of kLearnRows rows (a lane takes one column's rows); a persistent workgroup
+// of 6 waves keeps the weight table in LDS and walks the band's items.
 // ---------------------------------------------------------------------------
-constexpr int kL3Threads = 512;
+constexpr int kL3Threads = 384;
 
 // One nearby lens's term m (d1, d2)/r^2, d = theta - z: m/r^2 is the
 // hardware reciprocal estimate times m corrected once (relative error about
@@ -949,6 +967,13 @@ __device__ __forceinline__ void near_lens(double t1, double t2, double zx, doubl
 // cells of the rectangle, whose rays (with a sheet) it leaves out;
 // CORNER = true: rays of one of those cells, with the sheet's closed form
 // (its logarithms would otherwise set every ray's register budget).
+// rays of a lane: kLearnRows consecutive rows of one column
+constexpr int kLearnRows = 4;
+template <int A, int B>
+struct RowSpan {
+    static constexpr int first = A, last = B;
+};
+
 #define IRS_LEARNED_RAY_ARGS                                                                      \
     DevGeom g, LearnGeom lg, const double *__restrict__ lx, const double *__restrict__ ly,        \
         const double *__restrict__ lm, const int32_t *__restrict__ cell_start,                    \
@@ -967,32 +992,35 @@ __device__ __forceinline__ void learned_rays(IRS_LEARNED_RAY_ARGS)
     const int lane = threadIdx.x % kW;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);   // items are wave-uniform
     constexpr int kWaves = kL3Threads / kW;
+    constexpr int R = kLearnRows;
     const int64_t ntx = (i1 - i0 + kW - 1) / kW;
-    const int64_t items = (j1 - j0) * ntx;
+    const int64_t items = (j1 - j0 + R - 1) / R * ntx;
     const int q1 = lg.qc + 1;
     const int64_t nyc = (int64_t)g.n1y * lg.qc;
+    auto cell_row = [&](int64_t j) { return (int32_t)(((2 * j + 1) * nyc) / (2 * g.ny) / lg.qc); };
     unsigned long long nland = 0;
     for (int64_t it = (int64_t)blockIdx.x * kWaves + wave; it < items; it += (int64_t)gridDim.x * kWaves) {
-        const int64_t j = j0 + it / ntx;
+        // rows jg .. jg + nr - 1 of one column per lane
+        const int64_t jg = j0 + (it / ntx) * R;
+        const int nr = (int)min<int64_t>(R, j1 - jg);
         const int64_t i = i0 + (it % ntx) * kW + lane;
-        const int64_t r = j * g.nx + i;
-        bool valid = i < i1 && r >= ray_first && r < ray_last;
-        double b1 = 0.0, b2 = 0.0, sig = 0.0;
-        float hx = 0.5f, hy = 0.5f;
-        float D[16];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) D[e] = 0.0f;
-        const double t1 = ray_x(g, i), t2 = ray_y(g, j);
-        // nearby lenses, exactly, in a loop the whole wave shares (the item
-        // is one ray row, so the level-1 row is the wave's; where the wave's
-        // columns straddle two level-1 columns a lane gives the lenses
-        // outside its own 3 x 3 cells mass 0, adding exact zeros)
-        double n1 = 0.0, n2 = 0.0;
+        const bool in_col = i < i1;
         // the lane's square column and level-1 column (lanes past the
-        // range take its last column); the row's square row (wave-uniform)
-        const int2 sq = lcol[i < i1 ? i : i1 - 1];
-        const int64_t gyc = ((2 * j + 1) * nyc) / (2 * g.ny);
-        const int32_t cy_ = (int32_t)(gyc / lg.qc);
+        // range take its last column)
+        const int2 sq = lcol[in_col ? i : i1 - 1];
+        const double t1 = ray_x(g, in_col ? i : i1 - 1);
+        double t2s[R], n1[R], n2[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            t2s[k] = ray_y(g, jg + min(k, nr - 1));     // rows past the range repeat the last
+            n1[k] = 0.0;
+            n2[k] = 0.0;
+        }
+        // nearby lenses, exactly, in a loop the whole wave shares: the lens
+        // data come in scalar loads, each lens serves all the lane's rows of
+        // one level-1 row; where the wave's columns straddle two level-1
+        // columns a lane gives the lenses outside its own 3 x 3 cells mass 0,
+        // adding exact zeros
         {
             const int32_t cxl = sq.y;
             // columns grow with the lane: lane 0 has the first, lane 63 the last
@@ -1001,72 +1029,104 @@ __device__ __forceinline__ void learned_rays(IRS_LEARNED_RAY_ARGS)
             const int32_t cl = cxa > 0 ? cxa - 1 : 0, ch = cxb < g.n1x - 1 ? cxb + 1 : g.n1x - 1;
             const int32_t xl = cxl > 0 ? cxl - 1 : 0, xh = cxl < g.n1x - 1 ? cxl + 1 : g.n1x - 1;
             const bool straddle = cxa != cxb;
-            const int32_t yl = cy_ > 0 ? cy_ - 1 : 0, yh = cy_ < g.n1y - 1 ? cy_ + 1 : g.n1y - 1;
-            for (int32_t row = yl; row <= yh; ++row) {
-                const int32_t pb = cell_start[row * g.n1x + cl];
-                const int32_t pe = cell_start[row * g.n1x + ch + 1];
-                int32_t lpb = pb, lpe = pe;
-                if (straddle) {
-                    lpb = cell_start[row * g.n1x + xl];
-                    lpe = cell_start[row * g.n1x + xh + 1];
-                }
-                for (int32_t q_ = pb; q_ < pe; ++q_) {
-                    double m = UNIT ? 1.0 : lm[q_];
-                    if (straddle) m = (q_ >= lpb && q_ < lpe) ? m : 0.0;
-                    near_lens(t1, t2, lx[q_], ly[q_], m, n1, n2);
-                }
-            }
-        }
-        if (valid) {
-            const int64_t gxc = sq.x;
-            const int64_t cx = sq.y, cy = cy_;
-            const int a = (int)(gxc - cx * lg.qc), b = (int)(gyc - cy * lg.qc);
-            if (!CORNER && g.sheet && corner_cell_l(g, cx, cy)) valid = false;
-            const double X0 = corner_x(g, lg, gxc), X1 = corner_x(g, lg, gxc + 1);
-            const double Y0 = corner_y(g, lg, gyc), Y1 = corner_y(g, lg, gyc + 1);
-            const double dhx = (t1 - X0) / lg.sx, dhy = (t2 - Y0) / lg.sy;
-            double C[4][4];
-            load_corners(corner, (cy - cy0) * g.n1x + cx, q1, a, b, C);
-            Sq sq;
-            square_eval(C, X0, X1, Y0, Y1, lg, t1, t2, dhx, dhy, sq);
-            double Ar = sq.Ir, Ai = sq.Ii;
-            if (g.sheet) {
-                if constexpr (CORNER) {
-                    double I1, I2;
-                    sheet_unit(g, t1, t2, I1, I2);
-                    const double f = -g.kappa_star / M_PI;
-                    Ar += f * I1;
-                    Ai -= f * I2;
-                } else {
-                    Ar -= g.kappa_star * t1;          // -kappa_* conj(z)
-                    Ai += g.kappa_star * t2;
-                }
-            }
-            b1 = g.kpg * t1 + n1 + Ar;            // alpha without the learned correction
-            b2 = g.kmg * t2 + n2 - Ai;
-            sig = sq.sigma;
-            hx = (float)dhx;
-            hy = (float)dhy;
+            auto pass = [&](int32_t cyr, auto rows) {           // rows: compile-time [k0, k1)
+                constexpr int k0 = decltype(rows)::first, k1 = decltype(rows)::last;
+                const int32_t yl = cyr > 0 ? cyr - 1 : 0, yh = cyr < g.n1y - 1 ? cyr + 1 : g.n1y - 1;
+                for (int32_t row = yl; row <= yh; ++row) {
+                    const int32_t pb = cell_start[row * g.n1x + cl];
+                    const int32_t pe = cell_start[row * g.n1x + ch + 1];
+                    int32_t lpb = pb, lpe = pe;
+                    if (straddle) {
+                        lpb = cell_start[row * g.n1x + xl];
+                        lpe = cell_start[row * g.n1x + xh + 1];
+                    }
+                    for (int32_t q_ = pb; q_ < pe; ++q_) {
+                        double m = UNIT ? 1.0 : lm[q_];
+                        if (straddle) m = (q_ >= lpb && q_ < lpe) ? m : 0.0;
+                        const double zx = lx[q_], zy = ly[q_];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) D[e] = sq.D[e];
-        }
-        int32_t pix = -1;
-        if (valid) {
-            float pr, pi;
-            ltab_combine<kNO, 1>(s_tab, hx, hy, D, pr, pi);
-            const double a1 = b1 + sig * (double)pr;     // conj of the correction
-            const double a2 = b2 - sig * (double)pi;
-            pix = pixel_of(g, t1 - a1, t2 - a2);
-            if (!counts) {
-                const int64_t o = r - ray_first;
-                if (a1o) a1o[o] = a1;
-                if (a2o) a2o[o] = a2;
-                if (pixo) pixo[o] = pix;
+                        for (int k = k0; k < k1; ++k) near_lens(t1, t2s[k], zx, zy, m, n1[k], n2[k]);
+                    }
+                }
+            };
+            const int32_t cyA = cell_row(jg), cyB = cell_row(jg + nr - 1);   // wave-uniform
+            if (cyA == cyB) {
+                pass(cyA, RowSpan<0, R>{});
+            } else {                                        // rows sorted: split by cell row
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    if (k < nr) {
+                        const int32_t cyk = cell_row(jg + k);
+                        if (k == 0) pass(cyk, RowSpan<0, 1>{});
+                        else if (k == 1) pass(cyk, RowSpan<1, 2>{});
+                        else if (k == 2) pass(cyk, RowSpan<2, 3>{});
+                        else pass(cyk, RowSpan<3, 4>{});
+                    }
             }
         }
-        if (counts) {
-            bin_runs(counts, pix);
-            nland += __popcll(__ballot(pix >= 0));
+        // per row: the square's corners (cached loads) and, when the square
+        // row changes (a wave-uniform test), its local data; then each ray's
+        // base interpolant, learned correction, pixel and bin
+        const int64_t gxc = sq.x, cx = sq.y;
+        const int a = (int)(gxc - cx * lg.qc);
+        const double X0 = corner_x(g, lg, gxc), X1 = corner_x(g, lg, gxc + 1);
+        const float hx = (float)((t1 - X0) / lg.sx);
+        float D[16];
+        double sig = 0.0;
+        int64_t cgy = -1;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (k >= nr) break;                             // wave-uniform
+            const int64_t j = jg + k;
+            const int64_t gyc = ((2 * j + 1) * nyc) / (2 * g.ny);
+            const int64_t cy = gyc / lg.qc;
+            const double Y0 = corner_y(g, lg, gyc), Y1 = corner_y(g, lg, gyc + 1);
+            double C[4][4];
+            load_corners(corner, (cy - cy0) * g.n1x + cx, q1, a, (int)(gyc - cy * lg.qc), C);
+            if (gyc != cgy) {                               // wave-uniform
+                square_local(C, X0, X1, Y0, Y1, lg, D, sig);
+                cgy = gyc;
+            }
+            const double t2 = t2s[k];
+            const int64_t r = j * g.nx + i;
+            bool valid = in_col && r >= ray_first && r < ray_last;
+            if (!CORNER && g.sheet && corner_cell_l(g, cx, cy)) valid = false;
+            int32_t pix = -1;
+            if (valid) {
+                const double dhy = (t2 - Y0) / lg.sy;
+                double Ar, Ai;
+                square_base(C, X0, X1, Y0, Y1, t1, t2, (double)hx, dhy, Ar, Ai);
+                if (g.sheet) {
+                    if constexpr (CORNER) {
+                        double I1, I2;
+                        sheet_unit(g, t1, t2, I1, I2);
+                        const double f = -g.kappa_star / M_PI;
+                        Ar += f * I1;
+                        Ai -= f * I2;
+                    } else {
+                        Ar -= g.kappa_star * t1;          // -kappa_* conj(z)
+                        Ai += g.kappa_star * t2;
+                    }
+                }
+                float pr, pi;
+                ltab_combine<kNO, 1>(s_tab, hx, (float)dhy, D, pr, pi);
+                // alpha: the near lenses, the macro term, the base
+                // interpolant and the conjugate of the learned correction
+                const double a1 = (g.kpg * t1 + n1[k] + Ar) + sig * (double)pr;
+                const double a2 = (g.kmg * t2 + n2[k] - Ai) - sig * (double)pi;
+                pix = pixel_of(g, t1 - a1, t2 - a2);
+                if (!counts) {
+                    const int64_t o = r - ray_first;
+                    if (a1o) a1o[o] = a1;
+                    if (a2o) a2o[o] = a2;
+                    if (pixo) pixo[o] = pix;
+                }
+            }
+            if (counts) {
+                bin_runs(counts, pix);
+                nland += __popcll(__ballot(pix >= 0));
+            }
+            asm volatile("" ::: "memory");      // keep the next row's corner loads in its row
         }
     }
     if (counts && lane == 0 && nland) landed_add(landed, nland);
@@ -1075,9 +1135,9 @@ __device__ __forceinline__ void learned_rays(IRS_LEARNED_RAY_ARGS)
 #define IRS_LEARNED_RAY_PASS                                                                      \
     g, lg, lx, ly, lm, cell_start, corner, cy0, tab, lcol, i0, i1, j0, j1, ray_first, ray_last, a1o, \
         a2o, pixo, counts, landed
-// four waves a SIMD (the table's LDS allows two workgroups a CU)
+// three waves a SIMD: two workgroups of six waves a CU (the table's LDS allows two)
 template <bool UNIT>
-__global__ __launch_bounds__(kL3Threads, 4) void k_level3_learned(IRS_LEARNED_RAY_ARGS)
+__global__ __launch_bounds__(kL3Threads, 3) void k_level3_learned(IRS_LEARNED_RAY_ARGS)
 {
     learned_rays<UNIT, false>(IRS_LEARNED_RAY_PASS);
 }
@@ -1590,7 +1650,7 @@ irs_status launch_learned(irs_plan_s *p, const RaySel &sel)
         // rays of columns [i0, i1), rows [ja, jb): the main kernel, or one
         // corner cell's
         auto launch = [&](bool corner_cell, int64_t i0, int64_t i1, int64_t ja, int64_t jb) {
-            const int64_t items = (jb - ja) * ((i1 - i0 + kW - 1) / kW);
+            const int64_t items = (jb - ja + kLearnRows - 1) / kLearnRows * ((i1 - i0 + kW - 1) / kW);
             const unsigned nb = (unsigned)std::max<int64_t>(
                 1, std::min<int64_t>((int64_t)per_cu * ncu, (items + kL3Threads / kW - 1) / (kL3Threads / kW)));
 #define IRS_L3L(K)                                                                                 \
