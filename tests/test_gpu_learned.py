@@ -261,6 +261,28 @@ def test_learned_rays_match_oracle_and_direct(irs, trained):
     assert do.max() <= FWD_TOL * rep["base_max_abs"] + 1e-12
 
 
+def test_learned_rays_independent_of_the_call(irs, trained):
+    """A lane of the learned ray kernel takes four rows of one column, and
+    nothing is shared between rows but loads, so a ray's alpha and pixel are
+    the same bits whether it is shot alone or inside whole rows: here every
+    ray of rows that straddle level-1 cell rows, against single-ray calls."""
+    pl, p, L, og, rep = trained
+    if rep["fallback"]:
+        pytest.skip("the network missed the tolerance; the fallback is tested separately")
+    g = pl.geometry
+    nx = g["nx"]
+    j0, _ = pl.level1_row_rays(g["n1y"] // 2)       # a level-1 row's first ray row
+    first = (j0 - 3) * nx                           # rows j0-3 .. j0+2: two cell rows
+    n = 6 * nx
+    a1, a2, px = pl.deflect_grid(first, n)
+    rng = np.random.default_rng(8)
+    ids = np.sort(rng.choice(n, 600, replace=False))
+    for k in ids:
+        b1, b2, bp = pl.deflect_grid(first + int(k), 1)
+        assert (a1[k], a2[k], px[k]) == (b1[0], b2[0], bp[0]), int(k)
+    say(f"learned rows {j0 - 3}..{j0 + 2}: {n} rays, 600 single-ray calls identical")
+
+
 def test_learned_map_vs_direct(irs, trained):
     """Whole map: the learned map against the direct-sum map (the reference)."""
     pl, p, L, og, rep = trained
