@@ -552,26 +552,28 @@ irs_status irs_batch_run(irs_batch_t b, uint32_t *const *counts, irs_map_stats *
         b->graph_bpc = b->bpc;
         b->graph_band_rows = b->band_rows;
     }
-    hipEvent_t e0, e1;
-    IRS_HIP(hipEventCreate(&e0));
-    IRS_HIP(hipEventCreate(&e1));
-    (void)hipEventRecord(e0, b->stream);
-    hipError_t e = hipGraphLaunch(b->exec, b->stream);
-    if (e != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return hip_fail(e, "hipGraphLaunch");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+    const char *what = "irs_batch_run: timing events";
+    if (e == hipSuccess) {
+        e = hipGraphLaunch(b->exec, b->stream);
+        what = "hipGraphLaunch";
     }
-    (void)hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) (void)hipEventRecord(e1, b->stream);
     std::vector<unsigned long long> landed(1 + (size_t)n * kLandedSlots);
-    e = hipMemcpyAsync(landed.data(), b->d_cursor, sizeof(unsigned long long) * landed.size(),
-                       hipMemcpyDeviceToHost, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) {
+        e = hipMemcpyAsync(landed.data(), b->d_cursor, sizeof(unsigned long long) * landed.size(),
+                           hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        what = "irs_batch_run";
+    }
     float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (e != hipSuccess) return hip_fail(e, "irs_batch_run");
+    if (e == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, what);
     for (irs_plan_s *p : b->plans) {        // a replay leaves no band the host knows of
         p->coef_c0 = -1;
         p->coef_c1 = -2;
