@@ -242,9 +242,9 @@ irs_status time_direct(irs_batch_s *b, int variant, int bpc, uint32_t *scratch, 
     int64_t start[2] = {0, sample};
     IRS_HIP(hipMemcpyAsync(b->d_maps, &a, sizeof a, hipMemcpyHostToDevice, b->stream));
     IRS_HIP(hipMemcpyAsync(b->d_item_start, start, sizeof start, hipMemcpyHostToDevice, b->stream));
-    hipEvent_t e0, e1;
-    IRS_HIP(hipEventCreate(&e0));
-    IRS_HIP(hipEventCreate(&e1));
+    EventPair ev;
+    IRS_HIP(ev.create());
+    const hipEvent_t e0 = ev.a, e1 = ev.b;
     irs_status st = IRS_OK;
     ms = 0.0;
     for (int rep = 0; rep < 2 && st == IRS_OK; ++rep) {     // first run warms up
@@ -259,8 +259,6 @@ irs_status time_direct(irs_batch_s *b, int variant, int bpc, uint32_t *scratch, 
         if (st == IRS_OK) (void)hipEventElapsedTime(&f, e0, e1);
         ms = (double)f * (double)items / (double)sample;     // whole-map estimate
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (st != IRS_OK) set_error("autotuner: timing launch failed");
     return st;
 }
@@ -285,9 +283,9 @@ irs_status time_interp(irs_batch_s *b, int rows, uint32_t *scratch, double &ms)
         }
         j1 = lo;
     }
-    hipEvent_t e0, e1;
-    IRS_HIP(hipEventCreate(&e0));
-    IRS_HIP(hipEventCreate(&e1));
+    EventPair ev;
+    IRS_HIP(ev.create());
+    const hipEvent_t e0 = ev.a, e1 = ev.b;
     hipStream_t saved = p->stream;
     p->stream = b->stream;
     ms = 0.0;
@@ -312,8 +310,6 @@ irs_status time_interp(irs_batch_s *b, int rows, uint32_t *scratch, double &ms)
     p->stream = saved;
     p->coef_c0 = -1;
     p->coef_c1 = -2;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     return st;
 }
 
@@ -552,9 +548,9 @@ irs_status irs_batch_run(irs_batch_t b, uint32_t *const *counts, irs_map_stats *
         b->graph_bpc = b->bpc;
         b->graph_band_rows = b->band_rows;
     }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
+    EventPair ev;
+    hipError_t e = ev.create();
+    const hipEvent_t e0 = ev.a, e1 = ev.b;
     if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
     const char *what = "irs_batch_run: timing events";
     if (e == hipSuccess) {
@@ -571,8 +567,6 @@ irs_status irs_batch_run(irs_batch_t b, uint32_t *const *counts, irs_map_stats *
     }
     float ms = 0.0f;
     if (e == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, what);
     for (irs_plan_s *p : b->plans) {        // a replay leaves no band the host knows of
         p->coef_c0 = -1;

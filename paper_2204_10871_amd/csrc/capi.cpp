@@ -271,7 +271,11 @@ struct Timer {
     hipStream_t s;
     explicit Timer(hipStream_t st) : s(st)
     {
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) a = b = nullptr;
+        if (hipEventCreate(&a) != hipSuccess) a = nullptr;
+        if (a && hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            a = b = nullptr;
+        }
         if (a) (void)hipEventRecord(a, s);
     }
     double stop()

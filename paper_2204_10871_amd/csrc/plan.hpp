@@ -107,6 +107,25 @@ struct irs_plan_s {
 
 namespace irs {
 
+// Two timing events, released on every path (create() may fail part-way).
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t create()
+    {
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        return e;
+    }
+    EventPair() = default;
+    EventPair(const EventPair &) = delete;
+    EventPair &operator=(const EventPair &) = delete;
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
 // Every device allocation of the library: hipMalloc, or hipErrorOutOfMemory
 // (nothing allocated, *ptr null) for the allocation that the countdown of
 // irs_debug_fail_alloc selects; and its release (NULL ignored).  Both keep
