@@ -124,14 +124,16 @@ def test_batch_equals_single_plans(irs, method, precision):
 def test_interp_batch_mixed_maps(irs, which):
     """The one-launch level 3 over maps of different kinds: column tiles that
     follow the level-1 cells (124 columns a cell) and tiles that straddle them
-    (25), a map without the sheet (no corner-cell rays), a map of 2,000 rays;
-    and a batch of one map.  Every map equals its own plan bit for bit and
+    (25), a map without the sheet (no corner-cell rays), a map of 2,000 rays,
+    a map without lenses; and a batch of one map.  Every map equals its own plan bit for bit and
     meets the oracle's direct definition."""
     import torch
+    empty = synth.Lenses(np.zeros(0), np.zeros(0), None)
     specs = [((0.25, 0.0, 0.05, 4.0, 64), dict(n_rays=1_960_000)),
              ((0.3, 0.0, 0.3, 8.0, 64), dict(n_rays=150_000)),
              ((0.45, 0.05, 0.45, 6.0, 32), dict(n_rays=20_000, sheet=False)),
-             ((0.2, 0.2, 0.1, 10.0, 48), dict(n_rays=2_000))]
+             ((0.2, 0.2, 0.1, 10.0, 48), dict(n_rays=2_000)),
+             ((0.0, 0.23, 0.11, 3.7, 37), dict(n_rays=611 * 577, border=0.37, lenses=empty))]
     if which == "one":
         specs = specs[2:3]
     cases = [Case(*a, seed=90 + k, **kw) for k, (a, kw) in enumerate(specs)]
