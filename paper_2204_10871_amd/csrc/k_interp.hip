@@ -346,15 +346,31 @@ __global__ __launch_bounds__(kThreads) void k_level2_expand(
     double Lr[P], Li[P];
 #pragma unroll
     for (int n = 0; n < P; ++n) Lr[n] = Li[n] = 0.0;
+    // each thread's lens of the next stage is loaded while this stage is summed
+    double fx = 0.0, fy = 0.0, fm = 0.0;
+    uint32_t fc = 0u;
+    if (lo + tid < hi) {
+        fx = lx[lo + tid];
+        fy = ly[lo + tid];
+        if (!UNIT) fm = lm[lo + tid];
+        fc = lcxy[lo + tid];
+    }
     for (int32_t base = lo; base < hi; base += kThreads) {
         __syncthreads();
         if (base + tid < hi) {
-            s_x[tid] = lx[base + tid];
-            s_y[tid] = ly[base + tid];
-            if (!UNIT) s_m[tid] = lm[base + tid];
-            s_c[tid] = lcxy[base + tid];
+            s_x[tid] = fx;
+            s_y[tid] = fy;
+            if (!UNIT) s_m[tid] = fm;
+            s_c[tid] = fc;
         }
         __syncthreads();
+        if (base + kThreads + tid < hi) {
+            const int32_t li = base + kThreads + tid;
+            fx = lx[li];
+            fy = ly[li];
+            if (!UNIT) fm = lm[li];
+            fc = lcxy[li];
+        }
         const int cnt = min(kThreads, hi - base);
         // two lenses per lane at a time: two independent power chains
 #pragma unroll
@@ -463,15 +479,31 @@ __global__ __launch_bounds__(kThreads) void k_super_expand(
     double Lr[PS], Li[PS];
 #pragma unroll
     for (int n = 0; n < PS; ++n) Lr[n] = Li[n] = 0.0;
+    // each thread's lens of the next stage is loaded while this stage is summed
+    double fx = 0.0, fy = 0.0, fm = 0.0;
+    uint32_t fc = 0u;
+    if (lo + tid < hi) {
+        fx = lx[lo + tid];
+        fy = ly[lo + tid];
+        if (!UNIT) fm = lm[lo + tid];
+        fc = lcxy[lo + tid];
+    }
     for (int32_t base = lo; base < hi; base += kThreads) {
         __syncthreads();
         if (base + tid < hi) {
-            s_x[tid] = lx[base + tid];
-            s_y[tid] = ly[base + tid];
-            if (!UNIT) s_m[tid] = lm[base + tid];
-            s_c[tid] = lcxy[base + tid];
+            s_x[tid] = fx;
+            s_y[tid] = fy;
+            if (!UNIT) s_m[tid] = fm;
+            s_c[tid] = fc;
         }
         __syncthreads();
+        if (base + kThreads + tid < hi) {
+            const int32_t li = base + kThreads + tid;
+            fx = lx[li];
+            fy = ly[li];
+            if (!UNIT) fm = lm[li];
+            fc = lcxy[li];
+        }
         const int cnt = min(kThreads, hi - base);
 #pragma unroll
         for (int k = 0; k < kThreads / kWave; k += 2) {
@@ -548,8 +580,10 @@ __global__ __launch_bounds__(kThreads) void k_super_reduce(const double *__restr
 // children from c0:  out[(((cy - c0) nCx + cx) P + n) 2 + c].
 constexpr int kSuperRows = (2 * kSuperR + 1) * kSuperKMax; // cell rows of a parent block, at most
 
+// Two waves a SIMD: the 48-term instances need a few more registers than
+// 256 and would otherwise run one wave a SIMD (a few spills cost less).
 template <bool UNIT, int P, int PS>
-__global__ __launch_bounds__(kThreads) void k_level2_near(
+__global__ __launch_bounds__(kThreads, 2) void k_level2_near(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
     const double *__restrict__ lm, const uint32_t *__restrict__ lcxy,
     const int32_t *__restrict__ cell_start, const double *__restrict__ super, int32_t nSx,
@@ -593,23 +627,41 @@ __global__ __launch_bounds__(kThreads) void k_level2_near(
     double Lr[P], Li[P];
 #pragma unroll
     for (int n = 0; n < P; ++n) Lr[n] = Li[n] = 0.0;
+    // each thread's lens of the next stage is loaded while this stage is summed
+    auto lens_of = [&](int32_t gi) {              // row of lens gi: s_off[r] <= gi < s_off[r + 1]
+        int r = 0, rh = nrow - 1;
+        while (r < rh) {
+            const int mid = (r + rh + 1) >> 1;
+            if (s_off[mid] <= gi) r = mid;
+            else rh = mid - 1;
+        }
+        return s_pb[r] + (gi - s_off[r]);
+    };
+    double fx = 0.0, fy = 0.0, fm = 0.0;
+    uint32_t fc = 0u;
+    if (tid < total) {
+        const int32_t li = lens_of(tid);
+        fx = lx[li];
+        fy = ly[li];
+        if (!UNIT) fm = lm[li];
+        fc = lcxy[li];
+    }
     for (int32_t base = 0; base < total; base += kThreads) {
         __syncthreads();
         if (base + tid < total) {
-            const int32_t gi = base + tid;
-            int r = 0, rh = nrow - 1;                  // row of this lens: s_off[r] <= gi < s_off[r + 1]
-            while (r < rh) {
-                const int mid = (r + rh + 1) >> 1;
-                if (s_off[mid] <= gi) r = mid;
-                else rh = mid - 1;
-            }
-            const int32_t li = s_pb[r] + (gi - s_off[r]);
-            s_x[tid] = lx[li];
-            s_y[tid] = ly[li];
-            if (!UNIT) s_m[tid] = lm[li];
-            s_c[tid] = lcxy[li];
+            s_x[tid] = fx;
+            s_y[tid] = fy;
+            if (!UNIT) s_m[tid] = fm;
+            s_c[tid] = fc;
         }
         __syncthreads();
+        if (base + kThreads + tid < total) {
+            const int32_t li = lens_of(base + kThreads + tid);
+            fx = lx[li];
+            fy = ly[li];
+            if (!UNIT) fm = lm[li];
+            fc = lcxy[li];
+        }
         const int cnt = min(kThreads, total - base);
 #pragma unroll
         for (int k = 0; k < kThreads / kWave; k += 2) {
