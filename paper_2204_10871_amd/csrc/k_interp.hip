@@ -284,7 +284,7 @@ __global__ __launch_bounds__(kThreads) void k_level2(
 //
 // One workgroup = four cells of one level-1 row (one wave per cell).  Lens
 // tiles are staged in LDS once for the four waves; each lane takes four lenses
-// of a tile.  The expansions are reduced across lanes with shuffles.
+// of a tile.  The expansions are combined across lanes by a reduce-scatter.
 // -------------------------------------------------------------------------
 constexpr int kCellsPerBlock = kThreads / kWave;
 
@@ -299,25 +299,61 @@ __device__ __forceinline__ double rcp64(double d)
     return fma(v, e, v);
 }
 
-}  // namespace
-}  // namespace irs
-// the device library's whole-wave FP64 sum (declared by the HIP headers only
-// on request)
-extern "C" __device__ __attribute__((const)) double __ockl_wfred_add_f64(double);
-namespace irs {
-namespace {
-
-// whole-wave sum (every lane active) through the device library's cross-lane
-// (DPP) sequence; the order of the additions is fixed
-__device__ __forceinline__ double wave_sum(double v) { return __ockl_wfred_add_f64(v); }
-
-// the value lane n (uniform) holds
-__device__ __forceinline__ double lane_value(double v, int n)
+// Whole-wave reduce-scatter (every lane active): each lane holds v[0..N), N a
+// multiple of 64; afterwards lane L holds in v[0..N/64) the sums over the 64
+// lanes of entries L N/64 .. L N/64 + N/64 - 1.  Six halving steps: in the step
+// of lane bit b the lane keeps the lower half of its list if b is clear, the
+// upper half if set, and adds the partner's copy of that half (the partner
+// differs in bit b and agrees in every higher bit).  Bits 5 and 4 exchange
+// through gfx950's half-wave and row swaps, bits 3 .. 0 through DPP (row
+// mirror, half-row mirror, quad permutations).  The order of the additions is
+// fixed, so the sums are reproducible.
+__device__ __forceinline__ uint32_t lo32(double v) { return (uint32_t)__double_as_longlong(v); }
+__device__ __forceinline__ uint32_t hi32(double v) { return (uint32_t)((uint64_t)__double_as_longlong(v) >> 32); }
+__device__ __forceinline__ double from32(uint32_t lo, uint32_t hi)
 {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, n);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), n);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// one DPP halving step: H entries kept of 2H, partner lane by DPP control C
+template <int C, int H, int N>
+__device__ __forceinline__ void dpp_half(double (&v)[N], bool up)
+{
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const double keep = up ? v[i + H] : v[i];
+        const double send = up ? v[i] : v[i + H];
+        const uint32_t rl = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo32(send), C, 0xf, 0xf, false);
+        const uint32_t rh = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi32(send), C, 0xf, 0xf, false);
+        v[i] = keep + from32(rl, rh);
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void wave_reduce_scatter(double (&v)[N])
+{
+    static_assert(N % kWave == 0, "a multiple of the wave size");
+    // bit 5: lanes 0-31 keep the lower half, lanes 32-63 the upper
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i) {
+        const auto l = __builtin_amdgcn_permlane32_swap(lo32(v[i]), lo32(v[i + N / 2]), false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi32(v[i]), hi32(v[i + N / 2]), false, false);
+        v[i] = from32(l[0], h[0]) + from32(l[1], h[1]);
+    }
+    // bit 4: rows 0 and 2 keep the lower half, rows 1 and 3 the upper
+#pragma unroll
+    for (int i = 0; i < N / 4; ++i) {
+        const auto l = __builtin_amdgcn_permlane16_swap(lo32(v[i]), lo32(v[i + N / 4]), false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi32(v[i]), hi32(v[i + N / 4]), false, false);
+        v[i] = from32(l[0], h[0]) + from32(l[1], h[1]);
+    }
+    // bits 3 .. 0 (row mirror: lane ^ 15, half-row mirror: lane ^ 7, quad
+    // permutations: lane ^ 2, lane ^ 1)
+    const int lane = (int)(threadIdx.x % kWave);
+    dpp_half<0x140, N / 8>(v, (lane & 8) != 0);
+    dpp_half<0x141, N / 16>(v, (lane & 4) != 0);
+    dpp_half<0x4e, N / 32>(v, (lane & 2) != 0);
+    dpp_half<0xb1, N / 64>(v, (lane & 1) != 0);
 }
 
 template <bool UNIT, int P>
@@ -343,9 +379,11 @@ __global__ __launch_bounds__(kThreads) void k_level2_expand(
     const int32_t hi = min(nl, lo + chunk_len);
 
     // partial expansion of this chunk's lenses outside the (2R+1)^2 block
-    double Lr[P], Li[P];
+    // L[2n], L[2n + 1]: real and imaginary part of term n; zero padding to NV
+    constexpr int NV = (2 * P + kWave - 1) / kWave * kWave;
+    double L[NV];
 #pragma unroll
-    for (int n = 0; n < P; ++n) Lr[n] = Li[n] = 0.0;
+    for (int e = 0; e < NV; ++e) L[e] = 0.0;
     // each thread's lens of the next stage is loaded while this stage is summed
     double fx = 0.0, fy = 0.0, fm = 0.0;
     uint32_t fc = 0u;
@@ -401,8 +439,8 @@ __global__ __launch_bounds__(kThreads) void k_level2_expand(
             }
 #pragma unroll
             for (int n = 0; n < P; ++n) {
-                Lr[n] += tr[0] + tr[1];
-                Li[n] += ti[0] + ti[1];
+                L[2 * n] += tr[0] + tr[1];
+                L[2 * n + 1] += ti[0] + ti[1];
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const double nr = tr[e] * vr[e] - ti[e] * vi[e];
@@ -412,13 +450,13 @@ __global__ __launch_bounds__(kThreads) void k_level2_expand(
             }
         }
     }
+    wave_reduce_scatter(L);
+    if (live) {
+        double *dst = part + (((int64_t)(cy - cy0) * g.n1x + cx) * nchunk + chunk) * P * 2;
 #pragma unroll
-    for (int n = 0; n < P; ++n) {
-        const double r = wave_sum(Lr[n]), i = wave_sum(Li[n]);
-        if (lane == 0 && live) {
-            double *dst = part + ((((int64_t)(cy - cy0) * g.n1x + cx) * nchunk + chunk) * P + n) * 2;
-            dst[0] = r;
-            dst[1] = i;
+        for (int r = 0; r < NV / kWave; ++r) {
+            const int e = lane * (NV / kWave) + r;
+            if (e < 2 * P) dst[e] = L[r];
         }
     }
 }
@@ -476,9 +514,11 @@ __global__ __launch_bounds__(kThreads) void k_super_expand(
     const double isc = 1.0 / sS;
     const int32_t lo = chunk * chunk_len;
     const int32_t hi = min(nl, lo + chunk_len);
-    double Lr[PS], Li[PS];
+    // L[2n], L[2n + 1]: real and imaginary part of term n; zero padding to NV
+    constexpr int NV = (2 * PS + kWave - 1) / kWave * kWave;
+    double L[NV];
 #pragma unroll
-    for (int n = 0; n < PS; ++n) Lr[n] = Li[n] = 0.0;
+    for (int e = 0; e < NV; ++e) L[e] = 0.0;
     // each thread's lens of the next stage is loaded while this stage is summed
     double fx = 0.0, fy = 0.0, fm = 0.0;
     uint32_t fc = 0u;
@@ -533,8 +573,8 @@ __global__ __launch_bounds__(kThreads) void k_super_expand(
             }
 #pragma unroll
             for (int n = 0; n < PS; ++n) {
-                Lr[n] += tr[0] + tr[1];
-                Li[n] += ti[0] + ti[1];
+                L[2 * n] += tr[0] + tr[1];
+                L[2 * n + 1] += ti[0] + ti[1];
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const double nr = tr[e] * vr[e] - ti[e] * vi[e];
@@ -544,13 +584,13 @@ __global__ __launch_bounds__(kThreads) void k_super_expand(
             }
         }
     }
+    wave_reduce_scatter(L);
+    if (live) {
+        double *dst = part + (((int64_t)(Y - Y0) * nSx + X) * nchunk + chunk) * PS * 2;
 #pragma unroll
-    for (int n = 0; n < PS; ++n) {
-        const double r = wave_sum(Lr[n]), i = wave_sum(Li[n]);
-        if (lane == 0 && live) {
-            double *dst = part + ((((int64_t)(Y - Y0) * nSx + X) * nchunk + chunk) * PS + n) * 2;
-            dst[0] = r;
-            dst[1] = i;
+        for (int r = 0; r < NV / kWave; ++r) {
+            const int e = lane * (NV / kWave) + r;
+            if (e < 2 * PS) dst[e] = L[r];
         }
     }
 }
@@ -592,7 +632,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_level2_near(
 {
     __shared__ double s_x[kThreads], s_y[kThreads], s_m[UNIT ? 1 : kThreads];
     __shared__ uint32_t s_c[kThreads];
-    __shared__ double s_E[PS][2];
+    __shared__ double2 s_A[kWave + PS];     // n! E_n, zero from n = PS on
+    __shared__ double s_F[kWave];           // (sc/sS)^(k+1)/k!
     __shared__ int32_t s_pb[kSuperRows], s_off[kSuperRows + 1];
     const int tid = threadIdx.x;
     const int lane = tid % kWave, wave = tid / kWave;
@@ -602,8 +643,17 @@ __global__ __launch_bounds__(kThreads, 2) void k_level2_near(
     const bool live = cx < nCx;
     // ks / kc is a multiple of kCellsPerBlock: the workgroup's children share a parent
     const int32_t X = cx0 * kc / ks, Y = cy * kc / ks;
-    // the super expansion and the lens ranges of the super block, row by row
-    for (int e = tid; e < PS * 2; e += kThreads) s_E[e / 2][e % 2] = super[((int64_t)Y * nSx + X) * PS * 2 + e];
+    // the parent expansion and the lens ranges of the parent block, row by row
+    for (int n = tid; n < kWave + PS; n += kThreads) {
+        double2 a = {0.0, 0.0};
+        if (n < PS) {
+            double f = 1.0;                                   // n!
+            for (int t = 2; t <= n; ++t) f *= (double)t;
+            const double *src = super + (((int64_t)Y * nSx + X) * PS + n) * 2;
+            a = {src[0] * f, src[1] * f};
+        }
+        s_A[n] = a;
+    }
     const int32_t ya = max(0, (Y - kSuperR) * ks), yb = min(g.n1y, (Y + kSuperR + 1) * ks);
     const int32_t xa = max(0, (X - kSuperR) * ks), xb = min(g.n1x, (X + kSuperR + 1) * ks);
     const int nrow = yb - ya;
@@ -613,20 +663,30 @@ __global__ __launch_bounds__(kThreads, 2) void k_level2_near(
         s_off[tid + 1] = cell_start[row * g.n1x + xb] - cell_start[row * g.n1x + xa];
     }
     __syncthreads();
+    const double sc = kc * fmax(g.w1, g.h1), isc = 1.0 / sc;
+    double zSr, zSi, sS;
+    super_centre(g, X, Y, ks, zSr, zSi, sS);
     if (tid == 0) {
         s_off[0] = 0;
         for (int r = 0; r < nrow; ++r) s_off[r + 1] += s_off[r];
+        const double ratio = sc / sS;
+        double f = ratio;
+        for (int k = 0; k < kWave; ++k) {
+            s_F[k] = f;
+            f *= ratio / (double)(k + 1);
+        }
     }
     __syncthreads();
     const int32_t total = s_off[nrow];
 
-    const double sc = kc * fmax(g.w1, g.h1), isc = 1.0 / sc;
     const double zcr = g.a1 + ((double)(kc * cx) + 0.5 * kc) * g.w1;
     const double zci = g.b1 + ((double)(kc * cy) + 0.5 * kc) * g.h1;
 
-    double Lr[P], Li[P];
+    // L[2n], L[2n + 1]: real and imaginary part of term n; zero padding to NV
+    constexpr int NV = (2 * P + kWave - 1) / kWave * kWave;
+    double L[NV];
 #pragma unroll
-    for (int n = 0; n < P; ++n) Lr[n] = Li[n] = 0.0;
+    for (int e = 0; e < NV; ++e) L[e] = 0.0;
     // each thread's lens of the next stage is loaded while this stage is summed
     auto lens_of = [&](int32_t gi) {              // row of lens gi: s_off[r] <= gi < s_off[r + 1]
         int r = 0, rh = nrow - 1;
@@ -691,8 +751,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_level2_near(
             }
 #pragma unroll
             for (int n = 0; n < P; ++n) {
-                Lr[n] += tr[0] + tr[1];
-                Li[n] += ti[0] + ti[1];
+                L[2 * n] += tr[0] + tr[1];
+                L[2 * n + 1] += ti[0] + ti[1];
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const double nr = tr[e] * vr[e] - ti[e] * vi[e];
@@ -702,42 +762,51 @@ __global__ __launch_bounds__(kThreads, 2) void k_level2_near(
             }
         }
     }
-    // translation of the super expansion: lane k < P computes term k
-    double Tr = 0.0, Ti = 0.0;
+    // Translation of the parent expansion to this child, term k of
+    //     T_k = (sc/sS)^(k+1) sum_(n>=k) C(n,k) E_n d^(n-k),  d = (zc - zS)/sS,
+    // as F_k sum_j A_(k+j) b_j with A_n = n! E_n, b_j = d^j/j!, F_k =
+    // (sc/sS)^(k+1)/k!: every lane walks the same j, so b_j is uniform.  The
+    // lane computes the term whose sums it holds after the reduce-scatter
+    // (with P = 32 both lanes of a term).
+    constexpr int R = NV / kWave;
+    const int k = R == 1 ? lane >> 1 : lane;
+    double Tr, Ti;
     {
-        double zSr, zSi, sS;
-        super_centre(g, X, Y, ks, zSr, zSi, sS);
         const double dr = (zcr - zSr) / sS, di = (zci - zSi) / sS;
-        const int k = lane;
-        if (k < P) {
-            double pr = 1.0, pi = 0.0;        // d^(n-k)
-            double cb = 1.0;                  // C(n, k)
-            for (int n = k; n < PS; ++n) {
-                Tr += cb * (s_E[n][0] * pr - s_E[n][1] * pi);
-                Ti += cb * (s_E[n][0] * pi + s_E[n][1] * pr);
-                const double nr = pr * dr - pi * di;
-                pi = pr * di + pi * dr;
-                pr = nr;
-                cb = cb * (double)(n + 1) / (double)(n + 1 - k);
+        double br = 1.0, bi = 0.0;
+        double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0;   // even and odd j
+#pragma unroll
+        for (int j = 0; j < PS; ++j) {
+            const double2 a = s_A[k + j];
+            if (j & 1) {
+                ar1 = fma(a.x, br, fma(-a.y, bi, ar1));
+                ai1 = fma(a.x, bi, fma(a.y, br, ai1));
+            } else {
+                ar0 = fma(a.x, br, fma(-a.y, bi, ar0));
+                ai0 = fma(a.x, bi, fma(a.y, br, ai0));
             }
-            const double f = pow(sc / sS, (double)(k + 1));
-            Tr *= f;
-            Ti *= f;
-            if (fold && live && sheet_fold_ok(g, cx, cy)) {   // cells only: the sheet's series
-                const cplx t = sheet_cell_term(g, zcr, zci, sc, k);
-                Tr += t.r;
-                Ti += t.i;
-            }
+            const double inv = 1.0 / (double)(j + 1);
+            const double nr = (br * dr - bi * di) * inv;
+            bi = (br * di + bi * dr) * inv;
+            br = nr;
+        }
+        const double f = s_F[k];
+        Tr = (ar0 + ar1) * f;
+        Ti = (ai0 + ai1) * f;
+        if (fold && live && k < P && sheet_fold_ok(g, cx, cy)) {   // cells only: the sheet's series
+            const cplx t = sheet_cell_term(g, zcr, zci, sc, k);
+            Tr += t.r;
+            Ti += t.i;
         }
     }
+    wave_reduce_scatter(L);
+    if (live) {
+        double *dst = out + ((int64_t)(cy - c0) * nCx + cx) * P * 2;
 #pragma unroll
-    for (int n = 0; n < P; ++n) {
-        const double r = wave_sum(Lr[n]) + lane_value(Tr, n);
-        const double i = wave_sum(Li[n]) + lane_value(Ti, n);
-        if (lane == 0 && live) {
-            double *dst = out + ((((int64_t)(cy - c0) * nCx + cx)) * P + n) * 2;
-            dst[0] = r;
-            dst[1] = i;
+        for (int r = 0; r < R; ++r) {
+            const int e = lane * R + r;
+            const double t = R == 1 ? ((lane & 1) ? Ti : Tr) : (r ? Ti : Tr);
+            if (e < 2 * P) dst[e] = L[r] + t;
         }
     }
 }
