@@ -823,7 +823,14 @@ __device__ __forceinline__ bool sheet_closed_form(const DevGeom &g, int32_t fold
 // CLOSED = false: the cells that do not take the closed form; CLOSED = true:
 // the cells that do (a workgroup with none returns at once).  The closed
 // form's logarithms would otherwise set every point's register budget.
-template <bool UNIT, int P, bool CLOSED>
+// STAGED: the ring lenses of a workgroup's four cells, which lie in one block
+// of 7 rows x 10 columns of cells, are staged in LDS once; the host takes this
+// instance when no such block of the plan holds more than kRingCap lenses
+// (ring_fits), the other reads them from global memory.
+constexpr int kRingCap = 768;
+constexpr int kRingRows = 2 * kRing + 1, kRingCols = kCellsPerBlock + 2 * kRing;
+
+template <bool UNIT, int P, bool CLOSED, bool STAGED>
 __global__ __launch_bounds__(kThreads) void k_level2_points(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
     const double *__restrict__ lm, const int32_t *__restrict__ cell_start, int32_t cy0,
@@ -831,6 +838,10 @@ __global__ __launch_bounds__(kThreads) void k_level2_points(
     double *__restrict__ coef)
 {
     __shared__ double s_L[kCellsPerBlock][P][2];
+    constexpr int kCap = STAGED ? kRingCap : 1;
+    __shared__ double s_rx[kCap], s_ry[kCap], s_rm[UNIT ? 1 : kCap];
+    __shared__ int32_t s_cs[kRingRows][kRingCols + 1];   // cell_start over the block
+    __shared__ int32_t s_rb[kRingRows + 1];              // LDS offset of each row
     const int tid = threadIdx.x;
     const int32_t cy = cy0 + (int32_t)(blockIdx.x / (uint32_t)nxb);
     const int32_t cx0 = (int32_t)(blockIdx.x % (uint32_t)nxb) * kCellsPerBlock;
@@ -852,6 +863,31 @@ __global__ __launch_bounds__(kThreads) void k_level2_points(
             for (int k = 0; k < nchunk; ++k) acc += src[(int64_t)k * P * 2];
         }
         s_L[w][n][comp] = acc;
+    }
+    // the block of cells holding every ring lens of the four cells
+    const int32_t ya = max(0, cy - kRing), yb = min(g.n1y - 1, cy + kRing);
+    const int32_t ua = max(0, cx0 - kRing), ub = min(g.n1x - 1, cx0 + kCellsPerBlock - 1 + kRing);
+    const int nrow = yb - ya + 1, ncol = ub - ua + 1;
+    for (int e = tid; e < nrow * (ncol + 1); e += kThreads) {
+        const int r = e / (ncol + 1), c = e % (ncol + 1);
+        s_cs[r][c] = cell_start[(int64_t)(ya + r) * g.n1x + ua + c];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        s_rb[0] = 0;
+        for (int r = 0; r < nrow; ++r) s_rb[r + 1] = s_rb[r] + (s_cs[r][ncol] - s_cs[r][0]);
+    }
+    __syncthreads();
+    if constexpr (STAGED) {
+        const int total = min(s_rb[nrow], kRingCap);               // == s_rb[nrow] (ring_fits)
+        for (int i = tid; i < total; i += kThreads) {
+            int r = 0;
+            while (s_rb[r + 1] <= i) ++r;
+            const int32_t src = s_cs[r][0] + (i - s_rb[r]);
+            s_rx[i] = lx[src];
+            s_ry[i] = ly[src];
+            if (!UNIT) s_rm[i] = lm[src];
+        }
     }
     __syncthreads();
 
@@ -890,8 +926,25 @@ __global__ __launch_bounds__(kThreads) void k_level2_points(
             sk *= isc;
         }
         // ring lenses: inside the (2R+1)^2 block, outside the 3 x 3 block
-        const int32_t yl = max(0, cy - kRing), yh = min(g.n1y - 1, cy + kRing);
-        for (int32_t row = yl; row <= yh; ++row) {
+        auto ring_lens = [&](double X, double Y, double M) {
+            const double wr = x0 - X, wi = y0 - Y;
+            // 1/|w|^2: reciprocal estimate and one Newton step (~2^-48)
+            const double rr = fma(wr, wr, wi * wi);
+            double inv = __builtin_amdgcn_rcp(rr);
+            inv = fma(inv, fma(-rr, inv, 1.0), inv);
+            const cplx u = {wr * inv, -wi * inv};
+            cplx t1 = UNIT ? u : cplx{M * u.r, M * u.i};
+            c[0].r += t1.r; c[0].i += t1.i;
+            cplx t2 = cmul(t1, u);
+            c[1].r -= t2.r; c[1].i -= t2.i;
+            cplx t3 = cmul(t2, u);
+            c[2].r += t3.r; c[2].i += t3.i;
+            cplx t4 = cmul(t3, u);
+            c[3].r -= t4.r; c[3].i -= t4.i;
+            cplx t5 = cmul(t4, u);
+            c[4].r += t5.r; c[4].i += t5.i;
+        };
+        for (int32_t row = ya; row <= yb; ++row) {
             const bool mid = abs(row - cy) <= 1;
             for (int seg = 0; seg < (mid ? 2 : 1); ++seg) {
                 int32_t xa, xb;
@@ -901,25 +954,15 @@ __global__ __launch_bounds__(kThreads) void k_level2_points(
                 xa = max(xa, 0);
                 xb = min(xb, g.n1x - 1);
                 if (xa > xb) continue;
-                const int32_t pb = cell_start[row * g.n1x + xa];
-                const int32_t pe = cell_start[row * g.n1x + xb + 1];
-                for (int32_t pl = pb; pl < pe; ++pl) {
-                    const double wr = x0 - lx[pl], wi = y0 - ly[pl];
-                    // 1/|w|^2: reciprocal estimate and one Newton step (~2^-48)
-                    const double rr = fma(wr, wr, wi * wi);
-                    double inv = __builtin_amdgcn_rcp(rr);
-                    inv = fma(inv, fma(-rr, inv, 1.0), inv);
-                    const cplx u = {wr * inv, -wi * inv};
-                    cplx t1 = UNIT ? u : cplx{lm[pl] * u.r, lm[pl] * u.i};
-                    c[0].r += t1.r; c[0].i += t1.i;
-                    cplx t2 = cmul(t1, u);
-                    c[1].r -= t2.r; c[1].i -= t2.i;
-                    cplx t3 = cmul(t2, u);
-                    c[2].r += t3.r; c[2].i += t3.i;
-                    cplx t4 = cmul(t3, u);
-                    c[3].r -= t4.r; c[3].i -= t4.i;
-                    cplx t5 = cmul(t4, u);
-                    c[4].r += t5.r; c[4].i += t5.i;
+                const int r = row - ya;
+                const int32_t pb = s_cs[r][xa - ua], pe = s_cs[r][xb + 1 - ua];
+                if constexpr (STAGED) {
+                    const int32_t off = s_rb[r] - s_cs[r][0];
+                    const int32_t end = min(pe + off, kRingCap);
+                    for (int32_t pl = pb + off; pl < end; ++pl)
+                        ring_lens(s_rx[pl], s_ry[pl], UNIT ? 1.0 : s_rm[pl]);
+                } else {
+                    for (int32_t pl = pb; pl < pe; ++pl) ring_lens(lx[pl], ly[pl], UNIT ? 1.0 : lm[pl]);
                 }
             }
         }
@@ -1942,6 +1985,23 @@ int64_t lenses_in(const irs_plan_s *p, int64_t xa, int64_t xb, int64_t ya, int64
     return n;
 }
 
+// whether every workgroup of the level-2 points kernel (four cells of a row)
+// finds its cells' ring lenses, a block of 7 x 10 cells, within kRingCap;
+// computed once per plan from the host copy of the cell table
+bool ring_fits(irs_plan_s *p)
+{
+    if (p->ring_fit < 0) {
+        const DevGeom &g = p->dg;
+        bool ok = true;
+        for (int64_t cy = 0; cy < g.n1y && ok; ++cy)
+            for (int64_t cx0 = 0; cx0 < g.n1x && ok; cx0 += kCellsPerBlock)
+                ok = lenses_in(p, cx0 - kRing, cx0 + kCellsPerBlock + kRing, cy - kRing,
+                               cy + kRing + 1) <= kRingCap;
+        p->ring_fit = ok ? 1 : 0;
+    }
+    return p->ring_fit == 1;
+}
+
 // super rows [Ya, Yb] that are not cached, in runs of consecutive rows
 irs_status ensure_super_rows(irs_plan_s *p, int64_t Ya, int64_t Yb, double *flops)
 {
@@ -2482,11 +2542,16 @@ irs_status level2_band(irs_plan_s *p, int64_t c0, int64_t c1, double *coef, Call
     do {                                                                                      \
         if (cs && (st2 = cs->end(s)) != IRS_OK) return st2;                                  \
         if (cs && (st2 = cs->begin(s, 2)) != IRS_OK) return st2;                             \
-        hipLaunchKernelGGL((k_level2_points<U, PP, false>), dim3(nbB), dim3(kThreads), 0, s, \
-                           g, p->d_x, p->d_y, p->d_m, p->d_cell_start, (int32_t)c0, nxb,      \
-                           nchunk, fold, p->d_part, coef);                                   \
+        if (ring_fits(p))                                                                     \
+            hipLaunchKernelGGL((k_level2_points<U, PP, false, true>), dim3(nbB), dim3(kThreads), \
+                               0, s, g, p->d_x, p->d_y, p->d_m, p->d_cell_start, (int32_t)c0, \
+                               nxb, nchunk, fold, p->d_part, coef);                          \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_level2_points<U, PP, false, false>), dim3(nbB), dim3(kThreads), \
+                               0, s, g, p->d_x, p->d_y, p->d_m, p->d_cell_start, (int32_t)c0, \
+                               nxb, nchunk, fold, p->d_part, coef);                          \
         if (g.sheet)                                                                          \
-            hipLaunchKernelGGL((k_level2_points<U, PP, true>), dim3(nbB), dim3(kThreads), 0,  \
+            hipLaunchKernelGGL((k_level2_points<U, PP, true, false>), dim3(nbB), dim3(kThreads), 0, \
                                s, g, p->d_x, p->d_y, p->d_m, p->d_cell_start, (int32_t)c0,    \
                                nxb, nchunk, fold, p->d_part, coef);                          \
     } while (0)

@@ -76,6 +76,7 @@ struct irs_plan_s {
     int64_t coef_c0 = -1, coef_c1 = -2;   // level-1 rows whose coefficients it holds now
     double *d_part = nullptr;             // per-cell expansions (or per-chunk partials)
     size_t part_bytes = 0;
+    int ring_fit = -1;                    // level-2 points may stage ring lenses (-1: unknown)
     // Two-level distant field: expansions of the super cells, kept while the
     // plan lives (its lenses never change); super_ok[Y]: row Y is computed.
     double *d_super = nullptr;

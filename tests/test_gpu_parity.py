@@ -172,6 +172,57 @@ def test_interp_lenses_on_rays(irs, offset):
     assert np.all(np.isfinite(a1)) and np.all(np.isfinite(a2))
     assert e.max() < 1e-10
     assert np.mean(px == ref["pix"]) >= 1 - 1e-5
+def _ring_block_max(cs, n1x, n1y):
+    """Most lenses in one block of 7 rows x 10 columns of level-1 cells: the
+    ring lenses of four adjacent cells of a row (cell columns 4k .. 4k+3),
+    which the level-2 points kernel stages in LDS when no block holds more
+    than 768."""
+    cnt = np.diff(np.asarray(cs, dtype=np.int64)).reshape(n1y, n1x)
+    pre = np.zeros((n1y + 1, n1x + 1), np.int64)
+    pre[1:, 1:] = cnt.cumsum(0).cumsum(1)
+    best = 0
+    for cy in range(n1y):
+        ya, yb = max(0, cy - 3), min(n1y, cy + 4)
+        for cx0 in range(0, n1x, 4):
+            xa, xb = max(0, cx0 - 3), min(n1x, cx0 + 7)
+            best = max(best, int(pre[yb, xb] - pre[ya, xb] - pre[yb, xa] + pre[ya, xa]))
+    return best
+
+
+@pytest.mark.parametrize("cluster", [0, 1200])
+def test_interp_clustered_lenses(irs, cluster):
+    """The level-2 points kernel reads the ring lenses (between a cell's 3 x 3
+    and 7 x 7 blocks) from LDS when every four-cell workgroup's block of
+    cells holds few enough of them, else from global memory.  A uniform
+    field takes the first form; a cluster of 1200 lenses within a third of a
+    cell side takes the second.  Both equal the oracle's interpolation to
+    rounding."""
+    c0 = Case(0.45, 0.05, 0.45, 6.0, 64, n_rays=300_000, seed=81)
+    a1, a2, b1, b2 = c0.geo.rect
+    rng = np.random.default_rng(82)
+    side = np.sqrt((a2 - a1) * (b2 - b1) / (c0.lenses.n + cluster))   # level-1 side after
+    r = side / 3 * np.sqrt(rng.random(cluster))
+    t = 2 * np.pi * rng.random(cluster)
+    xc, yc = a1 + 0.31 * (a2 - a1), b1 + 0.43 * (b2 - b1)
+    L = synth.Lenses(np.concatenate([c0.lenses.x, xc + r * np.cos(t)]),
+                     np.concatenate([c0.lenses.y, yc + r * np.sin(t)]), None)
+    c = Case(0.45, 0.05, 0.45, 6.0, 64, n_rays=300_000, lenses=L)
+    g = c.geo
+    ref = c.oracle_interp()
+    with c.plan("interp", "fp64") as pl:
+        cs, _ = pl.level1()
+        a1d, a2d, px = pl.deflect_grid(0, pl.n_rays)
+        counts, _ = pl.shoot_map()
+    most = _ring_block_max(cs, g.n1x, g.n1y)
+    e = rel_err(a1d, a2d, ref["alpha1"], ref["alpha2"])
+    say(f"cluster {cluster}: {L.n} lenses, cells {g.n1x}x{g.n1y}, most ring lenses of a "
+        f"workgroup {most}, max e_r vs O-2 {e.max():.3e}")
+    assert (most > 768) == (cluster > 0)
+    assert e.max() < 1e-10
+    assert np.mean(px == ref["pix"]) >= 1 - 1e-5
+    check_map(counts, ref["counts"], px, ref["pix"], min_agree=1 - 1e-5, max_rel_l1=1e-5)
+
+
 @pytest.mark.parametrize("method,precision", [("direct", "fp64"), ("direct", "fp32"),
                                               ("interp", "fp64")])
 def test_star_free_map_exact(irs, method, precision):
