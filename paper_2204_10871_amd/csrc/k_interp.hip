@@ -413,6 +413,7 @@ __global__ __launch_bounds__(kThreads) void k_level2_expand(
         // two lenses per lane at a time: two independent power chains
 #pragma unroll
         for (int k = 0; k < kThreads / kWave; k += 2) {
+            if (k * kWave >= cnt) break;                  // the stage's lenses are done
             double tr[2], ti[2], vr[2], vi[2];
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
@@ -512,6 +513,11 @@ __global__ __launch_bounds__(kThreads) void k_super_expand(
     double zr, zi, sS;
     super_centre(g, X, Y, ks, zr, zi, sS);
     const double isc = 1.0 / sS;
+    // the 5 x 5 block of super cells around (X, Y), in level-1 cells: a lens
+    // in cell column c lies in super column c / ks, outside the block exactly
+    // when c < (X - R_S) ks or c >= (X + R_S + 1) ks
+    const int32_t ex0 = (X - kSuperR) * ks, ex1 = (X + kSuperR + 1) * ks;
+    const int32_t ey0 = (Y - kSuperR) * ks, ey1 = (Y + kSuperR + 1) * ks;
     const int32_t lo = chunk * chunk_len;
     const int32_t hi = min(nl, lo + chunk_len);
     // L[2n], L[2n + 1]: real and imaginary part of term n; zero padding to NV
@@ -547,6 +553,7 @@ __global__ __launch_bounds__(kThreads) void k_super_expand(
         const int cnt = min(kThreads, hi - base);
 #pragma unroll
         for (int k = 0; k < kThreads / kWave; k += 2) {
+            if (k * kWave >= cnt) break;                  // the stage's lenses are done
             double tr[2], ti[2], vr[2], vi[2];
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
@@ -555,8 +562,8 @@ __global__ __launch_bounds__(kThreads) void k_super_expand(
                 double Xl = zr + sS, Yl = zi, M = 0.0;     // harmless stand-in
                 if (use) {
                     const uint32_t c = s_c[t];
-                    const int32_t sx = (int32_t)(c & 0xffffu) / ks, sy = (int32_t)(c >> 16) / ks;
-                    use = abs(sx - X) > kSuperR || abs(sy - Y) > kSuperR;
+                    const int32_t lcx = (int32_t)(c & 0xffffu), lcy = (int32_t)(c >> 16);
+                    use = lcx < ex0 || lcx >= ex1 || lcy < ey0 || lcy >= ey1;
                     if (use) {
                         Xl = s_x[t];
                         Yl = s_y[t];
@@ -664,6 +671,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_level2_near(
     }
     __syncthreads();
     const double sc = kc * fmax(g.w1, g.h1), isc = 1.0 / sc;
+    // the child's exclusion block in level-1 cells (a lens in cell column c
+    // lies in child column c / kc: outside the block exactly when
+    // c < (cx - rc) kc or c >= (cx + rc + 1) kc)
+    const int32_t ex0 = (cx - rc) * kc, ex1 = (cx + rc + 1) * kc;
+    const int32_t ey0 = (cy - rc) * kc, ey1 = (cy + rc + 1) * kc;
     double zSr, zSi, sS;
     super_centre(g, X, Y, ks, zSr, zSi, sS);
     if (tid == 0) {
@@ -725,6 +737,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_level2_near(
         const int cnt = min(kThreads, total - base);
 #pragma unroll
         for (int k = 0; k < kThreads / kWave; k += 2) {
+            if (k * kWave >= cnt) break;                  // the stage's lenses are done
             double tr[2], ti[2], vr[2], vi[2];
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
@@ -733,8 +746,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_level2_near(
                 double Xl = zcr + sc, Yl = zci, M = 0.0;   // harmless stand-in
                 if (use) {
                     const uint32_t c = s_c[t];
-                    const int32_t lcx = (int32_t)(c & 0xffffu) / kc, lcy = (int32_t)(c >> 16) / kc;
-                    use = abs(lcx - cx) > rc || abs(lcy - cy) > rc;
+                    const int32_t lcx = (int32_t)(c & 0xffffu), lcy = (int32_t)(c >> 16);
+                    use = lcx < ex0 || lcx >= ex1 || lcy < ey0 || lcy >= ey1;
                     if (use) {
                         Xl = s_x[t];
                         Yl = s_y[t];
