@@ -1869,7 +1869,7 @@ int super_order(const irs_plan_s *p)
     // excluded lens: independent of the super-cell side
     const double rho = 0.5 * std::sqrt(g.w1 * g.w1 + g.h1 * g.h1) /
                        ((kSuperR + 0.5) * std::min(g.w1, g.h1));
-    for (int P : {32, 48}) {
+    for (int P : {32, 40, 48}) {
         double c4 = (double)P * (P - 1) * (P - 2) * (P - 3) / 24.0;
         if (c4 * std::pow(rho, P - 4) / std::pow(1.0 - rho, 5) < 1e-14) return P;
     }
@@ -2039,9 +2039,11 @@ irs_status ensure_super_rows(irs_plan_s *p, int64_t Ya, int64_t Yb, double *flop
                        kChunkLens, ks, p->d_super_part)
         if (p->unit_mass) {
             if (PS == 32) IRS_SE(true, 32);
+            else if (PS == 40) IRS_SE(true, 40);
             else IRS_SE(true, 48);
         } else {
             if (PS == 32) IRS_SE(false, 32);
+            else if (PS == 40) IRS_SE(false, 40);
             else IRS_SE(false, 48);
         }
 #undef IRS_SE
@@ -2112,9 +2114,11 @@ irs_status ensure_mid_rows(irs_plan_s *p, int64_t Ma, int64_t Mb, double *flops)
                        (int32_t)m0, nxb, ks, km, kSuperR, nMx, 0, dst)
         if (p->unit_mass) {
             if (PS == 32) IRS_MID(true, 32);
+            else if (PS == 40) IRS_MID(true, 40);
             else IRS_MID(true, 48);
         } else {
             if (PS == 32) IRS_MID(false, 32);
+            else if (PS == 40) IRS_MID(false, 40);
             else IRS_MID(false, 48);
         }
 #undef IRS_MID
@@ -2199,11 +2203,25 @@ irs_status launch_level2_expand(irs_plan_s *p, int64_t c0, int64_t c1, double *f
                        p->d_x, p->d_y, p->d_m, p->d_cxy, p->d_cell_start, parent, nSx,          \
                        (int32_t)c0, nxb, ks, 1, kRing, g.n1x, fold_sheet ? 1 : 0, p->d_part)
     if (p->unit_mass) {
-        if (P == 32) { if (PS == 32) IRS_LN(true, 32, 32); else IRS_LN(true, 32, 48); }
-        else { if (PS == 32) IRS_LN(true, 48, 32); else IRS_LN(true, 48, 48); }
+        if (P == 32) {
+            if (PS == 32) IRS_LN(true, 32, 32);
+            else if (PS == 40) IRS_LN(true, 32, 40);
+            else IRS_LN(true, 32, 48);
+        } else {
+            if (PS == 32) IRS_LN(true, 48, 32);
+            else if (PS == 40) IRS_LN(true, 48, 40);
+            else IRS_LN(true, 48, 48);
+        }
     } else {
-        if (P == 32) { if (PS == 32) IRS_LN(false, 32, 32); else IRS_LN(false, 32, 48); }
-        else { if (PS == 32) IRS_LN(false, 48, 32); else IRS_LN(false, 48, 48); }
+        if (P == 32) {
+            if (PS == 32) IRS_LN(false, 32, 32);
+            else if (PS == 40) IRS_LN(false, 32, 40);
+            else IRS_LN(false, 32, 48);
+        } else {
+            if (PS == 32) IRS_LN(false, 48, 32);
+            else if (PS == 40) IRS_LN(false, 48, 40);
+            else IRS_LN(false, 48, 48);
+        }
     }
 #undef IRS_LN
     IRS_HIP(hipGetLastError());
