@@ -77,23 +77,33 @@ __device__ __forceinline__ double log_arg(double u, double v, bool top)
     return th;
 }
 
+// corner c's signed terms of I1 and I2 (corners (a1,b1) (a2,b1) (a2,b2) (a1,b2))
+__device__ __forceinline__ void sheet_unit_corner(const DevGeom &g, double t1, double t2, int c,
+                                                  double &p1, double &p2)
+{
+    const double a = (c == 0 || c == 3) ? g.a1 : g.a2;
+    const double b = (c < 2) ? g.b1 : g.b2;
+    const double sgn = (c == 0 || c == 2) ? 1.0 : -1.0;
+    const double u = t1 - a, v = t2 - b;
+    const double lr = log(u * u + v * v);
+    const double tu = (u != 0.0) ? u * atan(v / u) : 0.0;
+    const double tv = (v != 0.0) ? v * atan(u / v) : 0.0;
+    const double lv = (v != 0.0) ? 0.5 * v * lr : 0.0;
+    const double lu = (u != 0.0) ? 0.5 * u * lr : 0.0;
+    p1 = sgn * (lv + tu);
+    p2 = sgn * (lu + tv);
+}
+
 __device__ __forceinline__ void sheet_unit(const DevGeom &g, double t1, double t2,
                                            double &I1, double &I2)
 {
     double s1 = 0.0, s2 = 0.0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        const double a = (c == 0 || c == 3) ? g.a1 : g.a2;
-        const double b = (c < 2) ? g.b1 : g.b2;
-        const double sgn = (c == 0 || c == 2) ? 1.0 : -1.0;   // (a1,b1) (a2,b1) (a2,b2) (a1,b2)
-        const double u = t1 - a, v = t2 - b;
-        const double lr = log(u * u + v * v);
-        const double tu = (u != 0.0) ? u * atan(v / u) : 0.0;
-        const double tv = (v != 0.0) ? v * atan(u / v) : 0.0;
-        const double lv = (v != 0.0) ? 0.5 * v * lr : 0.0;
-        const double lu = (u != 0.0) ? 0.5 * u * lr : 0.0;
-        s1 += sgn * (lv + tu);
-        s2 += sgn * (lu + tv);
+        double p1, p2;
+        sheet_unit_corner(g, t1, t2, c, p1, p2);
+        s1 += p1;
+        s2 += p2;
     }
     I1 = s1;
     I2 = s2;

@@ -120,30 +120,40 @@ __device__ __forceinline__ bool sheet_fold_ok(const DevGeom &g, int32_t cx, int3
     return hd2 <= 0.04 * (du * du + dv * dv);
 }
 
+// Corner c's part of the sheet's terms 0 and 1 of a cell expansion about
+// (x, y), whose sums over the four corners sheet_cell_term takes: for term 0
+// the signed terms of I1, I2 (sheet_unit); for term 1 the real and
+// imaginary part of s_c Log(z - c).  The logarithms and arctangents make
+// these the costly terms, so the cell kernel takes one corner a lane.
+__device__ __forceinline__ cplx sheet_corner_low(const DevGeom &g, double x, double y, int c,
+                                                 bool term1)
+{
+    if (!term1) {
+        double p1, p2;
+        sheet_unit_corner(g, x, y, c, p1, p2);
+        return {p1, p2};
+    }
+    const double a = (c == 0 || c == 3) ? g.a1 : g.a2;
+    const double b = (c < 2) ? g.b1 : g.b2;
+    const double sgn = (c == 0 || c == 2) ? 1.0 : -1.0;
+    const double u = x - a, v = y - b;
+    return {sgn * 0.5 * log(u * u + v * v), sgn * log_arg(u, v, c >= 2)};
+}
+
 // Term k of the sheet's part of a cell expansion about (x, y) with scale s,
 // in the cell expansions' convention ((1/s) sum_k L_k u^k, u = (z - zc)/s):
 // -kappa_* s^(k+1) G^(k)(zc)/k!, with G = F - conj(z), G' = 1 - (i/pi) sum_c
 // s_c Log(z - c), G^(k)/k! = -(i/pi) (-1)^k/(k (k-1)) sum_c s_c/(z - c)^(k-1).
-__device__ cplx sheet_cell_term(const DevGeom &g, double x, double y, double s, int k)
+// For k = 0 and 1, q is the sum of sheet_corner_low over the four corners.
+__device__ cplx sheet_cell_term(const DevGeom &g, double x, double y, double s, int k, cplx q)
 {
     const double ipi = 1.0 / M_PI;
     double vr, vi;
     if (k == 0) {
-        double I1, I2;
-        sheet_unit(g, x, y, I1, I2);
-        vr = (I1 * ipi - x) * s;
-        vi = (-I2 * ipi + y) * s;
+        vr = (q.r * ipi - x) * s;
+        vi = (-q.i * ipi + y) * s;
     } else if (k == 1) {
-        double lr = 0.0, li = 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const double a = (c == 0 || c == 3) ? g.a1 : g.a2;
-            const double b = (c < 2) ? g.b1 : g.b2;
-            const double sgn = (c == 0 || c == 2) ? 1.0 : -1.0;
-            const double u = x - a, v = y - b;
-            lr += sgn * 0.5 * log(u * u + v * v);
-            li += sgn * log_arg(u, v, c >= 2);
-        }
+        const double lr = q.r, li = q.i;
         vr = (1.0 + li * ipi) * s * s;
         vi = -lr * ipi * s * s;
     } else {
@@ -806,10 +816,21 @@ __global__ __launch_bounds__(kThreads, 2) void k_level2_near(
         const double f = s_F[k];
         Tr = (ar0 + ar1) * f;
         Ti = (ai0 + ai1) * f;
-        if (fold && live && k < P && sheet_fold_ok(g, cx, cy)) {   // cells only: the sheet's series
-            const cplx t = sheet_cell_term(g, zcr, zci, sc, k);
-            Tr += t.r;
-            Ti += t.i;
+        if (fold && live && sheet_fold_ok(g, cx, cy)) {   // cells only, wave-uniform: the sheet's series
+            // terms 0 and 1 one corner a lane (lanes 0-3: term 0, lanes 4-7:
+            // term 1), summed over each group of four lanes
+            cplx q = lane < 8 ? sheet_corner_low(g, zcr, zci, lane & 3, lane >= 4) : cplx{0.0, 0.0};
+            q.r += __shfl_xor(q.r, 1);
+            q.i += __shfl_xor(q.i, 1);
+            q.r += __shfl_xor(q.r, 2);
+            q.i += __shfl_xor(q.i, 2);
+            const int src = k == 1 ? 4 : 0;
+            q = {__shfl(q.r, src), __shfl(q.i, src)};
+            if (k < P) {
+                const cplx t = sheet_cell_term(g, zcr, zci, sc, k, q);
+                Tr += t.r;
+                Ti += t.i;
+            }
         }
     }
     wave_reduce_scatter(L);
