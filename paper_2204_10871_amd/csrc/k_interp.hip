@@ -863,6 +863,9 @@ __device__ __forceinline__ bool sheet_closed_form(const DevGeom &g, int32_t fold
 // (ring_fits), the other reads them from global memory.
 constexpr int kRingCap = 768;
 constexpr int kRingRows = 2 * kRing + 1, kRingCols = kCellsPerBlock + 2 * kRing;
+// a cell's ring as runs of cells in one row: one run in each of the 2 kRing - 2
+// outer rows, two (left and right of the 3 x 3 block) in each of the 3 inner
+constexpr int kRingSegs = (kRingRows - 3) + 2 * 3;
 
 template <bool UNIT, int P, bool CLOSED, bool STAGED>
 __global__ __launch_bounds__(kThreads) void k_level2_points(
@@ -876,6 +879,7 @@ __global__ __launch_bounds__(kThreads) void k_level2_points(
     __shared__ double s_rx[kCap], s_ry[kCap], s_rm[UNIT ? 1 : kCap];
     __shared__ int32_t s_cs[kRingRows][kRingCols + 1];   // cell_start over the block
     __shared__ int32_t s_rb[kRingRows + 1];              // LDS offset of each row
+    __shared__ int2 s_seg[kCellsPerBlock][kRingSegs];    // STAGED: each cell's runs in LDS
     const int tid = threadIdx.x;
     const int32_t cy = cy0 + (int32_t)(blockIdx.x / (uint32_t)nxb);
     const int32_t cx0 = (int32_t)(blockIdx.x % (uint32_t)nxb) * kCellsPerBlock;
@@ -921,6 +925,31 @@ __global__ __launch_bounds__(kThreads) void k_level2_points(
             s_rx[i] = lx[src];
             s_ry[i] = ly[src];
             if (!UNIT) s_rm[i] = lm[src];
+        }
+        // each cell's runs of ring cells as ranges of the staged lenses, in
+        // row order (rows cy - kRing .. cy + kRing; left run before right)
+        if (tid < kCellsPerBlock * kRingSegs) {
+            const int w = tid / kRingSegs, sg = tid % kRingSegs;
+            const int outer = kRing - 1;                      // outer rows on each side
+            int dr, kind;                                     // kind 0: whole, 1: left, 2: right
+            if (sg < outer) { dr = sg - kRing; kind = 0; }
+            else if (sg < outer + 6) { dr = (sg - outer) / 2 - 1; kind = 1 + ((sg - outer) & 1); }
+            else { dr = sg - outer - 6 + 2; kind = 0; }
+            const int32_t row = cy + dr, ccx = cx0 + w;
+            int2 be = {0, 0};
+            if (row >= ya && row <= yb && ccx < g.n1x) {
+                int32_t xa = kind == 2 ? ccx + 2 : ccx - kRing;
+                int32_t xb = kind == 1 ? ccx - 2 : ccx + kRing;
+                xa = max(xa, 0);
+                xb = min(xb, g.n1x - 1);
+                if (xa <= xb) {
+                    const int r = row - ya;
+                    const int32_t off = s_rb[r] - s_cs[r][0];
+                    be.x = min(s_cs[r][xa - ua] + off, kRingCap);
+                    be.y = min(s_cs[r][xb + 1 - ua] + off, kRingCap);
+                }
+            }
+            s_seg[w][sg] = be;
         }
     }
     __syncthreads();
@@ -978,24 +1007,24 @@ __global__ __launch_bounds__(kThreads) void k_level2_points(
             cplx t5 = cmul(t4, u);
             c[4].r += t5.r; c[4].i += t5.i;
         };
-        for (int32_t row = ya; row <= yb; ++row) {
-            const bool mid = abs(row - cy) <= 1;
-            for (int seg = 0; seg < (mid ? 2 : 1); ++seg) {
-                int32_t xa, xb;
-                if (!mid) { xa = ccx - kRing; xb = ccx + kRing; }
-                else if (seg == 0) { xa = ccx - kRing; xb = ccx - 2; }
-                else { xa = ccx + 2; xb = ccx + kRing; }
-                xa = max(xa, 0);
-                xb = min(xb, g.n1x - 1);
-                if (xa > xb) continue;
-                const int r = row - ya;
-                const int32_t pb = s_cs[r][xa - ua], pe = s_cs[r][xb + 1 - ua];
-                if constexpr (STAGED) {
-                    const int32_t off = s_rb[r] - s_cs[r][0];
-                    const int32_t end = min(pe + off, kRingCap);
-                    for (int32_t pl = pb + off; pl < end; ++pl)
-                        ring_lens(s_rx[pl], s_ry[pl], UNIT ? 1.0 : s_rm[pl]);
-                } else {
+        if constexpr (STAGED) {
+            for (int sg = 0; sg < kRingSegs; ++sg) {
+                const int2 be = s_seg[w][sg];
+                for (int32_t pl = be.x; pl < be.y; ++pl) ring_lens(s_rx[pl], s_ry[pl], UNIT ? 1.0 : s_rm[pl]);
+            }
+        } else {
+            for (int32_t row = ya; row <= yb; ++row) {
+                const bool mid = abs(row - cy) <= 1;
+                for (int seg = 0; seg < (mid ? 2 : 1); ++seg) {
+                    int32_t xa, xb;
+                    if (!mid) { xa = ccx - kRing; xb = ccx + kRing; }
+                    else if (seg == 0) { xa = ccx - kRing; xb = ccx - 2; }
+                    else { xa = ccx + 2; xb = ccx + kRing; }
+                    xa = max(xa, 0);
+                    xb = min(xb, g.n1x - 1);
+                    if (xa > xb) continue;
+                    const int r = row - ya;
+                    const int32_t pb = s_cs[r][xa - ua], pe = s_cs[r][xb + 1 - ua];
                     for (int32_t pl = pb; pl < pe; ++pl) ring_lens(lx[pl], ly[pl], UNIT ? 1.0 : lm[pl]);
                 }
             }
