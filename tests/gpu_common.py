@@ -60,6 +60,20 @@ class Case:
         return orc.shoot_interp(self.geo, self.lenses, cs, perm, coef, threads=THREADS, **kw)
 
 
+def super_order(geo):
+    """Terms of the super- and mid-cell expansions the library takes for a
+    geometry: the smallest of 32, 40, 48 whose truncation of c_4,
+    C(P,4) rho^(P-4)/(1-rho)^5 with rho = (half cell diagonal)/(2.5 x the
+    shorter cell side), stays below 1e-14 (0: none does)."""
+    w, h = geo.ix / geo.n1x, geo.iy / geo.n1y
+    rho = 0.5 * np.hypot(w, h) / (2.5 * min(w, h))
+    for P in (32, 40, 48):
+        c4 = P * (P - 1) * (P - 2) * (P - 3) / 24.0
+        if c4 * rho ** (P - 4) / (1.0 - rho) ** 5 < 1e-14:
+            return P
+    return 0
+
+
 def rel_err(a1, a2, r1, r2):
     return np.hypot(a1 - r1, a2 - r2) / np.maximum(np.hypot(r1, r2), 1.0)
 

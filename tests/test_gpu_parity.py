@@ -8,7 +8,7 @@ import pytest
 
 import oracle as orc
 import synth
-from gpu_common import Case, check_map, rel_err
+from gpu_common import Case, check_map, rel_err, super_order
 
 pytestmark = pytest.mark.gpu
 
@@ -345,6 +345,7 @@ def test_three_level_field_equals_paper_form(irs):
              n_lens=30000, seed=63)
     g = c.geo
     assert g.q == 4
+    assert super_order(g) == 40        # the 40-term super and mid instances
     L = c.lenses
     out = {}
     for paper in (False, True):
@@ -376,6 +377,8 @@ def test_level2_local_expansion_equals_paper_form(irs, kind):
         c = Case(0.45, 0.05, 0.45, 11.75, 64, n_rays=300_000, seed=62)
     g = c.geo
     say(f"level-2 forms {kind}: cells {g.n1x}x{g.n1y} w1={g.ix / g.n1x:.3f} h1={g.iy / g.n1y:.3f}")
+    # super and mid series: 40 terms for square cells, 48 for these oblong ones
+    assert super_order(g) == (40 if kind == "square_cells" else 48)
     import paper_2204_10871_amd as irs_mod
     L = c.lenses
     out = {}
