@@ -637,10 +637,10 @@ __global__ __launch_bounds__(kThreads) void k_super_reduce(const double *__restr
 // children from c0:  out[(((cy - c0) nCx + cx) P + n) 2 + c].
 constexpr int kSuperRows = (2 * kSuperR + 1) * kSuperKMax; // cell rows of a parent block, at most
 
-// Two waves a SIMD: the 48-term instances need a few more registers than
-// 256 and would otherwise run one wave a SIMD (a few spills cost less).
+// Waves a SIMD: three for the 32-term children (168 registers and a few
+// spills beat two waves without), two for the 40- and 48-term ones.
 template <bool UNIT, int P, int PS>
-__global__ __launch_bounds__(kThreads, 2) void k_level2_near(
+__global__ __launch_bounds__(kThreads, P == 32 ? 3 : 2) void k_level2_near(
     DevGeom g, const double *__restrict__ lx, const double *__restrict__ ly,
     const double *__restrict__ lm, const uint32_t *__restrict__ lcxy,
     const int32_t *__restrict__ cell_start, const double *__restrict__ super, int32_t nSx,
